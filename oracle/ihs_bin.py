@@ -1,0 +1,255 @@
+"""IHS-BIN in FP64, step by step in the paper's order (diagnostic oracle).
+
+Notation follows Section 4.  For an interval [lo, hi] with centre lam0:
+    P_S = (A^T S^T S A + lam0 I)^-1                                 (Section 4)
+    M(lam) = I - tau P_S (A^T A + lam I)                    (Eq. (equ:ihs))
+    x_k(lam) = tau sum_{i<k} M(lam)^i P_S A^T b
+             = tau sum_{j<k} (tau (lam - ref))^j  ut_j              (Proposition)
+with ut_j = sum_{i>=j} u_{i,j} and the recursion Eq. (equ:upd)
+    u_{0,0} = P_S A^T b,
+    u_{i+1,0} = (I - tau P_S H) u_{i,0},
+    u_{i+1,j} = (I - tau P_S H) u_{i,j} - P_S u_{i,j-1},   1 <= j <= i,
+    u_{i+1,i+1} = -P_S u_{i,i},
+where H = A^T A + ref I.  ``ref = 0`` is the printed expansion (powers of
+tau*lam); ``ref = lam0`` expands the same polynomial about the interval
+centre, M(lam) = (I - tau P_S (A^T A + lam0 I)) - tau (lam - lam0) P_S, whose
+terms do not grow with i.  Both give the same x_k(lam) in exact arithmetic.
+
+Readings taken where the text is ambiguous:
+* the seed is u_{0,0} = +P_S A^T b as in the Proposition (Algorithm 2 prints
+  a minus sign, which together with Algorithm 3 would return -x);
+* the basis is built once per interval, outside the loop over lambda
+  (Algorithm 3 places it inside the loop but prices it once);
+* L = floor(2 ln(lam_max / lam_min)) intervals (natural log), boundaries
+  lam^(l) = lam_min * beta^(l/L), centre lam0 = sqrt(lam^(l) lam^(l+1))
+  (Section 4.2 and Theorem 1); a lambda on a boundary belongs to the lower
+  interval;
+* step size from the spectrum of P_S (A^T A + lam0 I) in [mu_min, mu_max]:
+  for lam in [lo, hi] the spectrum of P_S (A^T A + lam I) lies in
+  [mu_min lo/lam0, mu_max hi/lam0], and tau = 2 / (c_min + c_max) is the
+  minimizer of max |1 - tau c| over that range (the optimality condition
+  of the proof of Theorem 1); the rate is r = (c_max - c_min)/(c_max + c_min).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import direct
+
+
+# ---------------------------------------------------------------- plan (4.2)
+def num_intervals(lam_min: float, lam_max: float) -> int:
+    """L = floor(2 ln beta), at least 1 (Section 4.2, Section 6.1)."""
+    beta = lam_max / lam_min
+    return max(1, int(math.floor(2.0 * math.log(beta)))) if beta > 1 else 1
+
+
+def plan(lam_min: float, lam_max: float, L: int | None = None):
+    """Interval boundaries lam^(0..L) and centres lam0^(0..L-1)."""
+    if not (lam_min > 0 and lam_max >= lam_min):
+        raise ValueError("need 0 < lam_min <= lam_max")
+    L = L or num_intervals(lam_min, lam_max)
+    beta = lam_max / lam_min
+    grid = np.array([lam_min * beta ** (l / L) for l in range(L + 1)])
+    grid[-1] = lam_max
+    lam0 = np.sqrt(grid[:-1] * grid[1:])
+    return grid, lam0
+
+
+def interval_of(lam: float, grid: np.ndarray) -> int:
+    """Index l with grid[l] <= lam <= grid[l+1]; boundaries go to the lower one."""
+    L = len(grid) - 1
+    l = int(np.searchsorted(grid[1:], lam, side="left"))
+    return min(max(l, 0), L - 1)
+
+
+# ------------------------------------------------------- operators (Section 4)
+class Operator:
+    """A^T A v for dense or CSR A, in FP64, without forming A^T A."""
+
+    def __init__(self, A):
+        if hasattr(A, "row_ptr"):
+            self._A = direct._sparse64(A)
+        else:
+            self._A = np.asarray(A, dtype=np.float64)
+
+    def AtA(self, V):
+        return self._A.T @ (self._A @ V)
+
+    def At(self, B):
+        return self._A.T @ np.asarray(B, dtype=np.float64)
+
+    def dense_gram(self):
+        G = self._A.T @ self._A
+        return np.asarray(G.todense()) if hasattr(G, "todense") else G
+
+
+class Precond:
+    """P_S = (SA^T SA + lam0 I)^-1 applied through its Cholesky factor."""
+
+    def __init__(self, SA: np.ndarray, lam0: float):
+        GS = SA.T @ SA
+        GS[np.diag_indices_from(GS)] += lam0
+        self.lam0 = lam0
+        self.chol = sla.cho_factor(GS, lower=True)
+
+    def __call__(self, V):
+        return sla.cho_solve(self.chol, V)
+
+    def factor(self) -> np.ndarray:
+        return np.tril(self.chol[0])
+
+
+def spectrum_bounds(op: Operator, P: Precond):
+    """Exact extreme eigenvalues of P_S (A^T A + lam0 I) (dense, small d only)."""
+    Lf = P.factor()
+    H = op.dense_gram()
+    H[np.diag_indices_from(H)] += P.lam0
+    X = sla.solve_triangular(Lf, H, lower=True)
+    Bm = sla.solve_triangular(Lf, X.T, lower=True)
+    ev = np.linalg.eigvalsh(0.5 * (Bm + Bm.T))
+    return float(ev[0]), float(ev[-1])
+
+
+def step_size(mu_min: float, mu_max: float, lo: float, hi: float, lam0: float):
+    """tau and predicted rate for the interval [lo, hi] (see module notes)."""
+    cmin = mu_min * lo / lam0
+    cmax = mu_max * hi / lam0
+    return 2.0 / (cmin + cmax), (cmax - cmin) / (cmax + cmin)
+
+
+# --------------------------------------------------- basis (Algorithm 2 / 5)
+def basis(op: Operator, P: Precond, C: np.ndarray, tau: float, k: int,
+          ref: float = 0.0):
+    """ut_0 .. ut_{k-1} (each d x K) by the recursion of the Proposition.
+
+    The working vectors u_j are updated in place for j descending, exactly
+    as Algorithm 2 orders them, so u_{j-1} still holds step i-1 when u_j
+    reads it.  H = A^T A + ref I.
+    """
+    def Hop(V):
+        return op.AtA(V) + ref * V
+
+    u = [None] * k
+    ut = [None] * k
+    u[0] = P(C)
+    ut[0] = u[0].copy()
+    for i in range(1, k):
+        u[i] = -P(u[i - 1])
+        for j in range(i - 1, 0, -1):
+            u[j] = u[j] - P(tau * Hop(u[j]) + u[j - 1])
+        u[0] = u[0] - P(tau * Hop(u[0]))
+        ut[i] = np.zeros_like(u[0])
+        for j in range(i + 1):
+            ut[j] = ut[j] + u[j]
+    return ut
+
+
+def compose(ut, tau: float, lam: float, ref: float = 0.0) -> np.ndarray:
+    """x_k(lam) = tau sum_j (tau (lam - ref))^j ut_j (Algorithm 3 / 6)."""
+    mu = tau * (lam - ref)
+    x = np.zeros_like(ut[0])
+    for j, v in enumerate(ut):
+        x = x + mu ** j * v
+    return tau * x
+
+
+def ihs_iterate(op: Operator, P: Precond, C: np.ndarray, tau: float, lam: float,
+                k: int) -> np.ndarray:
+    """k plain IHS steps x <- x - tau P_S (A^T A x + lam x - A^T b) from 0 (Eq. (equ:ihs))."""
+    x = np.zeros_like(C)
+    for _ in range(k):
+        x = x - tau * P(op.AtA(x) + lam * x - C)
+    return x
+
+
+# ------------------------------------------------------- whole path (Alg. 3)
+@dataclass
+class Interval:
+    lo: float
+    hi: float
+    lam0: float
+    tau: float
+    rate: float
+    k: int
+    ref: float
+    ut: list = field(default_factory=list)
+
+
+def _increment(u_list, tau, lam, ref):
+    mu = tau * (lam - ref)
+    s = np.zeros_like(u_list[0])
+    for j, v in enumerate(u_list):
+        s = s + mu ** j * v
+    return tau * s
+
+
+def basis_adaptive(op, P, C, tau, rate, lo, hi, ref, tol, k_max):
+    """Algorithm 2 with the step count chosen by the endpoint increment test.
+
+    After step i the increment of x(lam) is tau M^i P_S A^T b; the loop stops
+    once its norm times r/(1-r) is below tol * ||x(lam)|| at both interval
+    ends (the worst case over the interval, per the proof of Theorem 1).
+    """
+    u = [P(C)]
+    ut = [u[0].copy()]
+    k = 1
+    for i in range(1, k_max):
+        new = [None] * (i + 1)
+        new[i] = -P(u[i - 1])
+        for j in range(i - 1, 0, -1):
+            new[j] = u[j] - P(tau * (op.AtA(u[j]) + ref * u[j]) + u[j - 1])
+        new[0] = u[0] - P(tau * (op.AtA(u[0]) + ref * u[0]))
+        u = new
+        ut.append(np.zeros_like(u[0]))
+        for j in range(i + 1):
+            ut[j] = ut[j] + u[j]
+        k = i + 1
+        done = True
+        for lam in (lo, hi):
+            inc = np.linalg.norm(_increment(u, tau, lam, ref))
+            xn = np.linalg.norm(compose(ut, tau, lam, ref))
+            if not (inc * rate / max(1e-300, 1.0 - rate) <= tol * xn):
+                done = False
+        if done:
+            break
+    return ut, k
+
+
+def path(A, B, lambdas, SA, lam_min, lam_max, *, L=None, k=None, tol=1e-10,
+         k_max=200, centred=True, taus=None):
+    """IHS-BIN for every lambda: returns (X[T, d, K], list of Interval).
+
+    ``SA`` is the sketched matrix (m x d).  With ``k`` given every interval
+    runs exactly k steps; otherwise the endpoint test above decides.
+    ``taus`` fixes the per-interval step sizes (else the exact spectrum).
+    """
+    op = Operator(A)
+    C = op.At(np.asarray(B).reshape(A.shape[0], -1))
+    grid, lam0s = plan(lam_min, lam_max, L)
+    ivs = []
+    for l in range(len(lam0s)):
+        lo, hi, lam0 = grid[l], grid[l + 1], lam0s[l]
+        P = Precond(np.asarray(SA, dtype=np.float64), lam0)
+        if taus is None:
+            mu_min, mu_max = spectrum_bounds(op, P)
+            tau, rate = step_size(mu_min, mu_max, lo, hi, lam0)
+        else:
+            tau, rate = float(taus[l]), 0.5
+        ref = lam0 if centred else 0.0
+        if k is not None:
+            ut = basis(op, P, C, tau, k, ref)
+            kk = k
+        else:
+            ut, kk = basis_adaptive(op, P, C, tau, rate, lo, hi, ref, tol, k_max)
+        ivs.append(Interval(lo, hi, lam0, tau, rate, kk, ref, ut))
+    lambdas = np.atleast_1d(np.asarray(lambdas, dtype=np.float64))
+    X = np.empty((len(lambdas),) + C.shape)
+    for t, lam in enumerate(lambdas):
+        iv = ivs[interval_of(lam, grid)]
+        X[t] = compose(iv.ut, iv.tau, lam, iv.ref)
+    return X, ivs

@@ -1,0 +1,93 @@
+"""Pins for the oracle's generator and sketches."""
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.linalg import hadamard
+
+import workloads as W
+from oracle import rng, sketch
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_splitmix64_known_answers():
+    want = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    got = [int(rng.draw(0, i)) for i in range(len(want))]
+    assert got == want
+
+
+def test_counter_form_equals_sequential_generator():
+    # the counter form must equal stepping the state by GAMMA one output at a time
+    key = np.uint64(0x1234567)
+    state = int(key)
+    for i in range(50):
+        state = (state + 0x9E3779B97F4A7C15) & (2 ** 64 - 1)
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & (2 ** 64 - 1)
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & (2 ** 64 - 1)
+        z ^= z >> 31
+        assert int(rng.draw(key, i)) == z
+
+
+def test_bucket_range_and_balance():
+    h, s = rng.countsketch_draws(42, 200000, 97)
+    assert h.min() >= 0 and h.max() < 97
+    counts = np.bincount(h[:, 0], minlength=97)
+    assert stats.chisquare(counts).pvalue > 1e-4
+    assert abs(float(s.astype(float).mean())) < 0.01
+
+
+def test_sjlt_blocks():
+    h, s = rng.countsketch_draws(9, 1000, 12, s=3)
+    for b in range(3):
+        assert np.all((h[:, b] >= 4 * b) & (h[:, b] < 4 * (b + 1)))
+    S = sketch.countsketch_matrix(9, 1000, 12, 3).toarray()
+    np.testing.assert_allclose((S * S).sum(0), 1.0)   # each column has unit norm
+
+
+def test_countsketch_apply_equals_dense_matrix():
+    A = W.dense_decay(300, 7, seed=2)
+    h, s = rng.countsketch_draws(5, 300, 16)
+    S = np.zeros((16, 300))
+    S[h[:, 0], np.arange(300)] = s[:, 0]
+    np.testing.assert_allclose(sketch.countsketch_apply(A, 5, 16), S @ A, rtol=1e-13, atol=1e-13)
+
+
+def test_fwht_equals_sylvester_hadamard():
+    X = np.random.default_rng(1).standard_normal((64, 3))
+    np.testing.assert_allclose(sketch.fwht(X), hadamard(64) @ X, rtol=1e-12, atol=1e-12)
+
+
+def test_srht_apply_equals_dense_matrix_and_padding():
+    A = W.dense_decay(50, 4, seed=3)           # n' = 64, 14 zero rows appended
+    S = sketch.srht_matrix(77, 50, 20)
+    np.testing.assert_allclose(sketch.srht_apply(A, 77, 20), S @ A, rtol=1e-12, atol=1e-12)
+
+
+def test_srht_rows_orthogonal():
+    # with n = n', S S^T = (n'/m) * [R_k == R_k'] since (H D)(H D)^T = n' I
+    S = sketch.srht_matrix(4, 128, 16)
+    _, rows, npad = rng.srht_draws(4, 128, 16)
+    same = (rows[:, None] == rows[None, :]).astype(float)
+    np.testing.assert_allclose(S @ S.T, npad / 16 * same, atol=1e-12)
+
+
+def test_gaussian_entries_are_standard_normal():
+    S = rng.gaussian_matrix(3, 50, 4000)
+    z = (S * np.sqrt(50)).reshape(-1)
+    assert abs(z.mean()) < 0.01 and abs(z.var() - 1) < 0.01
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "countsketch"])
+def test_sketch_is_unbiased_isometry(kind):
+    # E[S^T S] = I: averaged over seeds, ||S a||^2 tracks ||a||^2
+    A = W.dense_decay(64, 3, seed=1)
+    ratios = []
+    for seed in range(200):
+        SA = sketch.apply(kind, A, seed, 16)
+        ratios.append(np.sum(SA[:, 0] ** 2) / np.sum(A[:, 0] ** 2))
+    assert abs(np.mean(ratios) - 1.0) < 0.08
