@@ -1,0 +1,231 @@
+/*
+ * ihsbin.h - C ABI of the MI355X ridge-regularization-path solver (IHS-BIN).
+ *
+ * Problem (Section 1, Eq. (least-square); matrix right-hand sides: Section 5.3,
+ * Eq. (least-square-max)):
+ *     x(lam) = argmin_x 0.5*||A x - b||^2 + 0.5*lam*||x||^2  for every lam in a
+ *     grid Lambda inside [lam_min, lam_max],
+ * solved by the iterative Hessian sketch with binomial decomposition
+ * (Section 4: the Proposition, Algorithms 2 and 3; Algorithms 5 and 6 for a
+ * matrix B).  The build step sketches A, factors the sketched Hessian once per
+ * lambda sub-interval (Section 4.2), runs the basis recursion Eq. (equ:upd)
+ * and keeps the lambda-independent basis on the device; the evaluation step
+ * composes x(lam) for any lam in [lam_min, lam_max] from that basis.
+ *
+ * Conventions for every call:
+ *  - Pointers documented "device" must point to device memory of the context's
+ *    device; "host" pointers to host memory.  The caller owns A, B, X and every
+ *    output buffer; the library owns what it allocates inside opaque handles.
+ *  - All device work is enqueued on the stream given to ihsbin_create; a call
+ *    returns after the results it documents are complete on that stream unless
+ *    stated otherwise.  Calls on one context must not overlap.
+ *  - Dense matrices are row-major with a row stride (ld, in elements).
+ *  - Every call returns an ihsbin_status code; no C++ exception crosses the
+ *    ABI.  On failure ihsbin_last_error(ctx) holds a message and the output
+ *    buffers hold unspecified values (except IHSBIN_ENOCONV, see below).
+ *  - Only the over-determined case n >= d is supported (the dual of
+ *    Section 5.2 is not built): n < d returns IHSBIN_EUNSUP.
+ *  - Arithmetic: the sketch, the sketched Hessian, its factors, the basis and
+ *    every product with A run in FP64; A and B are read in their stored type
+ *    (FP32 or FP64, converted exactly on load).
+ */
+#ifndef IHSBIN_H
+#define IHSBIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+typedef enum {
+  IHSBIN_OK = 0,
+  IHSBIN_EINVAL = -1,   /* bad argument (null pointer, size, lam range, CSR) */
+  IHSBIN_ENOMEM = -2,   /* device allocation failed                          */
+  IHSBIN_EHIP = -3,     /* a HIP runtime call failed                         */
+  IHSBIN_ENOTSPD = -4,  /* a sketched Hessian was not positive definite      */
+  IHSBIN_ENOCONV = -5,  /* an interval hit k_max before its stop test passed;
+                           the path is still built and usable                */
+  IHSBIN_ERANGE = -6,   /* a lam outside the prepared [lam_min, lam_max]     */
+  IHSBIN_EUNSUP = -7    /* unsupported combination (n < d, dtype, ...)       */
+} ihsbin_status;
+
+enum { IHSBIN_DENSE = 0, IHSBIN_CSR = 1 };
+enum { IHSBIN_F32 = 0, IHSBIN_F64 = 1 };
+
+/* Sketch families of Section 4 (bullets 1-4). */
+enum {
+  IHSBIN_GAUSSIAN = 0,    /* S_ij ~ N(0, 1/m)                                  */
+  IHSBIN_SRHT = 1,        /* sqrt(n'/m) R (H/sqrt(n')) D, rows with replacement */
+  IHSBIN_COUNTSKETCH = 2, /* one +-1 per column of S                           */
+  IHSBIN_SJLT = 3         /* s stacked CountSketches of m/s rows, 1/sqrt(s)    */
+};
+
+typedef struct ihsbin_ctx ihsbin_ctx;
+typedef struct ihsbin_path ihsbin_path;
+
+/* The data matrix A (n x d).  Dense: row-major, vals = device pointer to
+ * n*ld elements of dtype.  CSR: row_ptr (n+1, device int32, non-decreasing,
+ * row_ptr[0] = 0, row_ptr[n] = nnz), col_idx (nnz, device int32 in [0, d)),
+ * vals (nnz, device, dtype).  Duplicate column entries are summed. */
+typedef struct {
+  int32_t format;          /* IHSBIN_DENSE or IHSBIN_CSR          */
+  int32_t dtype;           /* IHSBIN_F32 or IHSBIN_F64            */
+  int64_t n, d;
+  int64_t ld;              /* dense row stride, >= d               */
+  int64_t nnz;             /* CSR only                             */
+  const void* vals;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+} ihsbin_matrix;
+
+/* Build options.  Fill with ihsbin_opts_default, then override. */
+typedef struct {
+  int32_t sketch;          /* IHSBIN_GAUSSIAN ... IHSBIN_SJLT                   */
+  int32_t sjlt_s;          /* SJLT blocks s (m must be a multiple), else ignored */
+  int64_t m;               /* initial sketch dimension m (Section 4)            */
+  uint64_t seed;           /* sketch seed (SplitMix64 counter-based draws)       */
+  double tol;              /* per-interval stop test: increment bound at both
+                              interval ends relative to ||x|| (default 1e-8)    */
+  int32_t k_max;           /* cap on basis steps k per interval (default 96)    */
+  int32_t k_fixed;         /* > 0: every interval runs exactly k_fixed steps    */
+  int32_t L;               /* intervals; 0 = floor(2 ln(lam_max/lam_min))       */
+  int32_t centred;         /* 1: expand about the interval centre lam0 (default);
+                              0: the printed expansion in powers of tau*lam     */
+  int32_t adaptive_m;      /* 1: grow m until the predicted rate of the lowest
+                              interval is <= rate_target (default 1)            */
+  double rate_target;      /* default 0.7                                      */
+  int64_t m_max;           /* cap for adaptive m; 0 = library default           */
+  int32_t lanczos_steps;   /* spectrum estimate steps per interval (default 16) */
+  int32_t timing;          /* 1: time the A^T A product kernels with events     */
+  const double* taus;      /* host, optional: fixed step size per interval (L)  */
+} ihsbin_opts;
+
+/* Filled by ihsbin_path_build. */
+typedef struct {
+  int64_t m_used;          /* final sketch dimension                             */
+  int32_t L;               /* number of intervals                                */
+  int32_t k_max_used;      /* largest k over intervals                           */
+  int32_t k_sum;           /* sum of k over intervals                            */
+  int32_t n_unconverged;   /* intervals that hit k_max                           */
+  int32_t sketch_trials;   /* sketches drawn (adaptive m)                        */
+  int32_t steps;           /* outer basis steps run (max k - 1)                  */
+  double ms_sketch, ms_factor, ms_spectrum, ms_basis, ms_total;
+  /* A^T A product kernels (Y = A U, then W = A^T Y), timing = 1 only:        */
+  int64_t ata_launches;    /* launches of each of the two product kernels        */
+  double ata_flops;        /* algorithmic flops of all those launches (4*nnz*w)  */
+  double ata_ms_y;         /* summed event time of the Y = A U launches          */
+  double ata_ms_w;         /* summed event time of the W = A^T Y launches (incl.
+                              the split-K reduction)                             */
+  double ata_bytes_a;      /* algorithmic bytes of A read by those launches      */
+} ihsbin_report;
+
+/* Per-interval description of a built path (host arrays of length L). */
+typedef struct {
+  int32_t L, K;
+  int64_t d, m_used;
+  double lam_min, lam_max;
+  int32_t centred;
+} ihsbin_path_info;
+
+/* ------------------------------------------------------------------ calls */
+
+/* Static string for a status code. */
+const char* ihsbin_status_str(int status);
+
+/* Library version string. */
+const char* ihsbin_version(void);
+
+/* Default options: Gaussian sketch, m = 0 (= 2 d), seed 0, tol 1e-8,
+ * k_max 96, L from Section 4.2, centred, adaptive m, rate 0.7, 16 Lanczos
+ * steps, no timing. */
+void ihsbin_opts_default(ihsbin_opts* opts);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t the
+ * library enqueues on (borrowed, not destroyed); NULL means the null stream.
+ * Errors: EINVAL (null out pointer, bad device), EHIP. */
+int ihsbin_create(ihsbin_ctx** ctx, int device, void* hip_stream);
+
+/* Free the context and its workspace.  Paths built on it stay valid until
+ * freed.  NULL is allowed. */
+int ihsbin_destroy(ihsbin_ctx* ctx);
+
+/* Message of the last failed call on ctx (static empty string when none). */
+const char* ihsbin_last_error(const ihsbin_ctx* ctx);
+
+/* Build the lambda-independent basis for [lam_min, lam_max] (Algorithm 3
+ * with the basis hoisted out of the lambda loop; Algorithm 6 for K > 1).
+ * B: device, n x K row-major with row stride ldb (>= K), dtype of A.
+ * On success *path owns the basis on the device.  report may be NULL.
+ * Errors: EINVAL (0 < lam_min <= lam_max violated, sizes), EUNSUP (n < d),
+ * ENOTSPD, ENOMEM, EHIP.  ENOCONV: some interval reached k_max; *path is
+ * still returned and usable (its error estimate is in the report). */
+int ihsbin_path_build(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
+                      int64_t K, int64_t ldb, double lam_min, double lam_max,
+                      const ihsbin_opts* opts, ihsbin_path** path,
+                      ihsbin_report* report);
+
+/* Compose x(lam_t) = tau sum_j (tau (lam_t - ref))^j ut_j for every t
+ * (Algorithm 3 / 6, the lambda loop).  lambdas: host, T values, any order,
+ * each inside [lam_min, lam_max] (else ERANGE).  X: device, T blocks of
+ * d x K row-major (row stride ldx >= K, block stride d*ldx), element type
+ * x_dtype (IHSBIN_F32 or IHSBIN_F64). */
+int ihsbin_path_eval(ihsbin_path* path, const double* lambdas, int64_t T,
+                     void* X, int64_t ldx, int32_t x_dtype);
+
+/* Sizes of a built path. */
+int ihsbin_path_get_info(const ihsbin_path* path, ihsbin_path_info* info);
+
+/* Per-interval plan and result, host arrays of length info.L (any may be
+ * NULL): boundaries lo/hi, centre lam0, step size tau, predicted rate, k. */
+int ihsbin_path_intervals(const ihsbin_path* path, double* lo, double* hi,
+                          double* lam0, double* tau, double* rate, int32_t* k);
+
+/* Copy the basis ut_{l,0..k_l-1} of interval l to `out` (device, k_l blocks
+ * of d x K row-major doubles, contiguous). */
+int ihsbin_path_basis(const ihsbin_path* path, int32_t l, double* out);
+
+/* Free a path (NULL allowed). */
+int ihsbin_path_free(ihsbin_path* path);
+
+/* Build, evaluate and free in one call. */
+int ihsbin_solve_path(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
+                      int64_t K, int64_t ldb, const double* lambdas, int64_t T,
+                      const ihsbin_opts* opts, void* X, int64_t ldx,
+                      int32_t x_dtype, ihsbin_report* report);
+
+/* ---------------------------------------------------- step-level calls */
+
+/* The integer draws of a sketch (Section 4), bit-exact with the SplitMix64
+ * specification in the documentation: COUNTSKETCH/SJLT: idx (device int32,
+ * n*s entries, row-major n x s) and sign (device int8, n*s); SRHT: sign
+ * (device int8, n entries, diagonal D) and idx (device int32, m entries,
+ * sampled rows of the order-n' transform).  GAUSSIAN: EINVAL. */
+int ihsbin_sketch_draws(ihsbin_ctx* ctx, int32_t sketch, uint64_t seed,
+                        int64_t n, int64_t m, int32_t sjlt_s, int32_t* idx,
+                        int8_t* sign);
+
+/* SA = S A (Section 4, Algorithm 3 first line), FP64, m x d row-major into
+ * SA (device, m*d doubles). */
+int ihsbin_sketch_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch,
+                        int32_t sjlt_s, int64_t m, uint64_t seed, double* SA);
+
+/* Lower Cholesky factors of (SA)^T SA + lam0_i I for i < nl (the matrix whose
+ * inverse is P_S, Section 4), and their inverses.  SA: device m x d doubles.
+ * lam0: host, nl values > 0.  Lfac, Linv: device, nl blocks of d x d doubles
+ * row-major (upper triangles zero); Linv may be NULL.  ENOTSPD on failure. */
+int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m,
+                          int64_t d, const double* lam0, int32_t nl,
+                          double* Lfac, double* Linv);
+
+/* W = A^T A U: the two products of every basis step (Algorithm 2).  U: device
+ * d x w doubles (row stride ldu), W: device d x w doubles (row stride ldw). */
+int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U,
+                     int64_t w, int64_t ldu, double* W, int64_t ldw);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IHSBIN_H */

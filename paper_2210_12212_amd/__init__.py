@@ -1,0 +1,297 @@
+"""MI355X ridge-regularization-path solver (IHS-BIN), Python binding.
+
+Every step of the computation runs in the HIP library behind the C ABI of
+include/ihsbin.h; this module only marshals arguments.  PyTorch supplies the
+device memory (tensors) and the stream.  The names follow the C calls:
+
+    ctx  = Context(device=0)
+    path = ctx.path_build(A, B, lam_min, lam_max, sketch="srht", m=1024)
+    X    = path.eval(lambdas)          # T x d x K float64 tensor
+    path.free()
+
+A is a dense CUDA tensor (n x d, float32 or float64, row-major) or a CsrInput
+of CUDA tensors.  B is n x K (or n) in A's dtype.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+__all__ = ["Context", "Path", "CsrInput", "IhsbinError", "solve_path", "default_opts"]
+
+
+class IhsbinError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{L.lib().ihsbin_status_str(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+@dataclass
+class CsrInput:
+    """CSR matrix on the device: int32 row_ptr (n+1), int32 col_idx, vals."""
+    row_ptr: object
+    col_idx: object
+    vals: object
+    n: int
+    d: int
+
+    @property
+    def shape(self):
+        return (self.n, self.d)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return L.F32
+    if t.dtype == torch.float64:
+        return L.F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _require_cuda(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+
+
+def _matrix(A) -> L.Matrix:
+    m = L.Matrix()
+    if isinstance(A, CsrInput):
+        for nm in ("row_ptr", "col_idx", "vals"):
+            _require_cuda(getattr(A, nm), nm)
+        torch = _torch()
+        if A.row_ptr.dtype != torch.int32 or A.col_idx.dtype != torch.int32:
+            raise TypeError("CSR indices must be int32")
+        m.format, m.dtype = L.CSR, _dtype_code(A.vals)
+        m.n, m.d, m.ld, m.nnz = A.n, A.d, A.d, A.vals.numel()
+        m.vals, m.row_ptr, m.col_idx = A.vals.data_ptr(), A.row_ptr.data_ptr(), A.col_idx.data_ptr()
+    else:
+        _require_cuda(A, "A")
+        if A.dim() != 2 or A.stride(1) != 1:
+            raise ValueError("A must be 2-D with unit column stride")
+        m.format, m.dtype = L.DENSE, _dtype_code(A)
+        m.n, m.d, m.ld, m.nnz = A.shape[0], A.shape[1], A.stride(0), 0
+        m.vals = A.data_ptr()
+    return m
+
+
+def default_opts(**kw) -> L.Opts:
+    o = L.Opts()
+    L.lib().ihsbin_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "sketch" and isinstance(v, str):
+            v = L.SKETCHES[v]
+        if k == "taus":
+            continue
+        if not hasattr(o, k):
+            raise KeyError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _taus_ptr(taus):
+    if taus is None:
+        return None, None
+    arr = (C.c_double * len(taus))(*[float(t) for t in taus])
+    return arr, C.cast(arr, C.POINTER(C.c_double))
+
+
+class Context:
+    """ihsbin_create / ihsbin_destroy on a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = L.lib().ihsbin_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if rc != L.OK:
+            raise IhsbinError(rc, "ihsbin_create")
+        self._h = h
+
+    def _check(self, rc, allow=()):
+        if rc != L.OK and rc not in allow:
+            raise IhsbinError(rc, L.lib().ihsbin_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ihsbin_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- path
+    def path_build(self, A, B, lam_min: float, lam_max: float, allow_noconv: bool = True, **opts):
+        """ihsbin_path_build; returns (Path, report dict)."""
+        Bm = B if B.dim() == 2 else B.reshape(-1, 1)
+        _require_cuda(Bm, "B")
+        if Bm.stride(1) != 1:
+            raise ValueError("B must have unit column stride")
+        o = default_opts(**opts)
+        keep, ptr = _taus_ptr(opts.get("taus"))
+        o.taus = ptr
+        mat = _matrix(A)
+        rep = L.Report()
+        ph = C.c_void_p()
+        rc = L.lib().ihsbin_path_build(self._h, C.byref(mat), C.c_void_p(Bm.data_ptr()), Bm.shape[1],
+                                       Bm.stride(0), float(lam_min), float(lam_max), C.byref(o),
+                                       C.byref(ph), C.byref(rep))
+        self._check(rc, allow=(L.ENOCONV,) if allow_noconv else ())
+        r = rep.as_dict()
+        r["status"] = rc
+        return Path(ph, self), r
+
+    def solve_path(self, A, B, lambdas, x_dtype=None, **opts):
+        """ihsbin_solve_path: build, evaluate at every lambda, free."""
+        torch = _torch()
+        Bm = B if B.dim() == 2 else B.reshape(-1, 1)
+        lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+        x_dtype = x_dtype or torch.float64
+        X = torch.empty((len(lam), A.shape[1], Bm.shape[1]), dtype=x_dtype, device=Bm.device)
+        o = default_opts(**opts)
+        keep, ptr = _taus_ptr(opts.get("taus"))
+        o.taus = ptr
+        mat = _matrix(A)
+        rep = L.Report()
+        rc = L.lib().ihsbin_solve_path(self._h, C.byref(mat), C.c_void_p(Bm.data_ptr()), Bm.shape[1],
+                                       Bm.stride(0), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                       len(lam), C.byref(o), C.c_void_p(X.data_ptr()), X.stride(1),
+                                       _dtype_code(X), C.byref(rep))
+        self._check(rc, allow=(L.ENOCONV,))
+        r = rep.as_dict()
+        r["status"] = rc
+        return X, r
+
+    # --------------------------------------------------------- step calls
+    def sketch_draws(self, sketch: str, seed: int, n: int, m: int, sjlt_s: int = 1):
+        """ihsbin_sketch_draws -> (idx int32, sign int8) device tensors."""
+        torch = _torch()
+        code = L.SKETCHES[sketch]
+        dev = torch.device("cuda", self.device)
+        if code == L.SRHT:
+            idx = torch.empty(m, dtype=torch.int32, device=dev)
+            sign = torch.empty(n, dtype=torch.int8, device=dev)
+        else:
+            s = sjlt_s if code == L.SJLT else 1
+            idx = torch.empty((n, s), dtype=torch.int32, device=dev)
+            sign = torch.empty((n, s), dtype=torch.int8, device=dev)
+        self._check(L.lib().ihsbin_sketch_draws(self._h, code, seed, n, m, sjlt_s,
+                                                C.c_void_p(idx.data_ptr()), C.c_void_p(sign.data_ptr())))
+        return idx, sign
+
+    def sketch_apply(self, A, sketch: str, m: int, seed: int, sjlt_s: int = 1):
+        """ihsbin_sketch_apply -> SA (m x d float64)."""
+        torch = _torch()
+        SA = torch.empty((m, A.shape[1]), dtype=torch.float64, device=torch.device("cuda", self.device))
+        mat = _matrix(A)
+        self._check(L.lib().ihsbin_sketch_apply(self._h, C.byref(mat), L.SKETCHES[sketch], sjlt_s, m,
+                                                seed, C.c_void_p(SA.data_ptr())))
+        return SA
+
+    def precond_factor(self, SA, lam0, want_inverse: bool = True):
+        """ihsbin_precond_factor -> (Lfac, Linv) as nl x d x d float64 tensors."""
+        torch = _torch()
+        lam0 = np.ascontiguousarray(np.atleast_1d(np.asarray(lam0, dtype=np.float64)))
+        m, d = SA.shape
+        Lf = torch.empty((len(lam0), d, d), dtype=torch.float64, device=SA.device)
+        Li = torch.empty_like(Lf) if want_inverse else None
+        self._check(L.lib().ihsbin_precond_factor(
+            self._h, C.c_void_p(SA.contiguous().data_ptr()), m, d,
+            lam0.ctypes.data_as(C.POINTER(C.c_double)), len(lam0), C.c_void_p(Lf.data_ptr()),
+            C.c_void_p(Li.data_ptr()) if Li is not None else None))
+        return Lf, Li
+
+    def ata_apply(self, A, U):
+        """ihsbin_ata_apply -> W = A^T A U (d x w float64)."""
+        U = U if U.dim() == 2 else U.reshape(-1, 1)
+        W = _torch().empty_like(U)
+        mat = _matrix(A)
+        self._check(L.lib().ihsbin_ata_apply(self._h, C.byref(mat), C.c_void_p(U.data_ptr()),
+                                             U.shape[1], U.stride(0), C.c_void_p(W.data_ptr()),
+                                             W.stride(0)))
+        return W
+
+
+class Path:
+    """A built path (ihsbin_path): basis resident on the device."""
+
+    def __init__(self, handle, ctx: Context):
+        self._h = handle
+        self._ctx = ctx
+        info = L.PathInfo()
+        rc = L.lib().ihsbin_path_get_info(self._h, C.byref(info))
+        if rc != L.OK:
+            raise IhsbinError(rc, "ihsbin_path_get_info")
+        self.L, self.K, self.d, self.m_used = info.L, info.K, info.d, info.m_used
+        self.lam_min, self.lam_max, self.centred = info.lam_min, info.lam_max, info.centred
+
+    def eval(self, lambdas, out=None, dtype=None):
+        """ihsbin_path_eval -> X (T x d x K)."""
+        torch = _torch()
+        lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+        if out is None:
+            out = torch.empty((len(lam), self.d, self.K), dtype=dtype or torch.float64,
+                              device=torch.device("cuda", self._ctx.device))
+        rc = L.lib().ihsbin_path_eval(self._h, lam.ctypes.data_as(C.POINTER(C.c_double)), len(lam),
+                                      C.c_void_p(out.data_ptr()), out.stride(1), _dtype_code(out))
+        if rc != L.OK:
+            raise IhsbinError(rc, "ihsbin_path_eval")
+        return out
+
+    def intervals(self):
+        """ihsbin_path_intervals -> dict of numpy arrays (lo, hi, lam0, tau, rate, k)."""
+        arrs = {k: np.zeros(self.L) for k in ("lo", "hi", "lam0", "tau", "rate")}
+        k = np.zeros(self.L, dtype=np.int32)
+        ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        rc = L.lib().ihsbin_path_intervals(self._h, ptr(arrs["lo"]), ptr(arrs["hi"]), ptr(arrs["lam0"]),
+                                           ptr(arrs["tau"]), ptr(arrs["rate"]),
+                                           k.ctypes.data_as(C.POINTER(C.c_int32)))
+        if rc != L.OK:
+            raise IhsbinError(rc, "ihsbin_path_intervals")
+        arrs["k"] = k
+        return arrs
+
+    def basis(self, l: int):
+        """ihsbin_path_basis -> k_l x d x K float64 tensor."""
+        torch = _torch()
+        k = int(self.intervals()["k"][l])
+        out = torch.empty((k, self.d, self.K), dtype=torch.float64,
+                          device=torch.device("cuda", self._ctx.device))
+        rc = L.lib().ihsbin_path_basis(self._h, l, C.c_void_p(out.data_ptr()))
+        if rc != L.OK:
+            raise IhsbinError(rc, "ihsbin_path_basis")
+        return out
+
+    def free(self):
+        if getattr(self, "_h", None):
+            L.lib().ihsbin_path_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def solve_path(A, B, lambdas, device: int = 0, **opts):
+    """One-shot ihsbin_solve_path on a temporary context."""
+    ctx = Context(device)
+    try:
+        return ctx.solve_path(A, B, lambdas, **opts)
+    finally:
+        ctx.close()

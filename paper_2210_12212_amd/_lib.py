@@ -1,0 +1,104 @@
+"""ctypes declarations of the C ABI in include/ihsbin.h.
+
+Loading fails loudly (ImportError) when libihsbin.so has not been built: there
+is no fallback implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libihsbin.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, ERANGE, EUNSUP = 0, -1, -2, -3, -4, -5, -6, -7
+DENSE, CSR = 0, 1
+F32, F64 = 0, 1
+GAUSSIAN, SRHT, COUNTSKETCH, SJLT = 0, 1, 2, 3
+SKETCHES = {"gaussian": GAUSSIAN, "srht": SRHT, "countsketch": COUNTSKETCH, "sjlt": SJLT}
+
+EXPORTED = [
+    "ihsbin_status_str", "ihsbin_version", "ihsbin_opts_default", "ihsbin_create",
+    "ihsbin_destroy", "ihsbin_last_error", "ihsbin_path_build", "ihsbin_path_eval",
+    "ihsbin_path_get_info", "ihsbin_path_intervals", "ihsbin_path_basis", "ihsbin_path_free",
+    "ihsbin_solve_path", "ihsbin_sketch_draws", "ihsbin_sketch_apply", "ihsbin_precond_factor",
+    "ihsbin_ata_apply",
+]
+
+
+class Matrix(C.Structure):
+    _fields_ = [("format", C.c_int32), ("dtype", C.c_int32), ("n", C.c_int64), ("d", C.c_int64),
+                ("ld", C.c_int64), ("nnz", C.c_int64), ("vals", C.c_void_p),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("sketch", C.c_int32), ("sjlt_s", C.c_int32), ("m", C.c_int64),
+                ("seed", C.c_uint64), ("tol", C.c_double), ("k_max", C.c_int32),
+                ("k_fixed", C.c_int32), ("L", C.c_int32), ("centred", C.c_int32),
+                ("adaptive_m", C.c_int32), ("rate_target", C.c_double), ("m_max", C.c_int64),
+                ("lanczos_steps", C.c_int32), ("timing", C.c_int32),
+                ("taus", C.POINTER(C.c_double))]
+
+
+class Report(C.Structure):
+    _fields_ = [("m_used", C.c_int64), ("L", C.c_int32), ("k_max_used", C.c_int32),
+                ("k_sum", C.c_int32), ("n_unconverged", C.c_int32),
+                ("sketch_trials", C.c_int32), ("steps", C.c_int32),
+                ("ms_sketch", C.c_double), ("ms_factor", C.c_double),
+                ("ms_spectrum", C.c_double), ("ms_basis", C.c_double), ("ms_total", C.c_double),
+                ("ata_launches", C.c_int64), ("ata_flops", C.c_double), ("ata_ms_y", C.c_double),
+                ("ata_ms_w", C.c_double), ("ata_bytes_a", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PathInfo(C.Structure):
+    _fields_ = [("L", C.c_int32), ("K", C.c_int32), ("d", C.c_int64), ("m_used", C.c_int64),
+                ("lam_min", C.c_double), ("lam_max", C.c_double), ("centred", C.c_int32)]
+
+
+def _declare(lib):
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    pd = C.POINTER(C.c_double)
+    sig = {
+        "ihsbin_status_str": (C.c_char_p, [C.c_int]),
+        "ihsbin_version": (C.c_char_p, []),
+        "ihsbin_opts_default": (None, [C.POINTER(Opts)]),
+        "ihsbin_create": (C.c_int, [C.POINTER(vp), C.c_int, vp]),
+        "ihsbin_destroy": (C.c_int, [vp]),
+        "ihsbin_last_error": (C.c_char_p, [vp]),
+        "ihsbin_path_build": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, dbl, dbl,
+                                        C.POINTER(Opts), C.POINTER(vp), C.POINTER(Report)]),
+        "ihsbin_path_eval": (C.c_int, [vp, pd, i64, vp, i64, i32]),
+        "ihsbin_path_get_info": (C.c_int, [vp, C.POINTER(PathInfo)]),
+        "ihsbin_path_intervals": (C.c_int, [vp, pd, pd, pd, pd, pd, C.POINTER(C.c_int32)]),
+        "ihsbin_path_basis": (C.c_int, [vp, i32, vp]),
+        "ihsbin_path_free": (C.c_int, [vp]),
+        "ihsbin_solve_path": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, pd, i64,
+                                        C.POINTER(Opts), vp, i64, i32, C.POINTER(Report)]),
+        "ihsbin_sketch_draws": (C.c_int, [vp, i32, u64, i64, i64, i32, vp, vp]),
+        "ihsbin_sketch_apply": (C.c_int, [vp, C.POINTER(Matrix), i32, i32, i64, u64, vp]),
+        "ihsbin_precond_factor": (C.c_int, [vp, vp, i64, i64, pd, i32, vp, vp]),
+        "ihsbin_ata_apply": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded library; raises ImportError when it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: run __graft_entry__.build() first "
+                              "(the solver has no non-HIP implementation)")
+        _LIB = _declare(C.CDLL(LIB_PATH))
+    return _LIB

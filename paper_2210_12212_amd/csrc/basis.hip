@@ -1,0 +1,299 @@
+// Element-wise and reduction kernels of the basis recursion (Proposition,
+// Eq. (equ:upd); Algorithm 2 / 5) and of the path composition (Algorithm 3 /
+// 6), plus the Lanczos helpers used to estimate the spectrum of
+// P_S (A^T A + lam0 I) for the step size.
+//
+// Column layout of the working set during step i: active interval a (in the
+// order of the active list) owns the contiguous columns
+// [a*i*K, (a+1)*i*K) of U, holding u_{i-1,j} (j < i) for every right-hand
+// side kk at column (a*i + j)*K + kk.  Rows are the d coordinates.
+#include "basis.hpp"
+
+namespace ihs {
+
+__global__ void seed_rhs_kernel(const double* __restrict__ C, int64_t d, int64_t K, int na,
+                                double* __restrict__ R, int64_t ldr) {
+  const int64_t total = d * K * na;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / (K * na), c = t % (K * na);
+    R[r * ldr + c] = C[r * K + c % K];
+  }
+}
+
+void launch_seed_rhs(const double* C, int64_t d, int64_t K, int na, double* R, int64_t ldr,
+                     hipStream_t st) {
+  int64_t blocks = cdiv(d * K * na, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(seed_rhs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, C, d, K, na, R, ldr);
+  IHS_CHECK_LAUNCH();
+}
+
+// ut_{l,0} = u_{0,0} (= U column block of position a), for every a.
+__global__ void store_first_kernel(const double* __restrict__ U, int64_t ldu, int64_t d, int64_t K,
+                                   int na, const int32_t* __restrict__ ids, int64_t kcap,
+                                   double* __restrict__ basis) {
+  const int64_t total = d * K * na;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / (K * na), c = t % (K * na);
+    const int a = (int)(c / K);
+    const int64_t kk = c % K;
+    basis[(((int64_t)ids[a] * kcap) * d + r) * K + kk] = U[r * ldu + c];
+  }
+}
+
+void launch_store_first(const double* U, int64_t ldu, int64_t d, int64_t K, int na,
+                        const int32_t* ids, int64_t kcap, double* basis, hipStream_t st) {
+  int64_t blocks = cdiv(d * K * na, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(store_first_kernel, dim3((unsigned)blocks), dim3(256), 0, st, U, ldu, d, K, na,
+                     ids, kcap, basis);
+  IHS_CHECK_LAUNCH();
+}
+
+// R_j = tau_a (W_j + ref_a U_j) [j < i] + U_{j-1} [j >= 1], for j = 0..i.
+__global__ void form_r_kernel(const double* __restrict__ W, const double* __restrict__ U,
+                              int64_t ld, int64_t d, int64_t K, int na, int i,
+                              const double* __restrict__ tau, const double* __restrict__ ref,
+                              double* __restrict__ R) {
+  const int64_t cw_new = (int64_t)(i + 1) * K;
+  const int64_t cols = cw_new * na;
+  const int64_t total = d * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / cols, c = t % cols;
+    const int a = (int)(c / cw_new);
+    const int64_t jc = c % cw_new;
+    const int j = (int)(jc / K);
+    const int64_t kk = jc % K;
+    const int64_t base_old = (int64_t)a * i * K;
+    double v = 0.0;
+    if (j < i) {
+      const int64_t co = base_old + (int64_t)j * K + kk;
+      v = tau[a] * (W[r * ld + co] + ref[a] * U[r * ld + co]);
+    }
+    if (j >= 1) v += U[r * ld + base_old + (int64_t)(j - 1) * K + kk];
+    R[r * ld + c] = v;
+  }
+}
+
+void launch_form_r(const double* W, const double* U, int64_t ld, int64_t d, int64_t K, int na,
+                   int i, const double* tau, const double* ref, double* R, hipStream_t st) {
+  int64_t blocks = cdiv(d * K * na * (i + 1), 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(form_r_kernel, dim3((unsigned)blocks), dim3(256), 0, st, W, U, ld, d, K, na, i,
+                     tau, ref, R);
+  IHS_CHECK_LAUNCH();
+}
+
+// u_{i,j} = u_{i-1,j} - Z_j (u_{i-1,i} := 0); ut_j += u_{i,j};
+// stop statistics per position a: ||sum_j mu^j u_{i,j}||^2 and
+// ||sum_j mu^j ut_j||^2 at mu_lo and mu_hi, as per-block partial sums.
+__global__ __launch_bounds__(256) void update_kernel(
+    const double* __restrict__ U, const double* __restrict__ Z, double* __restrict__ Unew,
+    int64_t ld, int64_t d, int64_t K, int i, const int32_t* __restrict__ ids, int64_t kcap,
+    double* __restrict__ basis, const double* __restrict__ mu_lo, const double* __restrict__ mu_hi,
+    double* __restrict__ partial) {
+  __shared__ double red[4][256];
+  const int a = blockIdx.y;
+  const int64_t l = ids[a];
+  const double ml = mu_lo[a], mh = mu_hi[a];
+  const int64_t base_old = (int64_t)a * i * K;
+  const int64_t base_new = (int64_t)a * (i + 1) * K;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int64_t total = d * K;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / K, kk = t % K;
+    double il = 0.0, ih = 0.0, xl = 0.0, xh = 0.0, pl = 1.0, ph = 1.0;
+    for (int j = 0; j <= i; ++j) {
+      const double old = j < i ? U[r * ld + base_old + (int64_t)j * K + kk] : 0.0;
+      const int64_t cn = base_new + (int64_t)j * K + kk;
+      const double un = old - Z[r * ld + cn];
+      Unew[r * ld + cn] = un;
+      double* bp = basis + ((l * kcap + j) * d + r) * K + kk;
+      const double ut = *bp + un;
+      *bp = ut;
+      il += pl * un;
+      ih += ph * un;
+      xl += pl * ut;
+      xh += ph * ut;
+      pl *= ml;
+      ph *= mh;
+    }
+    s0 += il * il;
+    s1 += ih * ih;
+    s2 += xl * xl;
+    s3 += xh * xh;
+  }
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  red[3][threadIdx.x] = s3;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[((int64_t)a * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+int launch_update(const double* U, const double* Z, double* Unew, int64_t ld, int64_t d, int64_t K,
+                  int na, int i, const int32_t* ids, int64_t kcap, double* basis,
+                  const double* mu_lo, const double* mu_hi, double* partial, hipStream_t st) {
+  int64_t bx = cdiv(d * K, 256);
+  if (bx > 64) bx = 64;
+  hipLaunchKernelGGL(update_kernel, dim3((unsigned)bx, (unsigned)na), dim3(256), 0, st, U, Z, Unew,
+                     ld, d, K, i, ids, kcap, basis, mu_lo, mu_hi, partial);
+  IHS_CHECK_LAUNCH();
+  return (int)bx;
+}
+
+// Keep the column blocks of the positions listed in keep[] (old positions).
+__global__ void compact_kernel(const double* __restrict__ Src, double* __restrict__ Dst, int64_t ld,
+                               int64_t d, int64_t cw, int na_new, const int32_t* __restrict__ keep) {
+  const int64_t cols = cw * na_new;
+  const int64_t total = d * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / cols, c = t % cols;
+    const int a = (int)(c / cw);
+    Dst[r * ld + c] = Src[r * ld + (int64_t)keep[a] * cw + c % cw];
+  }
+}
+
+void launch_compact(const double* Src, double* Dst, int64_t ld, int64_t d, int64_t cw, int na_new,
+                    const int32_t* keep, hipStream_t st) {
+  int64_t blocks = cdiv(d * cw * na_new, 256);
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) return;
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Src, Dst, ld, d, cw,
+                     na_new, keep);
+  IHS_CHECK_LAUNCH();
+}
+
+// x(lam_t) = tau_t sum_{j<k_t} mu_t^j ut_{l_t, j}, Horner from the top term.
+template <typename TO>
+__global__ void eval_kernel(const double* __restrict__ basis, int64_t kcap, int64_t d, int64_t K,
+                            const EvalItem* __restrict__ items, TO* __restrict__ X, int64_t ldx) {
+  const EvalItem it = items[blockIdx.y];
+  const int64_t total = d * K;
+  const double* B = basis + (int64_t)it.l * kcap * d * K;
+  TO* Xt = X + (int64_t)blockIdx.y * d * ldx;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / K, kk = t % K;
+    double acc = 0.0;
+    for (int j = it.k - 1; j >= 0; --j) acc = acc * it.mu + B[((int64_t)j * d + r) * K + kk];
+    Xt[r * ldx + kk] = (TO)(it.tau * acc);
+  }
+}
+
+void launch_eval(const double* basis, int64_t kcap, int64_t d, int64_t K, const EvalItem* items,
+                 int64_t T, void* X, int64_t ldx, int x_dtype, hipStream_t st) {
+  int64_t bx = cdiv(d * K, 256);
+  if (bx > 256) bx = 256;
+  for (int64_t t0 = 0; t0 < T; t0 += 65535) {
+    const int64_t tn = (T - t0) < 65535 ? (T - t0) : 65535;
+    if (x_dtype == IHSBIN_F32)
+      hipLaunchKernelGGL(eval_kernel<float>, dim3((unsigned)bx, (unsigned)tn), dim3(256), 0, st,
+                         basis, kcap, d, K, items + t0, (float*)X + t0 * d * ldx, ldx);
+    else
+      hipLaunchKernelGGL(eval_kernel<double>, dim3((unsigned)bx, (unsigned)tn), dim3(256), 0, st,
+                         basis, kcap, d, K, items + t0, (double*)X + t0 * d * ldx, ldx);
+    IHS_CHECK_LAUNCH();
+  }
+}
+
+// ------------------------------------------------------------- Lanczos
+__device__ inline double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+// q_0 for column a: uniform(-1, 1) draws, normalized.
+__global__ __launch_bounds__(256) void lanczos_start_kernel(uint64_t key, int64_t d, int na,
+                                                            double* Q0) {
+  __shared__ double red[256];
+  const int a = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
+    const uint64_t x = sm_draw(key, (uint64_t)(a * d + r));
+    const double v = (double)(x >> 11) * 0x1.0p-52 - 1.0;
+    Q0[r * na + a] = v;
+    s += v * v;
+  }
+  const double nrm = sqrt(block_sum(s, red));
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) Q0[r * na + a] /= nrm;
+}
+
+void launch_lanczos_start(uint64_t seed, int64_t d, int na, double* Q0, hipStream_t st) {
+  hipLaunchKernelGGL(lanczos_start_kernel, dim3(na), dim3(256), 0, st, stream_key(seed, 4), d, na, Q0);
+  IHS_CHECK_LAUNCH();
+}
+
+// S[:, a] += lam0[a] * T[:, a]
+__global__ void add_shift_kernel(double* S, const double* __restrict__ T, int64_t d, int na,
+                                 const double* __restrict__ lam0) {
+  const int64_t total = d * na;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x)
+    S[t] += lam0[t % na] * T[t];
+}
+
+void launch_add_shift(double* S, const double* T, int64_t d, int na, const double* lam0,
+                      hipStream_t st) {
+  int64_t blocks = cdiv(d * na, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(add_shift_kernel, dim3((unsigned)blocks), dim3(256), 0, st, S, T, d, na, lam0);
+  IHS_CHECK_LAUNCH();
+}
+
+// Full re-orthogonalization (two Gram-Schmidt passes) of w against q_0..q_j,
+// alpha_j = <q_j, B q_j>, beta_{j+1} = ||w||, q_{j+1} = w / beta.
+__global__ __launch_bounds__(256) void lanczos_orth_kernel(double* Q, double* Wv, int64_t d, int na,
+                                                           int j, int J, double* alpha,
+                                                           double* beta) {
+  __shared__ double red[256];
+  const int a = blockIdx.x;
+  double al = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = 0; q <= j; ++q) {
+      const double* Qq = Q + (int64_t)q * d * na;
+      double s = 0.0;
+      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Qq[r * na + a] * Wv[r * na + a];
+      const double h = block_sum(s, red);
+      if (q == j) al += h;
+      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) Wv[r * na + a] -= h * Qq[r * na + a];
+      __syncthreads();
+    }
+  }
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Wv[r * na + a] * Wv[r * na + a];
+  const double b = sqrt(block_sum(s, red));
+  double* Qn = Q + (int64_t)(j + 1) * d * na;
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x)
+    Qn[r * na + a] = b > 0.0 ? Wv[r * na + a] / b : 0.0;
+  if (threadIdx.x == 0) {
+    alpha[a * J + j] = al;
+    beta[a * J + j] = b;
+  }
+}
+
+void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int j, int J, double* alpha,
+                         double* beta, hipStream_t st) {
+  hipLaunchKernelGGL(lanczos_orth_kernel, dim3(na), dim3(256), 0, st, Q, Wv, d, na, j, J, alpha,
+                     beta);
+  IHS_CHECK_LAUNCH();
+}
+
+}  // namespace ihs

@@ -1,0 +1,34 @@
+// Launch wrappers of the basis-recursion, evaluation and Lanczos kernels.
+#pragma once
+
+#include "ops.hpp"
+
+namespace ihs {
+
+struct EvalItem {  // one lambda of an evaluation request
+  int32_t l;       // interval
+  int32_t k;       // basis terms of that interval
+  double tau;      // step size
+  double mu;       // tau * (lam - ref)
+};
+
+void launch_seed_rhs(const double* C, int64_t d, int64_t K, int na, double* R, int64_t ldr,
+                     hipStream_t st);
+void launch_store_first(const double* U, int64_t ldu, int64_t d, int64_t K, int na,
+                        const int32_t* ids, int64_t kcap, double* basis, hipStream_t st);
+void launch_form_r(const double* W, const double* U, int64_t ld, int64_t d, int64_t K, int na,
+                   int i, const double* tau, const double* ref, double* R, hipStream_t st);
+int launch_update(const double* U, const double* Z, double* Unew, int64_t ld, int64_t d, int64_t K,
+                  int na, int i, const int32_t* ids, int64_t kcap, double* basis,
+                  const double* mu_lo, const double* mu_hi, double* partial, hipStream_t st);
+void launch_compact(const double* Src, double* Dst, int64_t ld, int64_t d, int64_t cw, int na_new,
+                    const int32_t* keep, hipStream_t st);
+void launch_eval(const double* basis, int64_t kcap, int64_t d, int64_t K, const EvalItem* items,
+                 int64_t T, void* X, int64_t ldx, int x_dtype, hipStream_t st);
+void launch_lanczos_start(uint64_t seed, int64_t d, int na, double* Q0, hipStream_t st);
+void launch_add_shift(double* S, const double* T, int64_t d, int na, const double* lam0,
+                      hipStream_t st);
+void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int j, int J, double* alpha,
+                         double* beta, hipStream_t st);
+
+}  // namespace ihs

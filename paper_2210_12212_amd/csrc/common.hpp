@@ -1,0 +1,117 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ihsbin.h"
+
+namespace ihs {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int status;
+  Error(int s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] inline void fail(int status, const std::string& msg) { throw Error(status, msg); }
+
+#define IHS_HIP(call)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      ::ihs::fail(e_ == hipErrorOutOfMemory ? IHSBIN_ENOMEM : IHSBIN_EHIP,          \
+                  std::string(#call " failed: ") + hipGetErrorString(e_));          \
+  } while (0)
+
+#define IHS_CHECK_LAUNCH() IHS_HIP(hipGetLastError())
+
+// ------------------------------------------------------- device buffers
+// A grow-only device allocation.  Contents are not preserved on growth.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) {
+      (void)hipDeviceSynchronize();  // the buffer may still be read by queued work
+      (void)hipFree(p);
+    }
+    p = nullptr;
+    bytes = 0;
+  }
+  void* ensure(size_t n) {
+    if (n <= bytes && p) return p;
+    release();
+    if (n == 0) n = 256;
+    IHS_HIP(hipMalloc(&p, n));
+    bytes = n;
+    return p;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------- context
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  // scratch shared by the step kernels of one call
+  DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status;
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    IHS_HIP(hipGetDevice(&prev));
+    if (prev != dev) IHS_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// ---------------------------------------------------- SplitMix64 draws
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) in counter form: output i of a
+// generator whose state starts at `key` is mix(key + (i + 1) * GAMMA).
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ inline uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm_draw(uint64_t key, uint64_t i) {
+  return sm_mix(key + (i + 1ull) * kGamma);
+}
+// Stream keys: output t of SplitMix64(seed).  t = 0 CountSketch/SJLT,
+// 1 SRHT signs, 2 SRHT rows, 3 Gaussian entries, 4 Lanczos start vectors.
+inline uint64_t stream_key(uint64_t seed, uint64_t t) { return sm_draw(seed, t); }
+// Multiply-shift of the top 32 bits into [0, bound).
+__host__ __device__ inline uint32_t sm_range(uint64_t x, uint32_t bound) {
+  return (uint32_t)(((x >> 32) * (uint64_t)bound) >> 32);
+}
+
+// ------------------------------------------------------------ helpers
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct MatView {  // a validated ihsbin_matrix
+  int format, dtype;
+  int64_t n, d, ld, nnz;
+  const void* vals;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+};
+
+MatView check_matrix(const ihsbin_matrix* A);
+
+}  // namespace ihs

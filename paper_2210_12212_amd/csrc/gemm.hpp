@@ -1,0 +1,39 @@
+// FP64 matrix products on the CDNA matrix cores (v_mfma_f64_16x16x4f64).
+#pragma once
+
+#include "common.hpp"
+
+namespace ihs {
+
+enum class DT { F32, F64 };
+
+// C = alpha * op(A) op(B) + beta * C with op(A) M x K and op(B) K x N.
+// transA: A is stored K x M row-major (else M x K).  transB: B is stored
+// N x K row-major (else K x N).  All row-major with leading dimensions.
+struct Gemm {
+  int64_t M = 0, N = 0, K = 0;
+  const void* A = nullptr;
+  int64_t lda = 0, strideA = 0;
+  const void* B = nullptr;
+  int64_t ldb = 0, strideB = 0;
+  double* C = nullptr;
+  int64_t ldc = 0, strideC = 0;
+  double alpha = 1.0, beta = 0.0;
+  int batch = 1;         // independent problems (strides above)
+  int splits = 1;        // split-K: partial sums of (b, s) go to C + (b*splits+s)*strideC
+  int tri = 0;           // 1: op(A) lower triangular, 2: op(A) upper triangular
+  int lower_only = 0;    // compute only C tiles touching the lower triangle
+  const int32_t* amap = nullptr;  // optional device map: problem b uses A + amap[b]*strideA
+};
+
+void gemm(const Gemm& g, DT ta, bool transA, DT tb, bool transB, hipStream_t s);
+
+// C[b] = alpha * sum_s part[b*splits + s] + beta * C[b]   (M x N blocks)
+void reduce_splits(const double* part, int splits, int batch, int64_t M, int64_t N,
+                   int64_t ldp, int64_t stride_part, double* C, int64_t ldc,
+                   int64_t strideC, double alpha, double beta, hipStream_t s);
+
+// Choose split-K so that roughly `target` workgroups run.
+int pick_splits(int64_t M, int64_t N, int64_t K, int batch, int64_t target = 2048);
+
+}  // namespace ihs

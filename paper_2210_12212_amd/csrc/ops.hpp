@@ -1,0 +1,62 @@
+// Launch wrappers of the library's kernels (all enqueue on the given stream).
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace ihs {
+
+// ------------------------------------------------------------ sketches
+// CountSketch / SJLT draws: idx[i*s + b], sign[i*s + b] for row i, block b.
+void launch_draw_countsketch(uint64_t seed, int64_t n, int64_t m, int s, int32_t* idx,
+                             int8_t* sign, hipStream_t st);
+// SRHT draws: sign[i] for i < n, rows[k] in [0, npad) for k < m.
+void launch_draw_srht(uint64_t seed, int64_t n, int64_t npad, int64_t m, int8_t* sign,
+                      int32_t* rows, hipStream_t st);
+// S (rows x n, FP64) holding Gaussian rows [r0, r0 + rows) of the m x n sketch.
+void launch_gaussian_fill(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
+                          double* S, hipStream_t st);
+// SA += S A for CountSketch / SJLT (SA zeroed by the caller).
+void launch_countsketch_apply(const MatView& A, const int32_t* idx, const int8_t* sign, int s,
+                              double* SA, hipStream_t st);
+// Z (npad x d) = D A zero-padded, then the Walsh-Hadamard transform over rows.
+void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, double* Z,
+                           hipStream_t st);
+// SA[k] = scale * Z[rows[k]].
+void launch_gather_rows(const double* Z, int64_t d, const int32_t* rows, int64_t m, double scale,
+                        double* SA, hipStream_t st);
+
+// ------------------------------------------------------------ factorization
+// H_l = G + lam0_l I for l < nl (d x d each).
+void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, int nl, double* H,
+                          hipStream_t st);
+// In-place blocked Cholesky of nl matrices (lower factor, upper zeroed);
+// dinv receives the inverses of the diagonal blocks (nl x nblk x 64 x 64).
+// status_dev (int) is set non-zero when a pivot is not positive.
+void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_dev,
+                      hipStream_t st);
+// Linv = L^-1 for nl factors, using the diagonal-block inverses from above.
+void tri_inverse_batched(const double* Lf, int64_t d, int nl, const double* dinv, double* Linv,
+                         hipStream_t st);
+constexpr int kNB = 64;
+
+// ------------------------------------------------------------ products with A
+// W = A^T A U (d x w), FP64.  Uses ctx scratch for Y = A U and split-K partials.
+void ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
+               int64_t ldw, std::vector<hipEvent_t>* ev);
+// C = A^T B (d x K), FP64, B in A's dtype (row stride ldb).
+void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C);
+// CSR kernels
+void launch_csr_spmm(const MatView& A, const double* U, int64_t w, int64_t ldu, double* Y,
+                     int64_t ldy, hipStream_t st);
+void launch_csr_spmm_t(const MatView& A, const double* Y, int64_t w, int64_t ldy, double* W,
+                       int64_t ldw, hipStream_t st);
+void launch_csr_atb(const MatView& A, const void* B, int64_t K, int64_t ldb, double* C,
+                    hipStream_t st);
+
+// ------------------------------------------------------------ basis kernels
+struct StepParams;  // defined in basis.hip users
+void launch_fill(double* p, int64_t count, double v, hipStream_t st);
+void launch_zero_bytes(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace ihs

@@ -1,0 +1,227 @@
+// Products with the data matrix A: W = A^T A U for a batch of w columns
+// (every A^T A u_{i,j} of one basis step, Algorithm 2, across all intervals
+// and right-hand sides at once) and C = A^T B.
+//
+// Dense A: Y = A U (n x w) with the MFMA GEMM, then W = A^T Y with split-K
+// over n and a deterministic reduction; A is read in its stored type and
+// widened to FP64 in the GEMM staging.  Columns are processed in chunks so
+// the n x w intermediate stays within a fixed scratch budget.
+// CSR A: row-parallel gather for A U and a row-parallel scatter with FP64
+// atomics for A^T Y.
+#include "ops.hpp"
+
+namespace ihs {
+
+static constexpr size_t kYBudget = size_t(6) << 30;  // bytes for the n x w intermediate
+
+template <typename T>
+__global__ void csr_spmm_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                const T* __restrict__ v, int64_t n, const double* __restrict__ U,
+                                int64_t w, int64_t ldu, double* __restrict__ Y, int64_t ldy) {
+  // one wave per row, lanes over columns
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < n; i += nwaves) {
+    const int32_t p0 = rp[i], p1 = rp[i + 1];
+    for (int64_t c = lane; c < w; c += 64) {
+      double acc = 0.0;
+      for (int32_t p = p0; p < p1; ++p) acc += (double)v[p] * U[(int64_t)ci[p] * ldu + c];
+      Y[i * ldy + c] = acc;
+    }
+  }
+}
+
+template <typename T>
+__global__ void csr_spmm_t_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  const T* __restrict__ v, int64_t n, const double* __restrict__ Y,
+                                  int64_t w, int64_t ldy, double* W, int64_t ldw) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < n; i += nwaves) {
+    const int32_t p0 = rp[i], p1 = rp[i + 1];
+    for (int64_t c = lane; c < w; c += 64) {
+      const double y = Y[i * ldy + c];
+      if (y == 0.0) continue;
+      for (int32_t p = p0; p < p1; ++p) atomicAdd(W + (int64_t)ci[p] * ldw + c, (double)v[p] * y);
+    }
+  }
+}
+
+void launch_csr_spmm(const MatView& A, const double* U, int64_t w, int64_t ldu, double* Y,
+                     int64_t ldy, hipStream_t st) {
+  int64_t blocks = cdiv(A.n * 64, 256);
+  if (blocks > 65536) blocks = 65536;
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(csr_spmm_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, (const float*)A.vals, A.n, U, w, ldu, Y, ldy);
+  else
+    hipLaunchKernelGGL(csr_spmm_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, (const double*)A.vals, A.n, U, w, ldu, Y, ldy);
+  IHS_CHECK_LAUNCH();
+}
+
+void launch_csr_spmm_t(const MatView& A, const double* Y, int64_t w, int64_t ldy, double* W,
+                       int64_t ldw, hipStream_t st) {
+  int64_t blocks = cdiv(A.n * 64, 256);
+  if (blocks > 65536) blocks = 65536;
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(csr_spmm_t_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       A.row_ptr, A.col_idx, (const float*)A.vals, A.n, Y, w, ldy, W, ldw);
+  else
+    hipLaunchKernelGGL(csr_spmm_t_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       A.row_ptr, A.col_idx, (const double*)A.vals, A.n, Y, w, ldy, W, ldw);
+  IHS_CHECK_LAUNCH();
+}
+
+__global__ void zero_rows_kernel(double* W, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x)
+    W[(t / cols) * ld + t % cols] = 0.0;
+}
+
+static void zero_block(double* W, int64_t rows, int64_t cols, int64_t ld, hipStream_t st) {
+  int64_t blocks = cdiv(rows * cols, 256);
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) return;
+  hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, W, rows, cols, ld);
+  IHS_CHECK_LAUNCH();
+}
+
+template <typename T>
+__global__ void csr_atb_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                               const T* __restrict__ v, int64_t n, const T* __restrict__ B,
+                               int64_t K, int64_t ldb, double* C) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t c = 0; c < K; ++c) {
+      const double bv = (double)B[i * ldb + c];
+      for (int32_t p = rp[i]; p < rp[i + 1]; ++p) atomicAdd(C + (int64_t)ci[p] * K + c, (double)v[p] * bv);
+    }
+}
+
+void launch_csr_atb(const MatView& A, const void* B, int64_t K, int64_t ldb, double* C,
+                    hipStream_t st) {
+  zero_block(C, A.d, K, K, st);
+  int64_t blocks = cdiv(A.n, 256);
+  if (blocks > 16384) blocks = 16384;
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(csr_atb_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, (const float*)A.vals, A.n, (const float*)B, K, ldb, C);
+  else
+    hipLaunchKernelGGL(csr_atb_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, (const double*)A.vals, A.n, (const double*)B, K, ldb, C);
+  IHS_CHECK_LAUNCH();
+}
+
+void ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
+               int64_t ldw, std::vector<hipEvent_t>* ev) {
+  hipStream_t st = ctx.stream;
+  if (w <= 0) return;
+  int64_t wc = (int64_t)(kYBudget / (sizeof(double) * (size_t)A.n));
+  if (wc > w) wc = w;
+  if (wc < 1) wc = 1;
+  double* Y = ctx.ws_y.as<double>();
+  Y = static_cast<double*>(ctx.ws_y.ensure(sizeof(double) * (size_t)A.n * (size_t)wc));
+  const DT ta = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
+  for (int64_t c0 = 0; c0 < w; c0 += wc) {
+    const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
+    if (ev) {
+      hipEvent_t e;
+      IHS_HIP(hipEventCreate(&e));
+      IHS_HIP(hipEventRecord(e, st));
+      ev->push_back(e);
+    }
+    if (A.format == IHSBIN_DENSE) {
+      Gemm g1;
+      g1.M = A.n;
+      g1.N = cw;
+      g1.K = A.d;
+      g1.A = A.vals;
+      g1.lda = A.ld;
+      g1.B = U + c0;
+      g1.ldb = ldu;
+      g1.C = Y;
+      g1.ldc = cw;
+      gemm(g1, ta, false, DT::F64, false, st);
+    } else {
+      launch_csr_spmm(A, U + c0, cw, ldu, Y, cw, st);
+    }
+    if (ev) {
+      hipEvent_t e;
+      IHS_HIP(hipEventCreate(&e));
+      IHS_HIP(hipEventRecord(e, st));
+      ev->push_back(e);
+    }
+    if (A.format == IHSBIN_DENSE) {
+      const int splits = pick_splits(A.d, cw, A.n, 1);
+      Gemm g2;
+      g2.M = A.d;
+      g2.N = cw;
+      g2.K = A.n;
+      g2.A = A.vals;
+      g2.lda = A.ld;
+      g2.B = Y;
+      g2.ldb = cw;
+      if (splits > 1) {
+        double* part = static_cast<double*>(
+            ctx.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)A.d * (size_t)cw));
+        g2.C = part;
+        g2.ldc = cw;
+        g2.strideC = A.d * cw;
+        g2.splits = splits;
+        gemm(g2, ta, true, DT::F64, false, st);
+        reduce_splits(part, splits, 1, A.d, cw, cw, A.d * cw, W + c0, ldw, 0, 1.0, 0.0, st);
+      } else {
+        g2.C = W + c0;
+        g2.ldc = ldw;
+        gemm(g2, ta, true, DT::F64, false, st);
+      }
+    } else {
+      zero_block(W + c0, A.d, cw, ldw, st);
+      launch_csr_spmm_t(A, Y, cw, cw, W + c0, ldw, st);
+    }
+    if (ev) {
+      hipEvent_t e;
+      IHS_HIP(hipEventCreate(&e));
+      IHS_HIP(hipEventRecord(e, st));
+      ev->push_back(e);
+    }
+  }
+}
+
+void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C) {
+  hipStream_t st = ctx.stream;
+  if (A.format == IHSBIN_CSR) {
+    launch_csr_atb(A, B, K, ldb, C, st);
+    return;
+  }
+  const DT ta = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
+  const int splits = pick_splits(A.d, K, A.n, 1);
+  Gemm g;
+  g.M = A.d;
+  g.N = K;
+  g.K = A.n;
+  g.A = A.vals;
+  g.lda = A.ld;
+  g.B = B;
+  g.ldb = ldb;
+  if (splits > 1) {
+    double* part = static_cast<double*>(
+        ctx.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)A.d * (size_t)K));
+    g.C = part;
+    g.ldc = K;
+    g.strideC = A.d * K;
+    g.splits = splits;
+    gemm(g, ta, true, ta, false, st);
+    reduce_splits(part, splits, 1, A.d, K, K, A.d * K, C, K, 0, 1.0, 0.0, st);
+  } else {
+    g.C = C;
+    g.ldc = K;
+    gemm(g, ta, true, ta, false, st);
+  }
+}
+
+}  // namespace ihs

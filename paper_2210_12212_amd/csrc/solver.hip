@@ -1,0 +1,939 @@
+// IHS-BIN path build and evaluation (Section 4, Algorithms 2, 3, 5, 6) and the
+// C ABI.
+//
+// Build:
+//  1. C = A^T B.
+//  2. Sketch SA = S A and the sketched Gram G_S = (SA)^T SA.  With adaptive m
+//     the predicted contraction rate of the lowest interval decides whether m
+//     grows (Section 5.1 motivates growing m until the sketch is good enough).
+//  3. For every interval l (Section 4.2) factor G_S + lam0_l I = L_l L_l^T
+//     and form L_l^-1, so P_S R = L^-T (L^-1 R).
+//  4. Lanczos on L^-1 (A^T A + lam0 I) L^-T estimates the spectrum
+//     [mu_min, mu_max] of P_S (A^T A + lam0 I) per interval; the step size
+//     tau = 2 / (mu_min lo/lam0 + mu_max hi/lam0) minimizes the worst
+//     contraction over the interval (the optimality condition in the proof
+//     of Theorem 1, with measured instead of theoretical eigenvalue bounds).
+//  5. Basis recursion of the Proposition for all intervals and right-hand
+//     sides at once: one A^T A product over every live column per step; an
+//     interval leaves the batch when its increment at both interval ends is
+//     small enough.
+// Evaluate: x(lam) = tau sum_j (tau (lam - ref))^j ut_j per lambda.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "basis.hpp"
+
+struct ihsbin_ctx {
+  ihs::Ctx c;
+};
+
+struct ihsbin_path {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t d = 0, K = 0, m_used = 0, kcap = 0;
+  int L = 0;
+  double lam_min = 0, lam_max = 0;
+  int centred = 1;
+  std::vector<double> grid, lam0, tau, rate, ref;
+  std::vector<int32_t> k;
+  ihs::DevBuf basis, items;
+};
+
+namespace ihs {
+
+MatView check_matrix(const ihsbin_matrix* A) {
+  if (!A) fail(IHSBIN_EINVAL, "A is NULL");
+  MatView v{A->format, A->dtype, A->n, A->d, A->ld, A->nnz, A->vals, A->row_ptr, A->col_idx};
+  if (v.format != IHSBIN_DENSE && v.format != IHSBIN_CSR) fail(IHSBIN_EINVAL, "bad format");
+  if (v.dtype != IHSBIN_F32 && v.dtype != IHSBIN_F64) fail(IHSBIN_EINVAL, "bad dtype");
+  if (v.n <= 0 || v.d <= 0) fail(IHSBIN_EINVAL, "n and d must be positive");
+  if (v.n > INT32_MAX || v.d > INT32_MAX) fail(IHSBIN_EUNSUP, "n, d must fit int32");
+  if (v.format == IHSBIN_DENSE) {
+    if (v.ld < v.d) fail(IHSBIN_EINVAL, "ld < d");
+    if (!v.vals) fail(IHSBIN_EINVAL, "vals is NULL");
+  } else {
+    if (v.nnz < 0 || v.nnz > INT32_MAX) fail(IHSBIN_EINVAL, "bad nnz");
+    if (!v.row_ptr || (v.nnz > 0 && (!v.col_idx || !v.vals)))
+      fail(IHSBIN_EINVAL, "CSR arrays are NULL");
+  }
+  return v;
+}
+
+// CSR structure check on the device: row_ptr monotone from 0 to nnz, columns in range.
+__global__ void csr_check_kernel(const int32_t* rp, const int32_t* ci, int64_t n, int64_t d,
+                                 int64_t nnz, int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == 0 && rp[0] != 0) bad[0] = 1;
+    if (i == n && rp[n] != nnz) bad[0] = 1;
+    if (i < n) {
+      const int32_t a = rp[i], b = rp[i + 1];
+      if (b < a || a < 0 || b > nnz) {
+        bad[0] = 1;
+        continue;
+      }
+      for (int32_t p = a; p < b; ++p)
+        if (ci[p] < 0 || ci[p] >= d) bad[0] = 1;
+    }
+  }
+}
+
+static void validate_csr(Ctx& c, const MatView& A) {
+  int* bad = static_cast<int*>(c.ws_status.ensure(64));
+  IHS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c.stream));
+  int64_t blocks = cdiv(A.n + 1, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(csr_check_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream, A.row_ptr,
+                     A.col_idx, A.n, A.d, A.nnz, bad);
+  IHS_CHECK_LAUNCH();
+  int h = 0;
+  IHS_HIP(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  IHS_HIP(hipStreamSynchronize(c.stream));
+  if (h) fail(IHSBIN_EINVAL, "CSR structure invalid (row_ptr or col_idx)");
+}
+
+static int64_t next_pow2(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// ------------------------------------------------------------------ sketch
+static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t m, uint64_t seed,
+                              double* SA) {
+  hipStream_t st = c.stream;
+  if (m <= 0) fail(IHSBIN_EINVAL, "m must be positive");
+  if (m > INT32_MAX) fail(IHSBIN_EUNSUP, "m too large");
+  if (kind == IHSBIN_GAUSSIAN) {
+    if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "Gaussian sketch of a CSR matrix");
+    int64_t rows = (int64_t)((size_t(1) << 30) / (sizeof(double) * (size_t)A.n));
+    rows = std::max<int64_t>(64, (rows / 64) * 64);
+    if (rows > m) rows = m;
+    double* S = static_cast<double*>(c.ws_sketch.ensure(sizeof(double) * (size_t)rows * A.n));
+    const DT tb = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
+    for (int64_t r0 = 0; r0 < m; r0 += rows) {
+      const int64_t rn = std::min(rows, m - r0);
+      launch_gaussian_fill(seed, m, r0, rn, A.n, S, st);
+      const int splits = pick_splits(rn, A.d, A.n, 1);
+      Gemm g;
+      g.M = rn;
+      g.N = A.d;
+      g.K = A.n;
+      g.A = S;
+      g.lda = A.n;
+      g.B = A.vals;
+      g.ldb = A.ld;
+      if (splits > 1) {
+        double* part = static_cast<double*>(
+            c.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)rn * (size_t)A.d));
+        g.C = part;
+        g.ldc = A.d;
+        g.strideC = rn * A.d;
+        g.splits = splits;
+        gemm(g, DT::F64, false, tb, false, st);
+        reduce_splits(part, splits, 1, rn, A.d, A.d, rn * A.d, SA + r0 * A.d, A.d, 0, 1.0, 0.0, st);
+      } else {
+        g.C = SA + r0 * A.d;
+        g.ldc = A.d;
+        gemm(g, DT::F64, false, tb, false, st);
+      }
+    }
+  } else if (kind == IHSBIN_COUNTSKETCH || kind == IHSBIN_SJLT) {
+    if (kind == IHSBIN_COUNTSKETCH) s = 1;
+    if (s < 1 || m % s) fail(IHSBIN_EINVAL, "SJLT needs s >= 1 dividing m");
+    char* base = static_cast<char*>(c.ws_sketch.ensure((size_t)A.n * s * 5 + 256));
+    int32_t* idx = reinterpret_cast<int32_t*>(base);
+    int8_t* sg = reinterpret_cast<int8_t*>(base + (size_t)A.n * s * 4);
+    launch_draw_countsketch(seed, A.n, m, s, idx, sg, st);
+    IHS_HIP(hipMemsetAsync(SA, 0, sizeof(double) * (size_t)m * A.d, st));
+    launch_countsketch_apply(A, idx, sg, s, SA, st);
+  } else if (kind == IHSBIN_SRHT) {
+    const int64_t npad = next_pow2(A.n);
+    if (npad > (int64_t(1) << 31)) fail(IHSBIN_EUNSUP, "SRHT order too large");
+    char* base = static_cast<char*>(
+        c.ws_sketch.ensure(sizeof(double) * (size_t)npad * A.d + (size_t)A.n + 4 * (size_t)m + 512));
+    double* Z = reinterpret_cast<double*>(base);
+    int8_t* sg = reinterpret_cast<int8_t*>(base + sizeof(double) * (size_t)npad * A.d);
+    int32_t* rows = reinterpret_cast<int32_t*>(base + sizeof(double) * (size_t)npad * A.d +
+                                               ((A.n + 255) / 256) * 256);
+    launch_draw_srht(seed, A.n, npad, m, sg, rows, st);
+    launch_srht_transform(A, sg, npad, Z, st);
+    launch_gather_rows(Z, A.d, rows, m, 1.0 / std::sqrt((double)m), SA, st);
+  } else {
+    fail(IHSBIN_EINVAL, "unknown sketch type");
+  }
+}
+
+static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G) {
+  const int splits = pick_splits(d, d, m, 1);
+  Gemm g;
+  g.M = d;
+  g.N = d;
+  g.K = m;
+  g.A = SA;
+  g.lda = d;
+  g.B = SA;
+  g.ldb = d;
+  if (splits > 1) {
+    double* part = static_cast<double*>(
+        c.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)d * (size_t)d));
+    g.C = part;
+    g.ldc = d;
+    g.strideC = d * d;
+    g.splits = splits;
+    gemm(g, DT::F64, true, DT::F64, false, c.stream);
+    reduce_splits(part, splits, 1, d, d, d, d * d, G, d, 0, 1.0, 0.0, c.stream);
+  } else {
+    g.C = G;
+    g.ldc = d;
+    gemm(g, DT::F64, true, DT::F64, false, c.stream);
+  }
+}
+
+// H_l = G + lam0_l I, factor in place, and Linv_l = L_l^-1.
+static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<double>& lam0s,
+                        double* Lf, double* Linv, DevBuf& dinv_buf, DevBuf& lam_buf) {
+  const int nl = (int)lam0s.size();
+  double* lam_dev = static_cast<double*>(lam_buf.ensure(sizeof(double) * nl));
+  IHS_HIP(hipMemcpyAsync(lam_dev, lam0s.data(), sizeof(double) * nl, hipMemcpyHostToDevice, c.stream));
+  launch_build_shifted(G, d, lam_dev, nl, Lf, c.stream);
+  const int64_t nblk = cdiv(d, kNB);
+  double* dinv = static_cast<double*>(dinv_buf.ensure(sizeof(double) * nl * nblk * kNB * kNB));
+  int* status = static_cast<int*>(c.ws_status.ensure(64));
+  IHS_HIP(hipMemsetAsync(status, 0, sizeof(int), c.stream));
+  cholesky_batched(Lf, d, nl, dinv, status, c.stream);
+  int h = 0;
+  IHS_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  IHS_HIP(hipStreamSynchronize(c.stream));
+  if (h) fail(IHSBIN_ENOTSPD, "sketched Hessian not positive definite");
+  if (Linv) tri_inverse_batched(Lf, d, nl, dinv, Linv, c.stream);
+}
+
+// Z = P R for every active position: P_a = Linv_{ids[a]}^T Linv_{ids[a]}.
+static void apply_p(Ctx& c, const double* Linv_all, const int32_t* ids_dev, int na, int64_t d,
+                    int64_t cw, int64_t ld, const double* R, double* T, double* Z) {
+  Gemm g;
+  g.M = d;
+  g.N = cw;
+  g.K = d;
+  g.A = Linv_all;
+  g.lda = d;
+  g.strideA = d * d;
+  g.amap = ids_dev;
+  g.B = R;
+  g.ldb = ld;
+  g.strideB = cw;
+  g.C = T;
+  g.ldc = ld;
+  g.strideC = cw;
+  g.batch = na;
+  g.tri = 1;
+  gemm(g, DT::F64, false, DT::F64, false, c.stream);
+  g.B = T;
+  g.C = Z;
+  g.tri = 2;
+  gemm(g, DT::F64, true, DT::F64, false, c.stream);
+}
+
+// Symmetric eigen-decomposition of a small dense matrix by cyclic Jacobi.
+static void jacobi_eig(int n, std::vector<double>& a, std::vector<double>& v) {
+  v.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double x = a[(size_t)i * n + j] * a[(size_t)i * n + j];
+        tot += x;
+        if (i != j) off += x;
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+        const double th = (aqq - app) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+          a[(size_t)k * n + p] = cs * akp - sn * akq;
+          a[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+          a[(size_t)p * n + k] = cs * apk - sn * aqk;
+          a[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+          v[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          v[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+}
+
+struct Spec {
+  double mu_min, mu_max;
+};
+
+// Lanczos with full re-orthogonalization on B_l = Linv_l (A^T A + lam0_l I) Linv_l^T.
+static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* Linv_all,
+                                       const std::vector<int32_t>& ids,
+                                       const std::vector<double>& lam0_pos, int J, uint64_t seed) {
+  hipStream_t st = c.stream;
+  const int na = (int)ids.size();
+  const int64_t d = A.d;
+  if (J < 2) J = 2;
+  if (J > d) J = (int)d;
+  const size_t vec = sizeof(double) * (size_t)d * na;
+  DevBuf Qb, Tb, Sb, Wb, ab, idb, lb;
+  double* Q = static_cast<double*>(Qb.ensure(vec * (J + 1)));
+  double* T = static_cast<double*>(Tb.ensure(vec));
+  double* S = static_cast<double*>(Sb.ensure(vec));
+  double* Wv = static_cast<double*>(Wb.ensure(vec));
+  double* alpha = static_cast<double*>(ab.ensure(sizeof(double) * 2 * na * J));
+  double* beta = alpha + (size_t)na * J;
+  int32_t* ids_dev = static_cast<int32_t*>(idb.ensure(sizeof(int32_t) * na));
+  double* lam_dev = static_cast<double*>(lb.ensure(sizeof(double) * na));
+  IHS_HIP(hipMemcpyAsync(ids_dev, ids.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
+  IHS_HIP(hipMemcpyAsync(lam_dev, lam0_pos.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+  launch_lanczos_start(seed, d, na, Q, st);
+  for (int j = 0; j < J; ++j) {
+    Gemm g;
+    g.M = d;
+    g.N = 1;
+    g.K = d;
+    g.A = Linv_all;
+    g.lda = d;
+    g.strideA = d * d;
+    g.amap = ids_dev;
+    g.B = Q + (size_t)j * d * na;
+    g.ldb = na;
+    g.strideB = 1;
+    g.C = T;
+    g.ldc = na;
+    g.strideC = 1;
+    g.batch = na;
+    g.tri = 2;
+    gemm(g, DT::F64, true, DT::F64, false, st);  // T = Linv^T q
+    ata_apply(c, A, T, na, na, S, na, nullptr);   // S = A^T A T
+    launch_add_shift(S, T, d, na, lam_dev, st);   // S += lam0 T
+    g.B = S;
+    g.C = Wv;
+    g.tri = 1;
+    gemm(g, DT::F64, false, DT::F64, false, st);  // W = Linv S
+    launch_lanczos_orth(Q, Wv, d, na, j, J, alpha, beta, st);
+  }
+  std::vector<double> h(2 * (size_t)na * J);
+  IHS_HIP(hipMemcpyAsync(h.data(), alpha, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  IHS_HIP(hipStreamSynchronize(st));
+  std::vector<Spec> out(na);
+  for (int a = 0; a < na; ++a) {
+    // stop at an invariant subspace (tiny beta)
+    int n = J;
+    for (int j = 0; j < J - 1; ++j)
+      if (!(h[(size_t)na * J + (size_t)a * J + j] > 1e-14 * std::fabs(h[(size_t)a * J + j]) + 1e-300)) {
+        n = j + 1;
+        break;
+      }
+    std::vector<double> Tm((size_t)n * n, 0.0), V;
+    for (int j = 0; j < n; ++j) {
+      Tm[(size_t)j * n + j] = h[(size_t)a * J + j];
+      if (j + 1 < n) {
+        const double b = h[(size_t)na * J + (size_t)a * J + j];
+        Tm[(size_t)j * n + j + 1] = b;
+        Tm[(size_t)(j + 1) * n + j] = b;
+      }
+    }
+    jacobi_eig(n, Tm, V);
+    const double bres = n == J ? h[(size_t)na * J + (size_t)a * J + J - 1] : 0.0;
+    int imin = 0, imax = 0;
+    for (int i = 1; i < n; ++i) {
+      if (Tm[(size_t)i * n + i] < Tm[(size_t)imin * n + imin]) imin = i;
+      if (Tm[(size_t)i * n + i] > Tm[(size_t)imax * n + imax]) imax = i;
+    }
+    const double tmin = Tm[(size_t)imin * n + imin], tmax = Tm[(size_t)imax * n + imax];
+    const double rmin = std::fabs(bres * V[(size_t)(n - 1) * n + imin]);
+    const double rmax = std::fabs(bres * V[(size_t)(n - 1) * n + imax]);
+    Spec sp;
+    sp.mu_max = (tmax + rmax) * 1.02;
+    sp.mu_min = std::max(tmin - rmin, 0.5 * tmin);
+    if (!(sp.mu_min > 0.0) || !(sp.mu_max > sp.mu_min) || !std::isfinite(sp.mu_max))
+      fail(IHSBIN_ENOTSPD, "spectrum estimate failed");
+    out[a] = sp;
+  }
+  return out;
+}
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K, int64_t ldb,
+                      double lam_min, double lam_max, const ihsbin_opts* o_in,
+                      ihsbin_path** out, ihsbin_report* rep) {
+  if (!out) fail(IHSBIN_EINVAL, "path out-pointer is NULL");
+  *out = nullptr;
+  ihsbin_opts o;
+  if (o_in) o = *o_in;
+  else ihsbin_opts_default(&o);
+  const MatView A = check_matrix(Ain);
+  if (!B) fail(IHSBIN_EINVAL, "B is NULL");
+  if (K < 1 || ldb < K) fail(IHSBIN_EINVAL, "need K >= 1 and ldb >= K");
+  if (!(lam_min > 0.0) || !(lam_max >= lam_min) || !std::isfinite(lam_max))
+    fail(IHSBIN_EINVAL, "need 0 < lam_min <= lam_max");
+  if (A.n < A.d) fail(IHSBIN_EUNSUP, "n < d (the dual problem is not built)");
+  if (o.k_max < 1 || o.k_max > 4096) fail(IHSBIN_EINVAL, "k_max out of range");
+  if (o.k_fixed < 0 || o.k_fixed > 4096) fail(IHSBIN_EINVAL, "k_fixed out of range");
+  if (!(o.tol > 0.0)) fail(IHSBIN_EINVAL, "tol must be positive");
+  if (A.format == IHSBIN_CSR) validate_csr(c, A);
+  hipStream_t st = c.stream;
+  Timer total;
+  ihsbin_report r;
+  std::memset(&r, 0, sizeof(r));
+
+  // ---- interval plan (Section 4.2)
+  const double beta = lam_max / lam_min;
+  int L = o.L > 0 ? o.L : (beta > 1.0 ? std::max(1, (int)std::floor(2.0 * std::log(beta))) : 1);
+  std::vector<double> grid(L + 1), lam0(L);
+  for (int l = 0; l <= L; ++l) grid[l] = lam_min * std::pow(beta, (double)l / L);
+  grid[L] = lam_max;
+  for (int l = 0; l < L; ++l) lam0[l] = std::sqrt(grid[l] * grid[l + 1]);
+  const int64_t d = A.d;
+
+  // ---- C = A^T B
+  DevBuf Cb;
+  double* C = static_cast<double*>(Cb.ensure(sizeof(double) * d * K));
+  atb_apply(c, A, B, K, ldb, C);
+
+  // ---- sketch, with adaptive m
+  Timer tsk;
+  int64_t m = o.m > 0 ? o.m : 2 * d;
+  int s = o.sketch == IHSBIN_SJLT ? std::max(1, o.sjlt_s) : 1;
+  if (m % s) m += s - m % s;
+  int64_t m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(A.n, 32 * d));
+  if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(A.n)));
+  DevBuf SAb, Gb, Lb, Ib, dinvb, lamb;
+  double* G = static_cast<double*>(Gb.ensure(sizeof(double) * d * d));
+  std::vector<Spec> spec;
+  for (int trial = 0;; ++trial) {
+    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * m * d));
+    sketch_apply_impl(c, A, o.sketch, s, m, o.seed, SA);
+    gram_impl(c, SA, m, d, G);
+    r.sketch_trials = trial + 1;
+    if (!o.adaptive_m || m >= m_cap || trial >= 5 || o.taus) break;
+    double* Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
+    double* Li = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
+    factor_impl(c, G, d, {lam0[0]}, Lf, Li, dinvb, lamb);
+    auto sp = spectrum_impl(c, A, Li, {0}, {lam0[0]}, std::max(8, o.lanczos_steps), o.seed);
+    const double cmin = sp[0].mu_min * grid[0] / lam0[0], cmax = sp[0].mu_max * grid[1] / lam0[0];
+    const double r0 = (cmax - cmin) / (cmax + cmin);
+    if (r0 <= o.rate_target) break;
+    // Marchenko-Pastur-type edges (1 -+ sqrt(rho))^2 with rho ~ d_e / m: infer
+    // rho from the measured condition number and scale m to the target.
+    const double kap = sp[0].mu_max / sp[0].mu_min;
+    const double g = grid[1] / grid[0];
+    const double kt = (1.0 + o.rate_target) / ((1.0 - o.rate_target) * g);
+    double factor = 16.0;
+    if (kt > 1.0 && kap > 1.0) {
+      const double so = (std::sqrt(kap) - 1.0) / (std::sqrt(kap) + 1.0);
+      const double sg = (std::sqrt(kt) - 1.0) / (std::sqrt(kt) + 1.0);
+      factor = (so * so) / (sg * sg);
+    }
+    factor = std::min(16.0, std::max(2.0, factor));
+    int64_t mult = 1;
+    while (mult < factor) mult <<= 1;
+    const int64_t m_new = std::min(m_cap, m * mult);
+    if (m_new <= m) break;
+    m = m_new;
+  }
+  IHS_HIP(hipStreamSynchronize(st));
+  r.ms_sketch = tsk.ms();
+  r.m_used = m;
+
+  // ---- factor every interval
+  Timer tf;
+  double* Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d * L));
+  double* Linv = static_cast<double*>(Ib.ensure(sizeof(double) * d * d * L));
+  factor_impl(c, G, d, lam0, Lf, Linv, dinvb, lamb);
+  Gb.release();
+  SAb.release();
+  IHS_HIP(hipStreamSynchronize(st));
+  r.ms_factor = tf.ms();
+
+  // ---- step sizes
+  Timer tspec;
+  std::vector<double> tau(L), rate(L), ref(L);
+  std::vector<int32_t> all(L);
+  for (int l = 0; l < L; ++l) all[l] = l;
+  if (o.taus) {
+    for (int l = 0; l < L; ++l) {
+      tau[l] = o.taus[l];
+      if (!(tau[l] > 0.0)) fail(IHSBIN_EINVAL, "taus must be positive");
+    }
+  }
+  {
+    spec = spectrum_impl(c, A, Linv, all, lam0, std::max(2, o.lanczos_steps), o.seed + 1);
+    for (int l = 0; l < L; ++l) {
+      const double cmin = spec[l].mu_min * grid[l] / lam0[l];
+      const double cmax = spec[l].mu_max * grid[l + 1] / lam0[l];
+      if (!o.taus) tau[l] = 2.0 / (cmin + cmax);
+      const double rr = std::max(std::fabs(1.0 - tau[l] * cmin), std::fabs(1.0 - tau[l] * cmax));
+      rate[l] = std::min(rr, 0.999);
+    }
+  }
+  for (int l = 0; l < L; ++l) ref[l] = o.centred ? lam0[l] : 0.0;
+  IHS_HIP(hipStreamSynchronize(st));
+  r.ms_spectrum = tspec.ms();
+
+  // ---- basis recursion
+  Timer tb;
+  auto path = new ihsbin_path();
+  std::unique_ptr<ihsbin_path> guard(path);
+  path->device = c.device;
+  path->stream = st;
+  path->d = d;
+  path->K = K;
+  path->L = L;
+  path->m_used = m;
+  path->lam_min = lam_min;
+  path->lam_max = lam_max;
+  path->centred = o.centred ? 1 : 0;
+  path->grid = grid;
+  path->lam0 = lam0;
+  path->tau = tau;
+  path->rate = rate;
+  path->ref = ref;
+  path->k.assign(L, 1);
+  const int64_t kcap = o.k_fixed > 0 ? o.k_fixed : o.k_max;
+  path->kcap = kcap;
+  double* basis = static_cast<double*>(path->basis.ensure(sizeof(double) * L * kcap * d * K));
+  IHS_HIP(hipMemsetAsync(basis, 0, sizeof(double) * L * kcap * d * K, st));
+
+  const int64_t wcap = (int64_t)L * kcap * K;
+  DevBuf Ub0, Ub1, Rb, Tt, Zb, Wb, pb, parb, partial_b;
+  double* Ucur = static_cast<double*>(Ub0.ensure(sizeof(double) * d * wcap));
+  double* Unext = static_cast<double*>(Ub1.ensure(sizeof(double) * d * wcap));
+  double* R = static_cast<double*>(Rb.ensure(sizeof(double) * d * wcap));
+  double* Tm = static_cast<double*>(Tt.ensure(sizeof(double) * d * wcap));
+  double* Z = static_cast<double*>(Zb.ensure(sizeof(double) * d * wcap));
+  double* W = static_cast<double*>(Wb.ensure(sizeof(double) * d * wcap));
+  // per-position parameters: ids, keep (int32), tau, ref, mu_lo, mu_hi (double)
+  char* pbase = static_cast<char*>(pb.ensure((sizeof(int32_t) * 2 + sizeof(double) * 4) * L + 256));
+  int32_t* ids_dev = reinterpret_cast<int32_t*>(pbase);
+  int32_t* keep_dev = ids_dev + L;
+  double* tau_dev = reinterpret_cast<double*>(pbase + ((sizeof(int32_t) * 2 * L + 63) / 64) * 64);
+  double* ref_dev = tau_dev + L;
+  double* mlo_dev = ref_dev + L;
+  double* mhi_dev = mlo_dev + L;
+
+  std::vector<int32_t> act = all;
+  auto upload = [&]() {
+    const int na = (int)act.size();
+    std::vector<double> t(na), rf(na), ml(na), mh(na);
+    for (int a = 0; a < na; ++a) {
+      const int l = act[a];
+      t[a] = tau[l];
+      rf[a] = ref[l];
+      ml[a] = tau[l] * (grid[l] - ref[l]);
+      mh[a] = tau[l] * (grid[l + 1] - ref[l]);
+    }
+    IHS_HIP(hipMemcpyAsync(ids_dev, act.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(tau_dev, t.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(ref_dev, rf.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(mlo_dev, ml.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(mhi_dev, mh.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipStreamSynchronize(st));
+  };
+  upload();
+  // u_{0,0} = P_S C for every interval
+  launch_seed_rhs(C, d, K, L, R, wcap, st);
+  apply_p(c, Linv, ids_dev, L, d, K, wcap, R, Tm, Ucur);
+  launch_store_first(Ucur, wcap, d, K, L, ids_dev, kcap, basis, st);
+
+  std::vector<hipEvent_t> events;
+  std::vector<double> flops_per_launch;
+  std::vector<double> host_part;
+  int unconverged = 0;
+  int steps = 0;
+  for (int i = 1; i < kcap && !act.empty(); ++i) {
+    const int na = (int)act.size();
+    const int64_t w_old = (int64_t)na * i * K;
+    const size_t ev0 = events.size();
+    ata_apply(c, A, Ucur, w_old, wcap, W, wcap, o.timing ? &events : nullptr);
+    if (o.timing) {
+      const double per = A.format == IHSBIN_DENSE ? 4.0 * A.n * A.d : 4.0 * A.nnz;
+      const size_t chunks = (events.size() - ev0) / 3;
+      const int64_t wc = w_old / (int64_t)std::max<size_t>(1, chunks);
+      for (size_t q = 0; q < chunks; ++q) flops_per_launch.push_back(per * (double)wc);
+    }
+    launch_form_r(W, Ucur, wcap, d, K, na, i, tau_dev, ref_dev, R, st);
+    apply_p(c, Linv, ids_dev, na, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
+    double* part = static_cast<double*>(partial_b.ensure(sizeof(double) * 4 * na * 64));
+    const int nbx = launch_update(Ucur, Z, Unext, wcap, d, K, na, i, ids_dev, kcap, basis, mlo_dev,
+                                  mhi_dev, part, st);
+    host_part.resize((size_t)4 * na * nbx);
+    IHS_HIP(hipMemcpyAsync(host_part.data(), part, sizeof(double) * host_part.size(),
+                           hipMemcpyDeviceToHost, st));
+    IHS_HIP(hipStreamSynchronize(st));
+    steps = i;
+    std::vector<int32_t> keep_pos, next_act;
+    for (int a = 0; a < na; ++a) {
+      const int l = act[a];
+      path->k[l] = i + 1;
+      double sums[4] = {0, 0, 0, 0};
+      for (int b = 0; b < nbx; ++b)
+        for (int q = 0; q < 4; ++q) sums[q] += host_part[((size_t)a * nbx + b) * 4 + q];
+      bool stop;
+      const bool finite = std::isfinite(sums[0]) && std::isfinite(sums[1]) && std::isfinite(sums[2]) &&
+                          std::isfinite(sums[3]);
+      if (o.k_fixed > 0) {
+        stop = (i + 1 >= o.k_fixed);
+      } else if (!finite) {
+        stop = true;
+        ++unconverged;
+      } else {
+        const double rr = rate[l];
+        const double fac = rr / (1.0 - rr);
+        stop = std::sqrt(sums[0]) * fac <= o.tol * std::sqrt(sums[2]) &&
+               std::sqrt(sums[1]) * fac <= o.tol * std::sqrt(sums[3]);
+      }
+      if (!stop) {
+        keep_pos.push_back(a);
+        next_act.push_back(l);
+      }
+    }
+    if ((int)next_act.size() < na && !next_act.empty()) {
+      IHS_HIP(hipMemcpyAsync(keep_dev, keep_pos.data(), sizeof(int32_t) * keep_pos.size(),
+                             hipMemcpyHostToDevice, st));
+      launch_compact(Unext, Ucur, wcap, d, (int64_t)(i + 1) * K, (int)next_act.size(), keep_dev, st);
+      act = next_act;
+      upload();
+    } else {
+      std::swap(Ucur, Unext);
+      act = next_act;
+    }
+  }
+  if (o.k_fixed == 0) unconverged += (int)act.size();
+  IHS_HIP(hipStreamSynchronize(st));
+  r.ms_basis = tb.ms();
+  if (o.timing && !events.empty()) {
+    for (size_t q = 0; q + 2 < events.size(); q += 3) {
+      float ty = 0.f, tw = 0.f;
+      IHS_HIP(hipEventElapsedTime(&ty, events[q], events[q + 1]));
+      IHS_HIP(hipEventElapsedTime(&tw, events[q + 1], events[q + 2]));
+      r.ata_ms_y += ty;
+      r.ata_ms_w += tw;
+      r.ata_launches += 1;
+    }
+    for (double f : flops_per_launch) r.ata_flops += f;
+    const double abytes = A.format == IHSBIN_DENSE
+                              ? (double)A.n * A.d * (A.dtype == IHSBIN_F32 ? 4.0 : 8.0)
+                              : (double)A.nnz * ((A.dtype == IHSBIN_F32 ? 4.0 : 8.0) + 4.0);
+    r.ata_bytes_a = abytes * (double)r.ata_launches;
+  }
+  for (auto e : events) (void)hipEventDestroy(e);
+  r.L = L;
+  r.steps = steps;
+  for (int l = 0; l < L; ++l) {
+    r.k_max_used = std::max(r.k_max_used, path->k[l]);
+    r.k_sum += path->k[l];
+  }
+  r.n_unconverged = unconverged;
+  r.ms_total = total.ms();
+  if (rep) *rep = r;
+  *out = guard.release();
+  return unconverged > 0 ? IHSBIN_ENOCONV : IHSBIN_OK;
+}
+
+static int interval_of(const std::vector<double>& grid, double lam) {
+  const int L = (int)grid.size() - 1;
+  int l = (int)(std::lower_bound(grid.begin() + 1, grid.end(), lam) - (grid.begin() + 1));
+  return std::min(std::max(l, 0), L - 1);
+}
+
+static void eval_impl(ihsbin_path* p, const double* lambdas, int64_t T, void* X, int64_t ldx,
+                      int x_dtype) {
+  if (!p) fail(IHSBIN_EINVAL, "path is NULL");
+  if (T < 0 || (T > 0 && (!lambdas || !X))) fail(IHSBIN_EINVAL, "bad lambdas / X");
+  if (ldx < p->K) fail(IHSBIN_EINVAL, "ldx < K");
+  if (x_dtype != IHSBIN_F32 && x_dtype != IHSBIN_F64) fail(IHSBIN_EINVAL, "bad x_dtype");
+  if (T == 0) return;
+  DeviceGuard dg(p->device);
+  std::vector<EvalItem> items((size_t)T);
+  const double slack = 1e-12;
+  for (int64_t t = 0; t < T; ++t) {
+    const double lam = lambdas[t];
+    if (!(lam >= p->lam_min * (1 - slack)) || !(lam <= p->lam_max * (1 + slack)))
+      fail(IHSBIN_ERANGE, "lambda outside the prepared range");
+    const int l = interval_of(p->grid, lam);
+    items[t].l = l;
+    items[t].k = p->k[l];
+    items[t].tau = p->tau[l];
+    items[t].mu = p->tau[l] * (lam - p->ref[l]);
+  }
+  EvalItem* it = static_cast<EvalItem*>(p->items.ensure(sizeof(EvalItem) * (size_t)T));
+  IHS_HIP(hipMemcpyAsync(it, items.data(), sizeof(EvalItem) * (size_t)T, hipMemcpyHostToDevice,
+                         p->stream));
+  launch_eval(p->basis.as<double>(), p->kcap, p->d, p->K, it, T, X, ldx, x_dtype, p->stream);
+  IHS_HIP(hipStreamSynchronize(p->stream));
+}
+
+}  // namespace ihs
+
+// ====================================================================== ABI
+using namespace ihs;
+
+template <class F>
+static int guarded(ihsbin_ctx* ctx, F&& f) {
+  try {
+    int rc = f();
+    if (ctx && rc == IHSBIN_ENOCONV) ctx->c.last_error = "some interval reached k_max";
+    return rc;
+  } catch (const Error& e) {
+    if (ctx) ctx->c.last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->c.last_error = "host allocation failed";
+    return IHSBIN_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->c.last_error = e.what();
+    return IHSBIN_EHIP;
+  }
+}
+
+extern "C" {
+
+const char* ihsbin_status_str(int s) {
+  switch (s) {
+    case IHSBIN_OK: return "ok";
+    case IHSBIN_EINVAL: return "invalid argument";
+    case IHSBIN_ENOMEM: return "out of device memory";
+    case IHSBIN_EHIP: return "HIP runtime error";
+    case IHSBIN_ENOTSPD: return "sketched Hessian not positive definite";
+    case IHSBIN_ENOCONV: return "tolerance not reached within k_max";
+    case IHSBIN_ERANGE: return "lambda outside the prepared range";
+    case IHSBIN_EUNSUP: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* ihsbin_version(void) { return "ihsbin 0.1 (gfx950)"; }
+
+void ihsbin_opts_default(ihsbin_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sketch = IHSBIN_GAUSSIAN;
+  o->sjlt_s = 1;
+  o->m = 0;
+  o->seed = 0;
+  o->tol = 1e-8;
+  o->k_max = 96;
+  o->k_fixed = 0;
+  o->L = 0;
+  o->centred = 1;
+  o->adaptive_m = 1;
+  o->rate_target = 0.7;
+  o->m_max = 0;
+  o->lanczos_steps = 16;
+  o->timing = 0;
+  o->taus = nullptr;
+}
+
+int ihsbin_create(ihsbin_ctx** ctx, int device, void* stream) {
+  if (!ctx) return IHSBIN_EINVAL;
+  *ctx = nullptr;
+  try {
+    int n = 0;
+    IHS_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return IHSBIN_EINVAL;
+    auto c = new ihsbin_ctx();
+    c->c.device = device;
+    c->c.stream = static_cast<hipStream_t>(stream);
+    *ctx = c;
+    return IHSBIN_OK;
+  } catch (const Error& e) {
+    return e.status;
+  } catch (...) {
+    return IHSBIN_EHIP;
+  }
+}
+
+int ihsbin_destroy(ihsbin_ctx* ctx) {
+  if (!ctx) return IHSBIN_OK;
+  try {
+    DeviceGuard g(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    delete ctx;
+  } catch (...) {
+    delete ctx;
+    return IHSBIN_EHIP;
+  }
+  return IHSBIN_OK;
+}
+
+const char* ihsbin_last_error(const ihsbin_ctx* ctx) { return ctx ? ctx->c.last_error.c_str() : ""; }
+
+int ihsbin_path_build(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B, int64_t K,
+                      int64_t ldb, double lam_min, double lam_max, const ihsbin_opts* opts,
+                      ihsbin_path** path, ihsbin_report* report) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    return build_impl(ctx->c, A, B, K, ldb, lam_min, lam_max, opts, path, report);
+  });
+}
+
+int ihsbin_path_eval(ihsbin_path* path, const double* lambdas, int64_t T, void* X, int64_t ldx,
+                     int32_t x_dtype) {
+  return guarded(nullptr, [&] {
+    eval_impl(path, lambdas, T, X, ldx, x_dtype);
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_path_get_info(const ihsbin_path* p, ihsbin_path_info* info) {
+  if (!p || !info) return IHSBIN_EINVAL;
+  info->L = p->L;
+  info->K = (int32_t)p->K;
+  info->d = p->d;
+  info->m_used = p->m_used;
+  info->lam_min = p->lam_min;
+  info->lam_max = p->lam_max;
+  info->centred = p->centred;
+  return IHSBIN_OK;
+}
+
+int ihsbin_path_intervals(const ihsbin_path* p, double* lo, double* hi, double* lam0, double* tau,
+                          double* rate, int32_t* k) {
+  if (!p) return IHSBIN_EINVAL;
+  for (int l = 0; l < p->L; ++l) {
+    if (lo) lo[l] = p->grid[l];
+    if (hi) hi[l] = p->grid[l + 1];
+    if (lam0) lam0[l] = p->lam0[l];
+    if (tau) tau[l] = p->tau[l];
+    if (rate) rate[l] = p->rate[l];
+    if (k) k[l] = p->k[l];
+  }
+  return IHSBIN_OK;
+}
+
+int ihsbin_path_basis(const ihsbin_path* p, int32_t l, double* out) {
+  if (!p || !out || l < 0 || l >= p->L) return IHSBIN_EINVAL;
+  return guarded(nullptr, [&] {
+    DeviceGuard g(p->device);
+    const size_t blk = sizeof(double) * (size_t)p->d * p->K;
+    IHS_HIP(hipMemcpyAsync(out, p->basis.as<double>() + (size_t)l * p->kcap * p->d * p->K,
+                           blk * p->k[l], hipMemcpyDeviceToDevice, p->stream));
+    IHS_HIP(hipStreamSynchronize(p->stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_path_free(ihsbin_path* p) {
+  if (!p) return IHSBIN_OK;
+  try {
+    DeviceGuard g(p->device);
+    (void)hipStreamSynchronize(p->stream);
+  } catch (...) {
+  }
+  delete p;
+  return IHSBIN_OK;
+}
+
+int ihsbin_solve_path(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B, int64_t K,
+                      int64_t ldb, const double* lambdas, int64_t T, const ihsbin_opts* opts,
+                      void* X, int64_t ldx, int32_t x_dtype, ihsbin_report* report) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    if (T < 1 || !lambdas) fail(IHSBIN_EINVAL, "need T >= 1 lambdas");
+    double lo = lambdas[0], hi = lambdas[0];
+    for (int64_t t = 1; t < T; ++t) {
+      lo = std::min(lo, lambdas[t]);
+      hi = std::max(hi, lambdas[t]);
+    }
+    ihsbin_path* p = nullptr;
+    const int rc = build_impl(ctx->c, A, B, K, ldb, lo, hi, opts, &p, report);
+    std::unique_ptr<ihsbin_path> guard(p);
+    eval_impl(p, lambdas, T, X, ldx, x_dtype);
+    return rc;
+  });
+}
+
+int ihsbin_sketch_draws(ihsbin_ctx* ctx, int32_t sketch, uint64_t seed, int64_t n, int64_t m,
+                        int32_t sjlt_s, int32_t* idx, int8_t* sign) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    if (n <= 0 || m <= 0 || n > INT32_MAX || m > INT32_MAX || !idx || !sign)
+      fail(IHSBIN_EINVAL, "bad sizes or pointers");
+    if (sketch == IHSBIN_COUNTSKETCH || sketch == IHSBIN_SJLT) {
+      const int s = sketch == IHSBIN_SJLT ? sjlt_s : 1;
+      if (s < 1 || m % s) fail(IHSBIN_EINVAL, "SJLT needs s >= 1 dividing m");
+      launch_draw_countsketch(seed, n, m, s, idx, sign, ctx->c.stream);
+    } else if (sketch == IHSBIN_SRHT) {
+      launch_draw_srht(seed, n, next_pow2(n), m, sign, idx, ctx->c.stream);
+    } else {
+      fail(IHSBIN_EINVAL, "no integer draws for this sketch");
+    }
+    IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_sketch_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch, int32_t sjlt_s,
+                        int64_t m, uint64_t seed, double* SA) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    const MatView v = check_matrix(A);
+    if (!SA) fail(IHSBIN_EINVAL, "SA is NULL");
+    if (v.format == IHSBIN_CSR) validate_csr(ctx->c, v);
+    sketch_apply_impl(ctx->c, v, sketch, sjlt_s, m, seed, SA);
+    IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d,
+                          const double* lam0, int32_t nl, double* Lfac, double* Linv) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    if (!SA || !lam0 || !Lfac || m <= 0 || d <= 0 || nl <= 0) fail(IHSBIN_EINVAL, "bad arguments");
+    for (int i = 0; i < nl; ++i)
+      if (!(lam0[i] > 0.0)) fail(IHSBIN_EINVAL, "lam0 must be positive");
+    DevBuf Gb, dinvb, lamb;
+    double* G = static_cast<double*>(Gb.ensure(sizeof(double) * d * d));
+    gram_impl(ctx->c, SA, m, d, G);
+    std::vector<double> l0(lam0, lam0 + nl);
+    factor_impl(ctx->c, G, d, l0, Lfac, Linv, dinvb, lamb);
+    IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U, int64_t w,
+                     int64_t ldu, double* W, int64_t ldw) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    const MatView v = check_matrix(A);
+    if (!U || !W || w < 1 || ldu < w || ldw < w) fail(IHSBIN_EINVAL, "bad U / W");
+    if (v.format == IHSBIN_CSR) validate_csr(ctx->c, v);
+    ata_apply(ctx->c, v, U, w, ldu, W, ldw, nullptr);
+    IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+"""CPU checks of the C ABI boundary: the library loads and exports every
+symbol declared in include/ihsbin.h, and its host-only calls behave."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ihsbin.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ihsbin_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2210_12212_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2210_12212_amd import _lib
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_lib.EXPORTED)
+
+
+def test_status_strings_and_version(lib):
+    assert lib.ihsbin_status_str(0) == b"ok"
+    assert b"range" in lib.ihsbin_status_str(-6)
+    assert lib.ihsbin_version().startswith(b"ihsbin")
+
+
+def test_default_options(lib):
+    from paper_2210_12212_amd import _lib
+    o = _lib.Opts()
+    lib.ihsbin_opts_default(C.byref(o))
+    assert o.tol == 1e-8 and o.k_max == 96 and o.centred == 1 and o.adaptive_m == 1
+    assert o.lanczos_steps == 16 and not o.taus
+
+
+def test_null_arguments_are_rejected(lib):
+    assert lib.ihsbin_create(None, 0, None) == -1
+    assert lib.ihsbin_path_free(None) == 0
+    assert lib.ihsbin_destroy(None) == 0
+    assert lib.ihsbin_path_build(None, None, None, 1, 1, 1.0, 2.0, None, None, None) == -1
+    assert lib.ihsbin_last_error(None) == b""
+
+
+def test_struct_sizes_match_header_layout():
+    from paper_2210_12212_amd import _lib
+    # int32 x2, int64 x4, pointers x3
+    assert C.sizeof(_lib.Matrix) == 8 + 32 + 24
+    assert C.sizeof(_lib.PathInfo) == 4 + 4 + 8 + 8 + 8 + 8 + 8

@@ -1,0 +1,257 @@
+"""GPU parity of every step of the HIP path against the FP64 oracle.
+
+Step-level calls (draws, sketch, factor, A^T A products) are compared with the
+oracle's independent implementations; the whole path is compared with the
+direct per-lambda solve at 1e-6 relative error per lambda.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, ihs_bin, rng, sketch
+
+pytestmark = pytest.mark.gpu
+
+TOL_PATH = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2210_12212_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def csr_dev(torch, M):
+    from paper_2210_12212_amd import CsrInput
+    return CsrInput(dev(torch, M.row_ptr), dev(torch, M.col_idx), dev(torch, M.vals), M.n, M.d)
+
+
+# ---------------------------------------------------------------- products
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("n,d,w", [(300, 70, 5), (257, 33, 40), (1000, 130, 100), (64, 64, 1)])
+def test_ata_dense(torch, ctx, dt, n, d, w):
+    r = np.random.default_rng(n + d + w)
+    A = r.standard_normal((n, d)).astype(dt)
+    U = r.standard_normal((d, w))
+    Wg = ctx.ata_apply(dev(torch, A), dev(torch, U)).cpu().numpy()
+    A64 = A.astype(np.float64)
+    ref = A64.T @ (A64 @ U)
+    np.testing.assert_allclose(Wg, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_ata_csr(torch, ctx):
+    M = W.csr_zipf(2000, 300, 7, seed=3, dtype=np.float32)
+    U = np.random.default_rng(1).standard_normal((300, 9))
+    Wg = ctx.ata_apply(csr_dev(torch, M), dev(torch, U)).cpu().numpy()
+    op = ihs_bin.Operator(M)
+    ref = op.AtA(U)
+    np.testing.assert_allclose(Wg, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- sketches
+@pytest.mark.parametrize("n,m,s", [(1000, 37, 1), (4099, 64, 4), (1, 5, 1)])
+def test_countsketch_draws_bit_exact(torch, ctx, n, m, s):
+    kind = "sjlt" if s > 1 else "countsketch"
+    idx, sign = ctx.sketch_draws(kind, 12345, n, m, s)
+    h, sg = rng.countsketch_draws(12345, n, m, s)
+    assert np.array_equal(idx.cpu().numpy(), h)
+    assert np.array_equal(sign.cpu().numpy(), sg)
+
+
+@pytest.mark.parametrize("n,m", [(1000, 100), (4096, 333), (3, 7)])
+def test_srht_draws_bit_exact(torch, ctx, n, m):
+    rows, sign = ctx.sketch_draws("srht", 99, n, m)
+    sg, rr, _ = rng.srht_draws(99, n, m)
+    assert np.array_equal(sign.cpu().numpy(), sg)
+    assert np.array_equal(rows.cpu().numpy(), rr)
+
+
+@pytest.mark.parametrize("kind", ["countsketch", "srht", "gaussian", "sjlt"])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_sketch_apply_dense(torch, ctx, kind, dt):
+    A = W.dense_decay(1500, 45, seed=4, dtype=dt)   # n' = 2048 for SRHT (zero padding)
+    m = 96
+    SA = ctx.sketch_apply(dev(torch, A), kind, m, 321, sjlt_s=4).cpu().numpy()
+    ref = sketch.apply(kind, A, 321, m, s=4)
+    # the Gaussian entries go through device log/cos/sqrt: allow a few ulp
+    tol = 1e-12 if kind != "gaussian" else 1e-11
+    np.testing.assert_allclose(SA, ref, rtol=tol, atol=tol * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kind", ["countsketch", "srht"])
+def test_sketch_apply_csr(torch, ctx, kind):
+    M = W.csr_zipf(3000, 120, 5, seed=9, dtype=np.float32)
+    SA = ctx.sketch_apply(csr_dev(torch, M), kind, 64, 77).cpu().numpy()
+    ref = sketch.apply(kind, M, 77, 64)
+    np.testing.assert_allclose(SA, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_srht_large_order_three_passes(torch, ctx):
+    # n' = 2^19 needs three Walsh-Hadamard passes over row digits
+    A = W.dense_decay((1 << 18) + 5, 3, seed=5, dtype=np.float32)
+    SA = ctx.sketch_apply(dev(torch, A), "srht", 50, 8).cpu().numpy()
+    ref = sketch.apply("srht", A, 8, 50)
+    np.testing.assert_allclose(SA, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- factor
+@pytest.mark.parametrize("d", [40, 64, 200, 300])
+def test_precond_factor(torch, ctx, d):
+    r = np.random.default_rng(d)
+    SA = r.standard_normal((d // 2 + 3, d))
+    lam0 = np.array([1e-3, 0.5, 7.0])
+    Lf, Li = ctx.precond_factor(dev(torch, SA), lam0)
+    Lf, Li = Lf.cpu().numpy(), Li.cpu().numpy()
+    for t, l0 in enumerate(lam0):
+        H = SA.T @ SA + l0 * np.eye(d)
+        assert np.allclose(np.triu(Lf[t], 1), 0)
+        np.testing.assert_allclose(Lf[t] @ Lf[t].T, H, rtol=1e-11, atol=1e-11 * np.abs(H).max())
+        Lref = np.linalg.cholesky(H)
+        np.testing.assert_allclose(Lf[t], Lref, rtol=1e-8, atol=1e-9 * np.abs(Lref).max())
+        np.testing.assert_allclose(Li[t] @ Lf[t], np.eye(d), atol=1e-8)
+
+
+def test_precond_not_spd_is_reported(torch, ctx):
+    from paper_2210_12212_amd import IhsbinError
+    SA = np.zeros((4, 8))
+    with pytest.raises(IhsbinError):
+        ctx.precond_factor(dev(torch, SA), [-1.0])
+
+
+# ---------------------------------------------------------------- basis
+@pytest.mark.parametrize("centred", [1, 0])
+def test_basis_matches_oracle_recursion(torch, ctx, centred):
+    # same sketch, same step sizes, same k: the GPU basis equals the oracle's
+    A = W.dense_decay(800, 40, seed=12)
+    B, _ = W.rhs(A, 2, 0.1, seed=13)
+    lo, hi, k = 1e-2, 1e1, 6
+    grid, lam0 = ihs_bin.plan(lo, hi)
+    taus = [0.9 - 0.01 * l for l in range(len(lam0))]
+    path, rep = ctx.path_build(dev(torch, A), dev(torch, B), lo, hi, sketch="countsketch", m=160,
+                               seed=55, adaptive_m=0, k_fixed=k, taus=taus, centred=centred)
+    SA = sketch.apply("countsketch", A, 55, 160)
+    op = ihs_bin.Operator(A)
+    C = op.At(B)
+    iv = path.intervals()
+    np.testing.assert_allclose(iv["lo"], grid[:-1], rtol=1e-14)
+    np.testing.assert_allclose(iv["lam0"], lam0, rtol=1e-14)
+    assert list(iv["k"]) == [k] * len(lam0)
+    for l in (0, len(lam0) // 2, len(lam0) - 1):
+        P = ihs_bin.Precond(SA, lam0[l])
+        ref_pt = lam0[l] if centred else 0.0
+        ut = ihs_bin.basis(op, P, C, taus[l], k, ref_pt)
+        got = path.basis(l).cpu().numpy()
+        for j in range(k):
+            scale = np.abs(ut[j]).max()
+            np.testing.assert_allclose(got[j], ut[j], rtol=1e-8, atol=1e-9 * scale)
+    lams = W.lambda_grid(lo, hi, 11)
+    Xo, _ = ihs_bin.path(A, B, lams, SA, lo, hi, k=k, taus=taus, centred=bool(centred))
+    X = path.eval(lams).cpu().numpy()
+    assert direct.rel_err(X, Xo).max() < 1e-9
+    path.free()
+
+
+# ---------------------------------------------------------------- path
+def _check_path(X, A, B, lams, tol=TOL_PATH):
+    ref = direct.ridge_path(A, B, lams)
+    err = direct.rel_err(X, ref)
+    assert err.max() <= tol, f"max rel err {err.max():.3e} at lambda {lams[int(err.argmax())]:.3e}"
+    return err
+
+
+def test_path_dense_decay_2048x256(torch, ctx):
+    p = W.make("dense_decay_2048x256")
+    path, rep = ctx.path_build(dev(torch, p.A), dev(torch, p.B), p.lam_min, p.lam_max,
+                               sketch=p.sketch, m=p.m, seed=p.sketch_seed)
+    assert rep["status"] == 0, rep
+    X = path.eval(p.lambdas).cpu().numpy()
+    err = _check_path(X, p.A, p.B, p.lambdas)
+    print(f"dense_decay: m_used={rep['m_used']} k_max={rep['k_max_used']} max_err={err.max():.2e}")
+    path.free()
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "countsketch", "sjlt"])
+def test_path_each_sketch_matrix_rhs(torch, ctx, kind):
+    A = W.dense_decay(1200, 60, seed=21, dtype=np.float32)
+    B, _ = W.rhs(A, 3, 0.1, seed=22)
+    lams = W.lambda_grid(1e-3, 1e2, 23)
+    X, rep = ctx.solve_path(dev(torch, A), dev(torch, B), lams, sketch=kind, m=120, seed=4, sjlt_s=2)
+    assert rep["status"] == 0, rep
+    _check_path(X.cpu().numpy(), A, B, lams)
+
+
+def test_path_csr(torch, ctx):
+    M = W.csr_zipf(6000, 200, 8, seed=31, dtype=np.float32)
+    B, _ = W.rhs(M, 1, 0.1, seed=32)
+    lams = W.lambda_grid(1e-2, 1e2, 17)
+    X, rep = ctx.solve_path(csr_dev(torch, M), dev(torch, B), lams, sketch="countsketch", m=400, seed=3)
+    assert rep["status"] == 0, rep
+    _check_path(X.cpu().numpy(), M, B, lams)
+
+
+def test_eval_any_order_and_float32_output(torch, ctx):
+    A = W.dense_decay(900, 30, seed=41)
+    B, _ = W.rhs(A, 1, 0.1, seed=42)
+    path, _ = ctx.path_build(dev(torch, A), dev(torch, B), 1e-2, 1e1, sketch="srht", m=64, seed=1)
+    lams = np.array([3.0, 1e-2, 1e1, 0.05, 0.05])
+    X64 = path.eval(lams).cpu().numpy()
+    X32 = path.eval(lams, dtype=torch.float32).cpu().numpy()
+    _check_path(X64, A, B, lams)
+    np.testing.assert_allclose(X32, X64, rtol=1e-6, atol=1e-7 * np.abs(X64).max())
+    np.testing.assert_array_equal(X64[3], X64[4])
+    path.free()
+
+
+def test_errors(torch, ctx):
+    from paper_2210_12212_amd import IhsbinError
+    A = W.dense_decay(100, 10, seed=1)
+    B, _ = W.rhs(A, 1, 0.1, seed=2)
+    path, _ = ctx.path_build(dev(torch, A), dev(torch, B), 0.1, 1.0, sketch="gaussian", m=20)
+    with pytest.raises(IhsbinError) as e:
+        path.eval([2.0])
+    assert e.value.status == -6
+    path.free()
+    with pytest.raises(IhsbinError) as e:
+        ctx.path_build(dev(torch, A), dev(torch, B), 1.0, 0.1)
+    assert e.value.status == -1
+    At = np.ascontiguousarray(A[:8])
+    with pytest.raises(IhsbinError) as e:
+        ctx.path_build(dev(torch, At), dev(torch, B[:8]), 0.1, 1.0)
+    assert e.value.status == -7
+    bad = W.csr_zipf(50, 10, 3, seed=1)
+    bad.col_idx[5] = 10
+    with pytest.raises(IhsbinError) as e:
+        ctx.ata_apply(csr_dev(torch, bad), dev(torch, np.ones((10, 1))))
+    assert e.value.status == -1
+
+
+def test_k_max_reached_reports_noconv(torch, ctx):
+    A = W.dense_decay(600, 40, seed=51)
+    B, _ = W.rhs(A, 1, 0.1, seed=52)
+    path, rep = ctx.path_build(dev(torch, A), dev(torch, B), 1e-3, 1e2, sketch="gaussian", m=80,
+                               adaptive_m=0, k_max=2)
+    assert rep["status"] == -5 and rep["n_unconverged"] > 0
+    X = path.eval([1e-3, 1.0]).cpu().numpy()   # still usable
+    assert np.all(np.isfinite(X))
+    path.free()
+
+
+def test_run_twice_identical(torch, ctx):
+    A = W.dense_decay(700, 50, seed=61)
+    B, _ = W.rhs(A, 2, 0.1, seed=62)
+    lams = W.lambda_grid(1e-3, 1e2, 9)
+    X1, _ = ctx.solve_path(dev(torch, A), dev(torch, B), lams, sketch="srht", m=100, seed=5)
+    X2, _ = ctx.solve_path(dev(torch, A), dev(torch, B), lams, sketch="srht", m=100, seed=5)
+    assert torch.equal(X1, X2)
