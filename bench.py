@@ -1,0 +1,169 @@
+"""Benchmark: the whole IHS-BIN ridge path on one MI355X.
+
+A step is one pass of the hot path over one synthetic problem: sketch, sketched
+Gram, per-interval Cholesky and inverse factors, step-size estimate, basis
+recursion, and evaluation of x(lam) at all T lambdas (the path is freed after).
+The inputs are resident in HBM before the timed region starts.
+
+Default workload: dense A, n = 131072, d = 2048, FP32 storage, singular values
+exp(-i/300), b = A x* + 0.05 noise, SRHT sketch with initial m = 1024, T = 200
+lambdas log-spaced in [1e-4, 1e1].
+
+Prints one JSON line.  ``value`` = lambda-solves per second (T per step).
+Outside the timed region the result is checked on sampled lambdas against the
+FP64 CPU oracle, which is also timed on the host as ``cpu_baseline``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix, flop/s
+HBM_PEAK = 8.0e12          # bytes/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="dense_exp300_131072x2048")
+    ap.add_argument("--n", type=int, default=None, help="override n (smaller runs)")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--rate-target", type=float, default=0.7)
+    ap.add_argument("--oracle-lambdas", type=int, default=12,
+                    help="lambdas of the sample solved by the CPU oracle")
+    ap.add_argument("--no-oracle", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is built and "
+              "measured on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2210_12212_amd import Context
+
+    t0 = time.time()
+    p = W.make(args.workload, n=args.n)
+    log(f"[bench] workload {p.name}: n={p.n} d={p.d} K={p.B.shape[1]} T={len(p.lambdas)} "
+        f"sketch={p.sketch} m0={p.m} (generated in {time.time() - t0:.1f}s)")
+    dev = torch.device("cuda", 0)
+    A = torch.from_numpy(p.A).to(dev)
+    B = torch.from_numpy(p.B).to(dev)
+    torch.cuda.synchronize()
+    ctx = Context(0)
+    opts = dict(sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=args.tol,
+                rate_target=args.rate_target, timing=1)
+    X = torch.empty((len(p.lambdas), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
+
+    def step():
+        path, rep = ctx.path_build(A, B, p.lam_min, p.lam_max, **opts)
+        path.eval(p.lambdas, out=X)
+        path.free()
+        return rep
+
+    for w in range(args.warmup):
+        rep = step()
+        log(f"[bench] warmup {w}: {rep['ms_total']:.1f} ms  m_used={rep['m_used']} "
+            f"k_max={rep['k_max_used']} k_sum={rep['k_sum']} status={rep['status']}")
+    lat = []
+    reps = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        ts = time.perf_counter()
+        reps.append(step())
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+        log(f"[bench] step {s}: {lat[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    T = len(p.lambdas)
+    value = T * args.steps / elapsed
+    rep = reps[-1]
+
+    # dominant kernel: the two FP64 MFMA GEMMs of A^T A U (each 2*n*d*w flops)
+    launches = max(1, rep["ata_launches"])
+    half_flops = rep["ata_flops"] / 2.0
+    dom = "gemm_y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "gemm_w_AtY"
+    dom_ms = max(rep["ata_ms_y"], rep["ata_ms_w"])
+    achieved = (half_flops / launches) / (dom_ms / launches * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
+                "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": None,
+                "launches": rep["ata_launches"],
+                "flops_per_launch": half_flops / launches,
+                "avg_launch_ms": dom_ms / launches,
+                "ata_ms_y": rep["ata_ms_y"], "ata_ms_w": rep["ata_ms_w"]}
+
+    # accuracy on sampled lambdas, and the oracle timed on the host (outside the timed region)
+    Xh = X.cpu().numpy()
+    cpu = None
+    max_err = None
+    if not args.no_oracle:
+        from oracle import direct
+        cores = len(os.sched_getaffinity(0))
+        idx = np.unique(np.linspace(0, T - 1, min(T, args.oracle_lambdas)).round().astype(int))
+        tg = time.perf_counter()
+        G = direct.gram(p.A)
+        C = direct.atb(p.A, p.B)
+        t_gram = time.perf_counter() - tg
+        ts = time.perf_counter()
+        Xo = direct.solve_from_gram(G, C, p.lambdas[idx])
+        t_solve = (time.perf_counter() - ts) / len(idx)
+        err = direct.rel_err(Xh[idx], Xo)
+        max_err = float(err.max())
+        t_full = t_gram + T * t_solve
+        cpu = {"value": round(T / t_full, 3), "unit": "lambda-solves/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"G=A^T A and A^T b over the full matrix ({t_gram:.1f}s) plus {len(idx)} of "
+                         f"{T} per-lambda Cholesky solves ({t_solve * 1e3:.1f} ms each); the full "
+                         f"path time is t_G + T*t_solve = {t_full:.1f}s"}
+        log(f"[bench] oracle: gram {t_gram:.1f}s, solve {t_solve * 1e3:.1f} ms/lambda, "
+            f"max rel err on {len(idx)} lambdas = {max_err:.3e}")
+
+    out = {
+        "metric": "ridge-path lambda-solves/s at <=1e-6 rel err vs FP64",
+        "value": round(value, 3),
+        "unit": "lambda-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": p.name, "n": p.n, "d": p.d, "K": int(p.B.shape[1]), "T": T,
+                   "storage": str(p.A.dtype), "sketch": p.sketch, "m0": p.m,
+                   "m_used": rep["m_used"], "L": rep["L"], "k_max": rep["k_max_used"],
+                   "k_sum": rep["k_sum"], "lam": [p.lam_min, p.lam_max], "tol": args.tol},
+        "max_rel_err": max_err,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "phase_ms": {k: rep[k] for k in ("ms_sketch", "ms_factor", "ms_spectrum", "ms_basis",
+                                         "ms_total")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
