@@ -221,7 +221,7 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // q_0 for column a: uniform(-1, 1) draws, normalized.
-__global__ __launch_bounds__(256) void lanczos_start_kernel(uint64_t key, int64_t d, int na,
+__global__ __launch_bounds__(256) void lanczos_start_kernel(uint64_t key, int64_t d, int64_t ld,
                                                             double* Q0) {
   __shared__ double red[256];
   const int a = blockIdx.x;
@@ -229,69 +229,72 @@ __global__ __launch_bounds__(256) void lanczos_start_kernel(uint64_t key, int64_
   for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
     const uint64_t x = sm_draw(key, (uint64_t)(a * d + r));
     const double v = (double)(x >> 11) * 0x1.0p-52 - 1.0;
-    Q0[r * na + a] = v;
+    Q0[r * ld + a] = v;
     s += v * v;
   }
   const double nrm = sqrt(block_sum(s, red));
-  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) Q0[r * na + a] /= nrm;
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) Q0[r * ld + a] /= nrm;
 }
 
-void launch_lanczos_start(uint64_t seed, int64_t d, int na, double* Q0, hipStream_t st) {
-  hipLaunchKernelGGL(lanczos_start_kernel, dim3(na), dim3(256), 0, st, stream_key(seed, 4), d, na, Q0);
+void launch_lanczos_start(uint64_t seed, int64_t d, int na, int64_t ld, double* Q0, hipStream_t st) {
+  hipLaunchKernelGGL(lanczos_start_kernel, dim3(na), dim3(256), 0, st, stream_key(seed, 4), d, ld, Q0);
   IHS_CHECK_LAUNCH();
 }
 
 // S[:, a] += lam0[a] * T[:, a]
 __global__ void add_shift_kernel(double* S, const double* __restrict__ T, int64_t d, int na,
-                                 const double* __restrict__ lam0) {
+                                 int64_t ld, const double* __restrict__ lam0) {
   const int64_t total = d * na;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x)
-    S[t] += lam0[t % na] * T[t];
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / na, a = t % na;
+    S[r * ld + a] += lam0[a] * T[r * ld + a];
+  }
 }
 
-void launch_add_shift(double* S, const double* T, int64_t d, int na, const double* lam0,
+void launch_add_shift(double* S, const double* T, int64_t d, int na, int64_t ld, const double* lam0,
                       hipStream_t st) {
   int64_t blocks = cdiv(d * na, 256);
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(add_shift_kernel, dim3((unsigned)blocks), dim3(256), 0, st, S, T, d, na, lam0);
+  hipLaunchKernelGGL(add_shift_kernel, dim3((unsigned)blocks), dim3(256), 0, st, S, T, d, na, ld,
+                     lam0);
   IHS_CHECK_LAUNCH();
 }
 
 // Full re-orthogonalization (two Gram-Schmidt passes) of w against q_0..q_j,
 // alpha_j = <q_j, B q_j>, beta_{j+1} = ||w||, q_{j+1} = w / beta.
-__global__ __launch_bounds__(256) void lanczos_orth_kernel(double* Q, double* Wv, int64_t d, int na,
-                                                           int j, int J, double* alpha,
+__global__ __launch_bounds__(256) void lanczos_orth_kernel(double* Q, double* Wv, int64_t d,
+                                                           int64_t ld, int j, int J, double* alpha,
                                                            double* beta) {
   __shared__ double red[256];
   const int a = blockIdx.x;
   double al = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
     for (int q = 0; q <= j; ++q) {
-      const double* Qq = Q + (int64_t)q * d * na;
+      const double* Qq = Q + (int64_t)q * d * ld;
       double s = 0.0;
-      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Qq[r * na + a] * Wv[r * na + a];
+      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Qq[r * ld + a] * Wv[r * ld + a];
       const double h = block_sum(s, red);
       if (q == j) al += h;
-      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) Wv[r * na + a] -= h * Qq[r * na + a];
+      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) Wv[r * ld + a] -= h * Qq[r * ld + a];
       __syncthreads();
     }
   }
   double s = 0.0;
-  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Wv[r * na + a] * Wv[r * na + a];
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Wv[r * ld + a] * Wv[r * ld + a];
   const double b = sqrt(block_sum(s, red));
-  double* Qn = Q + (int64_t)(j + 1) * d * na;
+  double* Qn = Q + (int64_t)(j + 1) * d * ld;
   for (int64_t r = threadIdx.x; r < d; r += blockDim.x)
-    Qn[r * na + a] = b > 0.0 ? Wv[r * na + a] / b : 0.0;
+    Qn[r * ld + a] = b > 0.0 ? Wv[r * ld + a] / b : 0.0;
   if (threadIdx.x == 0) {
     alpha[a * J + j] = al;
     beta[a * J + j] = b;
   }
 }
 
-void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int j, int J, double* alpha,
-                         double* beta, hipStream_t st) {
-  hipLaunchKernelGGL(lanczos_orth_kernel, dim3(na), dim3(256), 0, st, Q, Wv, d, na, j, J, alpha,
+void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int64_t ld, int j, int J,
+                         double* alpha, double* beta, hipStream_t st) {
+  hipLaunchKernelGGL(lanczos_orth_kernel, dim3(na), dim3(256), 0, st, Q, Wv, d, ld, j, J, alpha,
                      beta);
   IHS_CHECK_LAUNCH();
 }

@@ -25,10 +25,10 @@ void launch_compact(const double* Src, double* Dst, int64_t ld, int64_t d, int64
                     const int32_t* keep, hipStream_t st);
 void launch_eval(const double* basis, int64_t kcap, int64_t d, int64_t K, const EvalItem* items,
                  int64_t T, void* X, int64_t ldx, int x_dtype, hipStream_t st);
-void launch_lanczos_start(uint64_t seed, int64_t d, int na, double* Q0, hipStream_t st);
-void launch_add_shift(double* S, const double* T, int64_t d, int na, const double* lam0,
+void launch_lanczos_start(uint64_t seed, int64_t d, int na, int64_t ld, double* Q0, hipStream_t st);
+void launch_add_shift(double* S, const double* T, int64_t d, int na, int64_t ld, const double* lam0,
                       hipStream_t st);
-void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int j, int J, double* alpha,
-                         double* beta, hipStream_t st);
+void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int64_t ld, int j, int J,
+                         double* alpha, double* beta, hipStream_t st);
 
 }  // namespace ihs

@@ -1,59 +1,236 @@
 // FP64 GEMM on MFMA for gfx950.
 //
 // A 256-thread workgroup (four wave64s) computes a BM x BN tile of C; each
-// wave owns a (BM/WM) x (BN/WN) sub-tile made of 16x16 accumulators fed by
-// v_mfma_f64_16x16x4f64.  Operands are staged through LDS in K-slices of 16,
-// stored K-major (As[k][m], Bs[k][n]) whatever the global layout, so one
-// inner loop serves every transpose case.  FP32 operands are widened to FP64
-// as they are staged (exact).  The next K-slice is prefetched into registers
-// while the matrix cores work on the current one.
+// wave owns a (BM/WM) x (BN/WN) sub-tile of 16x16 accumulators fed by
+// v_mfma_f64_16x16x4f64.  Operands are staged through LDS in K-slices of 16.
+// FP32 operands are widened to FP64 when written to LDS (exact).  The next
+// K-slice is prefetched into registers (16-byte vector loads where aligned and
+// in bounds) while the matrix cores work on the current one.
+//
+// LDS layouts are chosen per operand orientation so that the MFMA fragment
+// reads are free of bank conflicts: an operand whose contiguous global
+// dimension is K is kept row-major with K padded to 18 doubles; one whose
+// contiguous dimension is M or N is kept K-major with the row padded by 16
+// doubles (row pitch = 128 bytes mod 256).
 //
 // Fragment layout of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of lane l
 // holds D[4 r + l / 16][l % 16].
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; the linear block id
+// is remapped so that each XCD walks a contiguous range of tiles (N-tiles
+// fastest), so tiles sharing an A row panel share that XCD's L2.
 #include "gemm.hpp"
 
 namespace ihs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
+template <typename T>
+__device__ inline void ld4(const T* p, int, T (&o)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  } else {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+  }
+}
+
+// Checked load of up to four consecutive elements (nv valid, rest zero).
+template <typename T>
+__device__ inline void ld4c(const T* p, int nv, T (&o)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) o[j] = j < nv ? p[j] : T(0);
+}
+
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int WM, int WN, bool CHK>
+__device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ A,
+                                          const TB* __restrict__ B, int64_t m0, int64_t n0,
+                                          int64_t kb, int64_t ke, double* __restrict__ smem,
+                                          v4d (&acc)[BM / WM / 16][BN / WN / 16]) {
   constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
-  constexpr int AE = BM * BK / 256;
-  constexpr int BE = (BK * BN + 255) / 256;
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(FM >= 1 && FN >= 1, "tile");
-  __shared__ double As[BK][BM];
-  __shared__ double Bs[BK][BN];
-
+  constexpr int A_LD = TRA ? BM + (48 - BM % 32) % 32 : BK + 2;
+  constexpr int B_LD = TRB ? BK + 2 : BN + (48 - BN % 32) % 32;
+  constexpr int A_SZ = TRA ? BK * A_LD : BM * A_LD;
+  constexpr int B_SZ = TRB ? BN * B_LD : BK * B_LD;
+  constexpr int AVEC = BM * BK / 4;
+  constexpr int BVEC = BK * BN / 4;
+  constexpr int AV = (AVEC + 255) / 256;
+  constexpr int BV = (BVEC + 255) / 256;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = (wave % WM) * (BM / WM);
   const int wn = (wave / WM) * (BN / WN);
-  const int z = blockIdx.z;
+
+  TA ra[AV][4];
+  TB rb[BV][4];
+  auto loadA = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+      const int vid = tid + e * 256;
+      if (AVEC % 256 != 0 && vid >= AVEC) break;
+      int64_t r, c;
+      if constexpr (!TRA) {
+        r = m0 + vid / (BK / 4);
+        c = k0 + 4 * (vid % (BK / 4));
+      } else {
+        r = k0 + vid / (BM / 4);
+        c = m0 + 4 * (vid % (BM / 4));
+      }
+      const TA* p = A + r * g.lda + c;
+      if constexpr (!CHK) {
+        ld4<TA>(p, 4, ra[e]);
+      } else {
+        const int64_t rlim = TRA ? ke : g.M, clim = TRA ? g.M : ke;
+        const int nv = r < rlim ? (int)(clim - c < 4 ? (clim - c > 0 ? clim - c : 0) : 4) : 0;
+        ld4c<TA>(p, nv, ra[e]);
+      }
+    }
+  };
+  auto loadB = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < BV; ++e) {
+      const int vid = tid + e * 256;
+      if (BVEC % 256 != 0 && vid >= BVEC) break;
+      int64_t r, c;
+      if constexpr (!TRB) {
+        r = k0 + vid / (BN / 4);
+        c = n0 + 4 * (vid % (BN / 4));
+      } else {
+        r = n0 + vid / (BK / 4);
+        c = k0 + 4 * (vid % (BK / 4));
+      }
+      const TB* p = B + r * g.ldb + c;
+      if constexpr (!CHK) {
+        ld4<TB>(p, 4, rb[e]);
+      } else {
+        const int64_t rlim = TRB ? g.N : ke, clim = TRB ? ke : g.N;
+        const int nv = r < rlim ? (int)(clim - c < 4 ? (clim - c > 0 ? clim - c : 0) : 4) : 0;
+        ld4c<TB>(p, nv, rb[e]);
+      }
+    }
+  };
+  auto store = [&](double* As, double* Bs) {
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+      const int vid = tid + e * 256;
+      if (AVEC % 256 != 0 && vid >= AVEC) break;
+      const int o = TRA ? (vid / (BM / 4)) * A_LD + 4 * (vid % (BM / 4))
+                        : (vid / (BK / 4)) * A_LD + 4 * (vid % (BK / 4));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) As[o + j] = (double)ra[e][j];
+    }
+#pragma unroll
+    for (int e = 0; e < BV; ++e) {
+      const int vid = tid + e * 256;
+      if (BVEC % 256 != 0 && vid >= BVEC) break;
+      const int o = TRB ? (vid / (BK / 4)) * B_LD + 4 * (vid % (BK / 4))
+                        : (vid / (BN / 4)) * B_LD + 4 * (vid % (BN / 4));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Bs[o + j] = (double)rb[e][j];
+    }
+  };
+  auto compute = [&](const double* As, const double* Bs) {
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4), c16 = lane & 15;
+      double af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        af[i] = TRA ? As[kr * A_LD + wm + i * 16 + c16] : As[(wm + i * 16 + c16) * A_LD + kr];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        bf[j] = TRB ? Bs[(wn + j * 16 + c16) * B_LD + kr] : Bs[kr * B_LD + wn + j * 16 + c16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  if (kb >= ke) return;
+  double* As0 = smem;
+  double* Bs0 = smem + A_SZ;
+  double* As1 = smem + A_SZ + B_SZ;
+  double* Bs1 = As1 + A_SZ;
+  loadA(kb);
+  loadB(kb);
+  store(As0, Bs0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) {
+      loadA(k0 + BK);
+      loadB(k0 + BK);
+    }
+    if (buf == 0) compute(As0, Bs0);
+    else compute(As1, Bs1);
+    if (more) {
+      if (buf == 0) store(As1, Bs1);
+      else store(As0, Bs0);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
+  constexpr int BK = 16;
+  constexpr int FM = BM / WM / 16;
+  constexpr int FN = BN / WN / 16;
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(FM >= 1 && FN >= 1, "tile");
+  constexpr int A_LD = TRA ? BM + (48 - BM % 32) % 32 : BK + 2;
+  constexpr int B_LD = TRB ? BK + 2 : BN + (48 - BN % 32) % 32;
+  constexpr int A_SZ = TRA ? BK * A_LD : BM * A_LD;
+  constexpr int B_SZ = TRB ? BN * B_LD : BK * B_LD;
+  __shared__ double smem[2 * (A_SZ + B_SZ)];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = (wave % WM) * (BM / WM);
+  const int wn = (wave / WM) * (BN / WN);
+
+  // XCD-aware tile order
+  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const unsigned total = gx * gy * gz;
+  unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((total & 7u) == 0) lin = (lin & 7u) * (total >> 3) + (lin >> 3);
+  const unsigned bx = lin % gx, by = (lin / gx) % gy, bz = lin / (gx * gy);
+
+  const int z = (int)bz;
   const int b = z / g.splits;
   const int sp = z % g.splits;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const int64_t m0 = (int64_t)by * BM;
+  const int64_t n0 = (int64_t)bx * BN;
   if (g.lower_only && n0 > m0 + BM - 1) return;
 
   const int64_t aoff = g.amap ? (int64_t)g.amap[b] : (int64_t)b;
   const TA* __restrict__ A = static_cast<const TA*>(g.A) + aoff * g.strideA;
   const TB* __restrict__ B = static_cast<const TB*>(g.B) + (int64_t)b * g.strideB;
 
-  // K range of this tile (triangular operands skip structural zeros)
   int64_t kb = 0, ke = g.K;
   if (g.tri == 1) ke = ke < m0 + BM ? ke : m0 + BM;
   if (g.tri == 2) kb = (m0 / BK) * BK;
   if (g.splits > 1) {
-    int64_t tiles = (ke - kb + BK - 1) / BK;
-    int64_t per = (tiles + g.splits - 1) / g.splits;
-    int64_t s0 = kb + sp * per * BK;
-    int64_t s1 = s0 + per * BK;
+    const int64_t tiles = (ke - kb + BK - 1) / BK;
+    const int64_t per = (tiles + g.splits - 1) / g.splits;
+    const int64_t s0 = kb + sp * per * BK;
+    const int64_t s1 = s0 + per * BK;
     kb = s0;
     ke = s1 < ke ? s1 : ke;
   }
@@ -64,78 +241,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  double ra[AE], rb[BE];
-  auto loadA = [&](int64_t k0) {
-#pragma unroll
-    for (int e = 0; e < AE; ++e) {
-      const int idx = tid + e * 256;
-      const int mm = TRA ? idx % BM : idx / BK;
-      const int kk = TRA ? idx / BM : idx % BK;
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < g.M && gk < ke) v = (double)(TRA ? A[gk * g.lda + gm] : A[gm * g.lda + gk]);
-      ra[e] = v;
-    }
-  };
-  auto loadB = [&](int64_t k0) {
-#pragma unroll
-    for (int e = 0; e < BE; ++e) {
-      const int idx = tid + e * 256;
-      double v = 0.0;
-      if (idx < BK * BN) {
-        const int nn = TRB ? idx / BK : idx % BN;
-        const int kk = TRB ? idx % BK : idx / BN;
-        const int64_t gn = n0 + nn, gk = k0 + kk;
-        if (gn < g.N && gk < ke) v = (double)(TRB ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn]);
-      }
-      rb[e] = v;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int e = 0; e < AE; ++e) {
-      const int idx = tid + e * 256;
-      const int mm = TRA ? idx % BM : idx / BK;
-      const int kk = TRA ? idx / BM : idx % BK;
-      As[kk][mm] = ra[e];
-    }
-#pragma unroll
-    for (int e = 0; e < BE; ++e) {
-      const int idx = tid + e * 256;
-      if (idx < BK * BN) {
-        const int nn = TRB ? idx / BK : idx % BN;
-        const int kk = TRB ? idx % BK : idx / BN;
-        Bs[kk][nn] = rb[e];
-      }
-    }
-  };
-
-  if (kb < ke) {
-    loadA(kb);
-    loadB(kb);
-  }
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + BK < ke) {
-      loadA(k0 + BK);
-      loadB(k0 + BK);
-    }
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      double af[FM], bf[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = As[ks + (lane >> 4)][wm + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-  }
+  const bool fast = g.vec_ok && m0 + BM <= g.M && n0 + BN <= g.N && ((ke - kb) % BK) == 0;
+  if (fast)
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, WM, WN, false>(g, A, B, m0, n0, kb, ke, smem, acc);
+  else
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, WM, WN, true>(g, A, B, m0, n0, kb, ke, smem, acc);
 
   double* C = g.C + (int64_t)(g.splits > 1 ? z : b) * g.strideC;
 #pragma unroll
@@ -156,37 +266,80 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
       }
 }
 
+// Tile shapes: large-M problems use 128-256 row tiles; N picks the width.
+enum class Tile { T64x64, T64x32, T64x16, T128x128, T128x64, T256x32, T256x16 };
+
+static Tile pick_tile(int64_t M, int64_t N) {
+  if (M >= 1024) {
+    if (N <= 16) return Tile::T256x16;
+    if (N <= 32) return Tile::T256x32;
+    if (N <= 64) return Tile::T128x64;
+    // 128-wide tiles unless that pads 64 more columns than 64-wide ones
+    if (N >= 768 || cdiv(N, 128) * 128 == cdiv(N, 64) * 64) return Tile::T128x128;
+    return Tile::T128x64;
+  }
+  if (N >= 48) return Tile::T64x64;
+  if (N >= 24) return Tile::T64x32;
+  return Tile::T64x16;
+}
+
+static void tile_dims(Tile t, int& bm, int& bn) {
+  switch (t) {
+    case Tile::T64x64: bm = 64; bn = 64; break;
+    case Tile::T64x32: bm = 64; bn = 32; break;
+    case Tile::T64x16: bm = 64; bn = 16; break;
+    case Tile::T128x128: bm = 128; bn = 128; break;
+    case Tile::T128x64: bm = 128; bn = 64; break;
+    case Tile::T256x32: bm = 256; bn = 32; break;
+    default: bm = 256; bn = 16; break;
+  }
+}
+
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int WM, int WN>
+static void launch_one(const Gemm& g, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(g.N, BN), (unsigned)cdiv(g.M, BM), (unsigned)(g.batch * g.splits));
+  if (grid.y > 65535u || grid.z > 65535u) fail(IHSBIN_EUNSUP, "gemm grid too large");
+  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, WM, WN>), grid, dim3(256), 0, s, g);
+}
+
 template <typename TA, typename TB, bool TRA, bool TRB>
 static void launch_t(const Gemm& g, hipStream_t s) {
-  const int z = g.batch * g.splits;
-  if (g.N >= 48) {
-    dim3 grid((unsigned)cdiv(g.N, 64), (unsigned)cdiv(g.M, 64), (unsigned)z);
-    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, 64, 64, 2, 2>), grid, dim3(256), 0, s, g);
-  } else if (g.N >= 24) {
-    dim3 grid((unsigned)cdiv(g.N, 32), (unsigned)cdiv(g.M, 64), (unsigned)z);
-    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, 64, 32, 2, 2>), grid, dim3(256), 0, s, g);
-  } else {
-    dim3 grid((unsigned)cdiv(g.N, 16), (unsigned)cdiv(g.M, 64), (unsigned)z);
-    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, 64, 16, 4, 1>), grid, dim3(256), 0, s, g);
+  switch (pick_tile(g.M, g.N)) {
+    case Tile::T64x64: launch_one<TA, TB, TRA, TRB, 64, 64, 2, 2>(g, s); break;
+    case Tile::T64x32: launch_one<TA, TB, TRA, TRB, 64, 32, 2, 2>(g, s); break;
+    case Tile::T64x16: launch_one<TA, TB, TRA, TRB, 64, 16, 4, 1>(g, s); break;
+    case Tile::T128x128: launch_one<TA, TB, TRA, TRB, 128, 128, 2, 2>(g, s); break;
+    case Tile::T128x64: launch_one<TA, TB, TRA, TRB, 128, 64, 2, 2>(g, s); break;
+    case Tile::T256x32: launch_one<TA, TB, TRA, TRB, 256, 32, 4, 1>(g, s); break;
+    case Tile::T256x16: launch_one<TA, TB, TRA, TRB, 256, 16, 4, 1>(g, s); break;
   }
   IHS_CHECK_LAUNCH();
 }
 
-template <typename TA, typename TB>
-static void launch_tt(const Gemm& g, bool ta, bool tb, hipStream_t s) {
-  if (!ta && !tb) launch_t<TA, TB, false, false>(g, s);
-  else if (ta && !tb) launch_t<TA, TB, true, false>(g, s);
-  else if (!ta && tb) launch_t<TA, TB, false, true>(g, s);
-  else launch_t<TA, TB, true, true>(g, s);
+static bool aligned16(const void* p, int64_t ld, int64_t stride, size_t es) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && ((size_t)ld * es) % 16 == 0 &&
+         ((size_t)stride * es) % 16 == 0;
 }
 
-void gemm(const Gemm& g, DT ta, bool transA, DT tb, bool transB, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return;
-  if (g.M / 64 >= 65535) fail(IHSBIN_EUNSUP, "gemm: M too large for one launch");
-  if (ta == DT::F64 && tb == DT::F64) launch_tt<double, double>(g, transA, transB, s);
-  else if (ta == DT::F32 && tb == DT::F64) launch_tt<float, double>(g, transA, transB, s);
-  else if (ta == DT::F64 && tb == DT::F32) launch_tt<double, float>(g, transA, transB, s);
-  else launch_tt<float, float>(g, transA, transB, s);
+void gemm(const Gemm& g_in, DT ta, bool transA, DT tb, bool transB, hipStream_t s) {
+  if (g_in.M <= 0 || g_in.N <= 0) return;
+  Gemm g = g_in;
+  const size_t ea = ta == DT::F32 ? 4 : 8, eb = tb == DT::F32 ? 4 : 8;
+  g.vec_ok = aligned16(g.A, g.lda, g.strideA, ea) && aligned16(g.B, g.ldb, g.strideB, eb);
+  const bool f64 = ta == DT::F64 && tb == DT::F64;
+  if (f64 && !transA && !transB) launch_t<double, double, false, false>(g, s);
+  else if (f64 && transA && !transB) launch_t<double, double, true, false>(g, s);
+  else if (f64 && !transA && transB) launch_t<double, double, false, true>(g, s);
+  else if (ta == DT::F32 && tb == DT::F64 && !transB) {
+    if (transA) launch_t<float, double, true, false>(g, s);
+    else launch_t<float, double, false, false>(g, s);
+  } else if (ta == DT::F64 && tb == DT::F32 && !transA && !transB) {
+    launch_t<double, float, false, false>(g, s);
+  } else if (ta == DT::F32 && tb == DT::F32 && transA && !transB) {
+    launch_t<float, float, true, false>(g, s);
+  } else {
+    fail(IHSBIN_EUNSUP, "gemm: operand type / transpose combination not built");
+  }
 }
 
 __global__ void reduce_splits_kernel(const double* __restrict__ part, int splits, int64_t M,
@@ -216,13 +369,14 @@ void reduce_splits(const double* part, int splits, int batch, int64_t M, int64_t
 }
 
 int pick_splits(int64_t M, int64_t N, int64_t K, int batch, int64_t target) {
-  const int64_t bn = N >= 48 ? 64 : (N >= 24 ? 32 : 16);
-  const int64_t tiles = cdiv(M, 64) * cdiv(N, bn) * batch;
+  int bm = 64, bn = 64;
+  tile_dims(pick_tile(M, N), bm, bn);
+  const int64_t tiles = cdiv(M, bm) * cdiv(N, bn) * batch;
   int64_t s = cdiv(target, tiles);
   const int64_t kt = cdiv(K, 16);
-  if (s > kt / 4) s = kt / 4;  // keep at least four K-slices per split
+  if (s > kt / 8) s = kt / 8;  // keep at least eight K-slices per split
   if (s < 1) s = 1;
-  if (s > 64) s = 64;
+  if (s > 256) s = 256;
   return (int)s;
 }
 

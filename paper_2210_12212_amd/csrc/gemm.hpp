@@ -24,6 +24,7 @@ struct Gemm {
   int tri = 0;           // 1: op(A) lower triangular, 2: op(A) upper triangular
   int lower_only = 0;    // compute only C tiles touching the lower triangle
   const int32_t* amap = nullptr;  // optional device map: problem b uses A + amap[b]*strideA
+  int vec_ok = 0;        // set by gemm(): operands allow aligned 16-byte vector loads
 };
 
 void gemm(const Gemm& g, DT ta, bool transA, DT tb, bool transB, hipStream_t s);

@@ -42,8 +42,12 @@ constexpr int kNB = 64;
 
 // ------------------------------------------------------------ products with A
 // W = A^T A U (d x w), FP64.  Uses ctx scratch for Y = A U and split-K partials.
-void ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
-               int64_t ldw, std::vector<hipEvent_t>* ev);
+// When wmax > w, columns [w, padded width) of U and W (padded width <= wmax,
+// <= ldu, <= ldw) may be read and overwritten: the dense GEMMs then run on
+// whole tiles.  Returns the number of columns actually computed.
+int64_t padded_width(int64_t w);
+int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
+                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0);
 // C = A^T B (d x K), FP64, B in A's dtype (row stride ldb).
 void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C);
 // CSR kernels

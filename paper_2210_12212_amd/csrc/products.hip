@@ -116,25 +116,39 @@ void launch_csr_atb(const MatView& A, const void* B, int64_t K, int64_t ldb, dou
   IHS_CHECK_LAUNCH();
 }
 
-void ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
-               int64_t ldw, std::vector<hipEvent_t>* ev) {
+int64_t padded_width(int64_t w) {
+  if (w <= 16) return 16;
+  if (w <= 32) return 32;
+  return cdiv(w, 64) * 64;
+}
+
+int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
+                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax) {
   hipStream_t st = ctx.stream;
-  if (w <= 0) return;
+  if (w <= 0) return 0;
+  const bool dense = A.format == IHSBIN_DENSE;
+  int64_t wp = w;
+  if (dense && wmax > w) {
+    const int64_t p = padded_width(w);
+    if (p <= wmax && p <= ldu && p <= ldw) wp = p;
+  }
   int64_t wc = (int64_t)(kYBudget / (sizeof(double) * (size_t)A.n));
-  if (wc > w) wc = w;
+  if (wc >= 64) wc = (wc / 64) * 64;
+  if (wc > wp) wc = wp;
   if (wc < 1) wc = 1;
-  double* Y = ctx.ws_y.as<double>();
-  Y = static_cast<double*>(ctx.ws_y.ensure(sizeof(double) * (size_t)A.n * (size_t)wc));
+  double* Y = static_cast<double*>(ctx.ws_y.ensure(sizeof(double) * (size_t)A.n * (size_t)wc));
   const DT ta = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
-  for (int64_t c0 = 0; c0 < w; c0 += wc) {
-    const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
-    if (ev) {
-      hipEvent_t e;
-      IHS_HIP(hipEventCreate(&e));
-      IHS_HIP(hipEventRecord(e, st));
-      ev->push_back(e);
-    }
-    if (A.format == IHSBIN_DENSE) {
+  auto mark = [&]() {
+    if (!ev) return;
+    hipEvent_t e;
+    IHS_HIP(hipEventCreate(&e));
+    IHS_HIP(hipEventRecord(e, st));
+    ev->push_back(e);
+  };
+  for (int64_t c0 = 0; c0 < wp; c0 += wc) {
+    const int64_t cw = (wp - c0) < wc ? (wp - c0) : wc;
+    mark();
+    if (dense) {
       Gemm g1;
       g1.M = A.n;
       g1.N = cw;
@@ -149,13 +163,8 @@ void ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t l
     } else {
       launch_csr_spmm(A, U + c0, cw, ldu, Y, cw, st);
     }
-    if (ev) {
-      hipEvent_t e;
-      IHS_HIP(hipEventCreate(&e));
-      IHS_HIP(hipEventRecord(e, st));
-      ev->push_back(e);
-    }
-    if (A.format == IHSBIN_DENSE) {
+    mark();
+    if (dense) {
       const int splits = pick_splits(A.d, cw, A.n, 1);
       Gemm g2;
       g2.M = A.d;
@@ -183,13 +192,9 @@ void ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t l
       zero_block(W + c0, A.d, cw, ldw, st);
       launch_csr_spmm_t(A, Y, cw, cw, W + c0, ldw, st);
     }
-    if (ev) {
-      hipEvent_t e;
-      IHS_HIP(hipEventCreate(&e));
-      IHS_HIP(hipEventRecord(e, st));
-      ev->push_back(e);
-    }
+    mark();
   }
+  return wp;
 }
 
 void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C) {

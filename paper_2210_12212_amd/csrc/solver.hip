@@ -290,7 +290,8 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
   const int64_t d = A.d;
   if (J < 2) J = 2;
   if (J > d) J = (int)d;
-  const size_t vec = sizeof(double) * (size_t)d * na;
+  const int64_t ld = padded_width(na);  // padded so the A^T A product runs on whole tiles
+  const size_t vec = sizeof(double) * (size_t)d * ld;
   DevBuf Qb, Tb, Sb, Wb, ab, idb, lb;
   double* Q = static_cast<double*>(Qb.ensure(vec * (J + 1)));
   double* T = static_cast<double*>(Tb.ensure(vec));
@@ -302,7 +303,7 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
   double* lam_dev = static_cast<double*>(lb.ensure(sizeof(double) * na));
   IHS_HIP(hipMemcpyAsync(ids_dev, ids.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
   IHS_HIP(hipMemcpyAsync(lam_dev, lam0_pos.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
-  launch_lanczos_start(seed, d, na, Q, st);
+  launch_lanczos_start(seed, d, na, ld, Q, st);
   for (int j = 0; j < J; ++j) {
     Gemm g;
     g.M = d;
@@ -312,22 +313,22 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
     g.lda = d;
     g.strideA = d * d;
     g.amap = ids_dev;
-    g.B = Q + (size_t)j * d * na;
-    g.ldb = na;
+    g.B = Q + (size_t)j * d * ld;
+    g.ldb = ld;
     g.strideB = 1;
     g.C = T;
-    g.ldc = na;
+    g.ldc = ld;
     g.strideC = 1;
     g.batch = na;
     g.tri = 2;
     gemm(g, DT::F64, true, DT::F64, false, st);  // T = Linv^T q
-    ata_apply(c, A, T, na, na, S, na, nullptr);   // S = A^T A T
-    launch_add_shift(S, T, d, na, lam_dev, st);   // S += lam0 T
+    ata_apply(c, A, T, na, ld, S, ld, nullptr, ld);  // S = A^T A T
+    launch_add_shift(S, T, d, na, ld, lam_dev, st);   // S += lam0 T
     g.B = S;
     g.C = Wv;
     g.tri = 1;
     gemm(g, DT::F64, false, DT::F64, false, st);  // W = Linv S
-    launch_lanczos_orth(Q, Wv, d, na, j, J, alpha, beta, st);
+    launch_lanczos_orth(Q, Wv, d, na, ld, j, J, alpha, beta, st);
   }
   std::vector<double> h(2 * (size_t)na * J);
   IHS_HIP(hipMemcpyAsync(h.data(), alpha, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
@@ -518,7 +519,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   double* basis = static_cast<double*>(path->basis.ensure(sizeof(double) * L * kcap * d * K));
   IHS_HIP(hipMemsetAsync(basis, 0, sizeof(double) * L * kcap * d * K, st));
 
-  const int64_t wcap = (int64_t)L * kcap * K;
+  const int64_t wcap = padded_width((int64_t)L * kcap * K);
   DevBuf Ub0, Ub1, Rb, Tt, Zb, Wb, pb, parb, partial_b;
   double* Ucur = static_cast<double*>(Ub0.ensure(sizeof(double) * d * wcap));
   double* Unext = static_cast<double*>(Ub1.ensure(sizeof(double) * d * wcap));
@@ -568,7 +569,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     const int na = (int)act.size();
     const int64_t w_old = (int64_t)na * i * K;
     const size_t ev0 = events.size();
-    ata_apply(c, A, Ucur, w_old, wcap, W, wcap, o.timing ? &events : nullptr);
+    ata_apply(c, A, Ucur, w_old, wcap, W, wcap, o.timing ? &events : nullptr, wcap);
     if (o.timing) {
       const double per = A.format == IHSBIN_DENSE ? 4.0 * A.n * A.d : 4.0 * A.nnz;
       const size_t chunks = (events.size() - ev0) / 3;

@@ -40,7 +40,9 @@ def csr_dev(torch, M):
 
 # ---------------------------------------------------------------- products
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
-@pytest.mark.parametrize("n,d,w", [(300, 70, 5), (257, 33, 40), (1000, 130, 100), (64, 64, 1)])
+@pytest.mark.parametrize("n,d,w", [(300, 70, 5), (257, 33, 40), (1000, 130, 100), (64, 64, 1),
+                                   (2048, 100, 7), (3001, 257, 33), (4099, 64, 130),
+                                   (1500, 90, 200), (2000, 1100, 20), (1300, 1030, 65)])
 def test_ata_dense(torch, ctx, dt, n, d, w):
     r = np.random.default_rng(n + d + w)
     A = r.standard_normal((n, d)).astype(dt)
