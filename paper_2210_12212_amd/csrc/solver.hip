@@ -101,8 +101,10 @@ static int64_t next_pow2(int64_t n) {
 }
 
 // ------------------------------------------------------------------ sketch
+// reuse_transform: the SRHT transform D-signs + Walsh-Hadamard of A for this
+// seed is still in the context's sketch scratch (only the row sample depends on m).
 static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t m, uint64_t seed,
-                              double* SA) {
+                              double* SA, bool reuse_transform = false) {
   hipStream_t st = c.stream;
   if (m <= 0) fail(IHSBIN_EINVAL, "m must be positive");
   if (m > INT32_MAX) fail(IHSBIN_EUNSUP, "m too large");
@@ -153,13 +155,12 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
     const int64_t npad = next_pow2(A.n);
     if (npad > (int64_t(1) << 31)) fail(IHSBIN_EUNSUP, "SRHT order too large");
     char* base = static_cast<char*>(
-        c.ws_sketch.ensure(sizeof(double) * (size_t)npad * A.d + (size_t)A.n + 4 * (size_t)m + 512));
+        c.ws_sketch.ensure(sizeof(double) * (size_t)npad * A.d + (size_t)A.n + 256));
     double* Z = reinterpret_cast<double*>(base);
     int8_t* sg = reinterpret_cast<int8_t*>(base + sizeof(double) * (size_t)npad * A.d);
-    int32_t* rows = reinterpret_cast<int32_t*>(base + sizeof(double) * (size_t)npad * A.d +
-                                               ((A.n + 255) / 256) * 256);
+    int32_t* rows = static_cast<int32_t*>(c.ws_tmp.ensure(sizeof(int32_t) * (size_t)m));
     launch_draw_srht(seed, A.n, npad, m, sg, rows, st);
-    launch_srht_transform(A, sg, npad, Z, st);
+    if (!reuse_transform) launch_srht_transform(A, sg, npad, Z, st);
     launch_gather_rows(Z, A.d, rows, m, 1.0 / std::sqrt((double)m), SA, st);
   } else {
     fail(IHSBIN_EINVAL, "unknown sketch type");
@@ -425,22 +426,23 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   DevBuf SAb, Gb, Lb, Ib, dinvb, lamb;
   double* G = static_cast<double*>(Gb.ensure(sizeof(double) * d * d));
   std::vector<Spec> spec;
-  for (int trial = 0;; ++trial) {
-    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * m * d));
-    sketch_apply_impl(c, A, o.sketch, s, m, o.seed, SA);
-    gram_impl(c, SA, m, d, G);
-    r.sketch_trials = trial + 1;
-    if (!o.adaptive_m || m >= m_cap || trial >= 5 || o.taus) break;
-    double* Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
-    double* Li = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
-    factor_impl(c, G, d, {lam0[0]}, Lf, Li, dinvb, lamb);
-    auto sp = spectrum_impl(c, A, Li, {0}, {lam0[0]}, std::max(8, o.lanczos_steps), o.seed);
-    const double cmin = sp[0].mu_min * grid[0] / lam0[0], cmax = sp[0].mu_max * grid[1] / lam0[0];
-    const double r0 = (cmax - cmin) / (cmax + cmin);
-    if (r0 <= o.rate_target) break;
-    // Marchenko-Pastur-type edges (1 -+ sqrt(rho))^2 with rho ~ d_e / m: infer
-    // rho from the measured condition number and scale m to the target.
-    const double kap = sp[0].mu_max / sp[0].mu_min;
+  int trials = 0;
+  auto sketch_m = [&](int64_t mm) {
+    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * mm * d));
+    sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT);
+    gram_impl(c, SA, mm, d, G);
+    ++trials;
+  };
+  // Predicted contraction rate of interval l from its spectrum estimate.
+  auto rate_of = [&](const Spec& sp, int l) {
+    const double cmin = sp.mu_min * grid[l] / lam0[l], cmax = sp.mu_max * grid[l + 1] / lam0[l];
+    return (cmax - cmin) / (cmax + cmin);
+  };
+  // Next m when the lowest interval is too slow: the Gaussian theorem's edges
+  // (1 -+ sqrt(rho))^2 with rho ~ d_e / m give rho from the measured condition
+  // number; m is scaled (by a power of two in [2, 16]) to reach rate_target.
+  auto grow = [&](const Spec& sp) {
+    const double kap = sp.mu_max / sp.mu_min;
     const double g = grid[1] / grid[0];
     const double kt = (1.0 + o.rate_target) / ((1.0 - o.rate_target) * g);
     double factor = 16.0;
@@ -452,48 +454,75 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     factor = std::min(16.0, std::max(2.0, factor));
     int64_t mult = 1;
     while (mult < factor) mult <<= 1;
-    const int64_t m_new = std::min(m_cap, m * mult);
-    if (m_new <= m) break;
-    m = m_new;
+    return std::min(m_cap, m * mult);
+  };
+  const bool adapt = o.adaptive_m && !o.taus;
+  sketch_m(m);
+  if (adapt && m < m_cap) {
+    // cheap probe: factor and estimate the lowest interval only
+    double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
+    double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
+    factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb);
+    auto sp = spectrum_impl(c, A, Li1, {0}, {lam0[0]}, std::max(8, o.lanczos_steps), o.seed);
+    if (rate_of(sp[0], 0) > o.rate_target) {
+      const int64_t m_new = grow(sp[0]);
+      if (m_new > m) {
+        m = m_new;
+        sketch_m(m);
+      }
+    }
   }
   IHS_HIP(hipStreamSynchronize(st));
   r.ms_sketch = tsk.ms();
-  r.m_used = m;
 
-  // ---- factor every interval
-  Timer tf;
-  double* Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d * L));
-  double* Linv = static_cast<double*>(Ib.ensure(sizeof(double) * d * d * L));
-  factor_impl(c, G, d, lam0, Lf, Linv, dinvb, lamb);
-  Gb.release();
-  SAb.release();
-  IHS_HIP(hipStreamSynchronize(st));
-  r.ms_factor = tf.ms();
-
-  // ---- step sizes
-  Timer tspec;
+  // ---- factor every interval and estimate its spectrum; the batched estimate
+  // of the lowest interval re-checks the sketch size
   std::vector<double> tau(L), rate(L), ref(L);
   std::vector<int32_t> all(L);
   for (int l = 0; l < L; ++l) all[l] = l;
+  double* Lf = nullptr;
+  double* Linv = nullptr;
+  for (;;) {
+    Timer tf;
+    Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d * L));
+    Linv = static_cast<double*>(Ib.ensure(sizeof(double) * d * d * L));
+    factor_impl(c, G, d, lam0, Lf, Linv, dinvb, lamb);
+    IHS_HIP(hipStreamSynchronize(st));
+    r.ms_factor += tf.ms();
+    Timer tspec;
+    spec = spectrum_impl(c, A, Linv, all, lam0, std::max(2, o.lanczos_steps), o.seed + 1);
+    r.ms_spectrum += tspec.ms();
+    if (adapt && m < m_cap && trials < 6 && rate_of(spec[0], 0) > o.rate_target) {
+      const int64_t m_new = grow(spec[0]);
+      if (m_new > m) {
+        Timer t2;
+        m = m_new;
+        sketch_m(m);
+        IHS_HIP(hipStreamSynchronize(st));
+        r.ms_sketch += t2.ms();
+        continue;
+      }
+    }
+    break;
+  }
+  Gb.release();
+  SAb.release();
+  r.m_used = m;
+  r.sketch_trials = trials;
   if (o.taus) {
     for (int l = 0; l < L; ++l) {
       tau[l] = o.taus[l];
       if (!(tau[l] > 0.0)) fail(IHSBIN_EINVAL, "taus must be positive");
     }
   }
-  {
-    spec = spectrum_impl(c, A, Linv, all, lam0, std::max(2, o.lanczos_steps), o.seed + 1);
-    for (int l = 0; l < L; ++l) {
-      const double cmin = spec[l].mu_min * grid[l] / lam0[l];
-      const double cmax = spec[l].mu_max * grid[l + 1] / lam0[l];
-      if (!o.taus) tau[l] = 2.0 / (cmin + cmax);
-      const double rr = std::max(std::fabs(1.0 - tau[l] * cmin), std::fabs(1.0 - tau[l] * cmax));
-      rate[l] = std::min(rr, 0.999);
-    }
+  for (int l = 0; l < L; ++l) {
+    const double cmin = spec[l].mu_min * grid[l] / lam0[l];
+    const double cmax = spec[l].mu_max * grid[l + 1] / lam0[l];
+    if (!o.taus) tau[l] = 2.0 / (cmin + cmax);
+    const double rr = std::max(std::fabs(1.0 - tau[l] * cmin), std::fabs(1.0 - tau[l] * cmax));
+    rate[l] = std::min(rr, 0.999);
   }
   for (int l = 0; l < L; ++l) ref[l] = o.centred ? lam0[l] : 0.0;
-  IHS_HIP(hipStreamSynchronize(st));
-  r.ms_spectrum = tspec.ms();
 
   // ---- basis recursion
   Timer tb;
