@@ -42,8 +42,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense_exp300_131072x2048")
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs)")
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--rate-target", type=float, default=0.7)
+    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--rate-target", type=float, default=0.5)
     ap.add_argument("--oracle-lambdas", type=int, default=12,
                     help="lambdas of the sample solved by the CPU oracle")
     ap.add_argument("--no-oracle", action="store_true")

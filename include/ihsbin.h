@@ -95,7 +95,7 @@ typedef struct {
                               0: the printed expansion in powers of tau*lam     */
   int32_t adaptive_m;      /* 1: grow m until the predicted rate of the lowest
                               interval is <= rate_target (default 1)            */
-  double rate_target;      /* default 0.7                                      */
+  double rate_target;      /* default 0.6                                      */
   int64_t m_max;           /* cap for adaptive m; 0 = library default           */
   int32_t lanczos_steps;   /* spectrum estimate steps per interval (default 16) */
   int32_t timing;          /* 1: time the A^T A product kernels with events     */
@@ -138,7 +138,7 @@ const char* ihsbin_status_str(int status);
 const char* ihsbin_version(void);
 
 /* Default options: Gaussian sketch, m = 0 (= 2 d), seed 0, tol 1e-8,
- * k_max 96, L from Section 4.2, centred, adaptive m, rate 0.7, 16 Lanczos
+ * k_max 96, L from Section 4.2, centred, adaptive m, rate 0.6, 16 Lanczos
  * steps, no timing. */
 void ihsbin_opts_default(ihsbin_opts* opts);
 

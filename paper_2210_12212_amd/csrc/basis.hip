@@ -261,32 +261,56 @@ void launch_add_shift(double* S, const double* T, int64_t d, int na, int64_t ld,
   IHS_CHECK_LAUNCH();
 }
 
-// Full re-orthogonalization (two Gram-Schmidt passes) of w against q_0..q_j,
-// alpha_j = <q_j, B q_j>, beta_{j+1} = ||w||, q_{j+1} = w / beta.
+// Full re-orthogonalization (two classical Gram-Schmidt passes) of w against
+// q_0..q_j, alpha_j = <q_j, B q_j>, beta_{j+1} = ||w||, q_{j+1} = w / beta.
+// Each pass computes all j+1 inner products at once (one reduction), then
+// subtracts the projection.  One workgroup per column a.
+constexpr int kLanczosMax = 64;
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void lanczos_orth_kernel(double* Q, double* Wv, int64_t d,
                                                            int64_t ld, int j, int J, double* alpha,
                                                            double* beta) {
-  __shared__ double red[256];
+  __shared__ double red[kLanczosMax][4];
+  __shared__ double h[kLanczosMax];
+  __shared__ double bsum[4];
   const int a = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nq = j + 1;
   double al = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int q = 0; q <= j; ++q) {
+    for (int q = 0; q < nq; ++q) {
       const double* Qq = Q + (int64_t)q * d * ld;
       double s = 0.0;
-      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Qq[r * ld + a] * Wv[r * ld + a];
-      const double h = block_sum(s, red);
-      if (q == j) al += h;
-      for (int64_t r = threadIdx.x; r < d; r += blockDim.x) Wv[r * ld + a] -= h * Qq[r * ld + a];
-      __syncthreads();
+      for (int64_t r = tid; r < d; r += blockDim.x) s += Qq[r * ld + a] * Wv[r * ld + a];
+      s = wave_sum(s);
+      if (lane == 0) red[q][wave] = s;
     }
+    __syncthreads();
+    if (tid < nq) h[tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+    __syncthreads();
+    al += h[j];
+    for (int64_t r = tid; r < d; r += blockDim.x) {
+      double w = Wv[r * ld + a];
+      for (int q = 0; q < nq; ++q) w -= h[q] * Q[(int64_t)q * d * ld + r * ld + a];
+      Wv[r * ld + a] = w;
+    }
+    __syncthreads();
   }
   double s = 0.0;
-  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) s += Wv[r * ld + a] * Wv[r * ld + a];
-  const double b = sqrt(block_sum(s, red));
+  for (int64_t r = tid; r < d; r += blockDim.x) s += Wv[r * ld + a] * Wv[r * ld + a];
+  s = wave_sum(s);
+  if (lane == 0) bsum[wave] = s;
+  __syncthreads();
+  const double b = sqrt(bsum[0] + bsum[1] + bsum[2] + bsum[3]);
   double* Qn = Q + (int64_t)(j + 1) * d * ld;
-  for (int64_t r = threadIdx.x; r < d; r += blockDim.x)
+  for (int64_t r = tid; r < d; r += blockDim.x)
     Qn[r * ld + a] = b > 0.0 ? Wv[r * ld + a] / b : 0.0;
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     alpha[a * J + j] = al;
     beta[a * J + j] = b;
   }
@@ -294,9 +318,112 @@ __global__ __launch_bounds__(256) void lanczos_orth_kernel(double* Q, double* Wv
 
 void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int64_t ld, int j, int J,
                          double* alpha, double* beta, hipStream_t st) {
+  if (j + 1 > kLanczosMax) fail(IHSBIN_EINVAL, "too many Lanczos steps");
   hipLaunchKernelGGL(lanczos_orth_kernel, dim3(na), dim3(256), 0, st, Q, Wv, d, ld, j, J, alpha,
                      beta);
   IHS_CHECK_LAUNCH();
 }
+
+// y_b = L_{map[b]} x_b (lower triangular, row-major d x d): one wave per row,
+// 16-byte loads and four independent partial sums per lane.
+__global__ __launch_bounds__(256) void trmv_lower_kernel(const double* __restrict__ L, int64_t d,
+                                                         const int32_t* __restrict__ map, int nb,
+                                                         const double* __restrict__ X, int64_t ldx,
+                                                         double* __restrict__ Y, int64_t ldy) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t t = wave; t < d * nb; t += nwaves) {
+    const int b = (int)(t / d);
+    const int64_t r = t % d;
+    const double* row = L + (int64_t)map[b] * d * d + r * d;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int64_t len = r + 1;
+    const bool vec = ((d & 1) == 0);
+    int64_t k = 2 * lane;
+    if (vec) {
+      for (; k + 384 + 1 < len; k += 512) {
+        const double2 a0 = *reinterpret_cast<const double2*>(row + k);
+        const double2 a1 = *reinterpret_cast<const double2*>(row + k + 128);
+        const double2 a2 = *reinterpret_cast<const double2*>(row + k + 256);
+        const double2 a3 = *reinterpret_cast<const double2*>(row + k + 384);
+        s0 += a0.x * X[k * ldx + b] + a0.y * X[(k + 1) * ldx + b];
+        s1 += a1.x * X[(k + 128) * ldx + b] + a1.y * X[(k + 129) * ldx + b];
+        s2 += a2.x * X[(k + 256) * ldx + b] + a2.y * X[(k + 257) * ldx + b];
+        s3 += a3.x * X[(k + 384) * ldx + b] + a3.y * X[(k + 385) * ldx + b];
+      }
+    }
+    for (; k < len; k += 128) {
+      s0 += row[k] * X[k * ldx + b];
+      if (k + 1 < len) s1 += row[k + 1] * X[(k + 1) * ldx + b];
+    }
+    double s = wave_sum((s0 + s1) + (s2 + s3));
+    if (lane == 0) Y[r * ldy + b] = s;
+  }
+}
+
+// y_b = L_{map[b]}^T x_b, two stages.  Stage 1: one workgroup per (b, 64-column
+// panel, 256-row chunk) streams the chunk's rows r >= c0 of the panel and
+// writes partial sums; stage 2 adds the chunk partials in a fixed order.
+constexpr int kTrmvRows = 256;
+
+__global__ __launch_bounds__(256) void trmv_upper_t_partial_kernel(
+    const double* __restrict__ L, int64_t d, const int32_t* __restrict__ map, int nb,
+    const double* __restrict__ X, int64_t ldx, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int64_t panels = (d + 63) / 64, chunks = (d + kTrmvRows - 1) / kTrmvRows;
+  const int64_t job = blockIdx.x;
+  const int b = (int)(job / (panels * chunks));
+  const int64_t pc = job % (panels * chunks);
+  const int64_t c0 = (pc / chunks) * 64, r0 = (pc % chunks) * kTrmvRows;
+  const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const double* Lb = L + (int64_t)map[b] * d * d;
+  const int64_t c = c0 + cc;
+  double s = 0.0;
+  if (c < d && r0 + kTrmvRows > c0) {
+    const int64_t rs = r0 > c0 ? r0 : c0, re = (r0 + kTrmvRows) < d ? (r0 + kTrmvRows) : d;
+    for (int64_t r = rs + g; r < re; r += 4) s += Lb[r * d + c] * X[r * ldx + b];
+  }
+  red[g][cc] = s;
+  __syncthreads();
+  if (g == 0 && c < d)
+    part[((int64_t)b * chunks + (pc % chunks)) * d + c] = red[0][cc] + red[1][cc] + red[2][cc] + red[3][cc];
+}
+
+__global__ void trmv_upper_t_sum_kernel(const double* __restrict__ part, int64_t d, int nb,
+                                        int64_t chunks, double* __restrict__ Y, int64_t ldy) {
+  const int64_t total = d * nb;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(t / d);
+    const int64_t c = t % d;
+    double s = 0.0;
+    for (int64_t q = c / kTrmvRows; q < chunks; ++q) s += part[((int64_t)b * chunks + q) * d + c];
+    Y[c * ldy + b] = s;
+  }
+}
+
+void launch_trmv(const double* L, int64_t d, const int32_t* map, int nb, bool transpose,
+                 const double* X, int64_t ldx, double* Y, int64_t ldy, double* scratch,
+                 hipStream_t st) {
+  if (!transpose) {
+    int64_t blocks = cdiv(d * nb * 64, 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(trmv_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, d, map, nb, X,
+                       ldx, Y, ldy);
+  } else {
+    const int64_t chunks = cdiv(d, kTrmvRows);
+    hipLaunchKernelGGL(trmv_upper_t_partial_kernel, dim3((unsigned)(cdiv(d, 64) * chunks * nb)),
+                       dim3(256), 0, st, L, d, map, nb, X, ldx, scratch);
+    IHS_CHECK_LAUNCH();
+    int64_t blocks = cdiv(d * nb, 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(trmv_upper_t_sum_kernel, dim3((unsigned)blocks), dim3(256), 0, st, scratch, d,
+                       nb, chunks, Y, ldy);
+  }
+  IHS_CHECK_LAUNCH();
+}
+
+int64_t trmv_scratch_doubles(int64_t d, int nb) { return cdiv(d, kTrmvRows) * d * nb; }
 
 }  // namespace ihs

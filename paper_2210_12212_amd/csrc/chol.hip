@@ -37,12 +37,15 @@ void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, in
 }
 
 // Factor diagonal block p of every matrix in LDS, write L_pp back (upper part
-// zeroed) and its inverse into dinv[l][p].
+// zeroed) and its inverse into dinv[l][p].  Both the factorization and the
+// inversion are right-looking with one barrier per column: step j reads the
+// pivot that step j-1 finished and updates everything to its right/below.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, int p,
                                                          double* dinv, int nblk, int* status) {
   constexpr int NB = kNB;
-  __shared__ double a[NB][NB + 1];
-  __shared__ double col[NB];
+  __shared__ double a[NB][NB + 1];   // trailing matrix during the factorization
+  __shared__ double lf[NB][NB + 1];  // the factor L
+  __shared__ double x[NB][NB + 1];   // accumulators, then L^-1
   const int l = blockIdx.x;
   double* M = H + (int64_t)l * d * d;
   const int64_t o = (int64_t)p * NB;
@@ -51,54 +54,53 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, i
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int r = e / NB, c = e % NB;
     a[r][c] = (r < nb && c < nb) ? M[(o + r) * d + o + c] : (r == c ? 1.0 : 0.0);
+    lf[r][c] = 0.0;
+    x[r][c] = 0.0;
+  }
+  // four threads per row: thread (ti, tq) owns row ti, columns tq, tq + 4, ...
+  const int ti = tid >> 2, tq = tid & 3;
+  // factorization: a[i][k] -= a[i][j] a[k][j] / a[j][j] for j < k <= i
+  for (int j = 0; j < NB; ++j) {
+    __syncthreads();
+    double djj = a[j][j];
+    if (!(djj > 0.0)) {
+      if (tid == 0) status[0] = 1;
+      djj = 1.0;
+    }
+    const double piv = sqrt(djj), inv = 1.0 / djj;
+    if (tq == 0 && ti >= j) lf[ti][j] = (ti == j) ? piv : a[ti][j] / piv;
+    if (ti > j) {
+      const double f = a[ti][j] * inv;
+      for (int k = j + 1 + tq; k <= ti; k += 4) a[ti][k] -= f * a[k][j];
+    }
   }
   __syncthreads();
-  for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double v = a[j][j];
-      if (!(v > 0.0)) {
-        status[0] = 1;
-        v = 1.0;
-      }
-      a[j][j] = sqrt(v);
-    }
-    __syncthreads();
-    const double piv = a[j][j];
-    for (int i = j + 1 + tid; i < NB; i += blockDim.x) a[i][j] /= piv;
-    __syncthreads();
-    const int rem = NB - j - 1;
-    for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int i = j + 1 + e / rem, k = j + 1 + e % rem;
-      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
-    }
-    __syncthreads();
-  }
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int r = e / NB, c = e % NB;
-    if (r < nb && c < nb) M[(o + r) * d + o + c] = (c <= r) ? a[r][c] : 0.0;
+    if (r < nb && c < nb) M[(o + r) * d + o + c] = lf[r][c];
+  }
+  // inversion of L: row i of X is (e_i - acc_i) / L_ii, and rows below
+  // accumulate L[r][i] X[i][:]; row i is finalized one step later (no reader then)
+  for (int i = 0; i < NB; ++i) {
+    __syncthreads();
+    if (i > 0) {
+      const double lp = lf[i - 1][i - 1];
+      for (int c = tid; c < i; c += blockDim.x) x[i - 1][c] = ((i - 1 == c ? 1.0 : 0.0) - x[i - 1][c]) / lp;
+    }
+    const double lii = lf[i][i];
+    if (ti > i) {
+      const double f = lf[ti][i] / lii;
+      for (int c = tq; c <= i; c += 4) x[ti][c] += f * ((i == c ? 1.0 : 0.0) - x[i][c]);
+    }
   }
   __syncthreads();
-  // in-place inverse of the lower triangle, columns right to left:
-  // X_jj = 1/L_jj, X_ij = -(sum_{k=j+1..i} X_ik L_kj) X_jj for i > j
-  for (int j = NB - 1; j >= 0; --j) {
-    for (int i = tid; i < NB; i += blockDim.x) col[i] = a[i][j];
-    __syncthreads();
-    const double xjj = 1.0 / col[j];
-    for (int i = j + tid; i < NB; i += blockDim.x) {
-      if (i == j) {
-        a[j][j] = xjj;
-      } else {
-        double s = 0.0;
-        for (int k = j + 1; k <= i; ++k) s += a[i][k] * col[k];
-        a[i][j] = -s * xjj;
-      }
-    }
-    __syncthreads();
-  }
+  for (int c = tid; c < NB; c += blockDim.x)
+    x[NB - 1][c] = ((NB - 1 == c ? 1.0 : 0.0) - x[NB - 1][c]) / lf[NB - 1][NB - 1];
+  __syncthreads();
   double* Di = dinv + ((int64_t)l * nblk + p) * NB * NB;
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int r = e / NB, c = e % NB;
-    Di[e] = (c <= r) ? a[r][c] : 0.0;
+    Di[e] = (c <= r) ? x[r][c] : 0.0;
   }
 }
 

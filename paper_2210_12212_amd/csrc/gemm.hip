@@ -26,6 +26,18 @@ namespace ihs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// LDS pitches (in elements) that keep the MFMA fragment reads free of bank
+// conflicts: K-major rows start 64 bytes (FP32) / 128 bytes (FP64) apart
+// modulo the 256-byte bank period; row-major rows have an odd word stride.
+template <typename T>
+constexpr int kmajor_pitch(int x) {
+  return sizeof(T) == 8 ? x + (48 - x % 32) % 32 : x + (80 - x % 64) % 64;
+}
+template <typename T>
+constexpr int rowmajor_pitch(int bk) {
+  return sizeof(T) == 8 ? bk + 2 : bk + 1;
+}
+
 template <typename T>
 __device__ inline void ld4(const T* p, int, T (&o)[4]) {
   if constexpr (sizeof(T) == 4) {
@@ -51,16 +63,16 @@ __device__ inline void ld4c(const T* p, int nv, T (&o)[4]) {
   for (int j = 0; j < 4; ++j) o[j] = j < nv ? p[j] : T(0);
 }
 
-template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int WM, int WN, bool CHK>
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
+          bool CHK>
 __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ A,
                                           const TB* __restrict__ B, int64_t m0, int64_t n0,
-                                          int64_t kb, int64_t ke, double* __restrict__ smem,
+                                          int64_t kb, int64_t ke, char* __restrict__ smem,
                                           v4d (&acc)[BM / WM / 16][BN / WN / 16]) {
-  constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
-  constexpr int A_LD = TRA ? BM + (48 - BM % 32) % 32 : BK + 2;
-  constexpr int B_LD = TRB ? BK + 2 : BN + (48 - BN % 32) % 32;
+  constexpr int A_LD = TRA ? kmajor_pitch<TA>(BM) : rowmajor_pitch<TA>(BK);
+  constexpr int B_LD = TRB ? rowmajor_pitch<TB>(BK) : kmajor_pitch<TB>(BN);
   constexpr int A_SZ = TRA ? BK * A_LD : BM * A_LD;
   constexpr int B_SZ = TRB ? BN * B_LD : BK * B_LD;
   constexpr int AVEC = BM * BK / 4;
@@ -121,7 +133,7 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
       }
     }
   };
-  auto store = [&](double* As, double* Bs) {
+  auto store = [&](TA* As, TB* Bs) {
 #pragma unroll
     for (int e = 0; e < AV; ++e) {
       const int vid = tid + e * 256;
@@ -129,7 +141,7 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
       const int o = TRA ? (vid / (BM / 4)) * A_LD + 4 * (vid % (BM / 4))
                         : (vid / (BK / 4)) * A_LD + 4 * (vid % (BK / 4));
 #pragma unroll
-      for (int j = 0; j < 4; ++j) As[o + j] = (double)ra[e][j];
+      for (int j = 0; j < 4; ++j) As[o + j] = ra[e][j];
     }
 #pragma unroll
     for (int e = 0; e < BV; ++e) {
@@ -138,20 +150,20 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
       const int o = TRB ? (vid / (BK / 4)) * B_LD + 4 * (vid % (BK / 4))
                         : (vid / (BN / 4)) * B_LD + 4 * (vid % (BN / 4));
 #pragma unroll
-      for (int j = 0; j < 4; ++j) Bs[o + j] = (double)rb[e][j];
+      for (int j = 0; j < 4; ++j) Bs[o + j] = rb[e][j];
     }
   };
-  auto compute = [&](const double* As, const double* Bs) {
+  auto compute = [&](const TA* As, const TB* Bs) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4), c16 = lane & 15;
       double af[FM], bf[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
-        af[i] = TRA ? As[kr * A_LD + wm + i * 16 + c16] : As[(wm + i * 16 + c16) * A_LD + kr];
+        af[i] = (double)(TRA ? As[kr * A_LD + wm + i * 16 + c16] : As[(wm + i * 16 + c16) * A_LD + kr]);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
-        bf[j] = TRB ? Bs[(wn + j * 16 + c16) * B_LD + kr] : Bs[kr * B_LD + wn + j * 16 + c16];
+        bf[j] = (double)(TRB ? Bs[(wn + j * 16 + c16) * B_LD + kr] : Bs[kr * B_LD + wn + j * 16 + c16]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -161,10 +173,12 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   };
 
   if (kb >= ke) return;
-  double* As0 = smem;
-  double* Bs0 = smem + A_SZ;
-  double* As1 = smem + A_SZ + B_SZ;
-  double* Bs1 = As1 + A_SZ;
+  constexpr int A_BYTES = (A_SZ * (int)sizeof(TA) + 15) / 16 * 16;
+  constexpr int B_BYTES = (B_SZ * (int)sizeof(TB) + 15) / 16 * 16;
+  TA* As0 = reinterpret_cast<TA*>(smem);
+  TB* Bs0 = reinterpret_cast<TB*>(smem + A_BYTES);
+  TA* As1 = reinterpret_cast<TA*>(smem + A_BYTES + B_BYTES);
+  TB* Bs1 = reinterpret_cast<TB*>(smem + 2 * A_BYTES + B_BYTES);
   loadA(kb);
   loadB(kb);
   store(As0, Bs0);
@@ -187,18 +201,19 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   }
 }
 
-template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int WM, int WN>
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
-  constexpr int BK = 16;
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
   static_assert(WM * WN == 4, "four waves");
   static_assert(FM >= 1 && FN >= 1, "tile");
-  constexpr int A_LD = TRA ? BM + (48 - BM % 32) % 32 : BK + 2;
-  constexpr int B_LD = TRB ? BK + 2 : BN + (48 - BN % 32) % 32;
+  constexpr int A_LD = TRA ? kmajor_pitch<TA>(BM) : rowmajor_pitch<TA>(BK);
+  constexpr int B_LD = TRB ? rowmajor_pitch<TB>(BK) : kmajor_pitch<TB>(BN);
   constexpr int A_SZ = TRA ? BK * A_LD : BM * A_LD;
   constexpr int B_SZ = TRB ? BN * B_LD : BK * B_LD;
-  __shared__ double smem[2 * (A_SZ + B_SZ)];
+  constexpr int A_BYTES = (A_SZ * (int)sizeof(TA) + 15) / 16 * 16;
+  constexpr int B_BYTES = (B_SZ * (int)sizeof(TB) + 15) / 16 * 16;
+  __shared__ __attribute__((aligned(16))) char smem[2 * (A_BYTES + B_BYTES)];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -241,11 +256,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
+  // interior tiles with whole K-slices and aligned operands take the fast path
   const bool fast = g.vec_ok && m0 + BM <= g.M && n0 + BN <= g.N && ((ke - kb) % BK) == 0;
   if (fast)
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, WM, WN, false>(g, A, B, m0, n0, kb, ke, smem, acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, false>(g, A, B, m0, n0, kb, ke, smem, acc);
   else
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, WM, WN, true>(g, A, B, m0, n0, kb, ke, smem, acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true>(g, A, B, m0, n0, kb, ke, smem, acc);
 
   double* C = g.C + (int64_t)(g.splits > 1 ? z : b) * g.strideC;
 #pragma unroll
@@ -267,15 +283,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
 }
 
 // Tile shapes: large-M problems use 128-256 row tiles; N picks the width.
-enum class Tile { T64x64, T64x32, T64x16, T128x128, T128x64, T256x32, T256x16 };
+enum class Tile { T64x64, T64x32, T64x16, T128x64, T256x32, T256x16 };
 
 static Tile pick_tile(int64_t M, int64_t N) {
   if (M >= 1024) {
     if (N <= 16) return Tile::T256x16;
     if (N <= 32) return Tile::T256x32;
-    if (N <= 64) return Tile::T128x64;
-    // 128-wide tiles unless that pads 64 more columns than 64-wide ones
-    if (N >= 768 || cdiv(N, 128) * 128 == cdiv(N, 64) * 64) return Tile::T128x128;
+    // 128 x 64 measured best for wide products (two waves per SIMD; 128 x 128
+    // tiles hold one)
     return Tile::T128x64;
   }
   if (N >= 48) return Tile::T64x64;
@@ -288,30 +303,29 @@ static void tile_dims(Tile t, int& bm, int& bn) {
     case Tile::T64x64: bm = 64; bn = 64; break;
     case Tile::T64x32: bm = 64; bn = 32; break;
     case Tile::T64x16: bm = 64; bn = 16; break;
-    case Tile::T128x128: bm = 128; bn = 128; break;
     case Tile::T128x64: bm = 128; bn = 64; break;
     case Tile::T256x32: bm = 256; bn = 32; break;
     default: bm = 256; bn = 16; break;
   }
 }
 
-template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int WM, int WN>
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN>
 static void launch_one(const Gemm& g, hipStream_t s) {
   dim3 grid((unsigned)cdiv(g.N, BN), (unsigned)cdiv(g.M, BM), (unsigned)(g.batch * g.splits));
   if (grid.y > 65535u || grid.z > 65535u) fail(IHSBIN_EUNSUP, "gemm grid too large");
-  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, WM, WN>), grid, dim3(256), 0, s, g);
+  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, BK, WM, WN>), grid, dim3(256), 0, s,
+                     g);
 }
 
 template <typename TA, typename TB, bool TRA, bool TRB>
 static void launch_t(const Gemm& g, hipStream_t s) {
   switch (pick_tile(g.M, g.N)) {
-    case Tile::T64x64: launch_one<TA, TB, TRA, TRB, 64, 64, 2, 2>(g, s); break;
-    case Tile::T64x32: launch_one<TA, TB, TRA, TRB, 64, 32, 2, 2>(g, s); break;
-    case Tile::T64x16: launch_one<TA, TB, TRA, TRB, 64, 16, 4, 1>(g, s); break;
-    case Tile::T128x128: launch_one<TA, TB, TRA, TRB, 128, 128, 2, 2>(g, s); break;
-    case Tile::T128x64: launch_one<TA, TB, TRA, TRB, 128, 64, 2, 2>(g, s); break;
-    case Tile::T256x32: launch_one<TA, TB, TRA, TRB, 256, 32, 4, 1>(g, s); break;
-    case Tile::T256x16: launch_one<TA, TB, TRA, TRB, 256, 16, 4, 1>(g, s); break;
+    case Tile::T64x64: launch_one<TA, TB, TRA, TRB, 64, 64, 16, 2, 2>(g, s); break;
+    case Tile::T64x32: launch_one<TA, TB, TRA, TRB, 64, 32, 16, 2, 2>(g, s); break;
+    case Tile::T64x16: launch_one<TA, TB, TRA, TRB, 64, 16, 16, 4, 1>(g, s); break;
+    case Tile::T128x64: launch_one<TA, TB, TRA, TRB, 128, 64, 16, 2, 2>(g, s); break;
+    case Tile::T256x32: launch_one<TA, TB, TRA, TRB, 256, 32, 16, 4, 1>(g, s); break;
+    case Tile::T256x16: launch_one<TA, TB, TRA, TRB, 256, 16, 32, 4, 1>(g, s); break;
   }
   IHS_CHECK_LAUNCH();
 }

@@ -165,7 +165,7 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
     }
     mark();
     if (dense) {
-      const int splits = pick_splits(A.d, cw, A.n, 1);
+      const int splits = pick_splits(A.d, cw, A.n, 1, 1024);
       Gemm g2;
       g2.M = A.d;
       g2.N = cw;

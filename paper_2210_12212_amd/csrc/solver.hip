@@ -167,8 +167,10 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
   }
 }
 
+// Lower triangle (and the diagonal tiles) of G = (SA)^T SA; the strictly
+// upper tiles are not computed and hold unspecified values.
 static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G) {
-  const int splits = pick_splits(d, d, m, 1);
+  const int splits = pick_splits(d, d, m, 1, 1024);
   Gemm g;
   g.M = d;
   g.N = d;
@@ -177,6 +179,7 @@ static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G)
   g.lda = d;
   g.B = SA;
   g.ldb = d;
+  g.lower_only = 1;
   if (splits > 1) {
     double* part = static_cast<double*>(
         c.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)d * (size_t)d));
@@ -282,18 +285,61 @@ struct Spec {
   double mu_min, mu_max;
 };
 
+// Ritz values of the Lanczos tridiagonal of column a after n steps:
+// (theta_min, theta_max) and their residual bounds |beta_n s_n|.
+struct Ritz {
+  double tmin, tmax, rmin, rmax;
+};
+
+static Ritz ritz_extremes(const std::vector<double>& h, int na, int J, int a, int n_steps) {
+  int n = n_steps;
+  for (int j = 0; j < n_steps - 1; ++j)
+    if (!(h[(size_t)na * J + (size_t)a * J + j] > 1e-14 * std::fabs(h[(size_t)a * J + j]) + 1e-300)) {
+      n = j + 1;
+      break;
+    }
+  std::vector<double> Tm((size_t)n * n, 0.0), V;
+  for (int j = 0; j < n; ++j) {
+    Tm[(size_t)j * n + j] = h[(size_t)a * J + j];
+    if (j + 1 < n) {
+      const double b = h[(size_t)na * J + (size_t)a * J + j];
+      Tm[(size_t)j * n + j + 1] = b;
+      Tm[(size_t)(j + 1) * n + j] = b;
+    }
+  }
+  jacobi_eig(n, Tm, V);
+  const double bres = n == n_steps ? h[(size_t)na * J + (size_t)a * J + n_steps - 1] : 0.0;
+  int imin = 0, imax = 0;
+  for (int i = 1; i < n; ++i) {
+    if (Tm[(size_t)i * n + i] < Tm[(size_t)imin * n + imin]) imin = i;
+    if (Tm[(size_t)i * n + i] > Tm[(size_t)imax * n + imax]) imax = i;
+  }
+  Ritz r;
+  r.tmin = Tm[(size_t)imin * n + imin];
+  r.tmax = Tm[(size_t)imax * n + imax];
+  r.rmin = std::fabs(bres * V[(size_t)(n - 1) * n + imin]);
+  r.rmax = std::fabs(bres * V[(size_t)(n - 1) * n + imax]);
+  return r;
+}
+
 // Lanczos with full re-orthogonalization on B_l = Linv_l (A^T A + lam0_l I) Linv_l^T.
+// early: when set, the run may stop after a multiple of 6 steps once
+// early(ritz of column 0) returns true (Ritz values bound the spectrum from inside).
+template <class Early>
 static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* Linv_all,
                                        const std::vector<int32_t>& ids,
-                                       const std::vector<double>& lam0_pos, int J, uint64_t seed) {
+                                       const std::vector<double>& lam0_pos, int J, uint64_t seed,
+                                       Early early) {
   hipStream_t st = c.stream;
   const int na = (int)ids.size();
   const int64_t d = A.d;
   if (J < 2) J = 2;
   if (J > d) J = (int)d;
+  if (J > 63) J = 63;
   const int64_t ld = padded_width(na);  // padded so the A^T A product runs on whole tiles
   const size_t vec = sizeof(double) * (size_t)d * ld;
-  DevBuf Qb, Tb, Sb, Wb, ab, idb, lb;
+  DevBuf Qb, Tb, Sb, Wb, ab, idb, lb, trb;
+  double* trs = static_cast<double*>(trb.ensure(sizeof(double) * trmv_scratch_doubles(d, na)));
   double* Q = static_cast<double*>(Qb.ensure(vec * (J + 1)));
   double* T = static_cast<double*>(Tb.ensure(vec));
   double* S = static_cast<double*>(Sb.ensure(vec));
@@ -305,71 +351,56 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
   IHS_HIP(hipMemcpyAsync(ids_dev, ids.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
   IHS_HIP(hipMemcpyAsync(lam_dev, lam0_pos.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
   launch_lanczos_start(seed, d, na, ld, Q, st);
+  std::vector<double> h(2 * (size_t)na * J);
+  int steps = J;
   for (int j = 0; j < J; ++j) {
-    Gemm g;
-    g.M = d;
-    g.N = 1;
-    g.K = d;
-    g.A = Linv_all;
-    g.lda = d;
-    g.strideA = d * d;
-    g.amap = ids_dev;
-    g.B = Q + (size_t)j * d * ld;
-    g.ldb = ld;
-    g.strideB = 1;
-    g.C = T;
-    g.ldc = ld;
-    g.strideC = 1;
-    g.batch = na;
-    g.tri = 2;
-    gemm(g, DT::F64, true, DT::F64, false, st);  // T = Linv^T q
+    launch_trmv(Linv_all, d, ids_dev, na, true, Q + (size_t)j * d * ld, ld, T, ld, trs, st);  // T = Linv^T q
     ata_apply(c, A, T, na, ld, S, ld, nullptr, ld);  // S = A^T A T
     launch_add_shift(S, T, d, na, ld, lam_dev, st);   // S += lam0 T
-    g.B = S;
-    g.C = Wv;
-    g.tri = 1;
-    gemm(g, DT::F64, false, DT::F64, false, st);  // W = Linv S
+    launch_trmv(Linv_all, d, ids_dev, na, false, S, ld, Wv, ld, trs, st);                      // W = Linv S
     launch_lanczos_orth(Q, Wv, d, na, ld, j, J, alpha, beta, st);
+    if ((j + 1) % 6 == 0 && j + 1 < J && early.enabled) {
+      IHS_HIP(hipMemcpyAsync(h.data(), alpha, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+      IHS_HIP(hipStreamSynchronize(st));
+      if (early(ritz_extremes(h, na, J, 0, j + 1))) {
+        steps = j + 1;
+        break;
+      }
+    }
   }
-  std::vector<double> h(2 * (size_t)na * J);
   IHS_HIP(hipMemcpyAsync(h.data(), alpha, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
   IHS_HIP(hipStreamSynchronize(st));
   std::vector<Spec> out(na);
   for (int a = 0; a < na; ++a) {
-    // stop at an invariant subspace (tiny beta)
-    int n = J;
-    for (int j = 0; j < J - 1; ++j)
-      if (!(h[(size_t)na * J + (size_t)a * J + j] > 1e-14 * std::fabs(h[(size_t)a * J + j]) + 1e-300)) {
-        n = j + 1;
-        break;
-      }
-    std::vector<double> Tm((size_t)n * n, 0.0), V;
-    for (int j = 0; j < n; ++j) {
-      Tm[(size_t)j * n + j] = h[(size_t)a * J + j];
-      if (j + 1 < n) {
-        const double b = h[(size_t)na * J + (size_t)a * J + j];
-        Tm[(size_t)j * n + j + 1] = b;
-        Tm[(size_t)(j + 1) * n + j] = b;
-      }
-    }
-    jacobi_eig(n, Tm, V);
-    const double bres = n == J ? h[(size_t)na * J + (size_t)a * J + J - 1] : 0.0;
-    int imin = 0, imax = 0;
-    for (int i = 1; i < n; ++i) {
-      if (Tm[(size_t)i * n + i] < Tm[(size_t)imin * n + imin]) imin = i;
-      if (Tm[(size_t)i * n + i] > Tm[(size_t)imax * n + imax]) imax = i;
-    }
-    const double tmin = Tm[(size_t)imin * n + imin], tmax = Tm[(size_t)imax * n + imax];
-    const double rmin = std::fabs(bres * V[(size_t)(n - 1) * n + imin]);
-    const double rmax = std::fabs(bres * V[(size_t)(n - 1) * n + imax]);
+    const Ritz rz = ritz_extremes(h, na, J, a, steps);
     Spec sp;
-    sp.mu_max = (tmax + rmax) * 1.02;
-    sp.mu_min = std::max(tmin - rmin, 0.5 * tmin);
+    sp.mu_max = (rz.tmax + rz.rmax) * 1.02;
+    sp.mu_min = std::max(rz.tmin - rz.rmin, 0.5 * rz.tmin);
     if (!(sp.mu_min > 0.0) || !(sp.mu_max > sp.mu_min) || !std::isfinite(sp.mu_max))
       fail(IHSBIN_ENOTSPD, "spectrum estimate failed");
     out[a] = sp;
   }
   return out;
+}
+
+struct NoEarly {
+  bool enabled = false;
+  bool operator()(const Ritz&) const { return false; }
+};
+struct EarlyIfSlow {
+  bool enabled = true;
+  double lo, hi, lam0, target;
+  bool operator()(const Ritz& r) const {
+    // the Ritz interval lies inside the spectrum: its rate is a lower bound
+    const double cmin = r.tmin * lo / lam0, cmax = r.tmax * hi / lam0;
+    return (cmax - cmin) / (cmax + cmin) > target;
+  }
+};
+
+static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* Linv_all,
+                                       const std::vector<int32_t>& ids,
+                                       const std::vector<double>& lam0_pos, int J, uint64_t seed) {
+  return spectrum_impl(c, A, Linv_all, ids, lam0_pos, J, seed, NoEarly{});
 }
 
 struct Timer {
@@ -458,19 +489,29 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   };
   const bool adapt = o.adaptive_m && !o.taus;
   sketch_m(m);
-  if (adapt && m < m_cap) {
-    // cheap probe: factor and estimate the lowest interval only
+  // Probe: factor and estimate the lowest interval only (the Lanczos run stops
+  // early once its Ritz values already show a rate above the target).  When m
+  // is too small, sketches whose cost does not grow with m (SRHT: one
+  // transform; CountSketch/SJLT: one pass over A) go straight to the cap, since
+  // m then only enters through the 2 m d^2 Gram; the Gaussian sketch costs
+  // 2 m n d, so it grows by the measured factor and is probed again.
+  const bool cheap_sketch = o.sketch != IHSBIN_GAUSSIAN;
+  while (adapt && m < m_cap && trials < 6) {
     double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
     factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb);
-    auto sp = spectrum_impl(c, A, Li1, {0}, {lam0[0]}, std::max(8, o.lanczos_steps), o.seed);
-    if (rate_of(sp[0], 0) > o.rate_target) {
-      const int64_t m_new = grow(sp[0]);
-      if (m_new > m) {
-        m = m_new;
-        sketch_m(m);
-      }
-    }
+    EarlyIfSlow early;
+    early.lo = grid[0];
+    early.hi = grid[1];
+    early.lam0 = lam0[0];
+    early.target = o.rate_target;
+    auto sp = spectrum_impl(c, A, Li1, {0}, {lam0[0]}, std::max(8, o.lanczos_steps), o.seed, early);
+    if (rate_of(sp[0], 0) <= o.rate_target) break;
+    const int64_t m_new = cheap_sketch ? m_cap : grow(sp[0]);
+    if (m_new <= m) break;
+    m = m_new;
+    sketch_m(m);
+    if (cheap_sketch) break;
   }
   IHS_HIP(hipStreamSynchronize(st));
   r.ms_sketch = tsk.ms();
@@ -492,7 +533,9 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     Timer tspec;
     spec = spectrum_impl(c, A, Linv, all, lam0, std::max(2, o.lanczos_steps), o.seed + 1);
     r.ms_spectrum += tspec.ms();
-    if (adapt && m < m_cap && trials < 6 && rate_of(spec[0], 0) > o.rate_target) {
+    // the batched estimate of the lowest interval can still be well above the
+    // probe's (different start vector): grow once more in that case
+    if (adapt && m < m_cap && trials < 6 && rate_of(spec[0], 0) > o.rate_target + 0.1) {
       const int64_t m_new = grow(spec[0]);
       if (m_new > m) {
         Timer t2;
@@ -771,7 +814,7 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->L = 0;
   o->centred = 1;
   o->adaptive_m = 1;
-  o->rate_target = 0.7;
+  o->rate_target = 0.6;
   o->m_max = 0;
   o->lanczos_steps = 16;
   o->timing = 0;
