@@ -30,6 +30,13 @@ if ROOT not in sys.path:
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix, flop/s
 HBM_PEAK = 8.0e12          # bytes/s
 
+# HBM bytes per launch of the A^T A product GEMMs on the default workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy calibration
+# (profiles/gemm_ata_traffic_dense_131072x2048.md).  Valid for the kernel
+# version below; reported as null for other workloads.
+TRAFFIC_WORKLOAD = "dense_exp300_131072x2048"
+TRAFFIC_BYTES_PER_LAUNCH = {"gemm_y_AU": 1.520e9, "gemm_w_AtY": 1.555e9}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -47,6 +54,8 @@ def main():
     ap.add_argument("--oracle-lambdas", type=int, default=12,
                     help="lambdas of the sample solved by the CPU oracle")
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is built and "
@@ -54,6 +63,17 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        # a plain copy of known size: HBM counters read for it calibrate the
+        # FETCH_SIZE / WRITE_SIZE figures of the solver kernels
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.calibrate_copy} MiB three times")
+        return
     import workloads as W
     from paper_2210_12212_amd import Context
 
@@ -103,9 +123,10 @@ def main():
     dom = "gemm_y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "gemm_w_AtY"
     dom_ms = max(rep["ata_ms_y"], rep["ata_ms_w"])
     achieved = (half_flops / launches) / (dom_ms / launches * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    traffic = TRAFFIC_BYTES_PER_LAUNCH.get(dom) if p.name == TRAFFIC_WORKLOAD and args.n is None else None
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": None,
+                "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": traffic,
                 "launches": rep["ata_launches"],
                 "flops_per_launch": half_flops / launches,
                 "avg_launch_ms": dom_ms / launches,
