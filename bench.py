@@ -51,6 +51,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs)")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--rate-target", type=float, default=0.5)
+    ap.add_argument("--lanczos-steps", type=int, default=10)
     ap.add_argument("--oracle-lambdas", type=int, default=12,
                     help="lambdas of the sample solved by the CPU oracle")
     ap.add_argument("--no-oracle", action="store_true")
@@ -87,7 +88,7 @@ def main():
     torch.cuda.synchronize()
     ctx = Context(0)
     opts = dict(sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=args.tol,
-                rate_target=args.rate_target, timing=1)
+                rate_target=args.rate_target, lanczos_steps=args.lanczos_steps, timing=1)
     X = torch.empty((len(p.lambdas), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
 
     def step():
@@ -174,7 +175,8 @@ def main():
         "config": {"workload": p.name, "n": p.n, "d": p.d, "K": int(p.B.shape[1]), "T": T,
                    "storage": str(p.A.dtype), "sketch": p.sketch, "m0": p.m,
                    "m_used": rep["m_used"], "L": rep["L"], "k_max": rep["k_max_used"],
-                   "k_sum": rep["k_sum"], "lam": [p.lam_min, p.lam_max], "tol": args.tol},
+                   "k_sum": rep["k_sum"], "lam": [p.lam_min, p.lam_max], "tol": args.tol,
+                   "rate_target": args.rate_target, "lanczos_steps": args.lanczos_steps},
         "max_rel_err": max_err,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phase_ms": {k: rep[k] for k in ("ms_sketch", "ms_factor", "ms_spectrum", "ms_basis",

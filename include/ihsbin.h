@@ -97,7 +97,7 @@ typedef struct {
                               interval is <= rate_target (default 1)            */
   double rate_target;      /* default 0.6                                      */
   int64_t m_max;           /* cap for adaptive m; 0 = library default           */
-  int32_t lanczos_steps;   /* spectrum estimate steps per interval (default 16) */
+  int32_t lanczos_steps;   /* spectrum estimate steps per interval (default 12) */
   int32_t timing;          /* 1: time the A^T A product kernels with events     */
   const double* taus;      /* host, optional: fixed step size per interval (L)  */
 } ihsbin_opts;
@@ -138,7 +138,7 @@ const char* ihsbin_status_str(int status);
 const char* ihsbin_version(void);
 
 /* Default options: Gaussian sketch, m = 0 (= 2 d), seed 0, tol 1e-8,
- * k_max 96, L from Section 4.2, centred, adaptive m, rate 0.6, 16 Lanczos
+ * k_max 96, L from Section 4.2, centred, adaptive m, rate 0.6, 12 Lanczos
  * steps, no timing. */
 void ihsbin_opts_default(ihsbin_opts* opts);
 

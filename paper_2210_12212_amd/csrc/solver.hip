@@ -816,7 +816,7 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->adaptive_m = 1;
   o->rate_target = 0.6;
   o->m_max = 0;
-  o->lanczos_steps = 16;
+  o->lanczos_steps = 12;
   o->timing = 0;
   o->taus = nullptr;
 }

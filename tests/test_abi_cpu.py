@@ -43,7 +43,7 @@ def test_default_options(lib):
     o = _lib.Opts()
     lib.ihsbin_opts_default(C.byref(o))
     assert o.tol == 1e-8 and o.k_max == 96 and o.centred == 1 and o.adaptive_m == 1
-    assert o.lanczos_steps == 16 and not o.taus
+    assert o.lanczos_steps == 12 and not o.taus
 
 
 def test_null_arguments_are_rejected(lib):

@@ -1,0 +1,88 @@
+"""GPU parity on the configured workloads at their full sizes.
+
+The path is built in the configuration bench.py times; the oracle solves a
+sample of the lambdas (the dense d x d Cholesky per lambda is too slow for all
+of them at d = 8192), which must agree to 1e-6 relative error per lambda.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2210_12212_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _to_dev(torch, p):
+    from paper_2210_12212_amd import CsrInput
+    dev = torch.device("cuda", 0)
+    if isinstance(p.A, W.CsrMatrix):
+        A = CsrInput(torch.from_numpy(p.A.row_ptr).to(dev), torch.from_numpy(p.A.col_idx).to(dev),
+                     torch.from_numpy(p.A.vals).to(dev), p.A.n, p.A.d)
+    else:
+        A = torch.from_numpy(p.A).to(dev)
+    return A, torch.from_numpy(p.B).to(dev)
+
+
+def _sampled_check(p, X, count):
+    idx = np.unique(np.linspace(0, len(p.lambdas) - 1, count).round().astype(int))
+    G = direct.gram(p.A)
+    C = direct.atb(p.A, p.B)
+    err = direct.rel_err(X[idx], direct.solve_from_gram(G, C, p.lambdas[idx]))
+    print(f"{p.name}: sampled max rel err {err.max():.3e}")
+    assert err.max() <= 1e-6, err
+
+
+def test_dense_exp300_131072x2048_srht_as_benched(torch, ctx):
+    p = W.make("dense_exp300_131072x2048")
+    A, B = _to_dev(torch, p)
+    X, rep = ctx.solve_path(A, B, p.lambdas, sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=1e-7,
+                            rate_target=0.5, lanczos_steps=10)
+    assert rep["status"] == 0 and rep["n_unconverged"] == 0, rep
+    _sampled_check(p, X.cpu().numpy(), 9)
+
+
+def test_csr_zipf_1048576x8192_countsketch(torch, ctx):
+    p = W.make("csr_zipf_1048576x8192")
+    A, B = _to_dev(torch, p)
+    X, rep = ctx.solve_path(A, B, p.lambdas, sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=1e-7)
+    assert rep["status"] == 0, rep
+    _sampled_check(p, X.cpu().numpy(), 3)
+
+
+def test_dense_invsqrt_k64_reduced_n(torch, ctx):
+    # 64 right-hand sides (matrix-valued problem, Section 5.3) on n = 16384 rows
+    p = W.make("dense_invsqrt_262144x4096_k64", n=16384, d=1024)
+    A, B = _to_dev(torch, p)
+    X, rep = ctx.solve_path(A, B, p.lambdas, sketch=p.sketch, m=p.m // 4, seed=p.sketch_seed, tol=1e-7)
+    assert rep["status"] == 0, rep
+    _sampled_check(p, X.cpu().numpy(), 11)
+
+
+def test_strided_rows_and_rhs(torch, ctx):
+    # A given as a column slice of a wider matrix (row stride > d), B likewise
+    wide = W.dense_decay(3000, 80, seed=3)
+    Bw, _ = W.rhs(wide, 5, 0.1, seed=4)
+    dev = torch.device("cuda", 0)
+    At = torch.from_numpy(wide).to(dev)[:, :64]
+    Bt = torch.from_numpy(Bw).to(dev)[:, :2]
+    lams = W.lambda_grid(1e-2, 1e2, 13)
+    X, rep = ctx.solve_path(At, Bt, lams, sketch="srht", m=256, seed=1)
+    A = np.ascontiguousarray(wide[:, :64])
+    B = np.ascontiguousarray(Bw[:, :2])
+    err = direct.rel_err(X.cpu().numpy(), direct.ridge_path(A, B, lams))
+    assert err.max() <= 1e-6
