@@ -64,7 +64,7 @@ __device__ inline void ld4c(const T* p, int nv, T (&o)[4]) {
 }
 
 template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
-          bool CHK>
+          bool CHK, int NT>
 __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ A,
                                           const TB* __restrict__ B, int64_t m0, int64_t n0,
                                           int64_t kb, int64_t ke, char* __restrict__ smem,
@@ -77,8 +77,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   constexpr int B_SZ = TRB ? BN * B_LD : BK * B_LD;
   constexpr int AVEC = BM * BK / 4;
   constexpr int BVEC = BK * BN / 4;
-  constexpr int AV = (AVEC + 255) / 256;
-  constexpr int BV = (BVEC + 255) / 256;
+  constexpr int AV = (AVEC + NT - 1) / NT;
+  constexpr int BV = (BVEC + NT - 1) / NT;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -90,8 +90,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   auto loadA = [&](int64_t k0) {
 #pragma unroll
     for (int e = 0; e < AV; ++e) {
-      const int vid = tid + e * 256;
-      if (AVEC % 256 != 0 && vid >= AVEC) break;
+      const int vid = tid + e * NT;
+      if (AVEC % NT != 0 && vid >= AVEC) break;
       int64_t r, c;
       if constexpr (!TRA) {
         r = m0 + vid / (BK / 4);
@@ -113,8 +113,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   auto loadB = [&](int64_t k0) {
 #pragma unroll
     for (int e = 0; e < BV; ++e) {
-      const int vid = tid + e * 256;
-      if (BVEC % 256 != 0 && vid >= BVEC) break;
+      const int vid = tid + e * NT;
+      if (BVEC % NT != 0 && vid >= BVEC) break;
       int64_t r, c;
       if constexpr (!TRB) {
         r = k0 + vid / (BN / 4);
@@ -136,8 +136,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   auto store = [&](TA* As, TB* Bs) {
 #pragma unroll
     for (int e = 0; e < AV; ++e) {
-      const int vid = tid + e * 256;
-      if (AVEC % 256 != 0 && vid >= AVEC) break;
+      const int vid = tid + e * NT;
+      if (AVEC % NT != 0 && vid >= AVEC) break;
       const int o = TRA ? (vid / (BM / 4)) * A_LD + 4 * (vid % (BM / 4))
                         : (vid / (BK / 4)) * A_LD + 4 * (vid % (BK / 4));
 #pragma unroll
@@ -145,8 +145,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
     }
 #pragma unroll
     for (int e = 0; e < BV; ++e) {
-      const int vid = tid + e * 256;
-      if (BVEC % 256 != 0 && vid >= BVEC) break;
+      const int vid = tid + e * NT;
+      if (BVEC % NT != 0 && vid >= BVEC) break;
       const int o = TRB ? (vid / (BK / 4)) * B_LD + 4 * (vid % (BK / 4))
                         : (vid / (BN / 4)) * B_LD + 4 * (vid % (BN / 4));
 #pragma unroll
@@ -201,11 +201,12 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   }
 }
 
-template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
+          int NT = 256>
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
-  static_assert(WM * WN == 4, "four waves");
+  static_assert(WM * WN * 64 == NT, "one wave per sub-tile");
   static_assert(FM >= 1 && FN >= 1, "tile");
   constexpr int A_LD = TRA ? kmajor_pitch<TA>(BM) : rowmajor_pitch<TA>(BK);
   constexpr int B_LD = TRB ? rowmajor_pitch<TB>(BK) : kmajor_pitch<TB>(BN);
@@ -259,9 +260,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
   // interior tiles with whole K-slices and aligned operands take the fast path
   const bool fast = g.vec_ok && m0 + BM <= g.M && n0 + BN <= g.N && ((ke - kb) % BK) == 0;
   if (fast)
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, false>(g, A, B, m0, n0, kb, ke, smem, acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, false, NT>(g, A, B, m0, n0, kb, ke, smem, acc);
   else
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true>(g, A, B, m0, n0, kb, ke, smem, acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true, NT>(g, A, B, m0, n0, kb, ke, smem, acc);
 
   double* C = g.C + (int64_t)(g.splits > 1 ? z : b) * g.strideC;
 #pragma unroll
@@ -283,14 +284,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g) {
 }
 
 // Tile shapes: large-M problems use 128-256 row tiles; N picks the width.
-enum class Tile { T64x64, T64x32, T64x16, T128x64, T256x32, T256x16 };
+enum class Tile { T64x64, T64x32, T64x16, T128x64, T128x128W8, T256x32, T256x16 };
 
 static Tile pick_tile(int64_t M, int64_t N) {
   if (M >= 1024) {
     if (N <= 16) return Tile::T256x16;
     if (N <= 32) return Tile::T256x32;
-    // 128 x 64 measured best for wide products (two waves per SIMD; 128 x 128
-    // tiles hold one)
+    // widths that are whole multiples of 128 use the eight-wave 128 x 128 tile
+    // (K-slices of 32; ~6 % faster than 128 x 64 in the tile sweep), others 128 x 64
+    if (N % 128 == 0) return Tile::T128x128W8;
     return Tile::T128x64;
   }
   if (N >= 48) return Tile::T64x64;
@@ -304,17 +306,19 @@ static void tile_dims(Tile t, int& bm, int& bn) {
     case Tile::T64x32: bm = 64; bn = 32; break;
     case Tile::T64x16: bm = 64; bn = 16; break;
     case Tile::T128x64: bm = 128; bn = 64; break;
+    case Tile::T128x128W8: bm = 128; bn = 128; break;
     case Tile::T256x32: bm = 256; bn = 32; break;
     default: bm = 256; bn = 16; break;
   }
 }
 
-template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN>
+template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
+          int NT = 256>
 static void launch_one(const Gemm& g, hipStream_t s) {
   dim3 grid((unsigned)cdiv(g.N, BN), (unsigned)cdiv(g.M, BM), (unsigned)(g.batch * g.splits));
   if (grid.y > 65535u || grid.z > 65535u) fail(IHSBIN_EUNSUP, "gemm grid too large");
-  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, BK, WM, WN>), grid, dim3(256), 0, s,
-                     g);
+  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, NT>), grid, dim3(NT), 0,
+                     s, g);
 }
 
 template <typename TA, typename TB, bool TRA, bool TRB>
@@ -324,6 +328,7 @@ static void launch_t(const Gemm& g, hipStream_t s) {
     case Tile::T64x32: launch_one<TA, TB, TRA, TRB, 64, 32, 16, 2, 2>(g, s); break;
     case Tile::T64x16: launch_one<TA, TB, TRA, TRB, 64, 16, 16, 4, 1>(g, s); break;
     case Tile::T128x64: launch_one<TA, TB, TRA, TRB, 128, 64, 16, 2, 2>(g, s); break;
+    case Tile::T128x128W8: launch_one<TA, TB, TRA, TRB, 128, 128, 32, 2, 4, 512>(g, s); break;
     case Tile::T256x32: launch_one<TA, TB, TRA, TRB, 256, 32, 16, 4, 1>(g, s); break;
     case Tile::T256x16: launch_one<TA, TB, TRA, TRB, 256, 16, 32, 4, 1>(g, s); break;
   }
