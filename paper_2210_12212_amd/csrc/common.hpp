@@ -104,6 +104,10 @@ __host__ __device__ inline uint32_t sm_range(uint64_t x, uint32_t bound) {
 // ------------------------------------------------------------ helpers
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Diagnostic log to stderr, enabled by the environment variable IHSBIN_LOG=1.
+bool log_enabled();
+void logf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
 struct MatView {  // a validated ihsbin_matrix
   int format, dtype;
   int64_t n, d, ld, nnz;

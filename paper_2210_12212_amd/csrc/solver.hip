@@ -41,7 +41,28 @@ struct ihsbin_path {
   ihs::DevBuf basis, items;
 };
 
+#include <cstdarg>
+#include <cstdlib>
+
 namespace ihs {
+
+bool log_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("IHSBIN_LOG");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
+}
+
+void logf(const char* fmt, ...) {
+  if (!log_enabled()) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fputs("[ihsbin] ", stderr);
+  std::vfprintf(stderr, fmt, ap);
+  std::fputc('\n', stderr);
+  va_end(ap);
+}
 
 MatView check_matrix(const ihsbin_matrix* A) {
   if (!A) fail(IHSBIN_EINVAL, "A is NULL");
@@ -506,6 +527,8 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     early.lam0 = lam0[0];
     early.target = o.rate_target;
     auto sp = spectrum_impl(c, A, Li1, {0}, {lam0[0]}, std::max(8, o.lanczos_steps), o.seed, early);
+    logf("probe m=%lld: mu=[%.4g, %.4g] rate0=%.3f (target %.3f)", (long long)m, sp[0].mu_min,
+         sp[0].mu_max, rate_of(sp[0], 0), o.rate_target);
     if (rate_of(sp[0], 0) <= o.rate_target) break;
     const int64_t m_new = cheap_sketch ? m_cap : grow(sp[0]);
     if (m_new <= m) break;
@@ -552,6 +575,9 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   SAb.release();
   r.m_used = m;
   r.sketch_trials = trials;
+  for (int l = 0; l < L && log_enabled(); ++l)
+    logf("interval %d [%.4g, %.4g]: mu=[%.4g, %.4g]", l, grid[l], grid[l + 1], spec[l].mu_min,
+         spec[l].mu_max);
   if (o.taus) {
     for (int l = 0; l < L; ++l) {
       tau[l] = o.taus[l];
@@ -640,6 +666,8 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   for (int i = 1; i < kcap && !act.empty(); ++i) {
     const int na = (int)act.size();
     const int64_t w_old = (int64_t)na * i * K;
+    logf("step %d: active %d, product width %lld (padded %lld)", i, na, (long long)w_old,
+         (long long)padded_width(w_old));
     const size_t ev0 = events.size();
     ata_apply(c, A, Ucur, w_old, wcap, W, wcap, o.timing ? &events : nullptr, wcap);
     if (o.timing) {
