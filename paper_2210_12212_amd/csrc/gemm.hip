@@ -67,7 +67,8 @@ template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, 
           bool CHK, int NT>
 __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ A,
                                           const TB* __restrict__ B, int64_t m0, int64_t n0,
-                                          int64_t kb, int64_t ke, char* __restrict__ smem,
+                                          int64_t kb, int64_t ke, int nblk,
+                                          char* __restrict__ smem,
                                           v4d (&acc)[BM / WM / 16][BN / WN / 16]) {
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
@@ -173,15 +174,18 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   };
 
   if (kb >= ke) return;
+  // a wave whose columns all lie past N only helps stage the operands
+  const bool live = nblk > 0;
   constexpr int A_BYTES = (A_SZ * (int)sizeof(TA) + 15) / 16 * 16;
   constexpr int B_BYTES = (B_SZ * (int)sizeof(TB) + 15) / 16 * 16;
-  TA* As0 = reinterpret_cast<TA*>(smem);
-  TB* Bs0 = reinterpret_cast<TB*>(smem + A_BYTES);
-  TA* As1 = reinterpret_cast<TA*>(smem + A_BYTES + B_BYTES);
-  TB* Bs1 = reinterpret_cast<TB*>(smem + 2 * A_BYTES + B_BYTES);
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  // the two LDS stages are addressed arithmetically (no branch on the stage),
+  // so the accumulators keep one register assignment through the loop
+  auto As = [&](int buf) { return reinterpret_cast<TA*>(smem + buf * STAGE); };
+  auto Bs = [&](int buf) { return reinterpret_cast<TB*>(smem + buf * STAGE + A_BYTES); };
   loadA(kb);
   loadB(kb);
-  store(As0, Bs0);
+  store(As(0), Bs(0));
   __syncthreads();
   int buf = 0;
   for (int64_t k0 = kb; k0 < ke; k0 += BK) {
@@ -190,12 +194,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
       loadA(k0 + BK);
       loadB(k0 + BK);
     }
-    if (buf == 0) compute(As0, Bs0);
-    else compute(As1, Bs1);
-    if (more) {
-      if (buf == 0) store(As1, Bs1);
-      else store(As0, Bs0);
-    }
+    if (live) compute(As(buf), Bs(buf));
+    if (more) store(As(buf ^ 1), Bs(buf ^ 1));
     __syncthreads();
     buf ^= 1;
   }
@@ -257,12 +257,19 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
+  // 16-column blocks of this wave that hold columns < N (wave-uniform)
+  int nblk = (int)((g.N - (n0 + wn) + 15) / 16);
+  nblk = __builtin_amdgcn_readfirstlane(nblk < 0 ? 0 : (nblk > FN ? FN : nblk));
+
   // interior tiles with whole K-slices and aligned operands take the fast path
-  const bool fast = g.vec_ok && m0 + BM <= g.M && n0 + BN <= g.N && ((ke - kb) % BK) == 0;
+  const int64_t nr = g.n_read > g.N ? g.n_read : g.N;
+  const bool fast = g.vec_ok && m0 + BM <= g.M && n0 + BN <= nr && ((ke - kb) % BK) == 0;
   if (fast)
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, false, NT>(g, A, B, m0, n0, kb, ke, smem, acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, false, NT>(g, A, B, m0, n0, kb, ke, nblk, smem,
+                                                                acc);
   else
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true, NT>(g, A, B, m0, n0, kb, ke, smem, acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true, NT>(g, A, B, m0, n0, kb, ke, nblk, smem,
+                                                               acc);
 
   double* C = g.C + (int64_t)(g.splits > 1 ? z : b) * g.strideC;
 #pragma unroll

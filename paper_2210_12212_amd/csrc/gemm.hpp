@@ -25,6 +25,11 @@ struct Gemm {
   int lower_only = 0;    // compute only C tiles touching the lower triangle
   const int32_t* amap = nullptr;  // optional device map: problem b uses A + amap[b]*strideA
   int vec_ok = 0;        // set by gemm(): operands allow aligned 16-byte vector loads
+  // Columns of op(B) that may be read (0: N).  When n_read > N, memory for
+  // op(B) columns [N, n_read) exists (its values are ignored): tiles that end
+  // inside it still take the unchecked load path, and their 16-column blocks
+  // past N skip the matrix-core work.  Output columns >= N are never written.
+  int64_t n_read = 0;
 };
 
 void gemm(const Gemm& g, DT ta, bool transA, DT tb, bool transB, hipStream_t s);
