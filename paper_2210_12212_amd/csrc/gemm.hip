@@ -291,15 +291,12 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
 }
 
 // Tile shapes: large-M problems use 128-256 row tiles; N picks the width.
-enum class Tile { T64x64, T64x32, T64x16, T128x64, T128x128W8, T256x32, T256x16 };
+enum class Tile { T64x64, T64x32, T64x16, T128x64, T256x32, T256x16 };
 
 static Tile pick_tile(int64_t M, int64_t N) {
   if (M >= 1024) {
     if (N <= 16) return Tile::T256x16;
     if (N <= 32) return Tile::T256x32;
-    // widths that are whole multiples of 128 use the eight-wave 128 x 128 tile
-    // (K-slices of 32; ~6 % faster than 128 x 64 in the tile sweep), others 128 x 64
-    if (N % 128 == 0) return Tile::T128x128W8;
     return Tile::T128x64;
   }
   if (N >= 48) return Tile::T64x64;
@@ -313,7 +310,6 @@ static void tile_dims(Tile t, int& bm, int& bn) {
     case Tile::T64x32: bm = 64; bn = 32; break;
     case Tile::T64x16: bm = 64; bn = 16; break;
     case Tile::T128x64: bm = 128; bn = 64; break;
-    case Tile::T128x128W8: bm = 128; bn = 128; break;
     case Tile::T256x32: bm = 256; bn = 32; break;
     default: bm = 256; bn = 16; break;
   }
@@ -335,7 +331,6 @@ static void launch_t(const Gemm& g, hipStream_t s) {
     case Tile::T64x32: launch_one<TA, TB, TRA, TRB, 64, 32, 16, 2, 2>(g, s); break;
     case Tile::T64x16: launch_one<TA, TB, TRA, TRB, 64, 16, 16, 4, 1>(g, s); break;
     case Tile::T128x64: launch_one<TA, TB, TRA, TRB, 128, 64, 16, 2, 2>(g, s); break;
-    case Tile::T128x128W8: launch_one<TA, TB, TRA, TRB, 128, 128, 32, 2, 4, 512>(g, s); break;
     case Tile::T256x32: launch_one<TA, TB, TRA, TRB, 256, 32, 16, 4, 1>(g, s); break;
     case Tile::T256x16: launch_one<TA, TB, TRA, TRB, 256, 16, 32, 4, 1>(g, s); break;
   }
@@ -346,6 +341,71 @@ static bool aligned16(const void* p, int64_t ld, int64_t stride, size_t es) {
   return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && ((size_t)ld * es) % 16 == 0 &&
          ((size_t)stride * es) % 16 == 0;
 }
+
+// Column-matched tiles: 128 x 16q with the four waves stacked along M, so every
+// wave owns all 16q columns of its 32 rows (work stays balanced across SIMDs).
+template <typename TA, bool TRA>
+static void launch_cols(const Gemm& g, int q, hipStream_t s) {
+  switch (q) {
+    case 1: launch_one<TA, double, TRA, false, 128, 16, 32, 4, 1>(g, s); break;
+    case 2: launch_one<TA, double, TRA, false, 128, 32, 16, 4, 1>(g, s); break;
+    case 3: launch_one<TA, double, TRA, false, 128, 48, 16, 4, 1>(g, s); break;
+    case 4: launch_one<TA, double, TRA, false, 128, 64, 16, 4, 1>(g, s); break;
+    case 5: launch_one<TA, double, TRA, false, 128, 80, 16, 4, 1>(g, s); break;
+    case 6: launch_one<TA, double, TRA, false, 128, 96, 16, 4, 1>(g, s); break;
+    default: launch_one<TA, double, TRA, false, 128, 112, 16, 4, 1>(g, s); break;
+  }
+  IHS_CHECK_LAUNCH();
+}
+
+ColTiles pick_col_tiles(int64_t N) {
+  // cost ~ c (q + 1/4): a tile's fixed share (its pass over the A panel) is
+  // about a quarter of one 16-column block's work; never cover more columns
+  // than the padded width (16, 32 or a multiple of 64) that buffers are sized for
+  const int64_t nb = cdiv(N, 16);
+  const int64_t cap = nb <= 2 ? nb : 4 * cdiv(nb, 4);
+  ColTiles best{(int)cdiv(nb, 4), 4};
+  double best_cost = 1e300;
+  for (int64_t c = cdiv(nb, kColTileMaxQ); c <= nb; ++c) {
+    const int64_t q = cdiv(nb, c);
+    if (c * q > cap) continue;
+    const double cost = (double)c * ((double)q + 0.25);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = ColTiles{(int)c, (int)q};
+    }
+    if (q == 1) break;
+  }
+  return best;
+}
+
+void gemm_cols(const Gemm& g_in, DT ta, bool transA, const ColTiles& ct, hipStream_t s) {
+  if (g_in.M <= 0 || g_in.N <= 0) return;
+  if (ct.q < 1 || ct.q > kColTileMaxQ || (int64_t)ct.c * 16 * ct.q < g_in.N)
+    fail(IHSBIN_EINVAL, "gemm_cols: column tiling does not cover N");
+  Gemm g = g_in;
+  const size_t ea = ta == DT::F32 ? 4 : 8;
+  g.vec_ok = aligned16(g.A, g.lda, g.strideA, ea) && aligned16(g.B, g.ldb, g.strideB, 8);
+  if (g.n_read > (int64_t)ct.c * 16 * ct.q) g.n_read = (int64_t)ct.c * 16 * ct.q;
+  if (ta == DT::F32) {
+    if (transA) launch_cols<float, true>(g, ct.q, s);
+    else launch_cols<float, false>(g, ct.q, s);
+  } else {
+    if (transA) launch_cols<double, true>(g, ct.q, s);
+    else launch_cols<double, false>(g, ct.q, s);
+  }
+}
+
+int pick_splits_cols(int64_t M, const ColTiles& ct, int64_t K, int64_t target) {
+  const int64_t tiles = cdiv(M, 128) * ct.c;
+  int64_t sp = cdiv(target, tiles);
+  const int64_t kt = cdiv(K, 16);
+  if (sp > kt / 8) sp = kt / 8;
+  if (sp < 1) sp = 1;
+  if (sp > 256) sp = 256;
+  return (int)sp;
+}
+
 
 void gemm(const Gemm& g_in, DT ta, bool transA, DT tb, bool transB, hipStream_t s) {
   if (g_in.M <= 0 || g_in.N <= 0) return;

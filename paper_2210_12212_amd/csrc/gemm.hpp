@@ -39,6 +39,19 @@ void reduce_splits(const double* part, int splits, int batch, int64_t M, int64_t
                    int64_t ldp, int64_t stride_part, double* C, int64_t ldc,
                    int64_t strideC, double alpha, double beta, hipStream_t s);
 
+// Column tiling for products whose width N varies call to call (the A^T A
+// products): c column tiles of 16 q columns each, q <= kColTileMaxQ, chosen
+// to cover N with the fewest 16-column blocks.  The caller sets n_read so that
+// op(B) holds c * 16 q readable columns.
+constexpr int kColTileMaxQ = 7;
+struct ColTiles {
+  int c, q;
+};
+ColTiles pick_col_tiles(int64_t N);
+// op(A) of type ta (FP32/FP64), B FP64 not transposed, C FP64.
+void gemm_cols(const Gemm& g, DT ta, bool transA, const ColTiles& ct, hipStream_t s);
+int pick_splits_cols(int64_t M, const ColTiles& ct, int64_t K, int64_t target);
+
 // Choose split-K so that roughly `target` workgroups run.
 int pick_splits(int64_t M, int64_t N, int64_t K, int batch, int64_t target = 2048);
 

@@ -42,9 +42,10 @@ constexpr int kNB = 64;
 
 // ------------------------------------------------------------ products with A
 // W = A^T A U (d x w), FP64.  Uses ctx scratch for Y = A U and split-K partials.
-// When wmax > w, columns [w, padded width) of U and W (padded width <= wmax,
-// <= ldu, <= ldw) may be read and overwritten: the dense GEMMs then run on
-// whole tiles.  Returns the number of columns actually computed.
+// When wmax > w (and wmax <= ldu), columns [w, wmax) of U exist and may be read
+// (their values are ignored): the dense GEMMs then run ragged widths on the
+// unchecked load path.  padded_width(w) (16, 32 or a multiple of 64) bounds
+// the columns read.  Only columns [0, w) of W are written; returns w.
 int64_t padded_width(int64_t w);
 int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
                   int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0);

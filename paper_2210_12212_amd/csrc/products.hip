@@ -127,16 +127,15 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
   hipStream_t st = ctx.stream;
   if (w <= 0) return 0;
   const bool dense = A.format == IHSBIN_DENSE;
-  int64_t wp = w;
-  if (dense && wmax > w) {
-    const int64_t p = padded_width(w);
-    if (p <= wmax && p <= ldu && p <= ldw) wp = p;
-  }
+  // U holds `readable` columns (w unless the caller sized it wider): column
+  // tiles may read past w up to there, so ragged widths avoid the checked path
+  const int64_t readable = wmax > w && wmax <= ldu ? wmax : w;
   int64_t wc = (int64_t)(kYBudget / (sizeof(double) * (size_t)A.n));
   if (wc >= 64) wc = (wc / 64) * 64;
-  if (wc > wp) wc = wp;
+  if (wc > w) wc = w;
   if (wc < 1) wc = 1;
-  double* Y = static_cast<double*>(ctx.ws_y.ensure(sizeof(double) * (size_t)A.n * (size_t)wc));
+  const int64_t ycap = dense ? padded_width(wc) : wc;
+  double* Y = static_cast<double*>(ctx.ws_y.ensure(sizeof(double) * (size_t)A.n * (size_t)ycap));
   const DT ta = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
   auto mark = [&]() {
     if (!ev) return;
@@ -145,8 +144,12 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
     IHS_HIP(hipEventRecord(e, st));
     ev->push_back(e);
   };
-  for (int64_t c0 = 0; c0 < wp; c0 += wc) {
-    const int64_t cw = (wp - c0) < wc ? (wp - c0) : wc;
+  for (int64_t c0 = 0; c0 < w; c0 += wc) {
+    const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
+    const ColTiles ct = pick_col_tiles(cw);
+    const int64_t span = (int64_t)ct.c * 16 * ct.q;  // columns the tiles cover
+    int64_t nread = readable - c0;
+    if (nread > span) nread = span;
     mark();
     if (dense) {
       Gemm g1;
@@ -157,15 +160,18 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
       g1.lda = A.ld;
       g1.B = U + c0;
       g1.ldb = ldu;
+      g1.n_read = nread;
       g1.C = Y;
-      g1.ldc = cw;
-      gemm(g1, ta, false, DT::F64, false, st);
+      g1.ldc = ycap;
+      gemm_cols(g1, ta, false, ct, st);
     } else {
       launch_csr_spmm(A, U + c0, cw, ldu, Y, cw, st);
     }
     mark();
     if (dense) {
-      const int splits = pick_splits(A.d, cw, A.n, 1, 1024);
+      // Y columns [cw, span) are never written; the W tiles read them (their
+      // results land in columns >= cw, which are not stored)
+      const int splits = pick_splits_cols(A.d, ct, A.n, 1024);
       Gemm g2;
       g2.M = A.d;
       g2.N = cw;
@@ -173,7 +179,8 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
       g2.A = A.vals;
       g2.lda = A.ld;
       g2.B = Y;
-      g2.ldb = cw;
+      g2.ldb = ycap;
+      g2.n_read = span <= ycap ? span : ycap;
       if (splits > 1) {
         double* part = static_cast<double*>(
             ctx.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)A.d * (size_t)cw));
@@ -181,12 +188,12 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
         g2.ldc = cw;
         g2.strideC = A.d * cw;
         g2.splits = splits;
-        gemm(g2, ta, true, DT::F64, false, st);
+        gemm_cols(g2, ta, true, ct, st);
         reduce_splits(part, splits, 1, A.d, cw, cw, A.d * cw, W + c0, ldw, 0, 1.0, 0.0, st);
       } else {
         g2.C = W + c0;
         g2.ldc = ldw;
-        gemm(g2, ta, true, DT::F64, false, st);
+        gemm_cols(g2, ta, true, ct, st);
       }
     } else {
       zero_block(W + c0, A.d, cw, ldw, st);
@@ -194,7 +201,7 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
     }
     mark();
   }
-  return wp;
+  return w;
 }
 
 void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C) {

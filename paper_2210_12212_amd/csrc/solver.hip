@@ -666,8 +666,11 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   for (int i = 1; i < kcap && !act.empty(); ++i) {
     const int na = (int)act.size();
     const int64_t w_old = (int64_t)na * i * K;
-    logf("step %d: active %d, product width %lld (padded %lld)", i, na, (long long)w_old,
-         (long long)padded_width(w_old));
+    if (log_enabled()) {
+      const ColTiles ct = pick_col_tiles(w_old);
+      logf("step %d: active %d, product width %lld (%d column tiles of %d)", i, na,
+           (long long)w_old, ct.c, 16 * ct.q);
+    }
     const size_t ev0 = events.size();
     ata_apply(c, A, Ucur, w_old, wcap, W, wcap, o.timing ? &events : nullptr, wcap);
     if (o.timing) {
