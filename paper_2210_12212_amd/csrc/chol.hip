@@ -9,6 +9,7 @@
 // row block with the same GEMM, so that applying P_S = L^-T L^-1 to many
 // vectors is two triangular matrix products.
 #include <cmath>
+#include <utility>
 
 #include "ops.hpp"
 
@@ -36,71 +37,118 @@ void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, in
   IHS_CHECK_LAUNCH();
 }
 
-// Factor diagonal block p of every matrix in LDS, write L_pp back (upper part
-// zeroed) and its inverse into dinv[l][p].  Both the factorization and the
-// inversion are right-looking with one barrier per column: step j reads the
-// pivot that step j-1 finished and updates everything to its right/below.
+// Factor diagonal block p of every matrix, write L_pp back (upper part zeroed)
+// and its inverse into dinv[l][p].  Thread (r, q) keeps row r, columns
+// q, q + 4, ..., q + 60 of the block in registers; each column step publishes
+// one column (factorization) or one row (inversion) through LDS, so a step
+// costs one barrier and up to sixteen independent LDS reads.  The steps are
+// expanded at compile time so the register slots are addressed statically.
+namespace {
+constexpr int kS = kNB / 4;
+
+// factorization step j: owners publish column j; every row scales its entry
+// into L[r][j] and updates its columns c in (j, r]
+template <int J>
+__device__ __forceinline__ void potrf_step(double (&a)[kS], double (*colbuf)[kNB], int r, int q,
+                                           bool& bad) {
+  double* col = colbuf[J & 1];
+  if (q == (J & 3)) col[r] = a[J >> 2];
+  __syncthreads();
+  double djj = col[J];
+  if (!(djj > 0.0)) {
+    bad = true;
+    djj = 1.0;
+  }
+  // one division per step: entries of column J are scaled by 1 / sqrt(d_JJ)
+  const double rpiv = 1.0 / sqrt(djj);
+  const double lrj = r >= J ? col[r] * rpiv : 0.0;
+  if (q == (J & 3)) a[J >> 2] = lrj;
+#pragma unroll
+  for (int s = J >> 2; s < kS; ++s) {
+    const int c = q + 4 * s;
+    const double upd = lrj * (col[c] * rpiv);  // select, not branch: lanes differ in c
+    a[s] -= (c > J && c <= r) ? upd : 0.0;
+  }
+}
+
+// inversion step i: row i of X = L^-1 becomes final and is published; rows
+// below accumulate L[r][i] X[i]
+template <int I>
+__device__ __forceinline__ void trinv_step(double (&x)[kS], double (*rowbuf)[kNB],
+                                           const double (*lf)[kNB + 1], int r, int q) {
+  double* row = rowbuf[I & 1];
+  if (r == I) {
+    const double rlii = 1.0 / lf[I][I];
+#pragma unroll
+    for (int s = 0; s <= (I >> 2); ++s) {
+      const int c = q + 4 * s;
+      x[s] = c <= I ? ((c == I ? 1.0 : 0.0) - x[s]) * rlii : 0.0;
+      row[c] = x[s];
+    }
+  }
+  __syncthreads();
+  if (r > I) {
+    const double lri = lf[r][I];
+#pragma unroll
+    for (int s = 0; s <= (I >> 2); ++s) {
+      const int c = q + 4 * s;
+      const double upd = lri * row[c];
+      x[s] += c <= I ? upd : 0.0;
+    }
+  }
+}
+
+template <int... J>
+__device__ __forceinline__ void potrf_all(std::integer_sequence<int, J...>, double (&a)[kS],
+                                          double (*colbuf)[kNB], int r, int q, bool& bad) {
+  (potrf_step<J>(a, colbuf, r, q, bad), ...);
+}
+
+template <int... I>
+__device__ __forceinline__ void trinv_all(std::integer_sequence<int, I...>, double (&x)[kS],
+                                          double (*rowbuf)[kNB], const double (*lf)[kNB + 1],
+                                          int r, int q) {
+  (trinv_step<I>(x, rowbuf, lf, r, q), ...);
+}
+}  // namespace
+
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, int p,
                                                          double* dinv, int nblk, int* status) {
   constexpr int NB = kNB;
-  __shared__ double a[NB][NB + 1];   // trailing matrix during the factorization
-  __shared__ double lf[NB][NB + 1];  // the factor L
-  __shared__ double x[NB][NB + 1];   // accumulators, then L^-1
+  static_assert(NB == 64, "register layout assumes 64 x 64 blocks and 256 threads");
+  __shared__ double colbuf[2][NB];
+  __shared__ double lf[NB][NB + 1];
   const int l = blockIdx.x;
   double* M = H + (int64_t)l * d * d;
   const int64_t o = (int64_t)p * NB;
   const int nb = (int)((d - o) < NB ? (d - o) : NB);
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, c = e % NB;
-    a[r][c] = (r < nb && c < nb) ? M[(o + r) * d + o + c] : (r == c ? 1.0 : 0.0);
-    lf[r][c] = 0.0;
-    x[r][c] = 0.0;
+  const int r = tid >> 2, q = tid & 3;
+  double a[kS];
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    const int c = q + 4 * s;
+    a[s] = (c <= r) ? ((r < nb && c < nb) ? M[(o + r) * d + o + c] : (r == c ? 1.0 : 0.0)) : 0.0;
   }
-  // four threads per row: thread (ti, tq) owns row ti, columns tq, tq + 4, ...
-  const int ti = tid >> 2, tq = tid & 3;
-  // factorization: a[i][k] -= a[i][j] a[k][j] / a[j][j] for j < k <= i
-  for (int j = 0; j < NB; ++j) {
-    __syncthreads();
-    double djj = a[j][j];
-    if (!(djj > 0.0)) {
-      if (tid == 0) status[0] = 1;
-      djj = 1.0;
-    }
-    const double piv = sqrt(djj), inv = 1.0 / djj;
-    if (tq == 0 && ti >= j) lf[ti][j] = (ti == j) ? piv : a[ti][j] / piv;
-    if (ti > j) {
-      const double f = a[ti][j] * inv;
-      for (int k = j + 1 + tq; k <= ti; k += 4) a[ti][k] -= f * a[k][j];
-    }
+  bool bad = false;
+  potrf_all(std::make_integer_sequence<int, NB>{}, a, colbuf, r, q, bad);
+  if (bad) status[0] = 1;
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    const int c = q + 4 * s;
+    lf[r][c] = a[s];
+    if (r < nb && c < nb) M[(o + r) * d + o + c] = a[s];
   }
+  double x[kS];
+#pragma unroll
+  for (int s = 0; s < kS; ++s) x[s] = 0.0;
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, c = e % NB;
-    if (r < nb && c < nb) M[(o + r) * d + o + c] = lf[r][c];
-  }
-  // inversion of L: row i of X is (e_i - acc_i) / L_ii, and rows below
-  // accumulate L[r][i] X[i][:]; row i is finalized one step later (no reader then)
-  for (int i = 0; i < NB; ++i) {
-    __syncthreads();
-    if (i > 0) {
-      const double lp = lf[i - 1][i - 1];
-      for (int c = tid; c < i; c += blockDim.x) x[i - 1][c] = ((i - 1 == c ? 1.0 : 0.0) - x[i - 1][c]) / lp;
-    }
-    const double lii = lf[i][i];
-    if (ti > i) {
-      const double f = lf[ti][i] / lii;
-      for (int c = tq; c <= i; c += 4) x[ti][c] += f * ((i == c ? 1.0 : 0.0) - x[i][c]);
-    }
-  }
-  __syncthreads();
-  for (int c = tid; c < NB; c += blockDim.x)
-    x[NB - 1][c] = ((NB - 1 == c ? 1.0 : 0.0) - x[NB - 1][c]) / lf[NB - 1][NB - 1];
-  __syncthreads();
+  trinv_all(std::make_integer_sequence<int, NB>{}, x, colbuf, lf, r, q);
   double* Di = dinv + ((int64_t)l * nblk + p) * NB * NB;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, c = e % NB;
-    Di[e] = (c <= r) ? x[r][c] : 0.0;
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    const int c = q + 4 * s;
+    Di[r * NB + c] = c <= r ? x[s] : 0.0;
   }
 }
 
@@ -197,6 +245,7 @@ void tri_inverse_batched(const double* Lf, int64_t d, int nl, const double* dinv
       g.alpha = -1.0;
       g.beta = 0.0;
       g.batch = nl;
+      g.tri = 3;  // X[0:o, 0:o] is lower triangular
       gemm(g, DT::F64, false, DT::F64, false, st);
     }
     // X[I, 0:o+rows] = inv(L_II) X[I, 0:o+rows]   (in place, one row tile)

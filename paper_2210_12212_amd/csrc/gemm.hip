@@ -242,6 +242,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
   int64_t kb = 0, ke = g.K;
   if (g.tri == 1) ke = ke < m0 + BM ? ke : m0 + BM;
   if (g.tri == 2) kb = (m0 / BK) * BK;
+  if (g.tri == 3) kb = (n0 / BK) * BK;
   if (g.splits > 1) {
     const int64_t tiles = (ke - kb + BK - 1) / BK;
     const int64_t per = (tiles + g.splits - 1) / g.splits;
@@ -326,7 +327,7 @@ static void launch_one(const Gemm& g, hipStream_t s) {
 
 template <typename TA, typename TB, bool TRA, bool TRB>
 static void launch_t(const Gemm& g, hipStream_t s) {
-  switch (pick_tile(g.M, g.N)) {
+  switch (g.small_tiles ? Tile::T64x64 : pick_tile(g.M, g.N)) {
     case Tile::T64x64: launch_one<TA, TB, TRA, TRB, 64, 64, 16, 2, 2>(g, s); break;
     case Tile::T64x32: launch_one<TA, TB, TRA, TRB, 64, 32, 16, 2, 2>(g, s); break;
     case Tile::T64x16: launch_one<TA, TB, TRA, TRB, 64, 16, 16, 4, 1>(g, s); break;
@@ -452,6 +453,17 @@ void reduce_splits(const double* part, int splits, int batch, int64_t M, int64_t
   hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)blocks, (unsigned)batch), dim3(256), 0, s,
                      part, splits, M, N, ldp, stride_part, C, ldc, strideC, alpha, beta);
   IHS_CHECK_LAUNCH();
+}
+
+int pick_splits_lower(int64_t n, int64_t K, int64_t target) {
+  const int64_t nt = cdiv(n, 64);
+  const int64_t tiles = nt * (nt + 1) / 2;
+  int64_t s = cdiv(target, tiles);
+  const int64_t kt = cdiv(K, 16);
+  if (s > kt / 8) s = kt / 8;  // keep at least eight K-slices per split
+  if (s < 1) s = 1;
+  if (s > 64) s = 64;
+  return (int)s;
 }
 
 int pick_splits(int64_t M, int64_t N, int64_t K, int batch, int64_t target) {

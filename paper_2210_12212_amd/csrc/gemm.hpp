@@ -21,9 +21,12 @@ struct Gemm {
   double alpha = 1.0, beta = 0.0;
   int batch = 1;         // independent problems (strides above)
   int splits = 1;        // split-K: partial sums of (b, s) go to C + (b*splits+s)*strideC
-  int tri = 0;           // 1: op(A) lower triangular, 2: op(A) upper triangular
+  int tri = 0;           // 1: op(A) lower triangular, 2: op(A) upper triangular,
+                         // 3: op(B) lower triangular (zero K-slices are skipped)
   int lower_only = 0;    // compute only C tiles touching the lower triangle
   const int32_t* amap = nullptr;  // optional device map: problem b uses A + amap[b]*strideA
+  int small_tiles = 0;   // 1: 64 x 64 tiles even for large M (FP64 x FP64 products
+                         // with large N, e.g. the sketched Gram, reuse L2 better)
   int vec_ok = 0;        // set by gemm(): operands allow aligned 16-byte vector loads
   // Columns of op(B) that may be read (0: N).  When n_read > N, memory for
   // op(B) columns [N, n_read) exists (its values are ignored): tiles that end
@@ -51,6 +54,10 @@ ColTiles pick_col_tiles(int64_t N);
 // op(A) of type ta (FP32/FP64), B FP64 not transposed, C FP64.
 void gemm_cols(const Gemm& g, DT ta, bool transA, const ColTiles& ct, hipStream_t s);
 int pick_splits_cols(int64_t M, const ColTiles& ct, int64_t K, int64_t target);
+
+// Split-K for a lower_only product with M = N = n on 64 x 64 tiles (small_tiles):
+// roughly `target` workgroups over the lower tiles.
+int pick_splits_lower(int64_t n, int64_t K, int64_t target);
 
 // Choose split-K so that roughly `target` workgroups run.
 int pick_splits(int64_t M, int64_t N, int64_t K, int batch, int64_t target = 2048);

@@ -191,8 +191,10 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
 // Lower triangle (and the diagonal tiles) of G = (SA)^T SA; the strictly
 // upper tiles are not computed and hold unspecified values.
 static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G) {
-  const int splits = pick_splits(d, d, m, 1, 1024);
+  // 64 x 64 lower tiles with enough K-splits for ~16 workgroups per CU
+  const int splits = pick_splits_lower(d, m, 4096);
   Gemm g;
+  g.small_tiles = 1;
   g.M = d;
   g.N = d;
   g.K = m;
@@ -237,29 +239,46 @@ static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<do
 }
 
 // Z = P R for every active position: P_a = Linv_{ids[a]}^T Linv_{ids[a]}.
+// Each product reads a whole triangular factor for a few columns, so it is
+// bound by that read: K is split until ~2048 workgroups stream the factors.
 static void apply_p(Ctx& c, const double* Linv_all, const int32_t* ids_dev, int na, int64_t d,
                     int64_t cw, int64_t ld, const double* R, double* T, double* Z) {
-  Gemm g;
-  g.M = d;
-  g.N = cw;
-  g.K = d;
-  g.A = Linv_all;
-  g.lda = d;
-  g.strideA = d * d;
-  g.amap = ids_dev;
-  g.B = R;
-  g.ldb = ld;
-  g.strideB = cw;
-  g.C = T;
-  g.ldc = ld;
-  g.strideC = cw;
-  g.batch = na;
-  g.tri = 1;
-  gemm(g, DT::F64, false, DT::F64, false, c.stream);
-  g.B = T;
-  g.C = Z;
-  g.tri = 2;
-  gemm(g, DT::F64, true, DT::F64, false, c.stream);
+  const int64_t tiles = (int64_t)na * cdiv(d, 256) * cdiv(cw, cw <= 16 ? 16 : 32);
+  int splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, cdiv(2048, tiles)));
+  if (d < 1024 || cw > 32) splits = 1;
+  double* part = splits > 1 ? static_cast<double*>(c.ws_part.ensure(
+                                  sizeof(double) * (size_t)splits * na * (size_t)d * (size_t)cw))
+                            : nullptr;
+  auto tri_product = [&](bool trans, const double* X, double* Y) {
+    Gemm g;
+    g.M = d;
+    g.N = cw;
+    g.K = d;
+    g.A = Linv_all;
+    g.lda = d;
+    g.strideA = d * d;
+    g.amap = ids_dev;
+    g.B = X;
+    g.ldb = ld;
+    g.strideB = cw;
+    g.batch = na;
+    g.tri = trans ? 2 : 1;
+    if (splits > 1) {
+      g.C = part;
+      g.ldc = cw;
+      g.strideC = d * cw;
+      g.splits = splits;
+      gemm(g, DT::F64, trans, DT::F64, false, c.stream);
+      reduce_splits(part, splits, na, d, cw, cw, d * cw, Y, ld, cw, 1.0, 0.0, c.stream);
+    } else {
+      g.C = Y;
+      g.ldc = ld;
+      g.strideC = cw;
+      gemm(g, DT::F64, trans, DT::F64, false, c.stream);
+    }
+  };
+  tri_product(false, R, T);
+  tri_product(true, T, Z);
 }
 
 // Symmetric eigen-decomposition of a small dense matrix by cyclic Jacobi.
@@ -380,7 +399,9 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
     launch_add_shift(S, T, d, na, ld, lam_dev, st);   // S += lam0 T
     launch_trmv(Linv_all, d, ids_dev, na, false, S, ld, Wv, ld, trs, st);                      // W = Linv S
     launch_lanczos_orth(Q, Wv, d, na, ld, j, J, alpha, beta, st);
-    if ((j + 1) % 6 == 0 && j + 1 < J && early.enabled) {
+    // a sketch far too small shows within two or three steps (Ritz values
+    // bound the spectrum from inside), so the probe checks after every step
+    if (early.enabled && j + 1 >= 2 && j + 1 < J) {
       IHS_HIP(hipMemcpyAsync(h.data(), alpha, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
       IHS_HIP(hipStreamSynchronize(st));
       if (early(ritz_extremes(h, na, J, 0, j + 1))) {
