@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -60,11 +61,91 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Device memory reused across calls on one context.  A block handed back is
+// reused by later work on the context's stream without synchronizing: stream
+// order puts every earlier reader before the next writer.  Idle memory above
+// kKeepBytes is released (after a device synchronize).
+struct Pool {
+  static constexpr size_t kKeepBytes = size_t(32) << 30;
+  std::multimap<size_t, void*> idle;
+  std::map<void*, size_t> block_bytes;
+  size_t idle_bytes = 0;
+  Pool() = default;
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
+  ~Pool() { release_idle(); }
+  void* get(size_t n) {
+    n = (n + 65535) / 65536 * 65536;
+    auto it = idle.lower_bound(n);
+    // reuse a block of up to twice the request (or 64 MiB more)
+    if (it != idle.end() && (it->first <= 2 * n || it->first <= n + (size_t(64) << 20))) {
+      void* p = it->second;
+      idle_bytes -= it->first;
+      idle.erase(it);
+      return p;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipErrorOutOfMemory && !idle.empty()) {
+      (void)hipGetLastError();
+      release_idle();
+      e = hipMalloc(&p, n);
+    }
+    if (e != hipSuccess)
+      fail(e == hipErrorOutOfMemory ? IHSBIN_ENOMEM : IHSBIN_EHIP,
+           std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    block_bytes[p] = n;
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    const size_t n = block_bytes[p];
+    idle.emplace(n, p);
+    idle_bytes += n;
+    if (idle_bytes > kKeepBytes) release_idle();
+  }
+  void release_idle() {
+    if (idle.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& kv : idle) {
+      (void)hipFree(kv.second);
+      block_bytes.erase(kv.second);
+    }
+    idle.clear();
+    idle_bytes = 0;
+  }
+};
+
+// A grow-only buffer borrowed from a Pool and handed back on destruction.
+struct PoolBuf {
+  Pool* pool;
+  void* p = nullptr;
+  size_t bytes = 0;
+  explicit PoolBuf(Pool& pl) : pool(&pl) {}
+  PoolBuf(const PoolBuf&) = delete;
+  PoolBuf& operator=(const PoolBuf&) = delete;
+  ~PoolBuf() { pool->put(p); }
+  void release() {
+    pool->put(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void* ensure(size_t n) {
+    if (n <= bytes && p) return p;
+    pool->put(p);
+    if (n == 0) n = 256;
+    p = pool->get(n);
+    bytes = n;
+    return p;
+  }
+};
+
 // ------------------------------------------------------------- context
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
+  Pool pool;  // build-local buffers (declared first: outlives the workspaces below)
   // scratch shared by the step kernels of one call
   DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status;
 };

@@ -221,7 +221,7 @@ static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G)
 
 // H_l = G + lam0_l I, factor in place, and Linv_l = L_l^-1.
 static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<double>& lam0s,
-                        double* Lf, double* Linv, DevBuf& dinv_buf, DevBuf& lam_buf) {
+                        double* Lf, double* Linv, PoolBuf& dinv_buf, PoolBuf& lam_buf) {
   const int nl = (int)lam0s.size();
   double* lam_dev = static_cast<double*>(lam_buf.ensure(sizeof(double) * nl));
   IHS_HIP(hipMemcpyAsync(lam_dev, lam0s.data(), sizeof(double) * nl, hipMemcpyHostToDevice, c.stream));
@@ -378,7 +378,7 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
   if (J > 63) J = 63;
   const int64_t ld = padded_width(na);  // padded so the A^T A product runs on whole tiles
   const size_t vec = sizeof(double) * (size_t)d * ld;
-  DevBuf Qb, Tb, Sb, Wb, ab, idb, lb, trb;
+  PoolBuf Qb(c.pool), Tb(c.pool), Sb(c.pool), Wb(c.pool), ab(c.pool), idb(c.pool), lb(c.pool), trb(c.pool);
   double* trs = static_cast<double*>(trb.ensure(sizeof(double) * trmv_scratch_doubles(d, na)));
   double* Q = static_cast<double*>(Qb.ensure(vec * (J + 1)));
   double* T = static_cast<double*>(Tb.ensure(vec));
@@ -485,7 +485,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   const int64_t d = A.d;
 
   // ---- C = A^T B
-  DevBuf Cb;
+  PoolBuf Cb(c.pool);
   double* C = static_cast<double*>(Cb.ensure(sizeof(double) * d * K));
   atb_apply(c, A, B, K, ldb, C);
 
@@ -496,7 +496,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   if (m % s) m += s - m % s;
   int64_t m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(A.n, 32 * d));
   if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(A.n)));
-  DevBuf SAb, Gb, Lb, Ib, dinvb, lamb;
+  PoolBuf SAb(c.pool), Gb(c.pool), Lb(c.pool), Ib(c.pool), dinvb(c.pool), lamb(c.pool);
   double* G = static_cast<double*>(Gb.ensure(sizeof(double) * d * d));
   std::vector<Spec> spec;
   int trials = 0;
@@ -639,7 +639,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   IHS_HIP(hipMemsetAsync(basis, 0, sizeof(double) * L * kcap * d * K, st));
 
   const int64_t wcap = padded_width((int64_t)L * kcap * K);
-  DevBuf Ub0, Ub1, Rb, Tt, Zb, Wb, pb, parb, partial_b;
+  PoolBuf Ub0(c.pool), Ub1(c.pool), Rb(c.pool), Tt(c.pool), Zb(c.pool), Wb(c.pool), pb(c.pool), parb(c.pool), partial_b(c.pool);
   double* Ucur = static_cast<double*>(Ub0.ensure(sizeof(double) * d * wcap));
   double* Unext = static_cast<double*>(Ub1.ensure(sizeof(double) * d * wcap));
   double* R = static_cast<double*>(Rb.ensure(sizeof(double) * d * wcap));
@@ -1037,7 +1037,7 @@ int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t 
     if (!SA || !lam0 || !Lfac || m <= 0 || d <= 0 || nl <= 0) fail(IHSBIN_EINVAL, "bad arguments");
     for (int i = 0; i < nl; ++i)
       if (!(lam0[i] > 0.0)) fail(IHSBIN_EINVAL, "lam0 must be positive");
-    DevBuf Gb, dinvb, lamb;
+    PoolBuf Gb(ctx->c.pool), dinvb(ctx->c.pool), lamb(ctx->c.pool);
     double* G = static_cast<double*>(Gb.ensure(sizeof(double) * d * d));
     gram_impl(ctx->c, SA, m, d, G);
     std::vector<double> l0(lam0, lam0 + nl);
