@@ -324,8 +324,8 @@ void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int64_t ld, i
   IHS_CHECK_LAUNCH();
 }
 
-// y_b = L_{map[b]} x_b (lower triangular, row-major d x d): one wave per row,
-// 16-byte loads and four independent partial sums per lane.
+// y_b = L_{map[b]} x_b (lower triangular, row-major d x d): one wave per row
+// (general fallback for d above the LDS staging limit).
 __global__ __launch_bounds__(256) void trmv_lower_kernel(const double* __restrict__ L, int64_t d,
                                                          const int32_t* __restrict__ map, int nb,
                                                          const double* __restrict__ X, int64_t ldx,
@@ -337,27 +337,58 @@ __global__ __launch_bounds__(256) void trmv_lower_kernel(const double* __restric
     const int b = (int)(t / d);
     const int64_t r = t % d;
     const double* row = L + (int64_t)map[b] * d * d + r * d;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t k = lane; k <= r; k += 128) {
+      s0 += row[k] * X[k * ldx + b];
+      if (k + 64 <= r) s1 += row[k + 64] * X[(k + 64) * ldx + b];
+    }
+    const double s = wave_sum(s0 + s1);
+    if (lane == 0) Y[r * ldy + b] = s;
+  }
+}
+
+// Same product with x_b staged in LDS: block (chunk, b) takes kTrmvLRows rows
+// of L_b, one wave per row, streaming each row with 16-byte loads; the vector
+// is read from LDS instead of gathered column-strided from X.
+constexpr int kTrmvLRows = 32;
+constexpr int64_t kTrmvLdsMax = 8192;
+
+__global__ __launch_bounds__(256) void trmv_lower_lds_kernel(const double* __restrict__ L,
+                                                             int64_t d,
+                                                             const int32_t* __restrict__ map,
+                                                             const double* __restrict__ X,
+                                                             int64_t ldx, double* __restrict__ Y,
+                                                             int64_t ldy) {
+  __shared__ double xs[kTrmvLdsMax];
+  const int b = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * kTrmvLRows;
+  const int64_t rend = (r0 + kTrmvLRows) < d ? (r0 + kTrmvLRows) : d;
+  for (int64_t k = threadIdx.x; k < rend; k += blockDim.x) xs[k] = X[k * ldx + b];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* Lb = L + (int64_t)map[b] * d * d;
+  const bool vec = (d & 1) == 0;
+  for (int64_t r = r0 + w; r < rend; r += 4) {
+    const double* row = Lb + r * d;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const int64_t len = r + 1;
-    const bool vec = ((d & 1) == 0);
     int64_t k = 2 * lane;
     if (vec) {
-      for (; k + 384 + 1 < len; k += 512) {
+      for (; k + 384 + 1 <= r; k += 512) {
         const double2 a0 = *reinterpret_cast<const double2*>(row + k);
         const double2 a1 = *reinterpret_cast<const double2*>(row + k + 128);
         const double2 a2 = *reinterpret_cast<const double2*>(row + k + 256);
         const double2 a3 = *reinterpret_cast<const double2*>(row + k + 384);
-        s0 += a0.x * X[k * ldx + b] + a0.y * X[(k + 1) * ldx + b];
-        s1 += a1.x * X[(k + 128) * ldx + b] + a1.y * X[(k + 129) * ldx + b];
-        s2 += a2.x * X[(k + 256) * ldx + b] + a2.y * X[(k + 257) * ldx + b];
-        s3 += a3.x * X[(k + 384) * ldx + b] + a3.y * X[(k + 385) * ldx + b];
+        s0 += a0.x * xs[k] + a0.y * xs[k + 1];
+        s1 += a1.x * xs[k + 128] + a1.y * xs[k + 129];
+        s2 += a2.x * xs[k + 256] + a2.y * xs[k + 257];
+        s3 += a3.x * xs[k + 384] + a3.y * xs[k + 385];
       }
     }
-    for (; k < len; k += 128) {
-      s0 += row[k] * X[k * ldx + b];
-      if (k + 1 < len) s1 += row[k + 1] * X[(k + 1) * ldx + b];
+    for (; k <= r; k += 128) {
+      s0 += row[k] * xs[k];
+      if (k + 1 <= r) s1 += row[k + 1] * xs[k + 1];
     }
-    double s = wave_sum((s0 + s1) + (s2 + s3));
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) Y[r * ldy + b] = s;
   }
 }
@@ -407,10 +438,15 @@ void launch_trmv(const double* L, int64_t d, const int32_t* map, int nb, bool tr
                  const double* X, int64_t ldx, double* Y, int64_t ldy, double* scratch,
                  hipStream_t st) {
   if (!transpose) {
-    int64_t blocks = cdiv(d * nb * 64, 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(trmv_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, d, map, nb, X,
-                       ldx, Y, ldy);
+    if (d <= kTrmvLdsMax && nb <= 65535) {
+      hipLaunchKernelGGL(trmv_lower_lds_kernel, dim3((unsigned)cdiv(d, kTrmvLRows), (unsigned)nb),
+                         dim3(256), 0, st, L, d, map, X, ldx, Y, ldy);
+    } else {
+      int64_t blocks = cdiv(d * nb * 64, 256);
+      if (blocks > 65536) blocks = 65536;
+      hipLaunchKernelGGL(trmv_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, d, map,
+                         nb, X, ldx, Y, ldy);
+    }
   } else {
     const int64_t chunks = cdiv(d, kTrmvRows);
     hipLaunchKernelGGL(trmv_upper_t_partial_kernel, dim3((unsigned)(cdiv(d, 64) * chunks * nb)),

@@ -189,6 +189,108 @@ __global__ __launch_bounds__(256) void fwht_pass_kernel(const T* __restrict__ A,
   }
 }
 
+// Register-blocked pass for len = 16 V (16 <= len <= 512) over a tile of 16
+// columns: thread (c, g) first holds rows g + 16 k (k < V) of column c and
+// transforms over k in registers; one LDS exchange regroups the rows as
+// 16 kk + j (j < 16) and the transform over j finishes in registers.  The
+// Walsh-Hadamard matrix factorizes over the two bit groups of the row index,
+// so the two half-transforms compose to the full one.  Rows of 16 doubles
+// (128 bytes) are read and written per thread group.
+constexpr int kFwhtRC = 16;
+
+template <typename T, bool LOAD, int V>
+__global__ __launch_bounds__(256) void fwht_reg_kernel(const T* __restrict__ A, int64_t n,
+                                                       int64_t ld, const int8_t* __restrict__ sign,
+                                                       double* Z, int64_t npad, int64_t d,
+                                                       int64_t stride) {
+  constexpr int LEN = 16 * V;
+  constexpr int PER = V >= 16 ? V / 16 : 1;  // row sets of 16 per thread in phase 2
+  __shared__ double buf[LEN][kFwhtRC + 1];
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t groups = npad / ((int64_t)LEN * stride);
+  const int64_t ctiles = (d + kFwhtRC - 1) / kFwhtRC;
+  const int64_t total = groups * stride * ctiles;
+  for (int64_t job = blockIdx.x; job < total; job += gridDim.x) {
+    const int64_t ct = job % ctiles;
+    const int64_t hl = job / ctiles;
+    const int64_t l = hl % stride, h = hl / stride;
+    const int64_t col = ct * kFwhtRC + c;
+    const bool cok = col < d;
+    auto row_of = [&](int t) { return (h * LEN + t) * stride + l; };
+    double v[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const int64_t row = row_of(g + 16 * k);
+      double x = 0.0;
+      if (cok) {
+        if (LOAD) {
+          if (row < n) x = (double)sign[row] * (double)A[row * ld + col];
+        } else {
+          x = Z[row * d + col];
+        }
+      }
+      v[k] = x;
+    }
+#pragma unroll
+    for (int hh = 1; hh < V; hh <<= 1)
+#pragma unroll
+      for (int k = 0; k < V; ++k)
+        if ((k & hh) == 0) {
+          const double a = v[k], b = v[k + hh];
+          v[k] = a + b;
+          v[k + hh] = a - b;
+        }
+    __syncthreads();  // the previous job's phase-2 reads are done
+#pragma unroll
+    for (int k = 0; k < V; ++k) buf[g + 16 * k][c] = v[k];
+    __syncthreads();
+    if (V >= 16 || g < V) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int kk = V >= 16 ? g * PER + q : g;
+        double w[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) w[j] = buf[16 * kk + j][c];
+#pragma unroll
+        for (int hh = 1; hh < 16; hh <<= 1)
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if ((j & hh) == 0) {
+              const double a = w[j], b = w[j + hh];
+              w[j] = a + b;
+              w[j + hh] = a - b;
+            }
+        if (cok) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) Z[row_of(16 * kk + j) * d + col] = w[j];
+        }
+      }
+    }
+  }
+}
+
+template <typename T, bool LOAD>
+static void launch_fwht_reg(int dg, unsigned blocks, hipStream_t st, const T* A, int64_t n,
+                            int64_t ld, const int8_t* sign, double* Z, int64_t npad, int64_t d,
+                            int64_t stride) {
+  switch (dg) {
+#define IHS_FWHT_CASE(DG, V)                                                                   \
+  case DG:                                                                                     \
+    hipLaunchKernelGGL((fwht_reg_kernel<T, LOAD, V>), dim3(blocks), dim3(256), 0, st, A, n, ld, \
+                       sign, Z, npad, d, stride);                                              \
+    break;
+    IHS_FWHT_CASE(4, 1)
+    IHS_FWHT_CASE(5, 2)
+    IHS_FWHT_CASE(6, 4)
+    IHS_FWHT_CASE(7, 8)
+    IHS_FWHT_CASE(8, 16)
+    IHS_FWHT_CASE(9, 32)
+#undef IHS_FWHT_CASE
+    default:
+      fail(IHSBIN_EINVAL, "fwht: digit out of range");
+  }
+}
+
 // CSR rows are scattered into the (zeroed) Z with their signs first.
 template <typename T>
 __global__ void csr_signed_scatter_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -209,7 +311,7 @@ void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, d
   std::vector<int> digits;
   for (int left = p; left > 0;) {
     int take = left > 9 ? 9 : left;
-    if (left > 9 && left < 18) take = (left + 1) / 2;
+    if (left > 9 && left < 18) take = left / 2;  // the reading pass takes the smaller digit
     digits.push_back(take);
     left -= take;
   }
@@ -232,6 +334,25 @@ void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, d
   }
   for (int dg : digits) {
     const int len = 1 << dg;
+    if (dg >= 4) {
+      const int64_t rjobs = (npad / ((int64_t)len * stride)) * stride * cdiv(A.d, kFwhtRC);
+      const unsigned rblocks = (unsigned)(rjobs < 32768 ? rjobs : 32768);
+      if (first && A.format == IHSBIN_DENSE) {
+        if (A.dtype == IHSBIN_F32)
+          launch_fwht_reg<float, true>(dg, rblocks, st, (const float*)A.vals, A.n, A.ld, sign, Z,
+                                       npad, A.d, stride);
+        else
+          launch_fwht_reg<double, true>(dg, rblocks, st, (const double*)A.vals, A.n, A.ld, sign,
+                                        Z, npad, A.d, stride);
+      } else {
+        launch_fwht_reg<double, false>(dg, rblocks, st, (const double*)nullptr, A.n, A.ld, sign, Z,
+                                       npad, A.d, stride);
+      }
+      IHS_CHECK_LAUNCH();
+      first = false;
+      stride *= len;
+      continue;
+    }
     const int64_t jobs = (npad / ((int64_t)len * stride)) * stride * ctiles;
     const unsigned blocks = (unsigned)(jobs < 65536 ? jobs : 65536);
     if (first && A.format == IHSBIN_DENSE) {
