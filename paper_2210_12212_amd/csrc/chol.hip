@@ -152,45 +152,29 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, i
   }
 }
 
+// Two-level right-looking order: 64-column steps inside 256-column outer
+// panels update only their own panel; the trailing matrix right of an outer
+// panel is updated once per panel with K = 256, so it is read and written a
+// quarter as often as with 64-column steps.
 void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_dev,
                       hipStream_t st) {
   const int NB = kNB;
+  const int64_t OB = 4 * (int64_t)kNB;
   const int nblk = (int)cdiv(d, NB);
-  for (int p = 0; p < nblk; ++p) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(nl), dim3(256), 0, st, H, d, p, dinv, nblk,
-                       status_dev);
-    IHS_CHECK_LAUNCH();
-    const int64_t o = (int64_t)p * NB;
-    const int64_t below = d - o - NB;
-    if (below <= 0) break;
-    // panel: H[o+NB:, o:o+NB] <- H[o+NB:, o:o+NB] * inv(L_pp)^T  (in place, one column tile)
-    Gemm pg;
-    pg.M = below;
-    pg.N = NB;
-    pg.K = NB;
-    pg.A = H + (o + NB) * d + o;
-    pg.lda = d;
-    pg.strideA = d * d;
-    pg.B = dinv + (int64_t)p * NB * NB;
-    pg.ldb = NB;
-    pg.strideB = (int64_t)nblk * NB * NB;
-    pg.C = H + (o + NB) * d + o;
-    pg.ldc = d;
-    pg.strideC = d * d;
-    pg.batch = nl;
-    gemm(pg, DT::F64, false, DT::F64, true, st);
-    // trailing lower triangle: H22 -= P P^T
+  auto syrk_lower = [&](int64_t r0, int64_t c0, int64_t rows, int64_t cols, int64_t k0,
+                        int64_t kk) {
+    // H[r0:r0+rows, c0:c0+cols] -= H[r0:, k0:k0+kk] H[c0:, k0:k0+kk]^T  (tiles touching the lower part)
     Gemm tg;
-    tg.M = below;
-    tg.N = below;
-    tg.K = NB;
-    tg.A = H + (o + NB) * d + o;
+    tg.M = rows;
+    tg.N = cols;
+    tg.K = kk;
+    tg.A = H + r0 * d + k0;
     tg.lda = d;
     tg.strideA = d * d;
-    tg.B = H + (o + NB) * d + o;
+    tg.B = H + c0 * d + k0;
     tg.ldb = d;
     tg.strideB = d * d;
-    tg.C = H + (o + NB) * d + o + NB;
+    tg.C = H + r0 * d + c0;
     tg.ldc = d;
     tg.strideC = d * d;
     tg.alpha = -1.0;
@@ -198,72 +182,142 @@ void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_de
     tg.batch = nl;
     tg.lower_only = 1;
     gemm(tg, DT::F64, false, DT::F64, true, st);
+  };
+  for (int64_t O = 0; O < d; O += OB) {
+    const int64_t oe = (O + OB) < d ? (O + OB) : d;
+    for (int64_t o = O; o < oe; o += NB) {
+      const int p = (int)(o / NB);
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(nl), dim3(256), 0, st, H, d, p, dinv, nblk,
+                         status_dev);
+      IHS_CHECK_LAUNCH();
+      const int64_t below = d - o - NB;
+      if (below <= 0) break;
+      // panel: H[o+NB:, o:o+NB] <- H[o+NB:, o:o+NB] * inv(L_pp)^T  (in place, one column tile)
+      Gemm pg;
+      pg.M = below;
+      pg.N = NB;
+      pg.K = NB;
+      pg.A = H + (o + NB) * d + o;
+      pg.lda = d;
+      pg.strideA = d * d;
+      pg.B = dinv + (int64_t)p * NB * NB;
+      pg.ldb = NB;
+      pg.strideB = (int64_t)nblk * NB * NB;
+      pg.C = H + (o + NB) * d + o;
+      pg.ldc = d;
+      pg.strideC = d * d;
+      pg.batch = nl;
+      gemm(pg, DT::F64, false, DT::F64, true, st);
+      // the rest of the outer panel
+      const int64_t nc = oe - (o + NB);
+      if (nc > 0) syrk_lower(o + NB, o + NB, below, nc, o, NB);
+    }
+    const int64_t rest = d - oe;
+    if (rest > 0) syrk_lower(oe, oe, rest, rest, O, oe - O);
   }
 }
 
-__global__ void init_inverse_rows_kernel(double* X, int64_t d, int nl, int64_t r0, int64_t rows) {
-  const int64_t per = rows * d;
+// X <- block diagonal of the 64 x 64 inverses dinv, zero elsewhere.
+__global__ void init_inverse_kernel(double* X, int64_t d, int nl, const double* __restrict__ dinv,
+                                    int nblk) {
+  const int64_t per = d * d;
   const int64_t total = per * nl;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int l = (int)(t / per);
     const int64_t e = t % per;
-    const int64_t r = r0 + e / d, c = e % d;
-    X[(int64_t)l * d * d + r * d + c] = (r == c) ? 1.0 : 0.0;
+    const int64_t r = e / d, c = e % d;
+    const int64_t p = r / kNB;
+    double v = 0.0;
+    if (c / kNB == p && c <= r)
+      v = dinv[((int64_t)l * nblk + p) * kNB * kNB + (r - p * kNB) * kNB + (c - p * kNB)];
+    X[t] = v;
   }
 }
 
+// Doubling levels b = 64, 128, ...: diagonal blocks of size b already hold
+// their inverses; neighbouring pairs (P, Q) are joined by
+//   X_QP = -X_QQ (L_QP X_PP),
+// two batched products per level (over pairs and matrices).
+static int64_t level_pairs(int64_t d, int64_t b, int64_t& part_rows) {
+  const int64_t full = d / (2 * b);
+  const int64_t rem = d - full * 2 * b;
+  part_rows = rem > b ? rem - b : 0;  // a last pair with a short second block
+  return full;
+}
+
+int64_t tri_inverse_work_doubles(int64_t d, int nl) {
+  int64_t mx = 0;
+  for (int64_t b = kNB; b < d; b *= 2) {
+    int64_t pr = 0;
+    const int64_t full = level_pairs(d, b, pr);
+    const int64_t need = full * b * b + pr * b;
+    mx = need > mx ? need : mx;
+  }
+  return mx * nl;
+}
+
 void tri_inverse_batched(const double* Lf, int64_t d, int nl, const double* dinv, double* Linv,
-                         hipStream_t st) {
-  const int NB = kNB;
-  const int nblk = (int)cdiv(d, NB);
+                         double* work, hipStream_t st) {
+  const int nblk = (int)cdiv(d, kNB);
   {
     int64_t blocks = cdiv(d * d * nl, 256);
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(init_inverse_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Linv, d,
-                       nl, (int64_t)0, d);
+    hipLaunchKernelGGL(init_inverse_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Linv, d, nl,
+                       dinv, nblk);
     IHS_CHECK_LAUNCH();
   }
-  for (int I = 0; I < nblk; ++I) {
-    const int64_t o = (int64_t)I * NB;
-    const int64_t rows = (d - o) < NB ? (d - o) : NB;
-    if (I > 0) {
-      // X[I, 0:o] = -L[I, 0:o] X[0:o, 0:o]
-      Gemm g;
-      g.M = rows;
-      g.N = o;
-      g.K = o;
-      g.A = Lf + o * d;
-      g.lda = d;
-      g.strideA = d * d;
-      g.B = Linv;
-      g.ldb = d;
-      g.strideB = d * d;
-      g.C = Linv + o * d;
-      g.ldc = d;
-      g.strideC = d * d;
-      g.alpha = -1.0;
-      g.beta = 0.0;
-      g.batch = nl;
-      g.tri = 3;  // X[0:o, 0:o] is lower triangular
-      gemm(g, DT::F64, false, DT::F64, false, st);
-    }
-    // X[I, 0:o+rows] = inv(L_II) X[I, 0:o+rows]   (in place, one row tile)
-    Gemm h;
-    h.M = rows;
-    h.N = o + rows;
-    h.K = rows;
-    h.A = dinv + (int64_t)I * NB * NB;
-    h.lda = NB;
-    h.strideA = (int64_t)nblk * NB * NB;
-    h.B = Linv + o * d;
-    h.ldb = d;
-    h.strideB = d * d;
-    h.C = Linv + o * d;
-    h.ldc = d;
-    h.strideC = d * d;
-    h.batch = nl;
-    gemm(h, DT::F64, false, DT::F64, false, st);
+  for (int64_t b = kNB; b < d; b *= 2) {
+    int64_t pr = 0;
+    const int64_t full = level_pairs(d, b, pr);
+    // pairs start at diagonal offset o = 2 t b; P = [o, o + b), Q = [o + b, o + b + bq)
+    auto join = [&](int64_t o, int64_t bq, int npairs, double* T, int64_t strideT) {
+      // T = L_QP X_PP   (X_PP lower triangular)
+      Gemm g1;
+      g1.M = bq;
+      g1.N = b;
+      g1.K = b;
+      g1.A = Lf + (o + b) * d + o;
+      g1.lda = d;
+      g1.strideA = d * d;
+      g1.strideA2 = 2 * b * (d + 1);
+      g1.B = Linv + o * d + o;
+      g1.ldb = d;
+      g1.strideB = d * d;
+      g1.strideB2 = 2 * b * (d + 1);
+      g1.C = T;
+      g1.ldc = b;
+      g1.strideC = strideT * npairs;
+      g1.strideC2 = strideT;
+      g1.batch = nl;
+      g1.batch2 = npairs;
+      g1.tri = 3;
+      gemm(g1, DT::F64, false, DT::F64, false, st);
+      // X_QP = -X_QQ T   (X_QQ lower triangular)
+      Gemm g2;
+      g2.M = bq;
+      g2.N = b;
+      g2.K = bq;
+      g2.A = Linv + (o + b) * d + o + b;
+      g2.lda = d;
+      g2.strideA = d * d;
+      g2.strideA2 = 2 * b * (d + 1);
+      g2.B = T;
+      g2.ldb = b;
+      g2.strideB = strideT * npairs;
+      g2.strideB2 = strideT;
+      g2.C = Linv + (o + b) * d + o;
+      g2.ldc = d;
+      g2.strideC = d * d;
+      g2.strideC2 = 2 * b * (d + 1);
+      g2.alpha = -1.0;
+      g2.batch = nl;
+      g2.batch2 = npairs;
+      g2.tri = 1;
+      gemm(g2, DT::F64, false, DT::F64, false, st);
+    };
+    if (full > 0) join(0, b, (int)full, work, b * b);
+    if (pr > 0) join(full * 2 * b, pr, 1, work, pr * b);
   }
 }
 

@@ -229,15 +229,16 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
   const unsigned bx = lin % gx, by = (lin / gx) % gy, bz = lin / (gx * gy);
 
   const int z = (int)bz;
-  const int b = z / g.splits;
+  const int bb = z / g.splits;
   const int sp = z % g.splits;
+  const int b = bb % g.batch, b2 = bb / g.batch;
   const int64_t m0 = (int64_t)by * BM;
   const int64_t n0 = (int64_t)bx * BN;
   if (g.lower_only && n0 > m0 + BM - 1) return;
 
   const int64_t aoff = g.amap ? (int64_t)g.amap[b] : (int64_t)b;
-  const TA* __restrict__ A = static_cast<const TA*>(g.A) + aoff * g.strideA;
-  const TB* __restrict__ B = static_cast<const TB*>(g.B) + (int64_t)b * g.strideB;
+  const TA* __restrict__ A = static_cast<const TA*>(g.A) + aoff * g.strideA + b2 * g.strideA2;
+  const TB* __restrict__ B = static_cast<const TB*>(g.B) + (int64_t)b * g.strideB + b2 * g.strideB2;
 
   int64_t kb = 0, ke = g.K;
   if (g.tri == 1) ke = ke < m0 + BM ? ke : m0 + BM;
@@ -272,7 +273,8 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
     gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true, NT>(g, A, B, m0, n0, kb, ke, nblk, smem,
                                                                acc);
 
-  double* C = g.C + (int64_t)(g.splits > 1 ? z : b) * g.strideC;
+  double* C = g.splits > 1 ? g.C + (int64_t)z * g.strideC
+                           : g.C + (int64_t)b * g.strideC + (int64_t)b2 * g.strideC2;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -319,7 +321,9 @@ static void tile_dims(Tile t, int& bm, int& bn) {
 template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
           int NT = 256>
 static void launch_one(const Gemm& g, hipStream_t s) {
-  dim3 grid((unsigned)cdiv(g.N, BN), (unsigned)cdiv(g.M, BM), (unsigned)(g.batch * g.splits));
+  dim3 grid((unsigned)cdiv(g.N, BN), (unsigned)cdiv(g.M, BM),
+            (unsigned)(g.batch * g.batch2 * g.splits));
+  if (g.batch2 > 1 && g.splits > 1) fail(IHSBIN_EUNSUP, "gemm: batch2 with split-K");
   if (grid.y > 65535u || grid.z > 65535u) fail(IHSBIN_EUNSUP, "gemm grid too large");
   hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, NT>), grid, dim3(NT), 0,
                      s, g);

@@ -20,6 +20,9 @@ struct Gemm {
   int64_t ldc = 0, strideC = 0;
   double alpha = 1.0, beta = 0.0;
   int batch = 1;         // independent problems (strides above)
+  int batch2 = 1;        // second batch dimension (requires splits == 1): problem
+                         // (b, b2) adds b2 * strideX2 to each operand
+  int64_t strideA2 = 0, strideB2 = 0, strideC2 = 0;
   int splits = 1;        // split-K: partial sums of (b, s) go to C + (b*splits+s)*strideC
   int tri = 0;           // 1: op(A) lower triangular, 2: op(A) upper triangular,
                          // 3: op(B) lower triangular (zero K-slices are skipped)

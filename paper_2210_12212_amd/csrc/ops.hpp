@@ -36,8 +36,10 @@ void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, in
 void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_dev,
                       hipStream_t st);
 // Linv = L^-1 for nl factors, using the diagonal-block inverses from above.
+// work: tri_inverse_work_doubles(d, nl) doubles of device scratch.
 void tri_inverse_batched(const double* Lf, int64_t d, int nl, const double* dinv, double* Linv,
-                         hipStream_t st);
+                         double* work, hipStream_t st);
+int64_t tri_inverse_work_doubles(int64_t d, int nl);
 constexpr int kNB = 64;
 
 // ------------------------------------------------------------ products with A

@@ -235,7 +235,12 @@ static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<do
   IHS_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
   IHS_HIP(hipStreamSynchronize(c.stream));
   if (h) fail(IHSBIN_ENOTSPD, "sketched Hessian not positive definite");
-  if (Linv) tri_inverse_batched(Lf, d, nl, dinv, Linv, c.stream);
+  if (Linv) {
+    PoolBuf work(c.pool);
+    double* wk = static_cast<double*>(
+        work.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, tri_inverse_work_doubles(d, nl))));
+    tri_inverse_batched(Lf, d, nl, dinv, Linv, wk, c.stream);
+  }
 }
 
 // Z = P R for every active position: P_a = Linv_{ids[a]}^T Linv_{ids[a]}.
