@@ -24,11 +24,17 @@ Readings taken where the text is ambiguous:
   lam^(l) = lam_min * beta^(l/L), centre lam0 = sqrt(lam^(l) lam^(l+1))
   (Section 4.2 and Theorem 1); a lambda on a boundary belongs to the lower
   interval;
-* step size from the spectrum of P_S (A^T A + lam0 I) in [mu_min, mu_max]:
-  for lam in [lo, hi] the spectrum of P_S (A^T A + lam I) lies in
-  [mu_min lo/lam0, mu_max hi/lam0], and tau = 2 / (c_min + c_max) is the
-  minimizer of max |1 - tau c| over that range (the optimality condition
-  of the proof of Theorem 1); the rate is r = (c_max - c_min)/(c_max + c_min).
+* step size: the proof of Theorem 1 bounds the spectrum of P_S (A^T A + lam I)
+  over the whole interval and picks tau = 2 / (c_min + c_max), the minimizer
+  of max |1 - tau c| over [c_min, c_max]; the rate is
+  r = (c_max - c_min)/(c_max + c_min).  The bounds used here are the exact
+  ones over the interval: in the symmetric form L^-1 (A^T A + lam I) L^-T =
+  B_0 + lam L^-1 L^-T (P_S = L^-T L^-1) each Rayleigh quotient grows with
+  lam, so the smallest eigenvalue over [lo, hi] is the one at lo and the
+  largest the one at hi: c_min = lambda_min(P_S (A^T A + lo I)),
+  c_max = lambda_max(P_S (A^T A + hi I)).  (``step_size`` keeps the looser
+  form [mu_min lo/lam0, mu_max hi/lam0] built from the spectrum at lam0,
+  which with the theoretical bounds mu = 1/rho reproduces Theorem 1's alpha.)
 """
 from __future__ import annotations
 
@@ -113,6 +119,28 @@ def spectrum_bounds(op: Operator, P: Precond):
     Bm = sla.solve_triangular(Lf, X.T, lower=True)
     ev = np.linalg.eigvalsh(0.5 * (Bm + Bm.T))
     return float(ev[0]), float(ev[-1])
+
+
+def spectrum_at(op: Operator, P: Precond, lam: float):
+    """Exact extreme eigenvalues of P_S (A^T A + lam I) (dense, small d only)."""
+    Lf = P.factor()
+    H = op.dense_gram()
+    H[np.diag_indices_from(H)] += lam
+    X = sla.solve_triangular(Lf, H, lower=True)
+    Bm = sla.solve_triangular(Lf, X.T, lower=True)
+    ev = np.linalg.eigvalsh(0.5 * (Bm + Bm.T))
+    return float(ev[0]), float(ev[-1])
+
+
+def interval_bounds(op: Operator, P: Precond, lo: float, hi: float):
+    """[c_min, c_max] holding the spectrum of P_S (A^T A + lam I) for every
+    lam in [lo, hi]: the smallest eigenvalue at lo, the largest at hi."""
+    return spectrum_at(op, P, lo)[0], spectrum_at(op, P, hi)[1]
+
+
+def step_size_from_bounds(cmin: float, cmax: float):
+    """tau = 2 / (c_min + c_max) and the rate (c_max - c_min) / (c_max + c_min)."""
+    return 2.0 / (cmin + cmax), (cmax - cmin) / (cmax + cmin)
 
 
 def step_size(mu_min: float, mu_max: float, lo: float, hi: float, lam0: float):
@@ -236,8 +264,7 @@ def path(A, B, lambdas, SA, lam_min, lam_max, *, L=None, k=None, tol=1e-10,
         lo, hi, lam0 = grid[l], grid[l + 1], lam0s[l]
         P = Precond(np.asarray(SA, dtype=np.float64), lam0)
         if taus is None:
-            mu_min, mu_max = spectrum_bounds(op, P)
-            tau, rate = step_size(mu_min, mu_max, lo, hi, lam0)
+            tau, rate = step_size_from_bounds(*interval_bounds(op, P, lo, hi))
         else:
             tau, rate = float(taus[l]), 0.5
         ref = lam0 if centred else 0.0
