@@ -97,7 +97,10 @@ typedef struct {
                               interval is <= rate_target (default 1)            */
   double rate_target;      /* default 0.6                                      */
   int64_t m_max;           /* cap for adaptive m; 0 = library default           */
-  int32_t lanczos_steps;   /* spectrum estimate steps per interval (default 12) */
+  int32_t lanczos_steps;   /* Lanczos steps of each spectrum estimate (default
+                              12); one run per interval end: the smallest
+                              eigenvalue at the lower end and the largest at
+                              the upper end bound the whole interval          */
   int32_t timing;          /* 1: time the A^T A product kernels with events     */
   const double* taus;      /* host, optional: fixed step size per interval (L)  */
 } ihsbin_opts;

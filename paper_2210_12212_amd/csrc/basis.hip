@@ -347,61 +347,72 @@ __global__ __launch_bounds__(256) void trmv_lower_kernel(const double* __restric
   }
 }
 
-// Same product with x_b staged in LDS: block (chunk, b) takes kTrmvLRows rows
-// of L_b, one wave per row, streaming each row with 16-byte loads; the vector
-// is read from LDS instead of gathered column-strided from X.
+// Same product with the vectors staged in LDS: block (chunk, b) takes
+// kTrmvLRows rows of L_b, one wave per row, streaming each row once with
+// 16-byte loads for NV vectors (columns b and b + nm share the factor).
 constexpr int kTrmvLRows = 32;
 constexpr int64_t kTrmvLdsMax = 8192;
 
+template <int NV>
 __global__ __launch_bounds__(256) void trmv_lower_lds_kernel(const double* __restrict__ L,
                                                              int64_t d,
                                                              const int32_t* __restrict__ map,
-                                                             const double* __restrict__ X,
+                                                             int nm, const double* __restrict__ X,
                                                              int64_t ldx, double* __restrict__ Y,
                                                              int64_t ldy) {
-  __shared__ double xs[kTrmvLdsMax];
+  __shared__ double xs[NV][kTrmvLdsMax / NV];
   const int b = blockIdx.y;
   const int64_t r0 = (int64_t)blockIdx.x * kTrmvLRows;
   const int64_t rend = (r0 + kTrmvLRows) < d ? (r0 + kTrmvLRows) : d;
-  for (int64_t k = threadIdx.x; k < rend; k += blockDim.x) xs[k] = X[k * ldx + b];
+  for (int64_t k = threadIdx.x; k < rend; k += blockDim.x)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) xs[v][k] = X[k * ldx + b + v * nm];
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* Lb = L + (int64_t)map[b] * d * d;
   const bool vec = (d & 1) == 0;
   for (int64_t r = r0 + w; r < rend; r += 4) {
     const double* row = Lb + r * d;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s[NV][2];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v][0] = s[v][1] = 0.0;
     int64_t k = 2 * lane;
     if (vec) {
-      for (; k + 384 + 1 <= r; k += 512) {
+      for (; k + 128 + 1 <= r; k += 256) {
         const double2 a0 = *reinterpret_cast<const double2*>(row + k);
         const double2 a1 = *reinterpret_cast<const double2*>(row + k + 128);
-        const double2 a2 = *reinterpret_cast<const double2*>(row + k + 256);
-        const double2 a3 = *reinterpret_cast<const double2*>(row + k + 384);
-        s0 += a0.x * xs[k] + a0.y * xs[k + 1];
-        s1 += a1.x * xs[k + 128] + a1.y * xs[k + 129];
-        s2 += a2.x * xs[k + 256] + a2.y * xs[k + 257];
-        s3 += a3.x * xs[k + 384] + a3.y * xs[k + 385];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          s[v][0] += a0.x * xs[v][k] + a0.y * xs[v][k + 1];
+          s[v][1] += a1.x * xs[v][k + 128] + a1.y * xs[v][k + 129];
+        }
       }
     }
     for (; k <= r; k += 128) {
-      s0 += row[k] * xs[k];
-      if (k + 1 <= r) s1 += row[k + 1] * xs[k + 1];
+      const double a0 = row[k];
+      const double a1 = k + 1 <= r ? row[k + 1] : 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s[v][0] += a0 * xs[v][k] + a1 * xs[v][k + 1 <= r ? k + 1 : k];
     }
-    const double s = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) Y[r * ldy + b] = s;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double t = wave_sum(s[v][0] + s[v][1]);
+      if (lane == 0) Y[r * ldy + b + v * nm] = t;
+    }
   }
 }
 
 // y_b = L_{map[b]}^T x_b, two stages.  Stage 1: one workgroup per (b, 64-column
-// panel, 256-row chunk) streams the chunk's rows r >= c0 of the panel and
-// writes partial sums; stage 2 adds the chunk partials in a fixed order.
+// panel, 256-row chunk) streams the chunk's rows r >= c0 of the panel once for
+// NV vectors and writes partial sums; stage 2 adds the chunk partials in a
+// fixed order.
 constexpr int kTrmvRows = 256;
 
+template <int NV>
 __global__ __launch_bounds__(256) void trmv_upper_t_partial_kernel(
-    const double* __restrict__ L, int64_t d, const int32_t* __restrict__ map, int nb,
+    const double* __restrict__ L, int64_t d, const int32_t* __restrict__ map, int nm,
     const double* __restrict__ X, int64_t ldx, double* __restrict__ part) {
-  __shared__ double red[4][64];
+  __shared__ double red[NV][4][64];
   const int64_t panels = (d + 63) / 64, chunks = (d + kTrmvRows - 1) / kTrmvRows;
   const int64_t job = blockIdx.x;
   const int b = (int)(job / (panels * chunks));
@@ -410,15 +421,26 @@ __global__ __launch_bounds__(256) void trmv_upper_t_partial_kernel(
   const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
   const double* Lb = L + (int64_t)map[b] * d * d;
   const int64_t c = c0 + cc;
-  double s = 0.0;
+  double s[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) s[v] = 0.0;
   if (c < d && r0 + kTrmvRows > c0) {
     const int64_t rs = r0 > c0 ? r0 : c0, re = (r0 + kTrmvRows) < d ? (r0 + kTrmvRows) : d;
-    for (int64_t r = rs + g; r < re; r += 4) s += Lb[r * d + c] * X[r * ldx + b];
+    for (int64_t r = rs + g; r < re; r += 4) {
+      const double a = Lb[r * d + c];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s[v] += a * X[r * ldx + b + v * nm];
+    }
   }
-  red[g][cc] = s;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) red[v][g][cc] = s[v];
   __syncthreads();
-  if (g == 0 && c < d)
-    part[((int64_t)b * chunks + (pc % chunks)) * d + c] = red[0][cc] + red[1][cc] + red[2][cc] + red[3][cc];
+  if (g == 0 && c < d) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      part[((int64_t)(b + v * nm) * chunks + (pc % chunks)) * d + c] =
+          red[v][0][cc] + red[v][1][cc] + red[v][2][cc] + red[v][3][cc];
+  }
 }
 
 __global__ void trmv_upper_t_sum_kernel(const double* __restrict__ part, int64_t d, int nb,
@@ -436,21 +458,36 @@ __global__ void trmv_upper_t_sum_kernel(const double* __restrict__ part, int64_t
 
 void launch_trmv(const double* L, int64_t d, const int32_t* map, int nb, bool transpose,
                  const double* X, int64_t ldx, double* Y, int64_t ldy, double* scratch,
-                 hipStream_t st) {
+                 hipStream_t st, int nv) {
+  if (nv != 1 && nv != 2) fail(IHSBIN_EINVAL, "trmv: nv must be 1 or 2");
+  if (nb % nv) fail(IHSBIN_EINVAL, "trmv: columns not a multiple of nv");
+  const int nm = nb / nv;
   if (!transpose) {
-    if (d <= kTrmvLdsMax && nb <= 65535) {
-      hipLaunchKernelGGL(trmv_lower_lds_kernel, dim3((unsigned)cdiv(d, kTrmvLRows), (unsigned)nb),
-                         dim3(256), 0, st, L, d, map, X, ldx, Y, ldy);
+    if (nv == 2 && d <= kTrmvLdsMax / 2 && nm <= 65535) {
+      hipLaunchKernelGGL(trmv_lower_lds_kernel<2>, dim3((unsigned)cdiv(d, kTrmvLRows), (unsigned)nm),
+                         dim3(256), 0, st, L, d, map, nm, X, ldx, Y, ldy);
+    } else if (d <= kTrmvLdsMax && nb <= 65535) {
+      // one vector per block; the second half of a paired layout reuses map
+      for (int v = 0; v < nv; ++v)
+        hipLaunchKernelGGL(trmv_lower_lds_kernel<1>,
+                           dim3((unsigned)cdiv(d, kTrmvLRows), (unsigned)nm), dim3(256), 0, st, L,
+                           d, map, nm, X + v * nm, ldx, Y + v * nm, ldy);
     } else {
-      int64_t blocks = cdiv(d * nb * 64, 256);
+      int64_t blocks = cdiv(d * nm * 64, 256);
       if (blocks > 65536) blocks = 65536;
-      hipLaunchKernelGGL(trmv_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, d, map,
-                         nb, X, ldx, Y, ldy);
+      for (int v = 0; v < nv; ++v)
+        hipLaunchKernelGGL(trmv_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, d, map,
+                           nm, X + v * nm, ldx, Y + v * nm, ldy);
     }
   } else {
     const int64_t chunks = cdiv(d, kTrmvRows);
-    hipLaunchKernelGGL(trmv_upper_t_partial_kernel, dim3((unsigned)(cdiv(d, 64) * chunks * nb)),
-                       dim3(256), 0, st, L, d, map, nb, X, ldx, scratch);
+    const dim3 grid((unsigned)(cdiv(d, 64) * chunks * nm));
+    if (nv == 2)
+      hipLaunchKernelGGL(trmv_upper_t_partial_kernel<2>, grid, dim3(256), 0, st, L, d, map, nm, X,
+                         ldx, scratch);
+    else
+      hipLaunchKernelGGL(trmv_upper_t_partial_kernel<1>, grid, dim3(256), 0, st, L, d, map, nm, X,
+                         ldx, scratch);
     IHS_CHECK_LAUNCH();
     int64_t blocks = cdiv(d * nb, 256);
     if (blocks > 4096) blocks = 4096;

@@ -32,11 +32,13 @@ void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int64_t ld, i
                          double* alpha, double* beta, hipStream_t st);
 
 // y_b = L_{map[b]} x_b (transpose = false) or L_{map[b]}^T x_b (true) for nb
-// lower-triangular d x d factors; x_b, y_b are columns b of X, Y.
+// lower-triangular d x d factors; x_b, y_b are columns b of X, Y.  nv = 2:
+// columns b and b + nb/2 use the same factor map[b] (map holds nb/2 entries)
+// and each factor is read once for both.
 // scratch: trmv_scratch_doubles(d, nb) doubles (used when transpose is set).
 void launch_trmv(const double* L, int64_t d, const int32_t* map, int nb, bool transpose,
                  const double* X, int64_t ldx, double* Y, int64_t ldy, double* scratch,
-                 hipStream_t st);
+                 hipStream_t st, int nv = 1);
 int64_t trmv_scratch_doubles(int64_t d, int nb);
 
 }  // namespace ihs

@@ -367,16 +367,19 @@ static Ritz ritz_extremes(const std::vector<double>& h, int na, int J, int a, in
   return r;
 }
 
-// Lanczos with full re-orthogonalization on B_l = Linv_l (A^T A + lam0_l I) Linv_l^T.
-// early: when set, the run may stop after a multiple of 6 steps once
-// early(ritz of column 0) returns true (Ritz values bound the spectrum from inside).
+// Lanczos with full re-orthogonalization, one column a per operator
+// B_a = Linv_{ids[a]} (A^T A + shifts[a] I) Linv_{ids[a]}^T.  early: when
+// enabled, the run may stop once early(Ritz extremes of every column) returns
+// true (Ritz values bound the spectrum from inside).
+// nv = 2: columns a and a + na/2 share a factor (ids holds na/2 entries).
 template <class Early>
 static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* Linv_all,
                                        const std::vector<int32_t>& ids,
-                                       const std::vector<double>& lam0_pos, int J, uint64_t seed,
-                                       Early early) {
+                                       const std::vector<double>& shifts, int J, uint64_t seed,
+                                       Early early, int nv = 1) {
   hipStream_t st = c.stream;
-  const int na = (int)ids.size();
+  const int na = (int)shifts.size();
+  if ((int)ids.size() * nv != na) fail(IHSBIN_EINVAL, "spectrum: ids and shifts disagree");
   const int64_t d = A.d;
   if (J < 2) J = 2;
   if (J > d) J = (int)d;
@@ -393,23 +396,25 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
   double* beta = alpha + (size_t)na * J;
   int32_t* ids_dev = static_cast<int32_t*>(idb.ensure(sizeof(int32_t) * na));
   double* lam_dev = static_cast<double*>(lb.ensure(sizeof(double) * na));
-  IHS_HIP(hipMemcpyAsync(ids_dev, ids.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
-  IHS_HIP(hipMemcpyAsync(lam_dev, lam0_pos.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+  IHS_HIP(hipMemcpyAsync(ids_dev, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, st));
+  IHS_HIP(hipMemcpyAsync(lam_dev, shifts.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
   launch_lanczos_start(seed, d, na, ld, Q, st);
   std::vector<double> h(2 * (size_t)na * J);
   int steps = J;
   for (int j = 0; j < J; ++j) {
-    launch_trmv(Linv_all, d, ids_dev, na, true, Q + (size_t)j * d * ld, ld, T, ld, trs, st);  // T = Linv^T q
+    launch_trmv(Linv_all, d, ids_dev, na, true, Q + (size_t)j * d * ld, ld, T, ld, trs, st, nv);  // T = Linv^T q
     ata_apply(c, A, T, na, ld, S, ld, nullptr, ld);  // S = A^T A T
-    launch_add_shift(S, T, d, na, ld, lam_dev, st);   // S += lam0 T
-    launch_trmv(Linv_all, d, ids_dev, na, false, S, ld, Wv, ld, trs, st);                      // W = Linv S
+    launch_add_shift(S, T, d, na, ld, lam_dev, st);   // S += shift T
+    launch_trmv(Linv_all, d, ids_dev, na, false, S, ld, Wv, ld, trs, st, nv);                  // W = Linv S
     launch_lanczos_orth(Q, Wv, d, na, ld, j, J, alpha, beta, st);
-    // a sketch far too small shows within two or three steps (Ritz values
-    // bound the spectrum from inside), so the probe checks after every step
-    if (early.enabled && j + 1 >= 2 && j + 1 < J) {
+    // checked after every step from early.min_steps on (a sketch far too small
+    // shows within two or three steps; converged extremes stop the run)
+    if (early.enabled && j + 1 >= early.min_steps && j + 1 < J) {
       IHS_HIP(hipMemcpyAsync(h.data(), alpha, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
       IHS_HIP(hipStreamSynchronize(st));
-      if (early(ritz_extremes(h, na, J, 0, j + 1))) {
+      std::vector<Ritz> rz(na);
+      for (int a = 0; a < na; ++a) rz[a] = ritz_extremes(h, na, J, a, j + 1);
+      if (early(rz)) {
         steps = j + 1;
         break;
       }
@@ -417,9 +422,13 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
   }
   IHS_HIP(hipMemcpyAsync(h.data(), alpha, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
   IHS_HIP(hipStreamSynchronize(st));
+  logf("lanczos: %d columns, %d of %d steps", na, steps, J);
   std::vector<Spec> out(na);
   for (int a = 0; a < na; ++a) {
     const Ritz rz = ritz_extremes(h, na, J, a, steps);
+    if (log_enabled() && (a % 8 == 0 || a == na - 1))
+      logf("  column %d: ritz [%.6g, %.6g] residual bounds [%.3g, %.3g]", a, rz.tmin, rz.tmax,
+           rz.rmin, rz.rmax);
     Spec sp;
     sp.mu_max = (rz.tmax + rz.rmax) * 1.02;
     sp.mu_min = std::max(rz.tmin - rz.rmin, 0.5 * rz.tmin);
@@ -432,22 +441,46 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
 
 struct NoEarly {
   bool enabled = false;
-  bool operator()(const Ritz&) const { return false; }
+  int min_steps = 0;
+  bool operator()(const std::vector<Ritz>&) const { return false; }
 };
+// Columns 0 and 1 hold the lower and upper end of one interval: the Ritz
+// values lie inside the spectra, so their rate is a lower bound.
 struct EarlyIfSlow {
   bool enabled = true;
-  double lo, hi, lam0, target;
-  bool operator()(const Ritz& r) const {
-    // the Ritz interval lies inside the spectrum: its rate is a lower bound
-    const double cmin = r.tmin * lo / lam0, cmax = r.tmax * hi / lam0;
+  int min_steps = 2;
+  double target;
+  bool operator()(const std::vector<Ritz>& r) const {
+    const double cmin = r[0].tmin, cmax = r[1].tmax;
     return (cmax - cmin) / (cmax + cmin) > target;
   }
 };
 
-static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* Linv_all,
-                                       const std::vector<int32_t>& ids,
-                                       const std::vector<double>& lam0_pos, int J, uint64_t seed) {
-  return spectrum_impl(c, A, Linv_all, ids, lam0_pos, J, seed, NoEarly{});
+// Spectrum bounds over whole intervals.  In the symmetric form
+// Linv (A^T A + lam I) Linv^T = B_0 + lam Linv Linv^T every Rayleigh quotient
+// grows with lam, so for lam in [lo, hi] the spectrum of P_S (A^T A + lam I)
+// lies between the smallest eigenvalue at lo and the largest at hi.  One
+// Lanczos column per interval end; fids[i] is the factor of interval i.
+template <class Early>
+static std::vector<Spec> interval_spectra(Ctx& c, const MatView& A, const double* Linv_all,
+                                          const std::vector<int32_t>& fids,
+                                          const std::vector<double>& los,
+                                          const std::vector<double>& his, int J, uint64_t seed,
+                                          Early early) {
+  const int ni = (int)fids.size();
+  std::vector<double> shifts(2 * ni);
+  for (int i = 0; i < ni; ++i) {
+    shifts[i] = los[i];
+    shifts[ni + i] = his[i];
+  }
+  const std::vector<Spec> col = spectrum_impl(c, A, Linv_all, fids, shifts, J, seed, early, 2);
+  std::vector<Spec> out(ni);
+  for (int i = 0; i < ni; ++i) {
+    out[i].mu_min = col[i].mu_min;
+    out[i].mu_max = col[ni + i].mu_max;
+    if (!(out[i].mu_max > out[i].mu_min)) fail(IHSBIN_ENOTSPD, "spectrum estimate failed");
+  }
+  return out;
 }
 
 struct Timer {
@@ -512,17 +545,13 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     ++trials;
   };
   // Predicted contraction rate of interval l from its spectrum estimate.
-  auto rate_of = [&](const Spec& sp, int l) {
-    const double cmin = sp.mu_min * grid[l] / lam0[l], cmax = sp.mu_max * grid[l + 1] / lam0[l];
-    return (cmax - cmin) / (cmax + cmin);
-  };
+  auto rate_of = [&](const Spec& sp) { return (sp.mu_max - sp.mu_min) / (sp.mu_max + sp.mu_min); };
   // Next m when the lowest interval is too slow: the Gaussian theorem's edges
   // (1 -+ sqrt(rho))^2 with rho ~ d_e / m give rho from the measured condition
   // number; m is scaled (by a power of two in [2, 16]) to reach rate_target.
   auto grow = [&](const Spec& sp) {
     const double kap = sp.mu_max / sp.mu_min;
-    const double g = grid[1] / grid[0];
-    const double kt = (1.0 + o.rate_target) / ((1.0 - o.rate_target) * g);
+    const double kt = (1.0 + o.rate_target) / (1.0 - o.rate_target);
     double factor = 16.0;
     if (kt > 1.0 && kap > 1.0) {
       const double so = (std::sqrt(kap) - 1.0) / (std::sqrt(kap) + 1.0);
@@ -548,14 +577,12 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
     factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb);
     EarlyIfSlow early;
-    early.lo = grid[0];
-    early.hi = grid[1];
-    early.lam0 = lam0[0];
     early.target = o.rate_target;
-    auto sp = spectrum_impl(c, A, Li1, {0}, {lam0[0]}, std::max(8, o.lanczos_steps), o.seed, early);
-    logf("probe m=%lld: mu=[%.4g, %.4g] rate0=%.3f (target %.3f)", (long long)m, sp[0].mu_min,
-         sp[0].mu_max, rate_of(sp[0], 0), o.rate_target);
-    if (rate_of(sp[0], 0) <= o.rate_target) break;
+    auto sp = interval_spectra(c, A, Li1, {0}, {grid[0]}, {grid[1]}, std::max(8, o.lanczos_steps),
+                               o.seed, early);
+    logf("probe m=%lld: c=[%.4g, %.4g] rate0=%.3f (target %.3f)", (long long)m, sp[0].mu_min,
+         sp[0].mu_max, rate_of(sp[0]), o.rate_target);
+    if (rate_of(sp[0]) <= o.rate_target) break;
     const int64_t m_new = cheap_sketch ? m_cap : grow(sp[0]);
     if (m_new <= m) break;
     m = m_new;
@@ -580,11 +607,13 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     IHS_HIP(hipStreamSynchronize(st));
     r.ms_factor += tf.ms();
     Timer tspec;
-    spec = spectrum_impl(c, A, Linv, all, lam0, std::max(2, o.lanczos_steps), o.seed + 1);
+    spec = interval_spectra(c, A, Linv, all, std::vector<double>(grid.begin(), grid.end() - 1),
+                            std::vector<double>(grid.begin() + 1, grid.end()),
+                            std::max(2, o.lanczos_steps), o.seed + 1, NoEarly{});
     r.ms_spectrum += tspec.ms();
     // the batched estimate of the lowest interval can still be well above the
     // probe's (different start vector): grow once more in that case
-    if (adapt && m < m_cap && trials < 6 && rate_of(spec[0], 0) > o.rate_target + 0.1) {
+    if (adapt && m < m_cap && trials < 6 && rate_of(spec[0]) > o.rate_target + 0.1) {
       const int64_t m_new = grow(spec[0]);
       if (m_new > m) {
         Timer t2;
@@ -602,7 +631,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   r.m_used = m;
   r.sketch_trials = trials;
   for (int l = 0; l < L && log_enabled(); ++l)
-    logf("interval %d [%.4g, %.4g]: mu=[%.4g, %.4g]", l, grid[l], grid[l + 1], spec[l].mu_min,
+    logf("interval %d [%.4g, %.4g]: c=[%.4g, %.4g]", l, grid[l], grid[l + 1], spec[l].mu_min,
          spec[l].mu_max);
   if (o.taus) {
     for (int l = 0; l < L; ++l) {
@@ -611,8 +640,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     }
   }
   for (int l = 0; l < L; ++l) {
-    const double cmin = spec[l].mu_min * grid[l] / lam0[l];
-    const double cmax = spec[l].mu_max * grid[l + 1] / lam0[l];
+    const double cmin = spec[l].mu_min, cmax = spec[l].mu_max;
     if (!o.taus) tau[l] = 2.0 / (cmin + cmax);
     const double rr = std::max(std::fabs(1.0 - tau[l] * cmin), std::fabs(1.0 - tau[l] * cmax));
     rate[l] = std::min(rr, 0.999);

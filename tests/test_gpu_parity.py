@@ -260,8 +260,9 @@ def test_run_twice_identical(torch, ctx):
 
 
 def test_step_sizes_close_to_exact_spectrum(torch, ctx):
-    # the Lanczos estimate of [mu_min, mu_max] gives tau close to the exact
-    # minimax step (slightly smaller: mu_max is raised by its residual bound)
+    # the Lanczos estimates at the interval ends give tau close to the exact
+    # minimax step over the interval (slightly smaller: the largest eigenvalue
+    # is raised by its residual bound)
     A = W.dense_decay(900, 48, seed=71)
     B, _ = W.rhs(A, 1, 0.1, seed=72)
     lo, hi = 1e-2, 1e1
@@ -272,8 +273,8 @@ def test_step_sizes_close_to_exact_spectrum(torch, ctx):
     op = ihs_bin.Operator(A)
     for l in range(len(iv["lam0"])):
         P = ihs_bin.Precond(SA, iv["lam0"][l])
-        mu_min, mu_max = ihs_bin.spectrum_bounds(op, P)
-        tau_exact, rate_exact = ihs_bin.step_size(mu_min, mu_max, iv["lo"][l], iv["hi"][l], iv["lam0"][l])
+        tau_exact, rate_exact = ihs_bin.step_size_from_bounds(
+            *ihs_bin.interval_bounds(op, P, iv["lo"][l], iv["hi"][l]))
         assert 0.9 * tau_exact <= iv["tau"][l] <= 1.0 * tau_exact, (l, iv["tau"][l], tau_exact)
         assert iv["rate"][l] >= rate_exact - 1e-9
     path.free()
