@@ -30,12 +30,30 @@ if ROOT not in sys.path:
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix, flop/s
 HBM_PEAK = 8.0e12          # bytes/s
 
-# HBM bytes per launch of the A^T A product GEMMs on the default workload, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy calibration
-# (profiles/gemm_ata_traffic_dense_131072x2048.md).  Valid for the kernel
-# version below; reported as null for other workloads.
+# HBM bytes per launch of the A^T A product GEMMs on the default workload come
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
+# calibration, recorded in the profile summary below together with the sha256
+# of the GEMM source they were measured on.  When that source has changed
+# since (or for another workload) the figure is stale and reported as null.
 TRAFFIC_WORKLOAD = "dense_exp300_131072x2048"
-TRAFFIC_BYTES_PER_LAUNCH = {"gemm_y_AU": 1.520e9, "gemm_w_AtY": 1.555e9}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_ata_traffic_dense_131072x2048.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2210_12212_amd", "csrc", "gemm.hip")
+
+
+def recorded_traffic(kernel):
+    """Measured HBM bytes per launch of `kernel`, or None when stale/absent."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"gemm\.hip sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != src:
+        return None
+    m = re.search(r"bytes per launch %s: ([0-9.eE+]+)" % re.escape(kernel), text)
+    return float(m.group(1)) if m else None
 
 
 def log(msg):
@@ -124,7 +142,7 @@ def main():
     dom = "gemm_y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "gemm_w_AtY"
     dom_ms = max(rep["ata_ms_y"], rep["ata_ms_w"])
     achieved = (half_flops / launches) / (dom_ms / launches * 1e-3) / 1e12 if dom_ms > 0 else 0.0
-    traffic = TRAFFIC_BYTES_PER_LAUNCH.get(dom) if p.name == TRAFFIC_WORKLOAD and args.n is None else None
+    traffic = recorded_traffic(dom) if p.name == TRAFFIC_WORKLOAD and args.n is None else None
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                 "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": traffic,

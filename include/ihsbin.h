@@ -119,8 +119,8 @@ typedef struct {
   int64_t ata_launches;    /* launches of each of the two product kernels        */
   double ata_flops;        /* algorithmic flops of all those launches (4*nnz*w)  */
   double ata_ms_y;         /* summed event time of the Y = A U launches          */
-  double ata_ms_w;         /* summed event time of the W = A^T Y launches (incl.
-                              the split-K reduction)                             */
+  double ata_ms_w;         /* summed event time of the W = A^T Y launches (the
+                              product kernel; its split-K reduction excluded)   */
   double ata_bytes_a;      /* algorithmic bytes of A read by those launches      */
 } ihsbin_report;
 

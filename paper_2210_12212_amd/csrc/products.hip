@@ -189,17 +189,19 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
         g2.strideC = A.d * cw;
         g2.splits = splits;
         gemm_cols(g2, ta, true, ct, st);
+        mark();  // the timed span is the product kernel itself
         reduce_splits(part, splits, 1, A.d, cw, cw, A.d * cw, W + c0, ldw, 0, 1.0, 0.0, st);
       } else {
         g2.C = W + c0;
         g2.ldc = ldw;
         gemm_cols(g2, ta, true, ct, st);
+        mark();
       }
     } else {
       zero_block(W + c0, A.d, cw, ldw, st);
       launch_csr_spmm_t(A, Y, cw, cw, W + c0, ldw, st);
+      mark();
     }
-    mark();
   }
   return w;
 }
