@@ -151,6 +151,24 @@ def main():
                 "avg_launch_ms": dom_ms / launches,
                 "ata_ms_y": rep["ata_ms_y"], "ata_ms_w": rep["ata_ms_w"]}
 
+    # marginal cost of a lambda on a resident basis (outside the timed region):
+    # evaluation only, for the workload's T and for a dense grid of 100000 lambdas
+    path, _ = ctx.path_build(A, B, p.lam_min, p.lam_max, **opts)
+    eval_only = {}
+    for name, lams in (("T", p.lambdas), ("dense_100000", W.lambda_grid(p.lam_min, p.lam_max, 100000))):
+        out = torch.empty((len(lams), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
+        path.eval(lams, out=out)
+        torch.cuda.synchronize()
+        reps = 20 if len(lams) < 10000 else 3
+        te = time.perf_counter()
+        for _ in range(reps):
+            path.eval(lams, out=out)
+        torch.cuda.synchronize()
+        eval_only[name] = round(len(lams) * reps / (time.perf_counter() - te), 1)
+        del out
+    path.free()
+    log(f"[bench] eval only: {eval_only} lambda-solves/s")
+
     # accuracy on sampled lambdas, and the oracle timed on the host (outside the timed region)
     Xh = X.cpu().numpy()
     cpu = None
@@ -199,6 +217,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phase_ms": {k: rep[k] for k in ("ms_sketch", "ms_factor", "ms_spectrum", "ms_basis",
                                          "ms_total")},
+        "eval_only_lambda_solves_per_s": eval_only,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
