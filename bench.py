@@ -60,6 +60,30 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def ata_sweep(args, torch, W, Context):
+    """Time W = A^T A U through the C ABI at the widths the basis steps use."""
+    p = W.make(args.workload, n=args.n)
+    dev = torch.device("cuda", 0)
+    A = torch.from_numpy(p.A).to(dev)
+    ctx = Context(0)
+    g = torch.Generator(device=dev).manual_seed(7)
+    print(f"# W = A^T A U on {p.name} (n={p.n}, d={p.d}, {p.A.dtype}); flops 4 n d w per call")
+    print("| w | ms per call | TFLOP/s |\n|---:|---:|---:|")
+    for w in (16, 23, 32, 46, 48, 64, 69, 80, 92, 96, 115, 128, 138, 161, 184, 207, 230, 253, 256):
+        ldu = 16 if w <= 16 else 32 if w <= 32 else (w + 63) // 64 * 64
+        U = torch.randn((p.d, ldu), generator=g, device=dev, dtype=torch.float64)[:, :w]
+        ctx.ata_apply(A, U)
+        torch.cuda.synchronize()
+        reps = 5
+        t = time.perf_counter()
+        for _ in range(reps):
+            ctx.ata_apply(A, U)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        print(f"| {w} | {ms:.3f} | {4.0 * p.n * p.d * w / ms / 1e9:.1f} |", flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +99,8 @@ def main():
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--ata-sweep", action="store_true",
+                    help="only time the A^T A product (ihsbin_ata_apply) at basis-step widths")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is built and "
@@ -95,6 +121,10 @@ def main():
         return
     import workloads as W
     from paper_2210_12212_amd import Context
+
+    if args.ata_sweep:
+        ata_sweep(args, torch, W, Context)
+        return
 
     t0 = time.time()
     p = W.make(args.workload, n=args.n)

@@ -223,7 +223,10 @@ int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m,
                           double* Lfac, double* Linv);
 
 /* W = A^T A U: the two products of every basis step (Algorithm 2).  U: device
- * d x w doubles (row stride ldu), W: device d x w doubles (row stride ldw). */
+ * d x w doubles with row stride ldu; the buffer spans d * ldu doubles, and
+ * columns [w, ldu) may be read (their values are ignored) so that ragged
+ * widths run whole column tiles.  W: device d x w doubles (row stride ldw);
+ * only columns [0, w) are written. */
 int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U,
                      int64_t w, int64_t ldu, double* W, int64_t ldw);
 

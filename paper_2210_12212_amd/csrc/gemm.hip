@@ -402,8 +402,10 @@ void gemm_cols(const Gemm& g_in, DT ta, bool transA, const ColTiles& ct, hipStre
 }
 
 int pick_splits_cols(int64_t M, const ColTiles& ct, int64_t K, int64_t target) {
+  // rounded down: a grid just above a whole number of resident rounds leaves
+  // a nearly empty last round (22 splits of 48 tiles ran 17 % slower than 21)
   const int64_t tiles = cdiv(M, 128) * ct.c;
-  int64_t sp = cdiv(target, tiles);
+  int64_t sp = target / tiles;
   const int64_t kt = cdiv(K, 16);
   if (sp > kt / 8) sp = kt / 8;
   if (sp < 1) sp = 1;

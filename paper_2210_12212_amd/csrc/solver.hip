@@ -1088,7 +1088,7 @@ int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U, i
     const MatView v = check_matrix(A);
     if (!U || !W || w < 1 || ldu < w || ldw < w) fail(IHSBIN_EINVAL, "bad U / W");
     if (v.format == IHSBIN_CSR) validate_csr(ctx->c, v);
-    ata_apply(ctx->c, v, U, w, ldu, W, ldw, nullptr);
+    ata_apply(ctx->c, v, U, w, ldu, W, ldw, nullptr, ldu);
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
     return IHSBIN_OK;
   });

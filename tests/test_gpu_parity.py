@@ -53,6 +53,23 @@ def test_ata_dense(torch, ctx, dt, n, d, w):
     np.testing.assert_allclose(Wg, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("w,ldu", [(23, 32), (69, 128), (138, 192), (253, 256)])
+def test_ata_ragged_width_ignores_padding(torch, ctx, w, ldu):
+    # columns [w, ldu) of U are read by whole column tiles but must not matter:
+    # they hold NaN here, and only columns [0, w) of W are written
+    r = np.random.default_rng(w)
+    A = r.standard_normal((3000, 200)).astype(np.float32)
+    Ufull = r.standard_normal((200, ldu))
+    Ufull[:, w:] = np.nan
+    Ut = dev(torch, Ufull)[:, :w]
+    assert Ut.stride(0) == ldu
+    Wg = ctx.ata_apply(dev(torch, A), Ut).cpu().numpy()
+    A64 = A.astype(np.float64)
+    ref = A64.T @ (A64 @ Ufull[:, :w])
+    assert np.isfinite(Wg).all()
+    np.testing.assert_allclose(Wg, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
 def test_ata_csr(torch, ctx):
     M = W.csr_zipf(2000, 300, 7, seed=3, dtype=np.float32)
     U = np.random.default_rng(1).standard_normal((300, 9))
