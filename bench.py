@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs)")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--rate-target", type=float, default=0.5)
-    ap.add_argument("--lanczos-steps", type=int, default=8)
+    ap.add_argument("--lanczos-steps", type=int, default=6)
     ap.add_argument("--oracle-lambdas", type=int, default=12,
                     help="lambdas of the sample solved by the CPU oracle")
     ap.add_argument("--no-oracle", action="store_true")

@@ -40,17 +40,23 @@ void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, in
 // Factor diagonal block p of every matrix, write L_pp back (upper part zeroed)
 // and its inverse into dinv[l][p].  Thread (r, q) keeps row r, columns
 // q, q + 4, ..., q + 60 of the block in registers; each column step publishes
-// one column (factorization) or one row (inversion) through LDS, so a step
-// costs one barrier and up to sixteen independent LDS reads.  The steps are
+// one column (factorization) or one row (inversion) through LDS and costs one
+// barrier and at most four register updates (its 16-column panel); each
+// panel's rank-16 update of the rest follows in one pass.  The steps are
 // expanded at compile time so the register slots are addressed statically.
 namespace {
 constexpr int kS = kNB / 4;
 
+// The 64 columns are taken in four panels of 16.  Inside a panel a column
+// step updates only the panel's own columns; the columns right of the panel
+// receive the panel's rank-16 update once, after its last step.
+
 // factorization step j: owners publish column j; every row scales its entry
-// into L[r][j] and updates its columns c in (j, r]
+// into L[r][j] and updates its panel columns c in (j, r]
 template <int J>
 __device__ __forceinline__ void potrf_step(double (&a)[kS], double (*colbuf)[kNB], int r, int q,
                                            bool& bad) {
+  constexpr int SEND = 4 * (J / 16) + 4;  // slots of the panel holding column J
   double* col = colbuf[J & 1];
   if (q == (J & 3)) col[r] = a[J >> 2];
   __syncthreads();
@@ -64,18 +70,40 @@ __device__ __forceinline__ void potrf_step(double (&a)[kS], double (*colbuf)[kNB
   const double lrj = r >= J ? col[r] * rpiv : 0.0;
   if (q == (J & 3)) a[J >> 2] = lrj;
 #pragma unroll
-  for (int s = J >> 2; s < kS; ++s) {
+  for (int s = J >> 2; s < SEND; ++s) {
     const int c = q + 4 * s;
     const double upd = lrj * (col[c] * rpiv);  // select, not branch: lanes differ in c
     a[s] -= (c > J && c <= r) ? upd : 0.0;
   }
 }
 
+// after panel P: a[r][c] -= sum_k L[r][16P+k] L[c][16P+k] for columns c right
+// of the panel (the panel is published to lp first)
+template <int P>
+__device__ __forceinline__ void potrf_panel_update(double (&a)[kS], double (*lp)[17], int r,
+                                                   int q) {
+#pragma unroll
+  for (int s = 4 * P; s < 4 * P + 4; ++s) lp[r][q + 4 * s - 16 * P] = a[s];
+  __syncthreads();
+  double lr[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) lr[k] = lp[r][k];
+#pragma unroll
+  for (int s = 4 * P + 4; s < kS; ++s) {
+    const int c = q + 4 * s;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += lr[k] * lp[c][k];
+    a[s] -= c <= r ? acc : 0.0;
+  }
+}
+
 // inversion step i: row i of X = L^-1 becomes final and is published; rows
-// below accumulate L[r][i] X[i]
+// below it inside the panel accumulate L[r][i] X[i]
 template <int I>
 __device__ __forceinline__ void trinv_step(double (&x)[kS], double (*rowbuf)[kNB],
                                            const double (*lf)[kNB + 1], int r, int q) {
+  constexpr int PEND = 16 * (I / 16) + 16;  // first row after the panel
   double* row = rowbuf[I & 1];
   if (r == I) {
     const double rlii = 1.0 / lf[I][I];
@@ -87,7 +115,7 @@ __device__ __forceinline__ void trinv_step(double (&x)[kS], double (*rowbuf)[kNB
     }
   }
   __syncthreads();
-  if (r > I) {
+  if (r > I && r < PEND) {
     const double lri = lf[r][I];
 #pragma unroll
     for (int s = 0; s <= (I >> 2); ++s) {
@@ -98,17 +126,46 @@ __device__ __forceinline__ void trinv_step(double (&x)[kS], double (*rowbuf)[kNB
   }
 }
 
-template <int... J>
-__device__ __forceinline__ void potrf_all(std::integer_sequence<int, J...>, double (&a)[kS],
-                                          double (*colbuf)[kNB], int r, int q, bool& bad) {
-  (potrf_step<J>(a, colbuf, r, q, bad), ...);
+// after row panel P of X is final: rows below it accumulate
+// sum_k L[r][16P+k] X[16P+k][c] for c <= 16P+15 (X rows published to xp)
+template <int P>
+__device__ __forceinline__ void trinv_panel_update(double (&x)[kS], double (*xp)[kNB + 1],
+                                                   const double (*lf)[kNB + 1], int r, int q) {
+  if (r >= 16 * P && r < 16 * P + 16) {
+#pragma unroll
+    for (int s = 0; s < 4 * P + 4; ++s) xp[r - 16 * P][q + 4 * s] = x[s];
+  }
+  __syncthreads();
+  if (r >= 16 * P + 16) {
+    double lr[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) lr[k] = lf[r][16 * P + k];
+#pragma unroll
+    for (int s = 0; s < 4 * P + 4; ++s) {
+      const int c = q + 4 * s;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += lr[k] * xp[k][c];
+      x[s] += acc;
+    }
+  }
+  __syncthreads();  // xp is rewritten by the next panel
 }
 
-template <int... I>
-__device__ __forceinline__ void trinv_all(std::integer_sequence<int, I...>, double (&x)[kS],
-                                          double (*rowbuf)[kNB], const double (*lf)[kNB + 1],
-                                          int r, int q) {
-  (trinv_step<I>(x, rowbuf, lf, r, q), ...);
+template <int P, int... J>
+__device__ __forceinline__ void potrf_panel(std::integer_sequence<int, J...>, double (&a)[kS],
+                                            double (*colbuf)[kNB], double (*lp)[17], int r, int q,
+                                            bool& bad) {
+  (potrf_step<16 * P + J>(a, colbuf, r, q, bad), ...);
+  if constexpr (P < 3) potrf_panel_update<P>(a, lp, r, q);
+}
+
+template <int P, int... I>
+__device__ __forceinline__ void trinv_panel(std::integer_sequence<int, I...>, double (&x)[kS],
+                                            double (*rowbuf)[kNB], double (*xp)[kNB + 1],
+                                            const double (*lf)[kNB + 1], int r, int q) {
+  (trinv_step<16 * P + I>(x, rowbuf, lf, r, q), ...);
+  if constexpr (P < 3) trinv_panel_update<P>(x, xp, lf, r, q);
 }
 }  // namespace
 
@@ -118,6 +175,9 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, i
   static_assert(NB == 64, "register layout assumes 64 x 64 blocks and 256 threads");
   __shared__ double colbuf[2][NB];
   __shared__ double lf[NB][NB + 1];
+  __shared__ double pbuf[NB * (NB + 1)];  // panel exchange (lp: 64 x 17, xp: 16 x 65)
+  auto lp = reinterpret_cast<double (*)[17]>(pbuf);
+  auto xp = reinterpret_cast<double (*)[NB + 1]>(pbuf);
   const int l = blockIdx.x;
   double* M = H + (int64_t)l * d * d;
   const int64_t o = (int64_t)p * NB;
@@ -131,7 +191,11 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, i
     a[s] = (c <= r) ? ((r < nb && c < nb) ? M[(o + r) * d + o + c] : (r == c ? 1.0 : 0.0)) : 0.0;
   }
   bool bad = false;
-  potrf_all(std::make_integer_sequence<int, NB>{}, a, colbuf, r, q, bad);
+  const auto seq16 = std::make_integer_sequence<int, 16>{};
+  potrf_panel<0>(seq16, a, colbuf, lp, r, q, bad);
+  potrf_panel<1>(seq16, a, colbuf, lp, r, q, bad);
+  potrf_panel<2>(seq16, a, colbuf, lp, r, q, bad);
+  potrf_panel<3>(seq16, a, colbuf, lp, r, q, bad);
   if (bad) status[0] = 1;
 #pragma unroll
   for (int s = 0; s < kS; ++s) {
@@ -143,7 +207,10 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, i
 #pragma unroll
   for (int s = 0; s < kS; ++s) x[s] = 0.0;
   __syncthreads();
-  trinv_all(std::make_integer_sequence<int, NB>{}, x, colbuf, lf, r, q);
+  trinv_panel<0>(seq16, x, colbuf, xp, lf, r, q);
+  trinv_panel<1>(seq16, x, colbuf, xp, lf, r, q);
+  trinv_panel<2>(seq16, x, colbuf, xp, lf, r, q);
+  trinv_panel<3>(seq16, x, colbuf, xp, lf, r, q);
   double* Di = dinv + ((int64_t)l * nblk + p) * NB * NB;
 #pragma unroll
   for (int s = 0; s < kS; ++s) {

@@ -564,14 +564,22 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     return std::min(m_cap, m * mult);
   };
   const bool adapt = o.adaptive_m && !o.taus;
+  // Sketches whose cost does not grow with m (SRHT: one transform;
+  // CountSketch/SJLT: one pass over A) only pay for m through the 2 m d^2
+  // Gram.  With m < d such a sketch leaves P_S = 1/lam0 on the null space of
+  // SA (dimension >= d - m), plain scaling there, so they start at the cap
+  // without a probe; with m >= d the probe below decides.
+  const bool cheap_sketch = o.sketch != IHSBIN_GAUSSIAN;
+  if (adapt && cheap_sketch && m < d && m < m_cap) {
+    logf("m=%lld < d=%lld: starting at the cap m=%lld", (long long)m, (long long)d,
+         (long long)m_cap);
+    m = m_cap;
+  }
   sketch_m(m);
   // Probe: factor and estimate the lowest interval only (the Lanczos run stops
   // early once its Ritz values already show a rate above the target).  When m
-  // is too small, sketches whose cost does not grow with m (SRHT: one
-  // transform; CountSketch/SJLT: one pass over A) go straight to the cap, since
-  // m then only enters through the 2 m d^2 Gram; the Gaussian sketch costs
-  // 2 m n d, so it grows by the measured factor and is probed again.
-  const bool cheap_sketch = o.sketch != IHSBIN_GAUSSIAN;
+  // is too small, cheap sketches go straight to the cap; the Gaussian sketch
+  // costs 2 m n d, so it grows by the measured factor and is probed again.
   while (adapt && m < m_cap && trials < 6) {
     double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
