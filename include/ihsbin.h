@@ -107,7 +107,8 @@ typedef struct {
 
 /* Filled by ihsbin_path_build. */
 typedef struct {
-  int64_t m_used;          /* final sketch dimension                             */
+  int64_t m_used;          /* final sketch dimension (n when a sketch of m >= n
+                              rows was replaced by S = I, the exact Hessian)    */
   int32_t L;               /* number of intervals                                */
   int32_t k_max_used;      /* largest k over intervals                           */
   int32_t k_sum;           /* sum of k over intervals                            */
@@ -130,6 +131,7 @@ typedef struct {
   int64_t d, m_used;
   double lam_min, lam_max;
   int32_t centred;
+  int32_t dual;            /* 1: n < d, built on the dual problem (Section 5.2) */
 } ihsbin_path_info;
 
 /* ------------------------------------------------------------------ calls */
@@ -160,10 +162,15 @@ const char* ihsbin_last_error(const ihsbin_ctx* ctx);
 /* Build the lambda-independent basis for [lam_min, lam_max] (Algorithm 3
  * with the basis hoisted out of the lambda loop; Algorithm 6 for K > 1).
  * B: device, n x K row-major with row stride ldb (>= K), dtype of A.
+ * n < d (dense A only): the basis is built on the dual problem of Section
+ * 5.2, (A A^T + lam I) z = b with x = A^T z; sketch, factors and step sizes
+ * then live in R^n, the stored basis is mapped to x, and the stop test
+ * measures the dual iterate.  The path reports dual = 1.
  * On success *path owns the basis on the device.  report may be NULL.
- * Errors: EINVAL (0 < lam_min <= lam_max violated, sizes), EUNSUP (n < d),
- * ENOTSPD, ENOMEM, EHIP.  ENOCONV: some interval reached k_max; *path is
- * still returned and usable (its error estimate is in the report). */
+ * Errors: EINVAL (0 < lam_min <= lam_max violated, sizes), EUNSUP (n < d
+ * with a CSR matrix), ENOTSPD, ENOMEM, EHIP.  ENOCONV: some interval reached
+ * k_max; *path is still returned and usable (its error estimate is in the
+ * report). */
 int ihsbin_path_build(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
                       int64_t K, int64_t ldb, double lam_min, double lam_max,
                       const ihsbin_opts* opts, ihsbin_path** path,

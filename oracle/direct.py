@@ -70,6 +70,31 @@ def ridge_path(A, B, lambdas) -> np.ndarray:
     return solve_from_gram(gram(A), atb(A, B), lambdas)
 
 
+def ridge_path_dual(A, B, lambdas, chunk: int = 1 << 14) -> np.ndarray:
+    """The same exact path for n < d through the dual problem of Section 5.2:
+    x*(lam) = A^T (A A^T + lam I)^-1 b (the dual optimality condition and the
+    primal map x = A^T z), with the n x n matrix A A^T formed in FP64 column
+    chunk by column chunk.  Returns T x d x K."""
+    A64 = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    if B.ndim == 1:
+        B = B[:, None]
+    n, d = A64.shape
+    K = np.zeros((n, n))
+    for c0 in range(0, d, chunk):
+        blk = A64[:, c0:c0 + chunk]
+        K += blk @ blk.T
+    lambdas = np.atleast_1d(np.asarray(lambdas, dtype=np.float64))
+    out = np.empty((len(lambdas), d, B.shape[1]))
+    for t, lam in enumerate(lambdas):
+        H = K.copy()
+        H[np.diag_indices(n)] += lam
+        Z = sla.cho_solve(sla.cho_factor(H, lower=True, check_finite=False), B,
+                          check_finite=False)
+        out[t] = A64.T @ Z
+    return out
+
+
 def rel_err(X_hat, X_ref) -> np.ndarray:
     """Per-lambda relative Frobenius error ||X_hat - X_ref|| / ||X_ref||."""
     X_hat = np.asarray(X_hat, dtype=np.float64).reshape(X_ref.shape)

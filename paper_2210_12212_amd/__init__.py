@@ -238,6 +238,7 @@ class Path:
             raise IhsbinError(rc, "ihsbin_path_get_info")
         self.L, self.K, self.d, self.m_used = info.L, info.K, info.d, info.m_used
         self.lam_min, self.lam_max, self.centred = info.lam_min, info.lam_max, info.centred
+        self.dual = info.dual
 
     def eval(self, lambdas, out=None, dtype=None):
         """ihsbin_path_eval -> X (T x d x K)."""

@@ -56,7 +56,8 @@ class Report(C.Structure):
 
 class PathInfo(C.Structure):
     _fields_ = [("L", C.c_int32), ("K", C.c_int32), ("d", C.c_int64), ("m_used", C.c_int64),
-                ("lam_min", C.c_double), ("lam_max", C.c_double), ("centred", C.c_int32)]
+                ("lam_min", C.c_double), ("lam_max", C.c_double), ("centred", C.c_int32),
+                ("dual", C.c_int32)]
 
 
 def _declare(lib):

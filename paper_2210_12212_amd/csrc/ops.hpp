@@ -10,6 +10,8 @@ namespace ihs {
 // CountSketch / SJLT draws: idx[i*s + b], sign[i*s + b] for row i, block b.
 void launch_draw_countsketch(uint64_t seed, int64_t n, int64_t m, int s, int32_t* idx,
                              int8_t* sign, hipStream_t st);
+// idx[i] = i, sign[i] = +1 (row i to row i: the identity as a CountSketch)
+void launch_identity_draws(int64_t n, int32_t* idx, int8_t* sign, hipStream_t st);
 // SRHT draws: sign[i] for i < n, rows[k] in [0, npad) for k < m.
 void launch_draw_srht(uint64_t seed, int64_t n, int64_t npad, int64_t m, int8_t* sign,
                       int32_t* rows, hipStream_t st);
@@ -48,6 +50,11 @@ constexpr int kNB = 64;
 // (their values are ignored): the dense GEMMs then run ragged widths on the
 // unchecked load path.  padded_width(w) (16, 32 or a multiple of 64) bounds
 // the columns read.  Only columns [0, w) of W are written; returns w.
+// Dual (n < d) helpers: At = A^T (d x n row-major, A's dtype; dense A only)
+// and C = B widened to FP64 (rows x K contiguous).
+void launch_transpose(const MatView& A, void* At, hipStream_t st);
+void launch_widen_rows(const void* B, int dtype, int64_t rows, int64_t K, int64_t ldb, double* C,
+                       hipStream_t st);
 int64_t padded_width(int64_t w);
 int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
                   int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0);

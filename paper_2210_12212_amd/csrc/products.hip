@@ -116,6 +116,61 @@ void launch_csr_atb(const MatView& A, const void* B, int64_t K, int64_t ldb, dou
   IHS_CHECK_LAUNCH();
 }
 
+// ------------------------------------------------ dual (n < d) helpers
+// At = A^T (d x n row-major, ld n) through 32 x 32 LDS tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ A, int64_t n,
+                                                        int64_t d, int64_t lda, T* __restrict__ At) {
+  __shared__ T tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    if (r < n && c < d) tile[k][tx] = A[r * lda + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (r < n && c < d) At[c * n + r] = tile[tx][k];
+  }
+}
+
+void launch_transpose(const MatView& A, void* At, hipStream_t st) {
+  if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "transpose of a CSR matrix");
+  const unsigned gy = (unsigned)cdiv(A.n, 32), gx = (unsigned)cdiv(A.d, 32);
+  if (gy > 65535u) fail(IHSBIN_EUNSUP, "transpose: too many rows");
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(transpose_kernel<float>, dim3(gx, gy), dim3(256), 0, st,
+                       (const float*)A.vals, A.n, A.d, A.ld, (float*)At);
+  else
+    hipLaunchKernelGGL(transpose_kernel<double>, dim3(gx, gy), dim3(256), 0, st,
+                       (const double*)A.vals, A.n, A.d, A.ld, (double*)At);
+  IHS_CHECK_LAUNCH();
+}
+
+// C (rows x K, FP64, contiguous) = B (rows x K, stride ldb, FP32 or FP64)
+template <typename T>
+__global__ void widen_rows_kernel(const T* __restrict__ B, int64_t rows, int64_t K, int64_t ldb,
+                                  double* __restrict__ C) {
+  const int64_t total = rows * K;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x)
+    C[t] = (double)B[(t / K) * ldb + t % K];
+}
+
+void launch_widen_rows(const void* B, int dtype, int64_t rows, int64_t K, int64_t ldb, double* C,
+                       hipStream_t st) {
+  int64_t blocks = cdiv(rows * K, 256);
+  if (blocks > 16384) blocks = 16384;
+  if (dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(widen_rows_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const float*)B, rows, K, ldb, C);
+  else
+    hipLaunchKernelGGL(widen_rows_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const double*)B, rows, K, ldb, C);
+  IHS_CHECK_LAUNCH();
+}
+
 int64_t padded_width(int64_t w) {
   if (w <= 16) return 16;
   if (w <= 32) return 32;

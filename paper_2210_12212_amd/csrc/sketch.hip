@@ -21,6 +21,22 @@ __global__ void draw_countsketch_kernel(uint64_t key, int64_t n, int64_t m, int 
   }
 }
 
+__global__ void identity_draws_kernel(int64_t n, int32_t* __restrict__ idx,
+                                      int8_t* __restrict__ sign) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    idx[i] = (int32_t)i;
+    sign[i] = 1;
+  }
+}
+
+void launch_identity_draws(int64_t n, int32_t* idx, int8_t* sign, hipStream_t st) {
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(identity_draws_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, idx, sign);
+  IHS_CHECK_LAUNCH();
+}
+
 void launch_draw_countsketch(uint64_t seed, int64_t n, int64_t m, int s, int32_t* idx,
                              int8_t* sign, hipStream_t st) {
   int64_t blocks = cdiv(n * s, 256);

@@ -36,6 +36,7 @@ struct ihsbin_path {
   int L = 0;
   double lam_min = 0, lam_max = 0;
   int centred = 1;
+  int dual = 0;  // built on the dual problem (n < d); the basis is in x-space
   std::vector<double> grid, lam0, tau, rate, ref;
   std::vector<int32_t> k;
   ihs::DevBuf basis, items;
@@ -483,6 +484,21 @@ static std::vector<Spec> interval_spectra(Ctx& c, const MatView& A, const double
   return out;
 }
 
+// SA = A in FP64 (n x d contiguous): dense rows widened, CSR rows scattered
+// into their own rows.
+static void copy_rows_f64(Ctx& c, const MatView& A, double* SA) {
+  if (A.format == IHSBIN_DENSE) {
+    launch_widen_rows(A.vals, A.dtype, A.n, A.d, A.ld, SA, c.stream);
+    return;
+  }
+  char* base = static_cast<char*>(c.ws_sketch.ensure((size_t)A.n * 5 + 256));
+  int32_t* idx = reinterpret_cast<int32_t*>(base);
+  int8_t* sg = reinterpret_cast<int8_t*>(base + (size_t)A.n * 4);
+  launch_identity_draws(A.n, idx, sg, c.stream);
+  IHS_HIP(hipMemsetAsync(SA, 0, sizeof(double) * (size_t)A.n * A.d, c.stream));
+  launch_countsketch_apply(A, idx, sg, 1, SA, c.stream);
+}
+
 struct Timer {
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double ms() const {
@@ -498,12 +514,29 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   ihsbin_opts o;
   if (o_in) o = *o_in;
   else ihsbin_opts_default(&o);
-  const MatView A = check_matrix(Ain);
+  const MatView A0 = check_matrix(Ain);
   if (!B) fail(IHSBIN_EINVAL, "B is NULL");
   if (K < 1 || ldb < K) fail(IHSBIN_EINVAL, "need K >= 1 and ldb >= K");
   if (!(lam_min > 0.0) || !(lam_max >= lam_min) || !std::isfinite(lam_max))
     fail(IHSBIN_EINVAL, "need 0 < lam_min <= lam_max");
-  if (A.n < A.d) fail(IHSBIN_EUNSUP, "n < d (the dual problem is not built)");
+  // n < d: the dual problem (Section 5.2, Eq. (ls_reg:d)).  Its optimality
+  // condition (A A^T + lam I) z = b is the primal form for the d x n matrix
+  // A^T with right-hand side b itself, and x = A^T z.  Everything below runs
+  // on A^T (materialized once); the basis is mapped to x at the end.
+  const bool dual = A0.n < A0.d;
+  if (dual && A0.format != IHSBIN_DENSE)
+    fail(IHSBIN_EUNSUP, "n < d with a CSR matrix (the dual is built for dense A)");
+  PoolBuf Atb(c.pool);
+  MatView A = A0;
+  if (dual) {
+    const size_t es = A0.dtype == IHSBIN_F32 ? 4 : 8;
+    void* At = Atb.ensure(es * (size_t)A0.n * (size_t)A0.d);
+    launch_transpose(A0, At, c.stream);
+    A.n = A0.d;
+    A.d = A0.n;
+    A.ld = A0.n;
+    A.vals = At;
+  }
   if (o.k_max < 1 || o.k_max > 4096) fail(IHSBIN_EINVAL, "k_max out of range");
   if (o.k_fixed < 0 || o.k_fixed > 4096) fail(IHSBIN_EINVAL, "k_fixed out of range");
   if (!(o.tol > 0.0)) fail(IHSBIN_EINVAL, "tol must be positive");
@@ -522,10 +555,11 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   for (int l = 0; l < L; ++l) lam0[l] = std::sqrt(grid[l] * grid[l + 1]);
   const int64_t d = A.d;
 
-  // ---- C = A^T B
+  // ---- C = A^T B (dual: C = B)
   PoolBuf Cb(c.pool);
   double* C = static_cast<double*>(Cb.ensure(sizeof(double) * d * K));
-  atb_apply(c, A, B, K, ldb, C);
+  if (dual) launch_widen_rows(B, A0.dtype, d, K, ldb, C, st);
+  else atb_apply(c, A, B, K, ldb, C);
 
   // ---- sketch, with adaptive m
   Timer tsk;
@@ -538,10 +572,18 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   double* G = static_cast<double*>(Gb.ensure(sizeof(double) * d * d));
   std::vector<Spec> spec;
   int trials = 0;
+  // A sketch of m >= n rows is no cheaper than A itself and embeds it no better
+  // than S = I does: then SA = A and P_S is the exact (A^T A + lam0 I)^-1.
   auto sketch_m = [&](int64_t mm) {
-    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * mm * d));
-    sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT);
-    gram_impl(c, SA, mm, d, G);
+    const int64_t rows = mm >= A.n ? A.n : mm;
+    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * d));
+    if (mm >= A.n) {
+      logf("m=%lld >= n=%lld: exact Hessian (S = I)", (long long)mm, (long long)A.n);
+      copy_rows_f64(c, A, SA);
+    } else {
+      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT);
+    }
+    gram_impl(c, SA, rows, d, G);
     ++trials;
   };
   // Predicted contraction rate of interval l from its spectrum estimate.
@@ -636,7 +678,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   }
   Gb.release();
   SAb.release();
-  r.m_used = m;
+  r.m_used = std::min<int64_t>(m, A.n);
   r.sketch_trials = trials;
   for (int l = 0; l < L && log_enabled(); ++l)
     logf("interval %d [%.4g, %.4g]: c=[%.4g, %.4g]", l, grid[l], grid[l + 1], spec[l].mu_min,
@@ -664,7 +706,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   path->d = d;
   path->K = K;
   path->L = L;
-  path->m_used = m;
+  path->m_used = std::min<int64_t>(m, A.n);
   path->lam_min = lam_min;
   path->lam_max = lam_max;
   path->centred = o.centred ? 1 : 0;
@@ -790,6 +832,35 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   }
   if (o.k_fixed == 0) unconverged += (int)act.size();
   IHS_HIP(hipStreamSynchronize(st));
+  if (dual) {
+    // x = A^T z for every basis vector: basis_x[l][j] = (A^T) basis_z[l][j]
+    // (d0 x K blocks), one batched product over all L * kcap blocks
+    const int64_t d0 = A.n;
+    ihs::DevBuf bx;
+    double* bxp = static_cast<double*>(bx.ensure(sizeof(double) * L * kcap * d0 * K));
+    Gemm g;
+    g.M = d0;
+    g.N = K;
+    g.K = d;
+    g.A = A.vals;
+    g.lda = A.ld;
+    g.B = basis;
+    g.ldb = K;
+    g.strideB = d * K;
+    g.C = bxp;
+    g.ldc = K;
+    g.strideC = d0 * K;
+    g.batch = (int)(L * kcap);
+    if (g.batch > 65535) fail(IHSBIN_EUNSUP, "too many basis blocks for the dual map");
+    const ColTiles ct = pick_col_tiles(K);
+    g.n_read = std::min<int64_t>(K, (int64_t)ct.c * 16 * ct.q);
+    gemm_cols(g, A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64, false, ct, st);
+    IHS_HIP(hipStreamSynchronize(st));
+    std::swap(path->basis.p, bx.p);
+    std::swap(path->basis.bytes, bx.bytes);
+    path->d = d0;
+    path->dual = 1;
+  }
   r.ms_basis = tb.ms();
   if (o.timing && !events.empty()) {
     for (size_t q = 0; q + 2 < events.size(); q += 3) {
@@ -975,6 +1046,7 @@ int ihsbin_path_get_info(const ihsbin_path* p, ihsbin_path_info* info) {
   info->lam_min = p->lam_min;
   info->lam_max = p->lam_max;
   info->centred = p->centred;
+  info->dual = p->dual;
   return IHSBIN_OK;
 }
 

@@ -58,4 +58,4 @@ def test_struct_sizes_match_header_layout():
     from paper_2210_12212_amd import _lib
     # int32 x2, int64 x4, pointers x3
     assert C.sizeof(_lib.Matrix) == 8 + 32 + 24
-    assert C.sizeof(_lib.PathInfo) == 4 + 4 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(_lib.PathInfo) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4  # ..., centred, dual

@@ -245,10 +245,10 @@ def test_errors(torch, ctx):
     with pytest.raises(IhsbinError) as e:
         ctx.path_build(dev(torch, A), dev(torch, B), 1.0, 0.1)
     assert e.value.status == -1
-    At = np.ascontiguousarray(A[:8])
-    with pytest.raises(IhsbinError) as e:
-        ctx.path_build(dev(torch, At), dev(torch, B[:8]), 0.1, 1.0)
-    assert e.value.status == -7
+    At = np.ascontiguousarray(A[:8])  # n < d: built on the dual problem
+    path, _ = ctx.path_build(dev(torch, At), dev(torch, B[:8]), 0.1, 1.0)
+    assert path.dual == 1 and path.d == 10
+    path.free()
     bad = W.csr_zipf(50, 10, 3, seed=1)
     bad.col_idx[5] = 10
     with pytest.raises(IhsbinError) as e:
@@ -295,3 +295,30 @@ def test_step_sizes_close_to_exact_spectrum(torch, ctx):
         assert 0.9 * tau_exact <= iv["tau"][l] <= 1.0 * tau_exact, (l, iv["tau"][l], tau_exact)
         assert iv["rate"][l] >= rate_exact - 1e-9
     path.free()
+
+
+# ---------------------------------------------------------------- dual (n < d)
+@pytest.mark.parametrize("kind", ["gaussian", "srht", "countsketch"])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_dual_path_matches_direct(torch, ctx, kind, dt):
+    # Section 5.2: n < d is built on (A A^T + lam I) z = b, x = A^T z
+    A = W.dense_decay(300, 1200, seed=81, dtype=dt)
+    B, _ = W.rhs(A, 2, 0.1, seed=82)
+    lams = W.lambda_grid(1e-2, 1e3, 15)
+    path, rep = ctx.path_build(dev(torch, A), dev(torch, B), 1e-2, 1e3, sketch=kind, m=150,
+                               seed=83, tol=1e-9)
+    assert path.dual == 1 and path.d == 1200 and rep["n_unconverged"] == 0, rep
+    X = path.eval(lams).cpu().numpy()
+    path.free()
+    ref = direct.ridge_path_dual(A, B, lams)
+    err = direct.rel_err(X, ref)
+    assert err.max() <= 1e-6, err
+
+
+def test_dual_csr_is_unsupported(torch, ctx):
+    from paper_2210_12212_amd import IhsbinError
+    M = W.csr_zipf(100, 400, 5, seed=4, dtype=np.float32)
+    B = np.ones((100, 1), dtype=np.float32)
+    with pytest.raises(IhsbinError) as e:
+        ctx.solve_path(csr_dev(torch, M), dev(torch, B), [1.0], sketch="countsketch", m=50)
+    assert e.value.status == -7

@@ -107,3 +107,21 @@ def test_csr_matches_dense():
     lams = [1e-3, 1.0, 100.0]
     np.testing.assert_allclose(direct.ridge_path(Ac, B, lams), _svd_path(Ad, B, lams),
                                rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_dual_form_for_wide_matrices(dt):
+    # n < d: the dual form A^T (A A^T + lam I)^-1 b (Section 5.2) against the
+    # SVD closed form of Section 2.1 (the d x d primal Gram is rank n here) and
+    # the KKT residual computed with A
+    A = W.dense_decay(60, 240, seed=17, dtype=dt)
+    B, _ = W.rhs(A, 2, 0.1, seed=18)
+    lams = W.lambda_grid(1e-3, 1e2, 7)
+    X = direct.ridge_path_dual(A, B, lams)
+    A64 = np.asarray(A, dtype=np.float64)
+    assert direct.rel_err(X, _svd_path(A64, B, lams)).max() < 1e-10
+    assert direct.rel_err(X, direct.ridge_path(A, B, lams)).max() < 1e-9
+    AtB = A64.T @ B
+    for t, lam in enumerate(lams):
+        r = A64.T @ (A64 @ X[t] - B) + lam * X[t]
+        assert np.linalg.norm(r) / np.linalg.norm(AtB) < 1e-11

@@ -205,6 +205,10 @@ WORKLOADS = {
     "dense_invsqrt_262144x4096_k64": dict(kind="dense_spectrum", spectrum="invsqrt",
                                           n=262144, d=4096, K=64, noise=0.05, dtype="f32",
                                           sketch="gaussian", m=2048, lam=(1e-4, 1e1), T=100),
+    # under-determined (n < d): solved through the dual problem
+    "dense_decay_8192x65536_wide": dict(kind="dense_decay", n=8192, d=65536, K=1, noise=0.1,
+                                        dtype="f32", sketch="srht", m=4096,
+                                        lam=(1e-2, 1e3), T=100),
 }
 
 
