@@ -185,7 +185,9 @@ def main():
     # evaluation only, for the workload's T and for a dense grid of 100000 lambdas
     path, _ = ctx.path_build(A, B, p.lam_min, p.lam_max, **opts)
     eval_only = {}
-    for name, lams in (("T", p.lambdas), ("dense_100000", W.lambda_grid(p.lam_min, p.lam_max, 100000))):
+    n_dense = int(min(100000, 4e9 // (8 * p.d * p.B.shape[1])))  # output kept <= 4 GB
+    for name, lams in (("T", p.lambdas),
+                       (f"dense_{n_dense}", W.lambda_grid(p.lam_min, p.lam_max, n_dense))):
         out = torch.empty((len(lams), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
         path.eval(lams, out=out)
         torch.cuda.synchronize()
@@ -207,19 +209,27 @@ def main():
         from oracle import direct
         cores = len(os.sched_getaffinity(0))
         idx = np.unique(np.linspace(0, T - 1, min(T, args.oracle_lambdas)).round().astype(int))
+        wide = p.n < p.d  # the oracle takes the n x n dual form (Section 5.2)
         tg = time.perf_counter()
-        G = direct.gram(p.A)
-        C = direct.atb(p.A, p.B)
+        if wide:
+            G = direct.dual_gram(p.A)
+        else:
+            G = direct.gram(p.A)
+            C = direct.atb(p.A, p.B)
         t_gram = time.perf_counter() - tg
         ts = time.perf_counter()
-        Xo = direct.solve_from_gram(G, C, p.lambdas[idx])
+        if wide:
+            Xo = direct.solve_dual_from_gram(G, p.A, p.B, p.lambdas[idx])
+        else:
+            Xo = direct.solve_from_gram(G, C, p.lambdas[idx])
         t_solve = (time.perf_counter() - ts) / len(idx)
         err = direct.rel_err(Xh[idx], Xo)
         max_err = float(err.max())
         t_full = t_gram + T * t_solve
         cpu = {"value": round(T / t_full, 3), "unit": "lambda-solves/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"G=A^T A and A^T b over the full matrix ({t_gram:.1f}s) plus {len(idx)} of "
+               "sample": f"{'A A^T (dual form)' if wide else 'G=A^T A and A^T b'} over the full "
+                         f"matrix ({t_gram:.1f}s) plus {len(idx)} of "
                          f"{T} per-lambda Cholesky solves ({t_solve * 1e3:.1f} ms each); the full "
                          f"path time is t_G + T*t_solve = {t_full:.1f}s"}
         log(f"[bench] oracle: gram {t_gram:.1f}s, solve {t_solve * 1e3:.1f} ms/lambda, "

@@ -70,29 +70,40 @@ def ridge_path(A, B, lambdas) -> np.ndarray:
     return solve_from_gram(gram(A), atb(A, B), lambdas)
 
 
-def ridge_path_dual(A, B, lambdas, chunk: int = 1 << 14) -> np.ndarray:
-    """The same exact path for n < d through the dual problem of Section 5.2:
-    x*(lam) = A^T (A A^T + lam I)^-1 b (the dual optimality condition and the
-    primal map x = A^T z), with the n x n matrix A A^T formed in FP64 column
-    chunk by column chunk.  Returns T x d x K."""
+def dual_gram(A, chunk: int = 1 << 14) -> np.ndarray:
+    """A A^T in FP64 (n x n), formed column chunk by column chunk."""
     A64 = np.asarray(A, dtype=np.float64)
-    B = np.asarray(B, dtype=np.float64)
-    if B.ndim == 1:
-        B = B[:, None]
     n, d = A64.shape
     K = np.zeros((n, n))
     for c0 in range(0, d, chunk):
         blk = A64[:, c0:c0 + chunk]
         K += blk @ blk.T
+    return K
+
+
+def solve_dual_from_gram(Kmat: np.ndarray, A, B, lambdas) -> np.ndarray:
+    """X[t] = A^T (Kmat + lambdas[t] I)^-1 B with Kmat = A A^T; T x d x K."""
+    A64 = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    if B.ndim == 1:
+        B = B[:, None]
+    n, d = A64.shape
     lambdas = np.atleast_1d(np.asarray(lambdas, dtype=np.float64))
     out = np.empty((len(lambdas), d, B.shape[1]))
     for t, lam in enumerate(lambdas):
-        H = K.copy()
+        H = Kmat.copy()
         H[np.diag_indices(n)] += lam
         Z = sla.cho_solve(sla.cho_factor(H, lower=True, check_finite=False), B,
                           check_finite=False)
         out[t] = A64.T @ Z
     return out
+
+
+def ridge_path_dual(A, B, lambdas) -> np.ndarray:
+    """The same exact path for n < d through the dual problem of Section 5.2:
+    x*(lam) = A^T (A A^T + lam I)^-1 b (the dual optimality condition and the
+    primal map x = A^T z).  Returns T x d x K."""
+    return solve_dual_from_gram(dual_gram(A), A, B, lambdas)
 
 
 def rel_err(X_hat, X_ref) -> np.ndarray:

@@ -55,6 +55,12 @@ constexpr int kNB = 64;
 void launch_transpose(const MatView& A, void* At, hipStream_t st);
 void launch_widen_rows(const void* B, int dtype, int64_t rows, int64_t K, int64_t ldb, double* C,
                        hipStream_t st);
+// Z (rows x nb*K, row stride ldz) <- blocks blk[0..nb) of src[blocks][rows][K],
+// and the scatter back into dst[blocks][rows][K].
+void launch_gather_blocks(const double* src, const int32_t* blk, int nb, int64_t rows, int64_t K,
+                          double* Z, int64_t ldz, hipStream_t st);
+void launch_scatter_blocks(const double* Z, int64_t ldz, const int32_t* blk, int nb, int64_t rows,
+                           int64_t K, double* dst, hipStream_t st);
 int64_t padded_width(int64_t w);
 int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
                   int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0);

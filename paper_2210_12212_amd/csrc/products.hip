@@ -171,6 +171,50 @@ void launch_widen_rows(const void* B, int dtype, int64_t rows, int64_t K, int64_
   IHS_CHECK_LAUNCH();
 }
 
+// Z (rows x nb*K, row stride ldz) <- blocks blk[b] of a block array
+// src[blk][rows][K]; and the inverse scatter into dst[blk][rows][K].
+__global__ void gather_blocks_kernel(const double* __restrict__ src, const int32_t* __restrict__ blk,
+                                     int nb, int64_t rows, int64_t K, double* __restrict__ Z,
+                                     int64_t ldz) {
+  const int64_t cols = (int64_t)nb * K, total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / cols, col = t % cols;
+    const int64_t b = col / K, kk = col % K;
+    Z[r * ldz + col] = src[((int64_t)blk[b] * rows + r) * K + kk];
+  }
+}
+
+__global__ void scatter_blocks_kernel(const double* __restrict__ Z, int64_t ldz,
+                                      const int32_t* __restrict__ blk, int nb, int64_t rows,
+                                      int64_t K, double* __restrict__ dst) {
+  const int64_t cols = (int64_t)nb * K, total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / cols, col = t % cols;
+    const int64_t b = col / K, kk = col % K;
+    dst[((int64_t)blk[b] * rows + r) * K + kk] = Z[r * ldz + col];
+  }
+}
+
+void launch_gather_blocks(const double* src, const int32_t* blk, int nb, int64_t rows, int64_t K,
+                          double* Z, int64_t ldz, hipStream_t st) {
+  int64_t blocks = cdiv(rows * nb * K, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(gather_blocks_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, blk, nb,
+                     rows, K, Z, ldz);
+  IHS_CHECK_LAUNCH();
+}
+
+void launch_scatter_blocks(const double* Z, int64_t ldz, const int32_t* blk, int nb, int64_t rows,
+                           int64_t K, double* dst, hipStream_t st) {
+  int64_t blocks = cdiv(rows * nb * K, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(scatter_blocks_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Z, ldz, blk,
+                     nb, rows, K, dst);
+  IHS_CHECK_LAUNCH();
+}
+
 int64_t padded_width(int64_t w) {
   if (w <= 16) return 16;
   if (w <= 32) return 32;

@@ -833,28 +833,47 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   if (o.k_fixed == 0) unconverged += (int)act.size();
   IHS_HIP(hipStreamSynchronize(st));
   if (dual) {
-    // x = A^T z for every basis vector: basis_x[l][j] = (A^T) basis_z[l][j]
-    // (d0 x K blocks), one batched product over all L * kcap blocks
+    // x = A^T z for every stored basis vector (blocks j < k_l of each
+    // interval): gathered into one n x (blocks K) matrix, one product with
+    // the d0 x n matrix A^T, scattered back as d0 x K blocks
     const int64_t d0 = A.n;
+    std::vector<int32_t> blk;
+    for (int l = 0; l < L; ++l)
+      for (int j = 0; j < path->k[l]; ++j) blk.push_back((int32_t)(l * kcap + j));
+    const int nb = (int)blk.size();
+    const int64_t cols = (int64_t)nb * K;
+    const int64_t cpad = padded_width(cols);
     ihs::DevBuf bx;
+    PoolBuf zb(c.pool), xb(c.pool), ib(c.pool);
     double* bxp = static_cast<double*>(bx.ensure(sizeof(double) * L * kcap * d0 * K));
-    Gemm g;
-    g.M = d0;
-    g.N = K;
-    g.K = d;
-    g.A = A.vals;
-    g.lda = A.ld;
-    g.B = basis;
-    g.ldb = K;
-    g.strideB = d * K;
-    g.C = bxp;
-    g.ldc = K;
-    g.strideC = d0 * K;
-    g.batch = (int)(L * kcap);
-    if (g.batch > 65535) fail(IHSBIN_EUNSUP, "too many basis blocks for the dual map");
-    const ColTiles ct = pick_col_tiles(K);
-    g.n_read = std::min<int64_t>(K, (int64_t)ct.c * 16 * ct.q);
-    gemm_cols(g, A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64, false, ct, st);
+    double* Zt = static_cast<double*>(zb.ensure(sizeof(double) * d * cpad));
+    double* Xt = static_cast<double*>(xb.ensure(sizeof(double) * d0 * cpad));
+    int32_t* blk_dev = static_cast<int32_t*>(ib.ensure(sizeof(int32_t) * nb));
+    IHS_HIP(hipMemcpyAsync(blk_dev, blk.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemsetAsync(bxp, 0, sizeof(double) * L * kcap * d0 * K, st));
+    // Zt has row stride cpad so the product may read whole column tiles
+    if (cpad != cols) IHS_HIP(hipMemsetAsync(Zt, 0, sizeof(double) * d * cpad, st));
+    launch_gather_blocks(basis, blk_dev, nb, d, K, Zt, cpad, st);
+    int64_t done = 0;
+    const int64_t chunk = 8192;  // column chunks keep the tiling within its range
+    while (done < cols) {
+      const int64_t cw = std::min(chunk, cols - done);
+      const ColTiles ct = pick_col_tiles(cw);
+      Gemm g;
+      g.M = d0;
+      g.N = cw;
+      g.K = d;
+      g.A = A.vals;
+      g.lda = A.ld;
+      g.B = Zt + done;
+      g.ldb = cpad;
+      g.n_read = std::min<int64_t>(cpad - done, (int64_t)ct.c * 16 * ct.q);
+      g.C = Xt + done;
+      g.ldc = cpad;
+      gemm_cols(g, A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64, false, ct, st);
+      done += cw;
+    }
+    launch_scatter_blocks(Xt, cpad, blk_dev, nb, d0, K, bxp, st);
     IHS_HIP(hipStreamSynchronize(st));
     std::swap(path->basis.p, bx.p);
     std::swap(path->basis.bytes, bx.bytes);
