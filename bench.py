@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--rate-target", type=float, default=0.5)
     ap.add_argument("--lanczos-steps", type=int, default=6)
+    ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default="f64",
+                    help="sketched Gram precision (the factor and the recursion stay FP64)")
     ap.add_argument("--oracle-lambdas", type=int, default=12,
                     help="lambdas of the sample solved by the CPU oracle")
     ap.add_argument("--no-oracle", action="store_true")
@@ -136,7 +138,8 @@ def main():
     torch.cuda.synchronize()
     ctx = Context(0)
     opts = dict(sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=args.tol,
-                rate_target=args.rate_target, lanczos_steps=args.lanczos_steps, timing=1)
+                rate_target=args.rate_target, lanczos_steps=args.lanczos_steps, timing=1,
+                gram_prec={"f64": 0, "bf16x3": 1}[args.gram_prec])
     X = torch.empty((len(p.lambdas), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
 
     def step():
@@ -252,7 +255,8 @@ def main():
                    "storage": str(p.A.dtype), "sketch": p.sketch, "m0": p.m,
                    "m_used": rep["m_used"], "L": rep["L"], "k_max": rep["k_max_used"],
                    "k_sum": rep["k_sum"], "lam": [p.lam_min, p.lam_max], "tol": args.tol,
-                   "rate_target": args.rate_target, "lanczos_steps": args.lanczos_steps},
+                   "rate_target": args.rate_target, "lanczos_steps": args.lanczos_steps,
+                   "gram_prec": args.gram_prec},
         "max_rel_err": max_err,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phase_ms": {k: rep[k] for k in ("ms_sketch", "ms_factor", "ms_spectrum", "ms_basis",

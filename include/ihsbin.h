@@ -103,7 +103,15 @@ typedef struct {
                               the upper end bound the whole interval          */
   int32_t timing;          /* 1: time the A^T A product kernels with events     */
   const double* taus;      /* host, optional: fixed step size per interval (L)  */
+  int32_t gram_prec;       /* sketched Gram (SA)^T SA: IHSBIN_GRAM_F64 (default)
+                              or IHSBIN_GRAM_BF16X3 (BF16 matrix cores, three-
+                              term splits, ~1e-6 relative; the factor is still
+                              FP64 and used consistently, so the path keeps its
+                              fixed point)                                       */
 } ihsbin_opts;
+
+/* Precision of the sketched Gram. */
+enum { IHSBIN_GRAM_F64 = 0, IHSBIN_GRAM_BF16X3 = 1 };
 
 /* Filled by ihsbin_path_build. */
 typedef struct {
@@ -228,6 +236,13 @@ int ihsbin_sketch_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch,
 int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m,
                           int64_t d, const double* lam0, int32_t nl,
                           double* Lfac, double* Linv);
+
+/* G = (SA)^T SA for the preconditioner (Section 4, P_S).  SA: device m x d
+ * doubles (row-major, contiguous).  G: device d x d doubles; its lower triangle
+ * (and the diagonal 128 x 128 or 64 x 64 tiles) is written.  prec: IHSBIN_GRAM_*.
+ * EINVAL on bad sizes or prec. */
+int ihsbin_gram(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d, int32_t prec,
+                double* G);
 
 /* W = A^T A U: the two products of every basis step (Algorithm 2).  U: device
  * d x w doubles with row stride ldu; the buffer spans d * ldu doubles, and

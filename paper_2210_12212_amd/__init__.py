@@ -215,6 +215,18 @@ class Context:
             C.c_void_p(Li.data_ptr()) if Li is not None else None))
         return Lf, Li
 
+    def gram(self, SA, prec: str = "f64"):
+        """ihsbin_gram -> G = SA^T SA (d x d float64; lower triangle and the
+        diagonal tiles written).  prec: "f64" or "bf16x3"."""
+        torch = _torch()
+        SA = SA.contiguous()
+        m, d = SA.shape
+        G = torch.zeros((d, d), dtype=torch.float64, device=SA.device)
+        code = {"f64": 0, "bf16x3": 1}[prec]
+        self._check(L.lib().ihsbin_gram(self._h, C.c_void_p(SA.data_ptr()), m, d, code,
+                                        C.c_void_p(G.data_ptr())))
+        return G
+
     def ata_apply(self, A, U):
         """ihsbin_ata_apply -> W = A^T A U (d x w float64)."""
         U = U if U.dim() == 2 else U.reshape(-1, 1)

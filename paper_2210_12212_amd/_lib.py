@@ -23,6 +23,7 @@ EXPORTED = [
     "ihsbin_path_get_info", "ihsbin_path_intervals", "ihsbin_path_basis", "ihsbin_path_free",
     "ihsbin_solve_path", "ihsbin_sketch_draws", "ihsbin_sketch_apply", "ihsbin_precond_factor",
     "ihsbin_ata_apply",
+    "ihsbin_gram",
 ]
 
 
@@ -38,7 +39,7 @@ class Opts(C.Structure):
                 ("k_fixed", C.c_int32), ("L", C.c_int32), ("centred", C.c_int32),
                 ("adaptive_m", C.c_int32), ("rate_target", C.c_double), ("m_max", C.c_int64),
                 ("lanczos_steps", C.c_int32), ("timing", C.c_int32),
-                ("taus", C.POINTER(C.c_double))]
+                ("taus", C.POINTER(C.c_double)), ("gram_prec", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -83,6 +84,7 @@ def _declare(lib):
         "ihsbin_sketch_apply": (C.c_int, [vp, C.POINTER(Matrix), i32, i32, i64, u64, vp]),
         "ihsbin_precond_factor": (C.c_int, [vp, vp, i64, i64, pd, i32, vp, vp]),
         "ihsbin_ata_apply": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64]),
+        "ihsbin_gram": (C.c_int, [vp, vp, i64, i64, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

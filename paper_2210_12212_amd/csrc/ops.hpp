@@ -50,6 +50,16 @@ constexpr int kNB = 64;
 // (their values are ignored): the dense GEMMs then run ragged widths on the
 // unchecked load path.  padded_width(w) (16, 32 or a multiple of 64) bounds
 // the columns read.  Only columns [0, w) of W are written; returns w.
+// Sketched Gram on the BF16 matrix cores with three-term splits (FP32 sums of
+// at most kMaxSplitRows rows, split partials part[s] (d x d FP64) to be added
+// in FP64; every tile touching the lower triangle is written).  work:
+// gram_bf16x3_work_bytes(m, d) bytes for the split terms.
+constexpr int64_t kMaxSplitRows = 2048;
+int gram_bf16x3_splits(int64_t m);
+int64_t gram_bf16x3_work_bytes(int64_t m, int64_t d);
+void gram_bf16x3(const double* X, int64_t m, int64_t d, int64_t ldx, void* work, double* part,
+                 int splits, hipStream_t st);
+
 // Dual (n < d) helpers: At = A^T (d x n row-major, A's dtype; dense A only)
 // and C = B widened to FP64 (rows x K contiguous).
 void launch_transpose(const MatView& A, void* At, hipStream_t st);

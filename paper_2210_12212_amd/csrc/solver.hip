@@ -191,7 +191,19 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
 
 // Lower triangle (and the diagonal tiles) of G = (SA)^T SA; the strictly
 // upper tiles are not computed and hold unspecified values.
-static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G) {
+static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G,
+                      int prec = IHSBIN_GRAM_F64) {
+  if (prec == IHSBIN_GRAM_BF16X3) {
+    const int splits = gram_bf16x3_splits(m);
+    PoolBuf wb(c.pool);
+    void* work = wb.ensure((size_t)gram_bf16x3_work_bytes(m, d));
+    double* part = static_cast<double*>(
+        c.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)d * (size_t)d));
+    gram_bf16x3(SA, m, d, d, work, part, splits, c.stream);
+    reduce_splits(part, splits, 1, d, d, d, d * d, G, d, 0, 1.0, 0.0, c.stream);
+    return;
+  }
+  if (prec != IHSBIN_GRAM_F64) fail(IHSBIN_EINVAL, "unknown Gram precision");
   // 64 x 64 lower tiles with enough K-splits for ~16 workgroups per CU
   const int splits = pick_splits_lower(d, m, 4096);
   Gemm g;
@@ -583,7 +595,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     } else {
       sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT);
     }
-    gram_impl(c, SA, rows, d, G);
+    gram_impl(c, SA, rows, d, G, o.gram_prec);
     ++trials;
   };
   // Predicted contraction rate of interval l from its spectrum estimate.
@@ -1000,6 +1012,7 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->rate_target = 0.6;
   o->m_max = 0;
   o->lanczos_steps = 12;
+  o->gram_prec = IHSBIN_GRAM_F64;
   o->timing = 0;
   o->taus = nullptr;
 }
@@ -1174,6 +1187,18 @@ int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t 
     gram_impl(ctx->c, SA, m, d, G);
     std::vector<double> l0(lam0, lam0 + nl);
     factor_impl(ctx->c, G, d, l0, Lfac, Linv, dinvb, lamb);
+    IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_gram(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d, int32_t prec,
+                double* G) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    if (!SA || !G || m <= 0 || d <= 0) fail(IHSBIN_EINVAL, "bad arguments");
+    gram_impl(ctx->c, SA, m, d, G, prec);
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
     return IHSBIN_OK;
   });

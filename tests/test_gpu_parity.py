@@ -322,3 +322,32 @@ def test_dual_csr_is_unsupported(torch, ctx):
     with pytest.raises(IhsbinError) as e:
         ctx.solve_path(csr_dev(torch, M), dev(torch, B), [1.0], sketch="countsketch", m=50)
     assert e.value.status == -7
+
+
+# ---------------------------------------------------------------- sketched Gram
+@pytest.mark.parametrize("m,d", [(3000, 300), (700, 129), (5000, 64)])
+def test_gram_precisions(torch, ctx, m, d):
+    # FP64: the product itself; split BF16: within 1e-5 of sqrt(G_ii G_jj)
+    r = np.random.default_rng(m + d)
+    SA = r.standard_normal((m, d)) * np.exp(-np.arange(d) / 50.0)
+    ref = SA.T @ SA
+    low = np.tril_indices(d)
+    G64 = ctx.gram(dev(torch, SA), "f64").cpu().numpy()
+    np.testing.assert_allclose(G64[low], ref[low], rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    Gb = ctx.gram(dev(torch, SA), "bf16x3").cpu().numpy()
+    scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+    assert (np.abs(Gb - ref)[low] <= 1e-5 * scale[low]).all()
+
+
+@pytest.mark.parametrize("kind", ["srht", "countsketch"])
+def test_path_with_bf16x3_gram(torch, ctx, kind):
+    # the factor of a Gram accurate to ~1e-6 is a fixed SPD preconditioner:
+    # the path converges to the same solution
+    A = W.dense_decay(4000, 200, seed=91, dtype=np.float32)
+    B, _ = W.rhs(A, 2, 0.1, seed=92)
+    lams = W.lambda_grid(1e-3, 1e2, 13)
+    X, rep = ctx.solve_path(dev(torch, A), dev(torch, B), lams, sketch=kind, m=100, seed=93,
+                            gram_prec=1, tol=1e-9)
+    assert rep["status"] == 0, rep
+    err = direct.rel_err(X.cpu().numpy(), direct.ridge_path(A, B, lams))
+    assert err.max() <= 1e-6, err
