@@ -23,11 +23,13 @@
  *  - Every call returns an ihsbin_status code; no C++ exception crosses the
  *    ABI.  On failure ihsbin_last_error(ctx) holds a message and the output
  *    buffers hold unspecified values (except IHSBIN_ENOCONV, see below).
- *  - Only the over-determined case n >= d is supported (the dual of
- *    Section 5.2 is not built): n < d returns IHSBIN_EUNSUP.
- *  - Arithmetic: the sketch, the sketched Hessian, its factors, the basis and
- *    every product with A run in FP64; A and B are read in their stored type
- *    (FP32 or FP64, converted exactly on load).
+ *  - Under-determined problems (n < d) with a dense A are solved through the
+ *    dual problem of Section 5.2, Eq. (ls_reg:d); n < d with a CSR matrix
+ *    returns IHSBIN_EUNSUP.
+ *  - Arithmetic: the sketch, its factors, the basis and every product with A
+ *    run in FP64, and so does the sketched Hessian unless gram_prec selects
+ *    its split-BF16 form; A and B are read in their stored type (FP32 or
+ *    FP64, converted exactly on load).
  */
 #ifndef IHSBIN_H
 #define IHSBIN_H
@@ -93,8 +95,12 @@ typedef struct {
   int32_t L;               /* intervals; 0 = floor(2 ln(lam_max/lam_min))       */
   int32_t centred;         /* 1: expand about the interval centre lam0 (default);
                               0: the printed expansion in powers of tau*lam     */
-  int32_t adaptive_m;      /* 1: grow m until the predicted rate of the lowest
-                              interval is <= rate_target (default 1)            */
+  int32_t adaptive_m;      /* sketch dimension policy: 0 = m as given;
+                              1 (default) = grow m until the predicted rate of
+                              the lowest interval is <= rate_target;
+                              2 = Algorithm 4 (Section 5.1) at lam_min, from
+                              m0 = m (0: max(16, d / 4)), parameters
+                              from alg4          */
   double rate_target;      /* default 0.6                                      */
   int64_t m_max;           /* cap for adaptive m; 0 = library default           */
   int32_t lanczos_steps;   /* Lanczos steps of each spectrum estimate (default
@@ -108,7 +114,34 @@ typedef struct {
                               term splits, ~1e-6 relative; the factor is still
                               FP64 and used consistently, so the path keeps its
                               fixed point)                                       */
+  const struct ihsbin_alg4_opts* alg4; /* host, optional: Algorithm 4 parameters
+                              for adaptive_m = 2 (NULL: the defaults)            */
 } ihsbin_opts;
+
+/* Algorithm 4 (Section 5.1): IHS at lam with the direction
+ * D_k = (A^T S^T S A + lam I)^-1 grad f(X_k), delta_k = <D_k, grad f(X_k)>,
+ * the Armijo step of Eq. (armijo), and m doubled (S redrawn at 2m from the
+ * same seed) whenever an update leaves delta_{k+1} >= gamma3 delta_k.
+ * Fill with ihsbin_alg4_opts_default, then override. */
+typedef struct ihsbin_alg4_opts {
+  double gamma1;           /* Armijo steps tau = gamma1^j, in (0,1) (0.5)       */
+  double gamma2;           /* Armijo sufficient decrease, in (0,1) (1e-4)       */
+  double gamma3;           /* doubling threshold on delta_{k+1}/delta_k (0.5)    */
+  double eps;              /* stop once delta_k <= eps * delta_0 (1e-8)          */
+  int32_t max_iter;        /* IHS updates at most (50)                           */
+  int32_t max_armijo;      /* trial steps per line search at most (60); none
+                              accepted returns IHSBIN_ENOCONV                    */
+} ihsbin_alg4_opts;
+
+/* Filled by ihsbin_sketch_size. */
+typedef struct {
+  int64_t m;               /* sketch dimension at exit (n when S = I was used)  */
+  int32_t iters;           /* IHS updates taken                                  */
+  int32_t doublings;       /* times m was doubled                                */
+  double delta0;           /* delta of the first direction (X_0 = 0)            */
+  double delta;            /* delta at exit                                      */
+  double ms;               /* wall time of the call                              */
+} ihsbin_alg4_result;
 
 /* Precision of the sketched Gram. */
 enum { IHSBIN_GRAM_F64 = 0, IHSBIN_GRAM_BF16X3 = 1 };
@@ -154,6 +187,7 @@ const char* ihsbin_version(void);
  * k_max 96, L from Section 4.2, centred, adaptive m, rate 0.6, 12 Lanczos
  * steps, no timing. */
 void ihsbin_opts_default(ihsbin_opts* opts);
+void ihsbin_alg4_opts_default(ihsbin_alg4_opts* opts);
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t the
  * library enqueues on (borrowed, not destroyed); NULL means the null stream.
@@ -243,6 +277,21 @@ int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m,
  * EINVAL on bad sizes or prec. */
 int ihsbin_gram(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d, int32_t prec,
                 double* G);
+
+/* Adaptive sketch dimension (Section 5.1, Algorithm 4) for the problem at
+ * lam (the path's lam_min): runs the search from m0 = opts->m (0: max(16, d / 4),
+ * rounded up to a multiple of sjlt_s) with opts->sketch, sjlt_s, seed,
+ * gram_prec and the cap opts->m_max (0: min(n, 32 d); SRHT also at most the
+ * padded order), and returns the m it ends with.  A sketch of m >= n rows is
+ * replaced by S = I.  X (device, optional) receives the last iterate, d x K
+ * FP64 with row stride ldx (n < d: the dual iterate z, n x K).  trace (host,
+ * optional) receives 5 doubles per update, at most trace_rows updates:
+ * m in effect, tau_k, delta_k, delta_{k+1} from that sketch, 1.0 if m then
+ * doubled.  res (host) must not be NULL. */
+int ihsbin_sketch_size(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
+                       int64_t K, int64_t ldb, double lam, const ihsbin_opts* opts,
+                       const ihsbin_alg4_opts* alg4, ihsbin_alg4_result* res,
+                       double* X, int64_t ldx, double* trace, int32_t trace_rows);
 
 /* W = A^T A U: the two products of every basis step (Algorithm 2).  U: device
  * d x w doubles with row stride ldu; the buffer spans d * ldu doubles, and

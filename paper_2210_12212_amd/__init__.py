@@ -90,7 +90,7 @@ def default_opts(**kw) -> L.Opts:
     for k, v in kw.items():
         if k == "sketch" and isinstance(v, str):
             v = L.SKETCHES[v]
-        if k == "taus":
+        if k in ("taus", "alg4"):
             continue
         if not hasattr(o, k):
             raise KeyError(f"unknown option {k}")
@@ -103,6 +103,30 @@ def _taus_ptr(taus):
         return None, None
     arr = (C.c_double * len(taus))(*[float(t) for t in taus])
     return arr, C.cast(arr, C.POINTER(C.c_double))
+
+
+def alg4_opts(**kw) -> L.Alg4Opts:
+    """ihsbin_alg4_opts_default, then the given fields."""
+    a = L.Alg4Opts()
+    L.lib().ihsbin_alg4_opts_default(C.byref(a))
+    for k, v in kw.items():
+        if not hasattr(a, k):
+            raise KeyError(f"unknown Algorithm 4 option {k}")
+        setattr(a, k, v)
+    return a
+
+
+def _with_pointers(opts):
+    """Opts from keyword options plus the host arrays they point to (kept
+    alive by the caller for the duration of the call)."""
+    o = default_opts(**opts)
+    keep_t, ptr = _taus_ptr(opts.get("taus"))
+    o.taus = ptr
+    keep_a = None
+    if opts.get("alg4") is not None:
+        keep_a = alg4_opts(**opts["alg4"])
+        o.alg4 = C.pointer(keep_a)
+    return o, (keep_t, keep_a)
 
 
 class Context:
@@ -141,9 +165,7 @@ class Context:
         _require_cuda(Bm, "B")
         if Bm.stride(1) != 1:
             raise ValueError("B must have unit column stride")
-        o = default_opts(**opts)
-        keep, ptr = _taus_ptr(opts.get("taus"))
-        o.taus = ptr
+        o, keep = _with_pointers(opts)
         mat = _matrix(A)
         rep = L.Report()
         ph = C.c_void_p()
@@ -162,9 +184,7 @@ class Context:
         lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
         x_dtype = x_dtype or torch.float64
         X = torch.empty((len(lam), A.shape[1], Bm.shape[1]), dtype=x_dtype, device=Bm.device)
-        o = default_opts(**opts)
-        keep, ptr = _taus_ptr(opts.get("taus"))
-        o.taus = ptr
+        o, keep = _with_pointers(opts)
         mat = _matrix(A)
         rep = L.Report()
         rc = L.lib().ihsbin_solve_path(self._h, C.byref(mat), C.c_void_p(Bm.data_ptr()), Bm.shape[1],
@@ -175,6 +195,33 @@ class Context:
         r = rep.as_dict()
         r["status"] = rc
         return X, r
+
+    def sketch_size(self, A, B, lam: float, alg4=None, trace_rows: int = 64, **opts):
+        """ihsbin_sketch_size (Algorithm 4 at lam) -> (result dict, X, trace).
+
+        X is the last iterate (d x K float64; n < d: the dual iterate, n x K)
+        and trace a (updates x 5) float64 array of (m, tau, delta_k,
+        delta_{k+1}, doubled) rows."""
+        torch = _torch()
+        Bm = B if B.dim() == 2 else B.reshape(-1, 1)
+        _require_cuda(Bm, "B")
+        if Bm.stride(1) != 1:
+            raise ValueError("B must have unit column stride")
+        o, keep = _with_pointers(opts)
+        a = alg4_opts(**(alg4 or {}))
+        n, d = A.shape
+        rows = d if n >= d else n
+        X = torch.empty((rows, Bm.shape[1]), dtype=torch.float64, device=Bm.device)
+        tr = np.zeros((max(trace_rows, 0), 5))
+        res = L.Alg4Result()
+        mat = _matrix(A)
+        self._check(L.lib().ihsbin_sketch_size(
+            self._h, C.byref(mat), C.c_void_p(Bm.data_ptr()), Bm.shape[1], Bm.stride(0),
+            float(lam), C.byref(o), C.byref(a), C.byref(res), C.c_void_p(X.data_ptr()),
+            X.stride(0), tr.ctypes.data_as(C.POINTER(C.c_double)) if trace_rows > 0 else None,
+            int(trace_rows)))
+        r = res.as_dict()
+        return r, X, tr[:min(r["iters"], trace_rows)]
 
     # --------------------------------------------------------- step calls
     def sketch_draws(self, sketch: str, seed: int, n: int, m: int, sjlt_s: int = 1):

@@ -23,7 +23,7 @@ EXPORTED = [
     "ihsbin_path_get_info", "ihsbin_path_intervals", "ihsbin_path_basis", "ihsbin_path_free",
     "ihsbin_solve_path", "ihsbin_sketch_draws", "ihsbin_sketch_apply", "ihsbin_precond_factor",
     "ihsbin_ata_apply",
-    "ihsbin_gram",
+    "ihsbin_gram", "ihsbin_alg4_opts_default", "ihsbin_sketch_size",
 ]
 
 
@@ -33,13 +33,27 @@ class Matrix(C.Structure):
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p)]
 
 
+class Alg4Opts(C.Structure):
+    _fields_ = [("gamma1", C.c_double), ("gamma2", C.c_double), ("gamma3", C.c_double),
+                ("eps", C.c_double), ("max_iter", C.c_int32), ("max_armijo", C.c_int32)]
+
+
+class Alg4Result(C.Structure):
+    _fields_ = [("m", C.c_int64), ("iters", C.c_int32), ("doublings", C.c_int32),
+                ("delta0", C.c_double), ("delta", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Opts(C.Structure):
     _fields_ = [("sketch", C.c_int32), ("sjlt_s", C.c_int32), ("m", C.c_int64),
                 ("seed", C.c_uint64), ("tol", C.c_double), ("k_max", C.c_int32),
                 ("k_fixed", C.c_int32), ("L", C.c_int32), ("centred", C.c_int32),
                 ("adaptive_m", C.c_int32), ("rate_target", C.c_double), ("m_max", C.c_int64),
                 ("lanczos_steps", C.c_int32), ("timing", C.c_int32),
-                ("taus", C.POINTER(C.c_double)), ("gram_prec", C.c_int32)]
+                ("taus", C.POINTER(C.c_double)), ("gram_prec", C.c_int32),
+                ("alg4", C.POINTER(Alg4Opts))]
 
 
 class Report(C.Structure):
@@ -85,6 +99,10 @@ def _declare(lib):
         "ihsbin_precond_factor": (C.c_int, [vp, vp, i64, i64, pd, i32, vp, vp]),
         "ihsbin_ata_apply": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64]),
         "ihsbin_gram": (C.c_int, [vp, vp, i64, i64, i32, vp]),
+        "ihsbin_alg4_opts_default": (None, [C.POINTER(Alg4Opts)]),
+        "ihsbin_sketch_size": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, dbl,
+                                         C.POINTER(Opts), C.POINTER(Alg4Opts),
+                                         C.POINTER(Alg4Result), vp, i64, pd, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -84,6 +84,18 @@ void launch_csr_spmm_t(const MatView& A, const double* Y, int64_t w, int64_t ldy
 void launch_csr_atb(const MatView& A, const void* B, int64_t K, int64_t ldb, double* C,
                     hipStream_t st);
 
+// ------------------------------------------------ adaptive m (Algorithm 4)
+// out[0..2] = (D.G, D.W, D.D) over count entries (W may be null: out[1] = 0);
+// part: dots3_part_doubles() doubles of device scratch.  Fixed-order sums.
+int dots3_part_doubles();
+void launch_dots3(const double* D, const double* G, const double* W, int64_t count, double* part,
+                  double* out, hipStream_t st);
+// X -= tau D and Gr -= tau (W + lam D), elementwise over count entries.
+void launch_alg4_step(double* X, double* Gr, const double* D, const double* W, int64_t count,
+                      double tau, double lam, hipStream_t st);
+// X = 0 and Gr = -C.
+void launch_alg4_init(const double* C, double* X, double* Gr, int64_t count, hipStream_t st);
+
 // ------------------------------------------------------------ basis kernels
 struct StepParams;  // defined in basis.hip users
 void launch_fill(double* p, int64_t count, double v, hipStream_t st);

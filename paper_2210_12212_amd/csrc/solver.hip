@@ -519,6 +519,193 @@ struct Timer {
   }
 };
 
+// The primal form every step runs on: A itself, or for n < d the dual problem
+// (Section 5.2, Eq. (ls_reg:d)).  The dual's optimality condition
+// (A A^T + lam I) z = b is the primal form for the d x n matrix A^T with
+// right-hand side b itself, and x = A^T z; A^T is materialized once.
+// C = A^T B (dual: B widened), d x K.
+struct Form {
+  MatView A;
+  bool dual = false;
+  PoolBuf At, Cb;
+  double* C = nullptr;
+  explicit Form(Pool& p) : At(p), Cb(p) {}
+};
+
+static void make_form(Ctx& c, const MatView& A0, const void* B, int64_t K, int64_t ldb, Form& f) {
+  if (!B) fail(IHSBIN_EINVAL, "B is NULL");
+  if (K < 1 || ldb < K) fail(IHSBIN_EINVAL, "need K >= 1 and ldb >= K");
+  f.dual = A0.n < A0.d;
+  if (f.dual && A0.format != IHSBIN_DENSE)
+    fail(IHSBIN_EUNSUP, "n < d with a CSR matrix (the dual is built for dense A)");
+  f.A = A0;
+  if (f.dual) {
+    const size_t es = A0.dtype == IHSBIN_F32 ? 4 : 8;
+    void* At = f.At.ensure(es * (size_t)A0.n * (size_t)A0.d);
+    launch_transpose(A0, At, c.stream);
+    f.A.n = A0.d;
+    f.A.d = A0.n;
+    f.A.ld = A0.n;
+    f.A.vals = At;
+  }
+  if (f.A.format == IHSBIN_CSR) validate_csr(c, f.A);
+  const int64_t d = f.A.d;
+  f.C = static_cast<double*>(f.Cb.ensure(sizeof(double) * d * K));
+  if (f.dual) launch_widen_rows(B, A0.dtype, d, K, ldb, f.C, c.stream);
+  else atb_apply(c, f.A, B, K, ldb, f.C);
+}
+
+// Sketch of the working form at a given m into SA, then G = (SA)^T SA.  A
+// sketch of m >= n rows is no cheaper than A itself and embeds it no better
+// than S = I does: then SA = A and P_S is the exact (A^T A + lam0 I)^-1.
+struct Sketcher {
+  Ctx& c;
+  const MatView& A;
+  const ihsbin_opts& o;
+  int s;
+  int64_t m_cap;
+  PoolBuf SAb, Gb;
+  double* G;
+  int trials = 0;
+  Sketcher(Ctx& cc, const MatView& AA, const ihsbin_opts& oo)
+      : c(cc), A(AA), o(oo), SAb(cc.pool), Gb(cc.pool) {
+    s = o.sketch == IHSBIN_SJLT ? std::max(1, o.sjlt_s) : 1;
+    const int64_t m = initial_m(2 * A.d);
+    m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(A.n, 32 * A.d));
+    if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(A.n)));
+    G = static_cast<double*>(Gb.ensure(sizeof(double) * A.d * A.d));
+  }
+  // o.m rounded up to a multiple of s, or dflt when o.m is 0
+  int64_t initial_m(int64_t dflt) const {
+    int64_t m = o.m > 0 ? o.m : std::max<int64_t>(1, dflt);
+    if (m % s) m += s - m % s;
+    return m;
+  }
+  void operator()(int64_t mm) {
+    const int64_t rows = mm >= A.n ? A.n : mm;
+    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * A.d));
+    if (mm >= A.n) {
+      logf("m=%lld >= n=%lld: exact Hessian (S = I)", (long long)mm, (long long)A.n);
+      copy_rows_f64(c, A, SA);
+    } else {
+      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT);
+    }
+    gram_impl(c, SA, rows, A.d, G, o.gram_prec);
+    ++trials;
+  }
+  void release() {
+    SAb.release();
+    Gb.release();
+  }
+};
+
+// Adaptive sketch dimension (Section 5.1, Algorithm 4): IHS on
+// f(X) = 1/2 ||A X - B||^2 + lam/2 ||X||^2 from X = 0 with the direction
+// D = P_S grad f, delta = <D, grad f>, a backtracking (Armijo) step
+// tau = gamma1^j, and m doubled (S redrawn at 2m) whenever an update leaves
+// delta_{k+1} >= gamma3 delta_k.  f is quadratic, so with H D = A^T A D + lam D
+// from one pass over A, f(X - tau D) - f(X) = -tau delta + tau^2 <D, H D> / 2
+// decides every trial step, and grad f(X - tau D) = grad f - tau H D: one
+// pass per update.  The final sketch is left in sk (its G and SA).
+// trace (optional): 5 values per update (m, tau, delta_k, delta_{k+1} from
+// the same sketch, 1 if m doubled).
+static ihsbin_alg4_result alg4_impl(Ctx& c, const MatView& A, const double* C, int64_t K,
+                                    double lam, int64_t m0, const ihsbin_alg4_opts& p,
+                                    Sketcher& sk, double* X_out, int64_t ldx,
+                                    std::vector<double>* trace) {
+  if (!(p.gamma1 > 0.0 && p.gamma1 < 1.0) || !(p.gamma2 > 0.0 && p.gamma2 < 1.0) ||
+      !(p.gamma3 > 0.0) || !(p.eps >= 0.0) || p.max_iter < 0 || p.max_armijo < 1)
+    fail(IHSBIN_EINVAL, "Algorithm 4 parameters out of range");
+  if (!(lam > 0.0) || !std::isfinite(lam)) fail(IHSBIN_EINVAL, "need lam > 0");
+  Timer t0;
+  hipStream_t st = c.stream;
+  const int64_t d = A.d, cnt = d * K;
+  PoolBuf xb(c.pool), gb(c.pool), db(c.pool), tb(c.pool), wb(c.pool), lfb(c.pool), lib(c.pool),
+      dinvb(c.pool), lamb(c.pool), idb(c.pool), partb(c.pool);
+  double* X = static_cast<double*>(xb.ensure(sizeof(double) * cnt));
+  double* Gr = static_cast<double*>(gb.ensure(sizeof(double) * cnt));
+  double* D = static_cast<double*>(db.ensure(sizeof(double) * cnt));
+  double* T = static_cast<double*>(tb.ensure(sizeof(double) * cnt));
+  double* W = static_cast<double*>(wb.ensure(sizeof(double) * cnt));
+  double* Lf = static_cast<double*>(lfb.ensure(sizeof(double) * d * d));
+  double* Li = static_cast<double*>(lib.ensure(sizeof(double) * d * d));
+  int32_t* ids = static_cast<int32_t*>(idb.ensure(sizeof(int32_t)));
+  IHS_HIP(hipMemsetAsync(ids, 0, sizeof(int32_t), st));
+  double* part = static_cast<double*>(partb.ensure(sizeof(double) * (dots3_part_doubles() + 3)));
+  double* dev_out = part + dots3_part_doubles();
+  double h[3];
+  auto dots = [&](const double* Wp) {
+    launch_dots3(D, Gr, Wp, cnt, part, dev_out, st);
+    IHS_HIP(hipMemcpyAsync(h, dev_out, sizeof(h), hipMemcpyDeviceToHost, st));
+    IHS_HIP(hipStreamSynchronize(st));
+  };
+  auto redraw = [&](int64_t m) {
+    sk(m);
+    factor_impl(c, sk.G, d, {lam}, Lf, Li, dinvb, lamb);
+  };
+  // D = P_S Gr and delta = <D, Gr>
+  auto direction = [&]() {
+    apply_p(c, Li, ids, 1, d, K, K, Gr, T, D);
+    dots(nullptr);
+    return h[0];
+  };
+  ihsbin_alg4_result r;
+  std::memset(&r, 0, sizeof(r));
+  int64_t m = m0;
+  redraw(m);
+  launch_alg4_init(C, X, Gr, cnt, st);
+  double delta = direction();
+  r.delta0 = delta;
+  int k = 0;
+  while (delta > p.eps * r.delta0 && k < p.max_iter) {
+    ata_apply(c, A, D, K, K, W, K, nullptr);
+    dots(W);
+    const double q = h[1] + lam * h[2];  // <D, H D>
+    double tau = 1.0;
+    int j = 0;
+    while (!(-tau * delta + 0.5 * tau * tau * q <= -p.gamma2 * tau * delta)) {
+      if (++j >= p.max_armijo) fail(IHSBIN_ENOCONV, "Armijo search found no step");
+      tau *= p.gamma1;
+    }
+    launch_alg4_step(X, Gr, D, W, cnt, tau, lam, st);
+    const double dn = direction();
+    const int64_t m_step = m;
+    int doubled = 0;
+    double delta_new = dn;
+    if (dn >= p.gamma3 * delta && m < sk.m_cap) {
+      int64_t m_new = std::min(2 * m, sk.m_cap);
+      if (sk.s > 1 && m_new < A.n) m_new -= m_new % sk.s;
+      if (m_new > m) {
+        m = m_new;
+        redraw(m);
+        delta_new = direction();
+        doubled = 1;
+        ++r.doublings;
+      }
+    }
+    if (trace) {
+      trace->push_back((double)m_step);
+      trace->push_back(tau);
+      trace->push_back(delta);
+      trace->push_back(dn);
+      trace->push_back((double)doubled);
+    }
+    logf("alg4 k=%d m=%lld tau=%g delta=%.6g -> %.6g%s", k, (long long)m_step, tau, delta, dn,
+         doubled ? " (m doubled)" : "");
+    delta = delta_new;
+    ++k;
+  }
+  if (X_out)
+    IHS_HIP(hipMemcpy2DAsync(X_out, sizeof(double) * ldx, X, sizeof(double) * K,
+                             sizeof(double) * K, d, hipMemcpyDeviceToDevice, st));
+  IHS_HIP(hipStreamSynchronize(st));
+  r.m = std::min<int64_t>(m, A.n);
+  r.iters = k;
+  r.delta = delta;
+  r.ms = t0.ms();
+  return r;
+}
+
 static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K, int64_t ldb,
                       double lam_min, double lam_max, const ihsbin_opts* o_in,
                       ihsbin_path** out, ihsbin_report* rep) {
@@ -528,36 +715,21 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   if (o_in) o = *o_in;
   else ihsbin_opts_default(&o);
   const MatView A0 = check_matrix(Ain);
-  if (!B) fail(IHSBIN_EINVAL, "B is NULL");
-  if (K < 1 || ldb < K) fail(IHSBIN_EINVAL, "need K >= 1 and ldb >= K");
   if (!(lam_min > 0.0) || !(lam_max >= lam_min) || !std::isfinite(lam_max))
     fail(IHSBIN_EINVAL, "need 0 < lam_min <= lam_max");
-  // n < d: the dual problem (Section 5.2, Eq. (ls_reg:d)).  Its optimality
-  // condition (A A^T + lam I) z = b is the primal form for the d x n matrix
-  // A^T with right-hand side b itself, and x = A^T z.  Everything below runs
-  // on A^T (materialized once); the basis is mapped to x at the end.
-  const bool dual = A0.n < A0.d;
-  if (dual && A0.format != IHSBIN_DENSE)
-    fail(IHSBIN_EUNSUP, "n < d with a CSR matrix (the dual is built for dense A)");
-  PoolBuf Atb(c.pool);
-  MatView A = A0;
-  if (dual) {
-    const size_t es = A0.dtype == IHSBIN_F32 ? 4 : 8;
-    void* At = Atb.ensure(es * (size_t)A0.n * (size_t)A0.d);
-    launch_transpose(A0, At, c.stream);
-    A.n = A0.d;
-    A.d = A0.n;
-    A.ld = A0.n;
-    A.vals = At;
-  }
   if (o.k_max < 1 || o.k_max > 4096) fail(IHSBIN_EINVAL, "k_max out of range");
   if (o.k_fixed < 0 || o.k_fixed > 4096) fail(IHSBIN_EINVAL, "k_fixed out of range");
   if (!(o.tol > 0.0)) fail(IHSBIN_EINVAL, "tol must be positive");
-  if (A.format == IHSBIN_CSR) validate_csr(c, A);
+  if (o.adaptive_m < 0 || o.adaptive_m > 2) fail(IHSBIN_EINVAL, "adaptive_m out of range");
   hipStream_t st = c.stream;
   Timer total;
   ihsbin_report r;
   std::memset(&r, 0, sizeof(r));
+  Form form(c.pool);
+  make_form(c, A0, B, K, ldb, form);
+  const MatView& A = form.A;
+  const bool dual = form.dual;
+  const double* C = form.C;
 
   // ---- interval plan (Section 4.2)
   const double beta = lam_max / lam_min;
@@ -568,37 +740,15 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   for (int l = 0; l < L; ++l) lam0[l] = std::sqrt(grid[l] * grid[l + 1]);
   const int64_t d = A.d;
 
-  // ---- C = A^T B (dual: C = B)
-  PoolBuf Cb(c.pool);
-  double* C = static_cast<double*>(Cb.ensure(sizeof(double) * d * K));
-  if (dual) launch_widen_rows(B, A0.dtype, d, K, ldb, C, st);
-  else atb_apply(c, A, B, K, ldb, C);
-
   // ---- sketch, with adaptive m
   Timer tsk;
-  int64_t m = o.m > 0 ? o.m : 2 * d;
-  int s = o.sketch == IHSBIN_SJLT ? std::max(1, o.sjlt_s) : 1;
-  if (m % s) m += s - m % s;
-  int64_t m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(A.n, 32 * d));
-  if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(A.n)));
-  PoolBuf SAb(c.pool), Gb(c.pool), Lb(c.pool), Ib(c.pool), dinvb(c.pool), lamb(c.pool);
-  double* G = static_cast<double*>(Gb.ensure(sizeof(double) * d * d));
+  Sketcher sketch_m(c, A, o);
+  int64_t m = sketch_m.initial_m(2 * d);
+  const int64_t m_cap = sketch_m.m_cap;
+  const int& trials = sketch_m.trials;
+  PoolBuf Lb(c.pool), Ib(c.pool), dinvb(c.pool), lamb(c.pool);
+  double* G = sketch_m.G;
   std::vector<Spec> spec;
-  int trials = 0;
-  // A sketch of m >= n rows is no cheaper than A itself and embeds it no better
-  // than S = I does: then SA = A and P_S is the exact (A^T A + lam0 I)^-1.
-  auto sketch_m = [&](int64_t mm) {
-    const int64_t rows = mm >= A.n ? A.n : mm;
-    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * d));
-    if (mm >= A.n) {
-      logf("m=%lld >= n=%lld: exact Hessian (S = I)", (long long)mm, (long long)A.n);
-      copy_rows_f64(c, A, SA);
-    } else {
-      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT);
-    }
-    gram_impl(c, SA, rows, d, G, o.gram_prec);
-    ++trials;
-  };
   // Predicted contraction rate of interval l from its spectrum estimate.
   auto rate_of = [&](const Spec& sp) { return (sp.mu_max - sp.mu_min) / (sp.mu_max + sp.mu_min); };
   // Next m when the lowest interval is too slow: the Gaussian theorem's edges
@@ -618,7 +768,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     while (mult < factor) mult <<= 1;
     return std::min(m_cap, m * mult);
   };
-  const bool adapt = o.adaptive_m && !o.taus;
+  const bool adapt = o.adaptive_m == 1 && !o.taus;
   // Sketches whose cost does not grow with m (SRHT: one transform;
   // CountSketch/SJLT: one pass over A) only pay for m through the 2 m d^2
   // Gram.  With m < d such a sketch leaves P_S = 1/lam0 on the null space of
@@ -630,7 +780,19 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
          (long long)m_cap);
     m = m_cap;
   }
-  sketch_m(m);
+  if (o.adaptive_m == 2) {
+    // Algorithm 4 at lam_min from m0 = m (default d / 4); it leaves its
+    // final sketch in place
+    ihsbin_alg4_opts ap;
+    ihsbin_alg4_opts_default(&ap);
+    if (o.alg4) ap = *o.alg4;
+    const int64_t m0 = sketch_m.initial_m(std::max<int64_t>(16, d / 4));
+    const ihsbin_alg4_result ar = alg4_impl(c, A, C, K, lam_min, m0, ap, sketch_m, nullptr, 0,
+                                            nullptr);
+    m = ar.m;
+  } else {
+    sketch_m(m);
+  }
   // Probe: factor and estimate the lowest interval only (the Lanczos run stops
   // early once its Ritz values already show a rate above the target).  When m
   // is too small, cheap sketches go straight to the cap; the Gaussian sketch
@@ -689,8 +851,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     }
     break;
   }
-  Gb.release();
-  SAb.release();
+  sketch_m.release();
   r.m_used = std::min<int64_t>(m, A.n);
   r.sketch_trials = trials;
   for (int l = 0; l < L && log_enabled(); ++l)
@@ -1016,6 +1177,18 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->gram_prec = IHSBIN_GRAM_F64;
   o->timing = 0;
   o->taus = nullptr;
+  o->alg4 = nullptr;
+}
+
+void ihsbin_alg4_opts_default(ihsbin_alg4_opts* a) {
+  if (!a) return;
+  std::memset(a, 0, sizeof(*a));
+  a->gamma1 = 0.5;
+  a->gamma2 = 1e-4;
+  a->gamma3 = 0.5;
+  a->eps = 1e-8;
+  a->max_iter = 50;
+  a->max_armijo = 60;
 }
 
 int ihsbin_create(ihsbin_ctx** ctx, int device, void* stream) {
@@ -1189,6 +1362,36 @@ int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t 
     std::vector<double> l0(lam0, lam0 + nl);
     factor_impl(ctx->c, G, d, l0, Lfac, Linv, dinvb, lamb);
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_sketch_size(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B, int64_t K,
+                       int64_t ldb, double lam, const ihsbin_opts* opts,
+                       const ihsbin_alg4_opts* alg4, ihsbin_alg4_result* res, double* X,
+                       int64_t ldx, double* trace, int32_t trace_rows) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    if (!res) fail(IHSBIN_EINVAL, "res is NULL");
+    if (trace_rows < 0 || (trace_rows > 0 && !trace)) fail(IHSBIN_EINVAL, "bad trace buffer");
+    ihsbin_opts o;
+    if (opts) o = *opts;
+    else ihsbin_opts_default(&o);
+    ihsbin_alg4_opts ap;
+    if (alg4) ap = *alg4;
+    else ihsbin_alg4_opts_default(&ap);
+    const MatView A0 = check_matrix(A);
+    Form form(ctx->c.pool);
+    make_form(ctx->c, A0, B, K, ldb, form);
+    if (X && ldx < K) fail(IHSBIN_EINVAL, "ldx < K");
+    Sketcher sk(ctx->c, form.A, o);
+    const int64_t m0 = sk.initial_m(std::max<int64_t>(16, form.A.d / 4));
+    std::vector<double> tr;
+    *res = alg4_impl(ctx->c, form.A, form.C, K, lam, m0, ap, sk, X, ldx,
+                     trace_rows > 0 ? &tr : nullptr);
+    const size_t rows = std::min<size_t>(tr.size() / 5, (size_t)trace_rows);
+    if (rows) std::memcpy(trace, tr.data(), sizeof(double) * 5 * rows);
     return IHSBIN_OK;
   });
 }

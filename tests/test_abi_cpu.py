@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "ihsbin.h")
 
 def _declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(ihsbin_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(ihsbin_[a-z0-9_]+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")
@@ -59,3 +59,16 @@ def test_struct_sizes_match_header_layout():
     # int32 x2, int64 x4, pointers x3
     assert C.sizeof(_lib.Matrix) == 8 + 32 + 24
     assert C.sizeof(_lib.PathInfo) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4  # ..., centred, dual
+    assert C.sizeof(_lib.Alg4Opts) == 4 * 8 + 4 + 4
+    assert C.sizeof(_lib.Alg4Result) == 8 + 4 + 4 + 3 * 8
+
+
+def test_alg4_default_options(lib):
+    from paper_2210_12212_amd import _lib
+    a = _lib.Alg4Opts()
+    lib.ihsbin_alg4_opts_default(C.byref(a))
+    assert (a.gamma1, a.gamma2, a.gamma3, a.eps) == (0.5, 1e-4, 0.5, 1e-8)
+    assert a.max_iter == 50 and a.max_armijo == 60
+    o = _lib.Opts()
+    lib.ihsbin_opts_default(C.byref(o))
+    assert not o.alg4
