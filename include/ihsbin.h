@@ -50,7 +50,8 @@ typedef enum {
   IHSBIN_ENOCONV = -5,  /* an interval hit k_max before its stop test passed;
                            the path is still built and usable                */
   IHSBIN_ERANGE = -6,   /* a lam outside the prepared [lam_min, lam_max]     */
-  IHSBIN_EUNSUP = -7    /* unsupported combination (n < d, dtype, ...)       */
+  IHSBIN_EUNSUP = -7,   /* unsupported combination (n < d CSR, dtype, ...)    */
+  IHSBIN_EAGAIN = -8    /* a served request is not finished yet               */
 } ihsbin_status;
 
 enum { IHSBIN_DENSE = 0, IHSBIN_CSR = 1 };
@@ -164,6 +165,9 @@ typedef struct {
   double ata_ms_w;         /* summed event time of the W = A^T Y launches (the
                               product kernel; its split-K reduction excluded)   */
   double ata_bytes_a;      /* algorithmic bytes of A read by those launches      */
+  int64_t peak_bytes;      /* device memory held through the context at the
+                              build's peak: its pool, workspaces (including those
+                              kept from earlier calls) and the path's buffers    */
 } ihsbin_report;
 
 /* Per-interval description of a built path (host arrays of length L). */
@@ -300,6 +304,78 @@ int ihsbin_sketch_size(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
  * only columns [0, w) are written. */
 int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U,
                      int64_t w, int64_t ldu, double* W, int64_t ldw);
+
+/* ----------------------------------------------------------------- serving
+ * Independent path builds on one device, run concurrently by worker slots
+ * (each a context with its own stream) and admitted in arrival order while
+ * the sum of the admitted builds' ihsbin_build_footprint estimates stays
+ * within hbm_budget.  A build that still fails with IHSBIN_ENOMEM is queued
+ * again at the front and runs with nothing else in flight.  Every build runs
+ * the same kernels as it would alone, so a result does not depend on what
+ * else is served (CountSketch/SJLT and CSR products add with atomics, whose
+ * order can change the last bits).  The path of a finished request is the
+ * caller's: its basis stays resident for any number of ihsbin_path_eval
+ * calls until ihsbin_path_free.  Thread-safe: submit and wait may be called
+ * from any threads. */
+typedef struct ihsbin_server ihsbin_server;
+
+typedef struct {
+  int32_t workers;         /* concurrent builds (1..16, default 4)              */
+  int32_t reserved;
+  int64_t hbm_budget;      /* bytes the admitted builds may need together
+                              (0: 90 % of the free device memory at creation) */
+  int64_t keep_bytes;      /* device memory a worker keeps between builds
+                              (default 1 GiB); above it the worker trims       */
+} ihsbin_server_opts;
+
+typedef struct {
+  int32_t status;          /* the build's status (ihsbin_server_wait's result) */
+  int32_t worker;          /* worker slot that ran it                           */
+  int64_t footprint;       /* its admission estimate (bytes)                    */
+  double ms_queue;         /* submission to start of the build                  */
+  double ms_build;         /* the build                                         */
+  double ms_total;         /* submission to completion                          */
+  ihsbin_report report;
+  char message[160];       /* error text when status is not IHSBIN_OK           */
+} ihsbin_request_info;
+
+typedef struct {
+  int64_t submitted, completed;
+  int64_t retried;         /* builds re-run alone after IHSBIN_ENOMEM           */
+  int32_t workers, queued, inflight, max_concurrent;
+  int64_t budget, inflight_bytes, max_inflight_bytes;
+} ihsbin_server_stats;
+
+/* Upper estimate of the device memory one ihsbin_path_build allocates for a
+ * problem of this shape and these options (every buffer at its largest size,
+ * the sketch at its cap; A, B and outputs are the caller's).  Only A's
+ * format, dtype, n and d are read (its pointers may be NULL). */
+int ihsbin_build_footprint(const ihsbin_matrix* A, int64_t K, double lam_min,
+                           double lam_max, const ihsbin_opts* opts, int64_t* bytes);
+/* Bind a path to another stream for its later calls (waits for the old one). */
+int ihsbin_path_set_stream(ihsbin_path* path, void* hip_stream);
+
+void ihsbin_server_opts_default(ihsbin_server_opts* opts);
+int ihsbin_server_create(ihsbin_server** server, int device, const ihsbin_server_opts* opts);
+/* Queue a build (the arguments of ihsbin_path_build; opts may be NULL, and
+ * its taus / alg4 arrays are copied).  A and B must hold their values on the
+ * device when this is called and stay valid until the request is collected
+ * by ihsbin_server_wait.  IHSBIN_ENOMEM: the estimate exceeds the budget. */
+int ihsbin_server_submit(ihsbin_server* server, const ihsbin_matrix* A, const void* B,
+                         int64_t K, int64_t ldb, double lam_min, double lam_max,
+                         const ihsbin_opts* opts, int64_t* id);
+/* Wait for request id (timeout_ms < 0: without limit; IHSBIN_EAGAIN when it
+ * is not finished in time).  Once finished it is collected: path (optional)
+ * receives the built path bound to hip_stream (NULL: the null stream; freed
+ * here when path is NULL), info (optional) its timings and report; the return
+ * value is the build's status.  An id is collected once. */
+int ihsbin_server_wait(ihsbin_server* server, int64_t id, int64_t timeout_ms,
+                       void* hip_stream, ihsbin_path** path, ihsbin_request_info* info);
+int ihsbin_server_get_stats(ihsbin_server* server, ihsbin_server_stats* stats);
+const char* ihsbin_server_last_error(ihsbin_server* server);
+/* Finishes every queued request, then frees the workers and every path not
+ * yet collected. */
+int ihsbin_server_destroy(ihsbin_server* server);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["Context", "Path", "CsrInput", "IhsbinError", "solve_path", "default_opts"]
+__all__ = ["Context", "Path", "Server", "CsrInput", "IhsbinError", "solve_path",
+           "default_opts", "build_footprint"]
 
 
 class IhsbinError(RuntimeError):
@@ -285,12 +286,107 @@ class Context:
         return W
 
 
+def build_footprint(shape, K: int, lam_min: float, lam_max: float, csr: bool = False,
+                    dtype: str = "float32", **opts) -> int:
+    """ihsbin_build_footprint: upper estimate (bytes) of the device memory one
+    build allocates for an n x d problem with K right-hand sides."""
+    m = L.Matrix()
+    m.format = L.CSR if csr else L.DENSE
+    m.dtype = L.F32 if dtype == "float32" else L.F64
+    m.n, m.d = int(shape[0]), int(shape[1])
+    m.ld = m.d
+    o, keep = _with_pointers(opts)
+    out = C.c_int64()
+    rc = L.lib().ihsbin_build_footprint(C.byref(m), int(K), float(lam_min), float(lam_max),
+                                        C.byref(o), C.byref(out))
+    if rc != L.OK:
+        raise IhsbinError(rc, "ihsbin_build_footprint")
+    return int(out.value)
+
+
+class Server:
+    """ihsbin_server_*: concurrent path builds on one device.
+
+    submit() keeps references to A and B until the request is collected by
+    wait(), which returns (Path or None, info dict); the path is bound to the
+    given torch stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, workers: int = 4, hbm_budget: int = 0,
+                 keep_bytes: int | None = None):
+        o = L.ServerOpts()
+        L.lib().ihsbin_server_opts_default(C.byref(o))
+        o.workers, o.hbm_budget = workers, hbm_budget
+        if keep_bytes is not None:
+            o.keep_bytes = keep_bytes
+        h = C.c_void_p()
+        rc = L.lib().ihsbin_server_create(C.byref(h), device, C.byref(o))
+        if rc != L.OK:
+            raise IhsbinError(rc, "ihsbin_server_create")
+        self._h = h
+        self.device = device
+        self._held = {}
+
+    def submit(self, A, B, lam_min: float, lam_max: float, **opts) -> int:
+        Bm = B if B.dim() == 2 else B.reshape(-1, 1)
+        _require_cuda(Bm, "B")
+        if Bm.stride(1) != 1:
+            raise ValueError("B must have unit column stride")
+        o, keep = _with_pointers(opts)
+        mat = _matrix(A)
+        # the caller's pending work on A and B must be complete on the device
+        _torch().cuda.current_stream(self.device).synchronize()
+        rid = C.c_int64()
+        rc = L.lib().ihsbin_server_submit(self._h, C.byref(mat), C.c_void_p(Bm.data_ptr()),
+                                          Bm.shape[1], Bm.stride(0), float(lam_min),
+                                          float(lam_max), C.byref(o), C.byref(rid))
+        if rc != L.OK:
+            raise IhsbinError(rc, L.lib().ihsbin_server_last_error(self._h).decode())
+        self._held[rid.value] = (A, Bm)
+        return rid.value
+
+    def wait(self, rid: int, timeout_ms: int = -1, stream=None, allow_noconv: bool = True):
+        """-> (Path, info) once finished; (None, None) when timeout_ms runs out."""
+        torch = _torch()
+        stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ph = C.c_void_p()
+        info = L.RequestInfo()
+        rc = L.lib().ihsbin_server_wait(self._h, int(rid), int(timeout_ms),
+                                        C.c_void_p(stream.cuda_stream), C.byref(ph), C.byref(info))
+        if rc == L.EAGAIN:
+            return None, None
+        self._held.pop(rid, None)
+        d = info.as_dict()
+        if rc != L.OK and not (allow_noconv and rc == L.ENOCONV):
+            if ph.value:
+                L.lib().ihsbin_path_free(ph)
+            raise IhsbinError(rc, d["message"])
+        return Path(ph, device=self.device), d
+
+    def stats(self) -> dict:
+        st = L.ServerStats()
+        L.lib().ihsbin_server_get_stats(self._h, C.byref(st))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ihsbin_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Path:
     """A built path (ihsbin_path): basis resident on the device."""
 
-    def __init__(self, handle, ctx: Context):
+    def __init__(self, handle, ctx: Context | None = None, device: int | None = None):
         self._h = handle
         self._ctx = ctx
+        self.device = ctx.device if ctx is not None else (device or 0)
         info = L.PathInfo()
         rc = L.lib().ihsbin_path_get_info(self._h, C.byref(info))
         if rc != L.OK:
@@ -305,7 +401,7 @@ class Path:
         lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
         if out is None:
             out = torch.empty((len(lam), self.d, self.K), dtype=dtype or torch.float64,
-                              device=torch.device("cuda", self._ctx.device))
+                              device=torch.device("cuda", self.device))
         rc = L.lib().ihsbin_path_eval(self._h, lam.ctypes.data_as(C.POINTER(C.c_double)), len(lam),
                                       C.c_void_p(out.data_ptr()), out.stride(1), _dtype_code(out))
         if rc != L.OK:

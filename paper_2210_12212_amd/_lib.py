@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libihsbin.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, ERANGE, EUNSUP = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, ERANGE, EUNSUP, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7, -8
 DENSE, CSR = 0, 1
 F32, F64 = 0, 1
 GAUSSIAN, SRHT, COUNTSKETCH, SJLT = 0, 1, 2, 3
@@ -24,6 +24,9 @@ EXPORTED = [
     "ihsbin_solve_path", "ihsbin_sketch_draws", "ihsbin_sketch_apply", "ihsbin_precond_factor",
     "ihsbin_ata_apply",
     "ihsbin_gram", "ihsbin_alg4_opts_default", "ihsbin_sketch_size",
+    "ihsbin_build_footprint", "ihsbin_path_set_stream", "ihsbin_server_opts_default",
+    "ihsbin_server_create", "ihsbin_server_submit", "ihsbin_server_wait",
+    "ihsbin_server_get_stats", "ihsbin_server_last_error", "ihsbin_server_destroy",
 ]
 
 
@@ -63,7 +66,35 @@ class Report(C.Structure):
                 ("ms_sketch", C.c_double), ("ms_factor", C.c_double),
                 ("ms_spectrum", C.c_double), ("ms_basis", C.c_double), ("ms_total", C.c_double),
                 ("ata_launches", C.c_int64), ("ata_flops", C.c_double), ("ata_ms_y", C.c_double),
-                ("ata_ms_w", C.c_double), ("ata_bytes_a", C.c_double)]
+                ("ata_ms_w", C.c_double), ("ata_bytes_a", C.c_double),
+                ("peak_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("reserved", C.c_int32), ("hbm_budget", C.c_int64),
+                ("keep_bytes", C.c_int64)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("worker", C.c_int32), ("footprint", C.c_int64),
+                ("ms_queue", C.c_double), ("ms_build", C.c_double), ("ms_total", C.c_double),
+                ("report", Report), ("message", C.c_char * 160)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("report", "message")}
+        d["report"] = self.report.as_dict()
+        d["message"] = self.message.decode(errors="replace")
+        return d
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("retried", C.c_int64),
+                ("workers", C.c_int32), ("queued", C.c_int32), ("inflight", C.c_int32),
+                ("max_concurrent", C.c_int32), ("budget", C.c_int64),
+                ("inflight_bytes", C.c_int64), ("max_inflight_bytes", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -100,6 +131,18 @@ def _declare(lib):
         "ihsbin_ata_apply": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64]),
         "ihsbin_gram": (C.c_int, [vp, vp, i64, i64, i32, vp]),
         "ihsbin_alg4_opts_default": (None, [C.POINTER(Alg4Opts)]),
+        "ihsbin_build_footprint": (C.c_int, [C.POINTER(Matrix), i64, dbl, dbl, C.POINTER(Opts),
+                                             C.POINTER(C.c_int64)]),
+        "ihsbin_path_set_stream": (C.c_int, [vp, vp]),
+        "ihsbin_server_opts_default": (None, [C.POINTER(ServerOpts)]),
+        "ihsbin_server_create": (C.c_int, [C.POINTER(vp), C.c_int, C.POINTER(ServerOpts)]),
+        "ihsbin_server_submit": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, dbl, dbl,
+                                           C.POINTER(Opts), C.POINTER(C.c_int64)]),
+        "ihsbin_server_wait": (C.c_int, [vp, i64, i64, vp, C.POINTER(vp),
+                                         C.POINTER(RequestInfo)]),
+        "ihsbin_server_get_stats": (C.c_int, [vp, C.POINTER(ServerStats)]),
+        "ihsbin_server_last_error": (C.c_char_p, [vp]),
+        "ihsbin_server_destroy": (C.c_int, [vp]),
         "ihsbin_sketch_size": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, dbl,
                                          C.POINTER(Opts), C.POINTER(Alg4Opts),
                                          C.POINTER(Alg4Result), vp, i64, pd, i32]),

@@ -34,18 +34,46 @@ struct Error : std::runtime_error {
 #define IHS_CHECK_LAUNCH() IHS_HIP(hipGetLastError())
 
 // ------------------------------------------------------- device buffers
+// Device bytes held through one context (its pool and workspaces) and their
+// high-water mark.
+struct MemStats {
+  int64_t live = 0, peak = 0;
+  void add(int64_t b) {
+    live += b;
+    if (live > peak) peak = live;
+  }
+  void sub(int64_t b) { live -= b; }
+};
+
+// Waits until queued work may no longer read a buffer about to be freed: the
+// owning stream when one is bound (every user of the buffer runs on it),
+// otherwise the whole device.
+inline void sync_for_free(bool scoped, hipStream_t s) {
+  if (scoped) (void)hipStreamSynchronize(s);
+  else (void)hipDeviceSynchronize();
+}
+
 // A grow-only device allocation.  Contents are not preserved on growth.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool scoped = false;
+  hipStream_t stream = nullptr;
+  MemStats* stats = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
+  void bind(hipStream_t s, MemStats* st) {
+    scoped = true;
+    stream = s;
+    stats = st;
+  }
   void release() {
     if (p) {
-      (void)hipDeviceSynchronize();  // the buffer may still be read by queued work
+      sync_for_free(scoped, stream);
       (void)hipFree(p);
+      if (stats) stats->sub((int64_t)bytes);
     }
     p = nullptr;
     bytes = 0;
@@ -56,6 +84,7 @@ struct DevBuf {
     if (n == 0) n = 256;
     IHS_HIP(hipMalloc(&p, n));
     bytes = n;
+    if (stats) stats->add((int64_t)n);
     return p;
   }
   template <class T> T* as() const { return static_cast<T*>(p); }
@@ -64,9 +93,13 @@ struct DevBuf {
 // Device memory reused across calls on one context.  A block handed back is
 // reused by later work on the context's stream without synchronizing: stream
 // order puts every earlier reader before the next writer.  Idle memory above
-// kKeepBytes is released (after a device synchronize).
+// `keep` bytes is released (after the owning stream, or the device, is idle).
 struct Pool {
   static constexpr size_t kKeepBytes = size_t(32) << 30;
+  size_t keep = kKeepBytes;
+  bool scoped = false;
+  hipStream_t stream = nullptr;
+  MemStats* stats = nullptr;
   std::multimap<size_t, void*> idle;
   std::map<void*, size_t> block_bytes;
   size_t idle_bytes = 0;
@@ -74,6 +107,11 @@ struct Pool {
   Pool(const Pool&) = delete;
   Pool& operator=(const Pool&) = delete;
   ~Pool() { release_idle(); }
+  void bind(hipStream_t s, MemStats* st) {
+    scoped = true;
+    stream = s;
+    stats = st;
+  }
   void* get(size_t n) {
     n = (n + 65535) / 65536 * 65536;
     auto it = idle.lower_bound(n);
@@ -95,6 +133,7 @@ struct Pool {
       fail(e == hipErrorOutOfMemory ? IHSBIN_ENOMEM : IHSBIN_EHIP,
            std::string("hipMalloc failed: ") + hipGetErrorString(e));
     block_bytes[p] = n;
+    if (stats) stats->add((int64_t)n);
     return p;
   }
   void put(void* p) {
@@ -102,20 +141,20 @@ struct Pool {
     const size_t n = block_bytes[p];
     idle.emplace(n, p);
     idle_bytes += n;
-    if (idle_bytes > kKeepBytes) release_idle();
+    if (idle_bytes > keep) release_idle();
   }
   void release_idle() {
     if (idle.empty()) return;
-    (void)hipDeviceSynchronize();
+    sync_for_free(scoped, stream);
     for (auto& kv : idle) {
       (void)hipFree(kv.second);
       block_bytes.erase(kv.second);
+      if (stats) stats->sub((int64_t)kv.first);
     }
     idle.clear();
     idle_bytes = 0;
   }
 };
-
 // A grow-only buffer borrowed from a Pool and handed back on destruction.
 struct PoolBuf {
   Pool* pool;
@@ -145,10 +184,31 @@ struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
-  Pool pool;  // build-local buffers (declared first: outlives the workspaces below)
+  MemStats mem;  // declared before every buffer that reports to it
+  Pool pool;     // build-local buffers (declared first: outlives the workspaces below)
   // scratch shared by the step kernels of one call
   DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status;
+  // every buffer of the context is used on `stream` only
+  void bind() {
+    pool.bind(stream, &mem);
+    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status})
+      b->bind(stream, &mem);
+  }
+  // hand idle pool blocks and the workspaces back to the device
+  void trim() {
+    pool.release_idle();
+    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status}) b->release();
+  }
 };
+
+}  // namespace ihs
+
+// The context handle of the C ABI.
+struct ihsbin_ctx {
+  ihs::Ctx c;
+};
+
+namespace ihs {
 
 struct DeviceGuard {
   int prev = -1;

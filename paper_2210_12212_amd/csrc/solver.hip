@@ -25,10 +25,6 @@
 
 #include "basis.hpp"
 
-struct ihsbin_ctx {
-  ihs::Ctx c;
-};
-
 struct ihsbin_path {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -706,6 +702,79 @@ static ihsbin_alg4_result alg4_impl(Ctx& c, const MatView& A, const double* C, i
   return r;
 }
 
+// Upper estimate of the device memory a build allocates (A, B and X are the
+// caller's): every buffer of the build at its largest size, as if all were
+// live at once, with the sketch at its cap.
+static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min,
+                              double lam_max, const ihsbin_opts& o) {
+  if (!A0 || A0->n <= 0 || A0->d <= 0 || K < 1 || !(lam_min > 0.0) || !(lam_max >= lam_min))
+    fail(IHSBIN_EINVAL, "footprint: bad shape or lambda range");
+  if (A0->dtype != IHSBIN_F32 && A0->dtype != IHSBIN_F64) fail(IHSBIN_EINVAL, "bad dtype");
+  const bool dual = A0->n < A0->d;
+  const bool csr = A0->format == IHSBIN_CSR;
+  const int64_t N = dual ? A0->d : A0->n, D = dual ? A0->n : A0->d;
+  const int64_t es = A0->dtype == IHSBIN_F32 ? 4 : 8;
+  const double beta = lam_max / lam_min;
+  const int64_t L = o.L > 0 ? o.L : (beta > 1.0 ? std::max(1, (int)std::floor(2.0 * std::log(beta))) : 1);
+  const int64_t kcap = o.k_fixed > 0 ? o.k_fixed : o.k_max;
+  const int64_t s = o.sketch == IHSBIN_SJLT ? std::max(1, o.sjlt_s) : 1;
+  int64_t m = o.m > 0 ? o.m : 2 * D;
+  if (m % s) m += s - m % s;
+  int64_t m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(N, 32 * D));
+  if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(N)));
+  const int64_t mmax = o.adaptive_m ? std::max(m, m_cap) : m;
+  const int64_t rows = std::min(mmax, N);
+  double b = 0;
+  if (dual) b += (double)es * N * D;
+  b += 8.0 * D * K;  // C
+  // sketch scratch (also the identity draws of S = I for CSR)
+  double sk = 5.0 * N + 256;
+  if (o.sketch == IHSBIN_GAUSSIAN) {
+    int64_t blk = (int64_t)((size_t(1) << 30) / (8 * (size_t)N));
+    blk = std::min(mmax, std::max<int64_t>(64, (blk / 64) * 64));
+    sk = std::max(sk, 8.0 * blk * N);
+  } else if (o.sketch == IHSBIN_SRHT) {
+    sk = std::max(sk, 8.0 * next_pow2(N) * D + N + 256);
+  } else {
+    sk = std::max(sk, 5.0 * N * s + 256);
+  }
+  b += sk + 4.0 * mmax;
+  b += 2 * 8.0 * rows * D;  // SA (grown at most geometrically)
+  b += 8.0 * D * D;         // G
+  if (o.gram_prec == IHSBIN_GRAM_BF16X3) b += (double)gram_bf16x3_work_bytes(rows, D);
+  b += 2 * 8.0 * D * D + 8.0 * cdiv(D, kNB) * kNB * kNB;  // probe or Algorithm 4 factor
+  b += 2 * 8.0 * L * D * D + 8.0 * L * cdiv(D, kNB) * kNB * kNB +
+       8.0 * tri_inverse_work_doubles(D, (int)L);
+  // Lanczos at both ends of every interval
+  const int64_t na = 2 * L, ld = padded_width(na);
+  const int64_t J = std::min<int64_t>(63, std::max<int64_t>(8, o.lanczos_steps));
+  b += 8.0 * D * ld * (J + 4) + 8.0 * trmv_scratch_doubles(D, (int)na) + 16.0 * na * J;
+  // basis and the step vectors
+  const int64_t wcap = padded_width(L * kcap * K);
+  b += 8.0 * L * kcap * D * K + 6 * 8.0 * D * wcap;
+  // Y = A U
+  int64_t wc = (int64_t)((size_t(6) << 30) / (8 * (size_t)N));
+  if (wc >= 64) wc = (wc / 64) * 64;
+  wc = std::max<int64_t>(1, std::min(wc, std::max(wcap, ld)));
+  b += 8.0 * N * (csr ? wc : padded_width(wc));
+  // split-K partials (one buffer, sized by its largest use)
+  double part = o.gram_prec == IHSBIN_GRAM_BF16X3
+                    ? 8.0 * gram_bf16x3_splits(rows) * D * D
+                    : 8.0 * pick_splits_lower(D, rows, 16384) * D * D;
+  part = std::max(part, 8.0 * 1024 * 128 * 112);         // W = A^T Y column tiles
+  part = std::max(part, 8.0 * 4096 * 8192);              // P_S products
+  part = std::max(part, 8.0 * 4096 * 256 * 64);          // Gaussian S A
+  part = std::max(part, 8.0 * pick_splits(D, K, N, 1) * D * K);  // A^T B
+  b += part;
+  if (dual) {
+    const int64_t cpad = padded_width(L * kcap * K);
+    b += 8.0 * L * kcap * A0->d * K + 8.0 * D * cpad + 8.0 * A0->d * cpad;
+  }
+  if (o.adaptive_m == 2) b += 5 * 8.0 * D * K;
+  b += double(16 << 20);  // small buffers and the pool's 64 KiB rounding
+  return (int64_t)b;
+}
+
 static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K, int64_t ldb,
                       double lam_min, double lam_max, const ihsbin_opts* o_in,
                       ihsbin_path** out, ihsbin_report* rep) {
@@ -725,6 +794,18 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   Timer total;
   ihsbin_report r;
   std::memset(&r, 0, sizeof(r));
+  c.mem.peak = c.mem.live;
+  // path buffers (handed to the caller) count against the context while the
+  // build runs
+  struct Held {
+    MemStats& s;
+    int64_t b = 0;
+    void add(int64_t x) {
+      s.add(x);
+      b += x;
+    }
+    ~Held() { s.sub(b); }
+  } held{c.mem};
   Form form(c.pool);
   make_form(c, A0, B, K, ldb, form);
   const MatView& A = form.A;
@@ -877,6 +958,8 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   std::unique_ptr<ihsbin_path> guard(path);
   path->device = c.device;
   path->stream = st;
+  path->basis.bind(st, nullptr);
+  path->items.bind(st, nullptr);
   path->d = d;
   path->K = K;
   path->L = L;
@@ -893,6 +976,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   const int64_t kcap = o.k_fixed > 0 ? o.k_fixed : o.k_max;
   path->kcap = kcap;
   double* basis = static_cast<double*>(path->basis.ensure(sizeof(double) * L * kcap * d * K));
+  held.add((int64_t)path->basis.bytes);
   IHS_HIP(hipMemsetAsync(basis, 0, sizeof(double) * L * kcap * d * K, st));
 
   const int64_t wcap = padded_width((int64_t)L * kcap * K);
@@ -1018,8 +1102,10 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     const int64_t cols = (int64_t)nb * K;
     const int64_t cpad = padded_width(cols);
     ihs::DevBuf bx;
+    bx.bind(st, nullptr);
     PoolBuf zb(c.pool), xb(c.pool), ib(c.pool);
     double* bxp = static_cast<double*>(bx.ensure(sizeof(double) * L * kcap * d0 * K));
+    held.add((int64_t)bx.bytes);
     double* Zt = static_cast<double*>(zb.ensure(sizeof(double) * d * cpad));
     double* Xt = static_cast<double*>(xb.ensure(sizeof(double) * d0 * cpad));
     int32_t* blk_dev = static_cast<int32_t*>(ib.ensure(sizeof(int32_t) * nb));
@@ -1079,6 +1165,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   }
   r.n_unconverged = unconverged;
   r.ms_total = total.ms();
+  r.peak_bytes = c.mem.peak;
   if (rep) *rep = r;
   *out = guard.release();
   return unconverged > 0 ? IHSBIN_ENOCONV : IHSBIN_OK;
@@ -1152,6 +1239,7 @@ const char* ihsbin_status_str(int s) {
     case IHSBIN_ENOCONV: return "tolerance not reached within k_max";
     case IHSBIN_ERANGE: return "lambda outside the prepared range";
     case IHSBIN_EUNSUP: return "unsupported";
+    case IHSBIN_EAGAIN: return "not finished yet";
     default: return "unknown status";
   }
 }
@@ -1201,6 +1289,7 @@ int ihsbin_create(ihsbin_ctx** ctx, int device, void* stream) {
     auto c = new ihsbin_ctx();
     c->c.device = device;
     c->c.stream = static_cast<hipStream_t>(stream);
+    c->c.bind();
     *ctx = c;
     return IHSBIN_OK;
   } catch (const Error& e) {
@@ -1364,6 +1453,32 @@ int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t 
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
     return IHSBIN_OK;
   });
+}
+
+int ihsbin_build_footprint(const ihsbin_matrix* A, int64_t K, double lam_min, double lam_max,
+                           const ihsbin_opts* opts, int64_t* bytes) {
+  if (!bytes) return IHSBIN_EINVAL;
+  return guarded(nullptr, [&] {
+    ihsbin_opts o;
+    if (opts) o = *opts;
+    else ihsbin_opts_default(&o);
+    *bytes = footprint_impl(A, K, lam_min, lam_max, o);
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_path_set_stream(ihsbin_path* p, void* stream) {
+  if (!p) return IHSBIN_EINVAL;
+  try {
+    DeviceGuard g(p->device);
+    IHS_HIP(hipStreamSynchronize(p->stream));  // the basis is complete
+    p->stream = static_cast<hipStream_t>(stream);
+    p->basis.stream = p->stream;
+    p->items.stream = p->stream;
+  } catch (const Error& e) {
+    return e.status;
+  }
+  return IHSBIN_OK;
 }
 
 int ihsbin_sketch_size(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B, int64_t K,

@@ -72,3 +72,27 @@ def test_alg4_default_options(lib):
     o = _lib.Opts()
     lib.ihsbin_opts_default(C.byref(o))
     assert not o.alg4
+
+
+def test_serving_struct_sizes():
+    from paper_2210_12212_amd import _lib
+    assert C.sizeof(_lib.ServerOpts) == 4 + 4 + 8 + 8
+    assert C.sizeof(_lib.ServerStats) == 3 * 8 + 4 * 4 + 3 * 8
+    assert C.sizeof(_lib.RequestInfo) == 4 + 4 + 8 + 3 * 8 + C.sizeof(_lib.Report) + 160
+
+
+def test_footprint_estimate_host_only(lib):
+    # no device is touched: only shapes and options enter the estimate
+    from paper_2210_12212_amd import build_footprint
+    f1 = build_footprint((100000, 1024), 1, 1e-4, 10.0, sketch="srht")
+    f2 = build_footprint((200000, 1024), 1, 1e-4, 10.0, sketch="srht")
+    f3 = build_footprint((100000, 2048), 1, 1e-4, 10.0, sketch="srht")
+    f4 = build_footprint((100000, 1024), 8, 1e-4, 10.0, sketch="srht")
+    assert 0 < f1 < f2 and f1 < f3 and f1 < f4
+    # the factors alone: 2 L d^2 doubles, L = 23
+    assert f3 >= 2 * 23 * 2048 * 2048 * 8
+    fd = build_footprint((500, 20000), 1, 1e-2, 10.0, sketch="gaussian")  # dual
+    assert fd >= 500 * 20000 * 4
+    from paper_2210_12212_amd import IhsbinError
+    with pytest.raises(IhsbinError):
+        build_footprint((100, 10), 1, 0.0, 1.0)
