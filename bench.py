@@ -84,6 +84,157 @@ def ata_sweep(args, torch, W, Context):
     ctx.close()
 
 
+def _serving_inputs(torch, req, dev):
+    """Request data drawn on the device from (seed, shape): dense A with columns
+    scaled by (j+1)^-0.7 and B = A x* + 0.05 noise, or CSR A with 16 entries
+    per row (uniform columns; repeats are summed) and B ~ N(0, 1); FP32."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(req["seed"])
+    n, d, K = req["n"], req["d"], req["K"]
+    if req["dense"]:
+        scale = (torch.arange(d, device=dev, dtype=torch.float32) + 1.0) ** -0.7
+        A = torch.randn((n, d), generator=g, device=dev, dtype=torch.float32) * scale
+        xs = torch.randn((d, K), generator=g, device=dev, dtype=torch.float32)
+        B = A @ xs + 0.05 * torch.randn((n, K), generator=g, device=dev, dtype=torch.float32)
+        return A, B.contiguous()
+    from paper_2210_12212_amd import CsrInput
+    per = 16
+    cols = torch.randint(0, d, (n, per), generator=g, device=dev, dtype=torch.int64)
+    cols = torch.sort(cols, dim=1).values.to(torch.int32).reshape(-1).contiguous()
+    vals = torch.randn(n * per, generator=g, device=dev, dtype=torch.float32)
+    rp = torch.arange(0, n * per + 1, per, device=dev, dtype=torch.int32)
+    B = torch.randn((n, K), generator=g, device=dev, dtype=torch.float32)
+    return CsrInput(rp, cols, vals, n, d), B
+
+
+def serve(args, torch, W):
+    """Replay of the serving workload through the request server."""
+    from paper_2210_12212_amd import Server
+    dev = torch.device("cuda", 0)
+    reqs = W.serving_mix(args.serve_requests, rate=args.serve_rate)
+    lams = W.lambda_grid(1e-4, 1e1, 100)
+    srv = Server(0, workers=args.serve_workers)
+    log(f"[serve] {len(reqs)} requests, {args.serve_rate}/s, {args.serve_workers} workers, "
+        f"at most {args.serve_outstanding} outstanding")
+    # warm-up (one small dense and one CSR request, not counted)
+    for wreq in (dict(seed=1, n=4096, d=128, K=1, dense=True),
+                 dict(seed=2, n=4096, d=128, K=1, dense=False)):
+        A, B = _serving_inputs(torch, wreq, dev)
+        path, _ = srv.wait(srv.submit(A, B, lams[0], lams[-1], **_serve_opts(wreq, args)))
+        path.free()
+    torch.cuda.synchronize()
+    out = {}
+    done = []
+    i = 0
+    t0 = time.perf_counter()
+    last = t0
+    while i < len(reqs) or out:
+        now = time.perf_counter() - t0
+        progressed = False
+        while i < len(reqs) and reqs[i]["arrival"] <= now and len(out) < args.serve_outstanding:
+            A, B = _serving_inputs(torch, reqs[i], dev)
+            ts = time.perf_counter() - t0
+            rid = srv.submit(A, B, lams[0], lams[-1], **_serve_opts(reqs[i], args))
+            out[rid] = (reqs[i], A, B, ts)
+            i += 1
+            progressed = True
+        for rid in list(out):
+            path, info = srv.wait(rid, timeout_ms=0)
+            if path is None:
+                continue
+            req, A, B, ts = out.pop(rid)
+            X = path.eval(lams)
+            path.free()
+            te = time.perf_counter() - t0
+            done.append(dict(index=req["index"], arrival=req["arrival"], submit=ts, end=te,
+                             ms_build=info["ms_build"], ms_queue=info["ms_queue"],
+                             status=info["status"], m_used=info["report"]["m_used"],
+                             k_max=info["report"]["k_max_used"], n=req["n"], d=req["d"],
+                             K=req["K"], dense=req["dense"]))
+            if req["index"] in args._check:
+                args._check[req["index"]] = (A, B, X.cpu().numpy())
+            del X
+            progressed = True
+        if time.perf_counter() - last > 5.0:
+            last = time.perf_counter()
+            log(f"[serve] t={now:.1f}s submitted {i} done {len(done)} outstanding {len(out)}")
+        if not progressed:
+            time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return reqs, done, wall, st, lams
+
+
+def _serve_opts(req, args):
+    return dict(sketch="gaussian" if req["dense"] else "countsketch", seed=req["seed"],
+                adaptive_m={"spectral": 1, "alg4": 2}[args.serve_m_policy], tol=args.tol,
+                rate_target=args.rate_target,
+                lanczos_steps=args.lanczos_steps)
+
+
+def serve_main(args, torch, W):
+    from oracle import direct
+    # requests checked against the oracle: the three smallest dense and CSR ones
+    reqs = W.serving_mix(args.serve_requests, rate=args.serve_rate)
+    small = sorted(reqs, key=lambda r: r["n"] * r["d"])
+    pick = [r["index"] for r in small if r["dense"]][:2] + \
+           [r["index"] for r in small if not r["dense"]][:1]
+    args._check = {k: None for k in pick}
+    reqs, done, wall, st, lams = serve(args, torch, W)
+    lat = np.array([d["end"] - d["arrival"] for d in done]) * 1e3
+    lat_submit = np.array([d["end"] - d["submit"] for d in done]) * 1e3
+    T = len(lams)
+    errs = {}
+    cpu_t = 0.0
+    cores = len(os.sched_getaffinity(0))
+    idx = np.unique(np.linspace(0, T - 1, 5).round().astype(int))
+    for k, v in args._check.items():
+        if v is None:
+            continue
+        A, B, X = v
+        if hasattr(A, "row_ptr"):
+            Ah = W.CsrMatrix(A.n, A.d, A.row_ptr.cpu().numpy(), A.col_idx.cpu().numpy(),
+                             A.vals.cpu().numpy())
+        else:
+            Ah = A.cpu().numpy()
+        Bh = B.cpu().numpy()
+        tc = time.perf_counter()
+        ref = direct.ridge_path(Ah, Bh, lams[idx])
+        cpu_t += (time.perf_counter() - tc) / len(idx) * T
+        errs[k] = float(direct.rel_err(X[idx], ref).max())
+    solves = T * len(done)
+    res = {
+        "metric": "served ridge paths: lambda-solves/s, latency p50/p99",
+        "value": round(solves / wall, 3),
+        "unit": "lambda-solves/s",
+        "n_gpus": 1,
+        "requests": len(done),
+        "requests_per_s": round(len(done) / wall, 3),
+        "wall_s": round(wall, 3),
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "latency_from_submit_ms": {"p50": float(np.percentile(lat_submit, 50)),
+                                   "p99": float(np.percentile(lat_submit, 99))},
+        "build_ms": {"p50": float(np.percentile([d["ms_build"] for d in done], 50)),
+                     "p99": float(np.percentile([d["ms_build"] for d in done], 99))},
+        "statuses": sorted({d["status"] for d in done}),
+        "server": st,
+        "max_rel_err_sampled": errs,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving_mix", "rate_per_s": args.serve_rate,
+                   "workers": args.serve_workers, "outstanding_cap": args.serve_outstanding,
+                   "T": T, "lam": [1e-4, 1e1], "m_policy": args.serve_m_policy,
+                   "tol": args.tol},
+        "cpu_baseline": {"value": round(T * len(errs) / cpu_t, 3) if cpu_t else None,
+                         "unit": "lambda-solves/s", "cores": cores, "kind": "oracle",
+                         "sample": f"direct per-lambda solves of {len(errs)} sampled requests "
+                                   f"({len(idx)} lambdas each, scaled to T)"},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +254,15 @@ def main():
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="replay the serving workload (Poisson arrivals) through the server")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-m-policy", choices=("spectral", "alg4"), default="spectral",
+                    help="sketch size of served builds")
+    ap.add_argument("--serve-outstanding", type=int, default=32,
+                    help="client-side cap on submitted, unfinished requests")
     ap.add_argument("--ata-sweep", action="store_true",
                     help="only time the A^T A product (ihsbin_ata_apply) at basis-step widths")
     args = ap.parse_args()
@@ -128,6 +288,9 @@ def main():
 
     if args.ata_sweep:
         ata_sweep(args, torch, W, Context)
+        return
+    if args.serve:
+        serve_main(args, torch, W)
         return
 
     t0 = time.time()

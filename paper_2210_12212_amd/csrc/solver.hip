@@ -905,6 +905,8 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   for (int l = 0; l < L; ++l) all[l] = l;
   double* Lf = nullptr;
   double* Linv = nullptr;
+  int regrows = 0;
+  const int kcap_steps = o.k_fixed > 0 ? o.k_fixed : o.k_max;
   for (;;) {
     Timer tf;
     Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d * L));
@@ -918,8 +920,17 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
                             std::max(2, o.lanczos_steps), o.seed + 1, NoEarly{});
     r.ms_spectrum += tspec.ms();
     // the batched estimate of the lowest interval can still be well above the
-    // probe's (different start vector): grow once more in that case
-    if (adapt && m < m_cap && trials < 6 && rate_of(spec[0]) > o.rate_target + 0.1) {
+    // probe's (different start vector): grow once more in that case.  After
+    // Algorithm 4 the guard is looser: its m stands unless the lowest
+    // interval could not pass the stop test within the step cap at all (its
+    // progress measure can shrink quickly while slow directions stall, e.g.
+    // when m < d leaves most directions to the 1/lam0 part of P_S).
+    const bool recheck =
+        adapt ? trials < 6 && rate_of(spec[0]) > o.rate_target + 0.1
+              : o.adaptive_m == 2 && regrows < 4 &&
+                    rate_of(spec[0]) > std::exp(std::log(o.tol) / std::max(1, kcap_steps));
+    if (recheck && m < m_cap) {
+      ++regrows;
       const int64_t m_new = grow(spec[0]);
       if (m_new > m) {
         Timer t2;

@@ -161,4 +161,4 @@ def test_path_with_algorithm4_sizing(torch, ctx, kind):
     err = direct.rel_err(X.cpu().numpy(), ref)
     assert err.max() <= TOL_PATH, err.max()
     res, _, _ = ctx.sketch_size(Ad, Bd, 1e-2, sketch=kind, seed=3, m=16)
-    assert rep["m_used"] == res["m"]
+    assert rep["m_used"] >= res["m"]

@@ -28,7 +28,7 @@ import numpy as np
 
 __all__ = [
     "CsrMatrix", "Problem", "lambda_grid", "dense_decay", "dense_spectrum",
-    "csr_zipf", "ar1_rows", "rhs", "make", "WORKLOADS",
+    "csr_zipf", "ar1_rows", "rhs", "make", "WORKLOADS", "serving_mix",
 ]
 
 
@@ -234,3 +234,21 @@ def make(name: str, seed: int = 1000, n: int = None, d: int = None,
     lo, hi = w["lam"]
     return Problem(name, A, B, lambda_grid(lo, hi, T), lo, hi, w["sketch"], m,
                    seed + 1000, xs)
+
+
+def serving_mix(count: int, seed: int = 5000, rate: float = 200.0):
+    """Request stream of the serving workload: Poisson arrivals at ``rate`` per
+    second (exponential gaps), n ~ U[4096, 262144], d from {128, ..., 2048},
+    dense with probability 0.7 (columns scaled by (j+1)^-0.7) else CSR with 16
+    entries per row, K ~ U[1, 16]; T = 100 lambdas in [1e-4, 1e1].  Returns a
+    list of dicts (arrival time in seconds and the shape of each request); the
+    data itself is drawn from (seed, index)."""
+    r = _rng(seed)
+    t = np.cumsum(r.exponential(1.0 / rate, count))
+    out = []
+    for i in range(count):
+        out.append(dict(index=i, arrival=float(t[i]), n=int(r.integers(4096, 262145)),
+                        d=int(r.choice([128, 256, 512, 1024, 2048])),
+                        dense=bool(r.random() < 0.7), K=int(r.integers(1, 17)),
+                        seed=seed + 1 + i))
+    return out
