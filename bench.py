@@ -169,6 +169,7 @@ def serve(args, torch, W):
 def _serve_opts(req, args):
     return dict(sketch="gaussian" if req["dense"] else "countsketch", seed=req["seed"],
                 adaptive_m={"spectral": 1, "alg4": 2}[args.serve_m_policy], tol=args.tol,
+                sketch_prec={"f64": 0, "bf16": 1}[args.serve_sketch_prec],
                 rate_target=args.rate_target,
                 lanczos_steps=args.lanczos_steps)
 
@@ -226,6 +227,7 @@ def serve_main(args, torch, W):
         "config": {"workload": "serving_mix", "rate_per_s": args.serve_rate,
                    "workers": args.serve_workers, "outstanding_cap": args.serve_outstanding,
                    "T": T, "lam": [1e-4, 1e1], "m_policy": args.serve_m_policy,
+                   "sketch_prec": args.serve_sketch_prec,
                    "tol": args.tol},
         "cpu_baseline": {"value": round(T * len(errs) / cpu_t, 3) if cpu_t else None,
                          "unit": "lambda-solves/s", "cores": cores, "kind": "oracle",
@@ -261,6 +263,8 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-m-policy", choices=("spectral", "alg4"), default="spectral",
                     help="sketch size of served builds")
+    ap.add_argument("--serve-sketch-prec", choices=("f64", "bf16"), default="bf16",
+                    help="arithmetic of the Gaussian sketch product of served dense requests")
     ap.add_argument("--serve-outstanding", type=int, default=32,
                     help="client-side cap on submitted, unfinished requests")
     ap.add_argument("--ata-sweep", action="store_true",

@@ -117,7 +117,15 @@ typedef struct {
                               fixed point)                                       */
   const struct ihsbin_alg4_opts* alg4; /* host, optional: Algorithm 4 parameters
                               for adaptive_m = 2 (NULL: the defaults)            */
+  int32_t sketch_prec;     /* Gaussian S A: IHSBIN_SKETCH_F64 (default) or
+                              IHSBIN_SKETCH_BF16 (BF16 matrix cores: S rounded
+                              to BF16 - still a Gaussian-type sketch - and A in
+                              three BF16 terms, FP32 sums of <= 2048 rows, then
+                              FP64); other sketches ignore it                    */
 } ihsbin_opts;
+
+/* Arithmetic of the Gaussian sketch product. */
+enum { IHSBIN_SKETCH_F64 = 0, IHSBIN_SKETCH_BF16 = 1 };
 
 /* Algorithm 4 (Section 5.1): IHS at lam with the direction
  * D_k = (A^T S^T S A + lam I)^-1 grad f(X_k), delta_k = <D_k, grad f(X_k)>,
@@ -263,7 +271,12 @@ int ihsbin_sketch_draws(ihsbin_ctx* ctx, int32_t sketch, uint64_t seed,
                         int8_t* sign);
 
 /* SA = S A (Section 4, Algorithm 3 first line), FP64, m x d row-major into
- * SA (device, m*d doubles). */
+ * SA (device, m*d doubles).  ihsbin_sketch_apply_prec selects the Gaussian
+ * product's arithmetic (IHSBIN_SKETCH_F64 or IHSBIN_SKETCH_BF16, for which
+ * S = BF16(FP32(z)) / sqrt(m) of the same draws z; dense A only). */
+int ihsbin_sketch_apply_prec(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch,
+                             int32_t sjlt_s, int64_t m, uint64_t seed, int32_t prec,
+                             double* SA);
 int ihsbin_sketch_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch,
                         int32_t sjlt_s, int64_t m, uint64_t seed, double* SA);
 

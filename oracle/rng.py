@@ -87,13 +87,33 @@ def srht_draws(seed: int, n: int, m: int):
     return signs, rows.astype(np.int32), npad
 
 
-def gaussian_matrix(seed: int, m: int, n: int) -> np.ndarray:
-    """Dense S (m x n) with entries N(0, 1/m) by Box-Muller, float64."""
+def gaussian_draws(seed: int, m: int, n: int) -> np.ndarray:
+    """The N(0, 1) draws z (m x n, float64) of the Gaussian sketch, entry q =
+    r * n + k from the pair (2q, 2q + 1) of its stream by Box-Muller."""
     key = stream_key(seed, 3)
     q = np.arange(m * n, dtype=np.uint64)
     x1 = draw(key, q * np.uint64(2))
     x2 = draw(key, q * np.uint64(2) + np.uint64(1))
     u1 = ((x1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
     u2 = (x2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
-    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
-    return (z / np.sqrt(m)).reshape(m, n)
+    return (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).reshape(m, n)
+
+
+def gaussian_matrix(seed: int, m: int, n: int) -> np.ndarray:
+    """Dense S (m x n) with entries N(0, 1/m) by Box-Muller, float64."""
+    return gaussian_draws(seed, m, n) / np.sqrt(m)
+
+
+def round_bf16(x) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), through FP32 first:
+    BF16(FP32(x)), returned as float64.  BF16 keeps the top 16 bits of an FP32
+    number; rounding adds 0x7FFF plus the lowest kept bit before truncating."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def gaussian_matrix_bf16(seed: int, m: int, n: int) -> np.ndarray:
+    """The BF16 Gaussian sketch: BF16(FP32(z)) / sqrt(m) of the same draws."""
+    return round_bf16(gaussian_draws(seed, m, n)) / np.sqrt(m)

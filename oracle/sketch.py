@@ -1,6 +1,7 @@
 """The sketch families of Section 4, built or applied plainly in FP64.
 
-Gaussian    S_ij ~ N(0, 1/m)                         (Section 4, bullet 1)
+Gaussian    S_ij ~ N(0, 1/m)                         (Section 4, bullet 1);
+            its BF16 form rounds the N(0,1) draws to BF16 before the 1/sqrt(m)
 CountSketch one +-1 per column of S at a hashed row    (Section 4, bullet 2)
 SJLT        s stacked CountSketches of m/s rows each, scaled 1/sqrt(s)
                                                        (Section 4, bullet 3)
@@ -93,6 +94,12 @@ def gaussian_apply(A, seed: int, m: int) -> np.ndarray:
     S = rng.gaussian_matrix(seed, m, A.shape[0])
     if hasattr(A, "row_ptr"):
         return np.asarray((_sparse64(A).T @ S.T).T)
+    return S @ np.asarray(A, dtype=np.float64)
+
+
+def gaussian_bf16_apply(A, seed: int, m: int) -> np.ndarray:
+    """S A for the BF16 Gaussian sketch S = BF16(FP32(z)) / sqrt(m), FP64."""
+    S = rng.gaussian_matrix_bf16(seed, m, A.shape[0])
     return S @ np.asarray(A, dtype=np.float64)
 
 

@@ -241,13 +241,16 @@ class Context:
                                                 C.c_void_p(idx.data_ptr()), C.c_void_p(sign.data_ptr())))
         return idx, sign
 
-    def sketch_apply(self, A, sketch: str, m: int, seed: int, sjlt_s: int = 1):
-        """ihsbin_sketch_apply -> SA (m x d float64)."""
+    def sketch_apply(self, A, sketch: str, m: int, seed: int, sjlt_s: int = 1,
+                     prec: str = "f64"):
+        """ihsbin_sketch_apply_prec -> SA (m x d float64); prec "f64" or
+        "bf16" (the Gaussian sketch on the BF16 matrix cores)."""
         torch = _torch()
         SA = torch.empty((m, A.shape[1]), dtype=torch.float64, device=torch.device("cuda", self.device))
         mat = _matrix(A)
-        self._check(L.lib().ihsbin_sketch_apply(self._h, C.byref(mat), L.SKETCHES[sketch], sjlt_s, m,
-                                                seed, C.c_void_p(SA.data_ptr())))
+        self._check(L.lib().ihsbin_sketch_apply_prec(
+            self._h, C.byref(mat), L.SKETCHES[sketch], sjlt_s, m, seed,
+            {"f64": 0, "bf16": 1}[prec], C.c_void_p(SA.data_ptr())))
         return SA
 
     def precond_factor(self, SA, lam0, want_inverse: bool = True):

@@ -24,7 +24,7 @@ EXPORTED = [
     "ihsbin_solve_path", "ihsbin_sketch_draws", "ihsbin_sketch_apply", "ihsbin_precond_factor",
     "ihsbin_ata_apply",
     "ihsbin_gram", "ihsbin_alg4_opts_default", "ihsbin_sketch_size",
-    "ihsbin_build_footprint", "ihsbin_path_set_stream", "ihsbin_server_opts_default",
+    "ihsbin_build_footprint", "ihsbin_sketch_apply_prec", "ihsbin_path_set_stream", "ihsbin_server_opts_default",
     "ihsbin_server_create", "ihsbin_server_submit", "ihsbin_server_wait",
     "ihsbin_server_get_stats", "ihsbin_server_last_error", "ihsbin_server_destroy",
 ]
@@ -56,7 +56,7 @@ class Opts(C.Structure):
                 ("adaptive_m", C.c_int32), ("rate_target", C.c_double), ("m_max", C.c_int64),
                 ("lanczos_steps", C.c_int32), ("timing", C.c_int32),
                 ("taus", C.POINTER(C.c_double)), ("gram_prec", C.c_int32),
-                ("alg4", C.POINTER(Alg4Opts))]
+                ("alg4", C.POINTER(Alg4Opts)), ("sketch_prec", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -127,6 +127,7 @@ def _declare(lib):
                                         C.POINTER(Opts), vp, i64, i32, C.POINTER(Report)]),
         "ihsbin_sketch_draws": (C.c_int, [vp, i32, u64, i64, i64, i32, vp, vp]),
         "ihsbin_sketch_apply": (C.c_int, [vp, C.POINTER(Matrix), i32, i32, i64, u64, vp]),
+        "ihsbin_sketch_apply_prec": (C.c_int, [vp, C.POINTER(Matrix), i32, i32, i64, u64, i32, vp]),
         "ihsbin_precond_factor": (C.c_int, [vp, vp, i64, i64, pd, i32, vp, vp]),
         "ihsbin_ata_apply": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64]),
         "ihsbin_gram": (C.c_int, [vp, vp, i64, i64, i32, vp]),

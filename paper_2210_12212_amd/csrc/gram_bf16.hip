@@ -42,30 +42,49 @@ __device__ __forceinline__ void split3(double x, __bf16& a, __bf16& b, __bf16& c
 }
 }  // namespace
 
-// XS[p][c][k] = term p of X[k][c]; rows k >= m are zero (32 x 32 tiles via LDS).
-__global__ __launch_bounds__(256) void split_transpose_kernel(const double* __restrict__ X,
-                                                              int64_t m, int64_t d, int64_t ldx,
-                                                              int64_t mpad,
+// XS[p][c][k] = term p of X[k][c]; rows k >= m are zero (32 x 32 tiles via LDS;
+// the row tiles are strided over gridDim.y).  FP32 input splits exactly.
+template <typename T>
+__global__ __launch_bounds__(256) void split_transpose_kernel(const T* __restrict__ X, int64_t m,
+                                                              int64_t d, int64_t ldx, int64_t mpad,
                                                               __bf16* __restrict__ XS) {
   __shared__ double tile[32][33];
-  const int64_t k0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int64_t c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t k = k0 + r, c = c0 + tx;
-    tile[r][tx] = (k < m && c < d) ? X[k * ldx + c] : 0.0;
-  }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t c = c0 + r, k = k0 + tx;
-    if (c < d) {
-      __bf16 a, b, e;
-      split3(tile[tx][r], a, b, e);
-      const int64_t o = c * mpad + k;
-      XS[o] = a;
-      XS[d * mpad + o] = b;
-      XS[2 * d * mpad + o] = e;
+  for (int64_t k0 = (int64_t)blockIdx.y * 32; k0 < mpad; k0 += (int64_t)gridDim.y * 32) {
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t k = k0 + r, c = c0 + tx;
+      tile[r][tx] = (k < m && c < d) ? (double)X[k * ldx + c] : 0.0;
     }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t c = c0 + r, k = k0 + tx;
+      if (c < d) {
+        __bf16 a, b, e;
+        split3(tile[tx][r], a, b, e);
+        const int64_t o = c * mpad + k;
+        XS[o] = a;
+        XS[d * mpad + o] = b;
+        XS[2 * d * mpad + o] = e;
+      }
+    }
+    __syncthreads();
   }
+}
+
+void launch_split3_transpose(const void* X, bool f32, int64_t m, int64_t d, int64_t ldx,
+                             int64_t mpad, void* XS, hipStream_t st) {
+  if (m <= 0 || d <= 0) return;
+  const unsigned gx = (unsigned)cdiv(d, 32);
+  const unsigned gy = (unsigned)std::min<int64_t>(cdiv(mpad, 32), 32768);
+  if (gx > 65535u) fail(IHSBIN_EUNSUP, "split: too many columns");
+  if (f32)
+    hipLaunchKernelGGL(split_transpose_kernel<float>, dim3(gx, gy), dim3(256), 0, st,
+                       static_cast<const float*>(X), m, d, ldx, mpad, static_cast<__bf16*>(XS));
+  else
+    hipLaunchKernelGGL(split_transpose_kernel<double>, dim3(gx, gy), dim3(256), 0, st,
+                       static_cast<const double*>(X), m, d, ldx, mpad, static_cast<__bf16*>(XS));
+  IHS_CHECK_LAUNCH();
 }
 
 __global__ __launch_bounds__(256) void gram_bf16x3_kernel(const __bf16* __restrict__ XS,
@@ -179,13 +198,7 @@ void gram_bf16x3(const double* X, int64_t m, int64_t d, int64_t ldx, void* work,
   if (m <= 0 || d <= 0) return;
   const int64_t mpad = cdiv(m, kBK) * kBK;
   __bf16* XS = static_cast<__bf16*>(work);
-  {
-    const unsigned gx = (unsigned)cdiv(d, 32), gy = (unsigned)cdiv(mpad, 32);
-    if (gy > 65535u) fail(IHSBIN_EUNSUP, "gram: too many sketch rows");
-    hipLaunchKernelGGL(split_transpose_kernel, dim3(gx, gy), dim3(256), 0, st, X, m, d, ldx, mpad,
-                       XS);
-    IHS_CHECK_LAUNCH();
-  }
+  launch_split3_transpose(X, false, m, d, ldx, mpad, XS, st);
   int64_t rows_per = cdiv(mpad, splits);
   rows_per = cdiv(rows_per, kBK) * kBK;
   const unsigned nt = (unsigned)cdiv(d, kT);

@@ -122,11 +122,19 @@ static int64_t next_pow2(int64_t n) {
 // reuse_transform: the SRHT transform D-signs + Walsh-Hadamard of A for this
 // seed is still in the context's sketch scratch (only the row sample depends on m).
 static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t m, uint64_t seed,
-                              double* SA, bool reuse_transform = false) {
+                              double* SA, bool reuse_transform = false,
+                              int prec = IHSBIN_SKETCH_F64) {
   hipStream_t st = c.stream;
   if (m <= 0) fail(IHSBIN_EINVAL, "m must be positive");
   if (m > INT32_MAX) fail(IHSBIN_EUNSUP, "m too large");
-  if (kind == IHSBIN_GAUSSIAN) {
+  if (prec != IHSBIN_SKETCH_F64 && prec != IHSBIN_SKETCH_BF16)
+    fail(IHSBIN_EINVAL, "unknown sketch precision");
+  if (kind == IHSBIN_GAUSSIAN && prec == IHSBIN_SKETCH_BF16) {
+    void* work = c.ws_sketch.ensure((size_t)sketch_bf16_work_bytes(m, A.n, A.d));
+    const int64_t pd = gaussian_sketch_bf16_part_doubles(m, A.n, A.d);
+    double* part = static_cast<double*>(c.ws_part.ensure(sizeof(double) * (size_t)pd));
+    gaussian_sketch_bf16(A, seed, m, SA, work, part, pd, st);
+  } else if (kind == IHSBIN_GAUSSIAN) {
     if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "Gaussian sketch of a CSR matrix");
     int64_t rows = (int64_t)((size_t(1) << 30) / (sizeof(double) * (size_t)A.n));
     rows = std::max<int64_t>(64, (rows / 64) * 64);
@@ -584,7 +592,8 @@ struct Sketcher {
       logf("m=%lld >= n=%lld: exact Hessian (S = I)", (long long)mm, (long long)A.n);
       copy_rows_f64(c, A, SA);
     } else {
-      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT);
+      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT,
+                        o.sketch_prec);
     }
     gram_impl(c, SA, rows, A.d, G, o.gram_prec);
     ++trials;
@@ -729,7 +738,9 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
   b += 8.0 * D * K;  // C
   // sketch scratch (also the identity draws of S = I for CSR)
   double sk = 5.0 * N + 256;
-  if (o.sketch == IHSBIN_GAUSSIAN) {
+  if (o.sketch == IHSBIN_GAUSSIAN && o.sketch_prec == IHSBIN_SKETCH_BF16) {
+    sk = std::max(sk, (double)sketch_bf16_work_bytes(mmax, N, D));
+  } else if (o.sketch == IHSBIN_GAUSSIAN) {
     int64_t blk = (int64_t)((size_t(1) << 30) / (8 * (size_t)N));
     blk = std::min(mmax, std::max<int64_t>(64, (blk / 64) * 64));
     sk = std::max(sk, 8.0 * blk * N);
@@ -1277,6 +1288,7 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->timing = 0;
   o->taus = nullptr;
   o->alg4 = nullptr;
+  o->sketch_prec = IHSBIN_SKETCH_F64;
 }
 
 void ihsbin_alg4_opts_default(ihsbin_alg4_opts* a) {
@@ -1434,18 +1446,23 @@ int ihsbin_sketch_draws(ihsbin_ctx* ctx, int32_t sketch, uint64_t seed, int64_t 
   });
 }
 
-int ihsbin_sketch_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch, int32_t sjlt_s,
-                        int64_t m, uint64_t seed, double* SA) {
+int ihsbin_sketch_apply_prec(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch,
+                             int32_t sjlt_s, int64_t m, uint64_t seed, int32_t prec, double* SA) {
   if (!ctx) return IHSBIN_EINVAL;
   return guarded(ctx, [&] {
     DeviceGuard g(ctx->c.device);
     const MatView v = check_matrix(A);
     if (!SA) fail(IHSBIN_EINVAL, "SA is NULL");
     if (v.format == IHSBIN_CSR) validate_csr(ctx->c, v);
-    sketch_apply_impl(ctx->c, v, sketch, sjlt_s, m, seed, SA);
+    sketch_apply_impl(ctx->c, v, sketch, sjlt_s, m, seed, SA, false, prec);
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
     return IHSBIN_OK;
   });
+}
+
+int ihsbin_sketch_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch, int32_t sjlt_s,
+                        int64_t m, uint64_t seed, double* SA) {
+  return ihsbin_sketch_apply_prec(ctx, A, sketch, sjlt_s, m, seed, IHSBIN_SKETCH_F64, SA);
 }
 
 int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d,

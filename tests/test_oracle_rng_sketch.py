@@ -91,3 +91,36 @@ def test_sketch_is_unbiased_isometry(kind):
         SA = sketch.apply(kind, A, seed, 16)
         ratios.append(np.sum(SA[:, 0] ** 2) / np.sum(A[:, 0] ** 2))
     assert abs(np.mean(ratios) - 1.0) < 0.08
+
+
+def test_round_bf16_matches_torch_and_ties():
+    # torch's CPU float32 -> bfloat16 conversion rounds to nearest, ties to
+    # even: an independent implementation of the same rounding
+    import torch
+    r = np.random.default_rng(3)
+    x = np.concatenate([r.standard_normal(20000) * 10.0 ** r.integers(-6, 6, 20000),
+                        [0.0, -0.0, 1.0, -2.5]])
+    f = x.astype(np.float32)
+    ref = torch.from_numpy(f).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(rng.round_bf16(x), ref)
+    # exact ties: 1 + 2^-8 sits halfway between 1 and 1 + 2^-7 -> even (1);
+    # 1 + 3 * 2^-8 sits between 1 + 2^-7 and 1 + 2^-6 -> even (1 + 2^-6)
+    assert rng.round_bf16(1.0 + 2.0 ** -8) == 1.0
+    assert rng.round_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+
+
+def test_bf16_gaussian_sketch_is_the_rounded_gaussian():
+    m, n = 64, 3000
+    z = rng.gaussian_draws(5, m, n)
+    S = rng.gaussian_matrix(5, m, n)
+    S16 = rng.gaussian_matrix_bf16(5, m, n)
+    np.testing.assert_allclose(S * np.sqrt(m), z, rtol=1e-15)
+    # within half a BF16 unit (2^-8 relative) of the FP64 sketch, and a
+    # BF16 value times 1/sqrt(m)
+    np.testing.assert_allclose(S16, S, rtol=2.0 ** -8, atol=0)
+    q = S16 * np.sqrt(m)
+    np.testing.assert_array_equal(rng.round_bf16(q), q)
+    # the apply is the product with that matrix
+    A = np.random.default_rng(1).standard_normal((n, 4))
+    SA = sketch.gaussian_bf16_apply(A, 5, m)
+    np.testing.assert_allclose(SA, S16 @ A, rtol=1e-12)
