@@ -302,7 +302,13 @@ def main():
     log(f"[bench] workload {p.name}: n={p.n} d={p.d} K={p.B.shape[1]} T={len(p.lambdas)} "
         f"sketch={p.sketch} m0={p.m} (generated in {time.time() - t0:.1f}s)")
     dev = torch.device("cuda", 0)
-    A = torch.from_numpy(p.A).to(dev)
+    csr = hasattr(p.A, "row_ptr")
+    if csr:
+        from paper_2210_12212_amd import CsrInput
+        A = CsrInput(torch.from_numpy(p.A.row_ptr).to(dev), torch.from_numpy(p.A.col_idx).to(dev),
+                     torch.from_numpy(p.A.vals).to(dev), p.A.n, p.A.d)
+    else:
+        A = torch.from_numpy(p.A).to(dev)
     B = torch.from_numpy(p.B).to(dev)
     torch.cuda.synchronize()
     ctx = Context(0)
@@ -339,20 +345,32 @@ def main():
     value = T * args.steps / elapsed
     rep = reps[-1]
 
-    # dominant kernel: the two FP64 MFMA GEMMs of A^T A U (each 2*n*d*w flops)
+    # dominant kernel: the two products of A^T A U (dense: FP64 MFMA GEMMs of
+    # 2*n*d*w flops each)
     launches = max(1, rep["ata_launches"])
     half_flops = rep["ata_flops"] / 2.0
-    dom = "gemm_y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "gemm_w_AtY"
     dom_ms = max(rep["ata_ms_y"], rep["ata_ms_w"])
-    achieved = (half_flops / launches) / (dom_ms / launches * 1e-3) / 1e12 if dom_ms > 0 else 0.0
-    traffic = recorded_traffic(dom) if p.name == TRAFFIC_WORKLOAD and args.n is None else None
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
-                "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": traffic,
-                "launches": rep["ata_launches"],
-                "flops_per_launch": half_flops / launches,
-                "avg_launch_ms": dom_ms / launches,
-                "ata_ms_y": rep["ata_ms_y"], "ata_ms_w": rep["ata_ms_w"]}
+    if csr:
+        # CSR products: nnz multiply-adds per column, bound by their loads;
+        # algorithmic bytes per launch = A once (values and column indices)
+        dom = "csr_spmm_Y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "csr_spmm_t_W_AtY"
+        abytes = rep["ata_bytes_a"] / launches
+        achieved = abytes / (dom_ms / launches * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 3),
+                    "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": None,
+                    "bytes_per_launch": abytes}
+    else:
+        dom = "gemm_y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "gemm_w_AtY"
+        achieved = (half_flops / launches) / (dom_ms / launches * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+        traffic = recorded_traffic(dom) if p.name == TRAFFIC_WORKLOAD and args.n is None else None
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
+                    "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                    "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": traffic}
+    roofline.update({"launches": rep["ata_launches"],
+                     "flops_per_launch": half_flops / launches,
+                     "avg_launch_ms": dom_ms / launches,
+                     "ata_ms_y": rep["ata_ms_y"], "ata_ms_w": rep["ata_ms_w"]})
 
     # marginal cost of a lambda on a resident basis (outside the timed region):
     # evaluation only, for the workload's T and for a dense grid of 100000 lambdas

@@ -249,12 +249,14 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 bool log_enabled();
 void logf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
+struct Csc;
 struct MatView {  // a validated ihsbin_matrix
   int format, dtype;
   int64_t n, d, ld, nnz;
   const void* vals;
   const int32_t* row_ptr;
   const int32_t* col_idx;
+  const Csc* csc = nullptr;  // CSR only, optional: its column-major copy
 };
 
 MatView check_matrix(const ihsbin_matrix* A);

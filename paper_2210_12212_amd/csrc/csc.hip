@@ -1,0 +1,264 @@
+// Column-major copy of a CSR matrix and the transposed product W = A^T Y
+// gathered from it (no atomics, fixed summation order).
+//
+// The copy is a stable sort of the entries by column (LSD radix sort of the
+// column indices with the entry positions as values), so every column lists
+// its entries by increasing row: the result is the same bits on every run.
+// Columns are cut into chunks of at most kCscChunk entries so that a heavy
+// column (a skewed column distribution puts most rows into a few columns)
+// is summed by many waves; a second pass adds the chunk partials of every
+// column in chunk order.
+#include <hipcub/hipcub.hpp>
+
+#include "ops.hpp"
+
+namespace ihs {
+
+namespace {
+constexpr int kCscChunk = 1024;
+
+__global__ void row_of_entry_kernel(const int32_t* __restrict__ rp, int64_t n,
+                                    int32_t* __restrict__ row) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) row[p] = (int32_t)i;
+}
+
+__global__ void iota_kernel(int32_t* __restrict__ v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = (int32_t)i;
+}
+
+// col_ptr[c] = first sorted position whose column is >= c (c = 0..d)
+__global__ void col_ptr_kernel(const int32_t* __restrict__ keys, int64_t nnz, int64_t d,
+                               int32_t* __restrict__ col_ptr) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= d;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (keys[mid] < c) lo = mid + 1;
+      else hi = mid;
+    }
+    col_ptr[c] = (int32_t)lo;
+  }
+}
+
+template <typename T>
+__global__ void permute_kernel(const int32_t* __restrict__ perm, const int32_t* __restrict__ row_of,
+                               const T* __restrict__ v, int64_t nnz, int32_t* __restrict__ row,
+                               T* __restrict__ val) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = perm[q];
+    row[q] = row_of[p];
+    val[q] = v[p];
+  }
+}
+
+__global__ void chunk_count_kernel(const int32_t* __restrict__ col_ptr, int64_t d,
+                                   int32_t* __restrict__ cnt) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < d;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t len = col_ptr[c + 1] - col_ptr[c];
+    cnt[c] = (len + kCscChunk - 1) / kCscChunk;
+  }
+}
+
+__global__ void chunk_table_kernel(const int32_t* __restrict__ col_chunk, int64_t d,
+                                   int32_t* __restrict__ chunk_col) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < d;
+       c += (int64_t)gridDim.x * blockDim.x)
+    for (int32_t t = col_chunk[c]; t < col_chunk[c + 1]; ++t) chunk_col[t] = (int32_t)c;
+}
+
+unsigned grid_for(int64_t count) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 256), 16384));
+}
+
+int pow2ceil(int64_t w) {
+  int g = 1;
+  while (g < w && g < 64) g <<= 1;
+  return g;
+}
+}  // namespace
+
+int64_t csc_work_bytes(const MatView& A) {
+  const int64_t nnz = A.nnz, d = A.d;
+  const int64_t es = A.dtype == IHSBIN_F32 ? 4 : 8;
+  size_t sort_tmp = 0, scan_tmp = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const int32_t*)nullptr,
+                                           (int32_t*)nullptr, (const int32_t*)nullptr,
+                                           (int32_t*)nullptr, (int)nnz, 0, 32);
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (const int32_t*)nullptr,
+                                         (int32_t*)nullptr, (int)(d + 1));
+  // kept: col_ptr, col_chunk (d+1 each), row, val (nnz), chunk_col (<= nnz/chunk + d)
+  // transient: row_of, keys_out, perm in/out (nnz each), counts, sort/scan scratch
+  const int64_t kept = 4 * 2 * (d + 1) + (4 + es) * nnz + 4 * (nnz / kCscChunk + d + 1);
+  const int64_t transient = 4 * 4 * nnz + 4 * (d + 1) + (int64_t)std::max(sort_tmp, scan_tmp);
+  return kept + transient + 16 * 256;
+}
+
+void build_csc(const MatView& A, void* work, Csc& out, hipStream_t st) {
+  if (A.format != IHSBIN_CSR) fail(IHSBIN_EINVAL, "CSC copy of a dense matrix");
+  const int64_t nnz = A.nnz, d = A.d, n = A.n;
+  if (nnz >= INT32_MAX || d >= INT32_MAX) fail(IHSBIN_EUNSUP, "CSC copy: too many entries");
+  const int64_t es = A.dtype == IHSBIN_F32 ? 4 : 8;
+  char* p = static_cast<char*>(work);
+  auto take = [&](int64_t bytes) {
+    char* r = p;
+    p += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  int32_t* col_ptr = reinterpret_cast<int32_t*>(take(4 * (d + 1)));
+  int32_t* col_chunk = reinterpret_cast<int32_t*>(take(4 * (d + 1)));
+  int32_t* row = reinterpret_cast<int32_t*>(take(4 * nnz));
+  void* val = take(es * nnz);
+  int32_t* chunk_col = reinterpret_cast<int32_t*>(take(4 * (nnz / kCscChunk + d + 1)));
+  int32_t* row_of = reinterpret_cast<int32_t*>(take(4 * nnz));
+  int32_t* keys_out = reinterpret_cast<int32_t*>(take(4 * nnz));
+  int32_t* perm_in = reinterpret_cast<int32_t*>(take(4 * nnz));
+  int32_t* perm_out = reinterpret_cast<int32_t*>(take(4 * nnz));
+  int32_t* cnt = reinterpret_cast<int32_t*>(take(4 * (d + 1)));
+  int end_bit = 1;
+  while ((int64_t(1) << end_bit) < d) ++end_bit;
+  size_t sort_tmp = 0, scan_tmp = 0;
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, A.col_idx, keys_out, perm_in,
+                                             perm_out, (int)nnz, 0, end_bit, st));
+  IHS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, cnt, col_chunk, (int)(d + 1), st));
+  void* tmp = take((int64_t)std::max(sort_tmp, scan_tmp));
+
+  hipLaunchKernelGGL(row_of_entry_kernel, dim3(grid_for(n)), dim3(256), 0, st, A.row_ptr, n, row_of);
+  IHS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(iota_kernel, dim3(grid_for(nnz)), dim3(256), 0, st, perm_in, nnz);
+  IHS_CHECK_LAUNCH();
+  size_t bytes = sort_tmp;
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, bytes, A.col_idx, keys_out, perm_in, perm_out,
+                                             (int)nnz, 0, end_bit, st));
+  hipLaunchKernelGGL(col_ptr_kernel, dim3(grid_for(d + 1)), dim3(256), 0, st, keys_out, nnz, d,
+                     col_ptr);
+  IHS_CHECK_LAUNCH();
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(permute_kernel<float>, dim3(grid_for(nnz)), dim3(256), 0, st, perm_out,
+                       row_of, static_cast<const float*>(A.vals), nnz, row, static_cast<float*>(val));
+  else
+    hipLaunchKernelGGL(permute_kernel<double>, dim3(grid_for(nnz)), dim3(256), 0, st, perm_out,
+                       row_of, static_cast<const double*>(A.vals), nnz, row,
+                       static_cast<double*>(val));
+  IHS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(chunk_count_kernel, dim3(grid_for(d)), dim3(256), 0, st, col_ptr, d, cnt);
+  IHS_CHECK_LAUNCH();
+  IHS_HIP(hipMemsetAsync(cnt + d, 0, sizeof(int32_t), st));
+  bytes = scan_tmp;
+  IHS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, cnt, col_chunk, (int)(d + 1), st));
+  hipLaunchKernelGGL(chunk_table_kernel, dim3(grid_for(d)), dim3(256), 0, st, col_chunk, d,
+                     chunk_col);
+  IHS_CHECK_LAUNCH();
+  int32_t nch = 0;
+  IHS_HIP(hipMemcpyAsync(&nch, col_chunk + d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  IHS_HIP(hipStreamSynchronize(st));
+  out.col_ptr = col_ptr;
+  out.col_chunk = col_chunk;
+  out.row = row;
+  out.val = val;
+  out.chunk_col = chunk_col;
+  out.nchunks = nch;
+}
+
+// P[t][j] = sum over the entries of chunk t of val * Y[row][j].  Lanes form
+// groups of G = min(64, pow2ceil(w)) columns; the 64 / G groups of a wave take
+// every (64/G)-th entry of the chunk and are added by a fixed butterfly.
+template <typename T, typename TY>
+__global__ __launch_bounds__(256) void csc_gather_kernel(
+    const int32_t* __restrict__ col_ptr, const int32_t* __restrict__ col_chunk,
+    const int32_t* __restrict__ chunk_col, const int32_t* __restrict__ row,
+    const T* __restrict__ val, int64_t nchunks, const TY* __restrict__ Y, int64_t w, int64_t ldy,
+    int G, int strips, double* __restrict__ P) {
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= nchunks * strips) return;
+  const int64_t t = item / strips;
+  const int strip = (int)(item - t * strips);
+  const int c = chunk_col[t];
+  const int32_t q0 = col_ptr[c] + (int32_t)(t - col_chunk[c]) * kCscChunk;
+  const int32_t q1 = min(q0 + kCscChunk, col_ptr[c + 1]);
+  const int groups = 64 / G;
+  const int grp = lane / G, cl = lane - grp * G;
+  const int64_t j = (int64_t)strip * G + cl;
+  double acc = 0.0;
+  if (j < w) {
+    int32_t q = q0 + grp;
+    // four entries in flight per lane
+    for (; q + 3 * groups < q1; q += 4 * groups) {
+      const int32_t r0 = row[q], r1 = row[q + groups], r2 = row[q + 2 * groups],
+                    r3 = row[q + 3 * groups];
+      const double v0 = (double)val[q], v1 = (double)val[q + groups],
+                   v2 = (double)val[q + 2 * groups], v3 = (double)val[q + 3 * groups];
+      const double y0 = (double)Y[(int64_t)r0 * ldy + j], y1 = (double)Y[(int64_t)r1 * ldy + j],
+                   y2 = (double)Y[(int64_t)r2 * ldy + j], y3 = (double)Y[(int64_t)r3 * ldy + j];
+      acc += v0 * y0;
+      acc += v1 * y1;
+      acc += v2 * y2;
+      acc += v3 * y3;
+    }
+    for (; q < q1; q += groups) acc += (double)val[q] * (double)Y[(int64_t)row[q] * ldy + j];
+  }
+  for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (grp == 0 && j < w) P[t * w + j] = acc;
+}
+
+// W[c][j] = sum of the chunk partials of column c in chunk order (0 if none)
+__global__ void csc_reduce_kernel(const int32_t* __restrict__ col_chunk, int64_t d, int64_t w,
+                                  const double* __restrict__ P, double* __restrict__ W,
+                                  int64_t ldw) {
+  const int64_t total = d * w;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / w, j = e - c * w;
+    double s = 0.0;
+    for (int32_t t = col_chunk[c]; t < col_chunk[c + 1]; ++t) s += P[(int64_t)t * w + j];
+    W[c * ldw + j] = s;
+  }
+}
+
+int64_t csc_partial_doubles(const Csc& csc, int64_t w) { return csc.nchunks * w; }
+
+void launch_csc_atb(const MatView& A, const Csc& csc, const void* Y, bool y_f32, int64_t w,
+                    int64_t ldy, double* P, double* W, int64_t ldw, hipStream_t st) {
+  if (w <= 0) return;
+  const int G = pow2ceil(w);
+  const int strips = (int)cdiv(w, G);
+  const int64_t items = csc.nchunks * strips;
+  if (items > 0) {
+    const unsigned blocks = (unsigned)cdiv(items, 4);
+    if (cdiv(items, 4) > INT32_MAX) fail(IHSBIN_EUNSUP, "CSC product: grid too large");
+    const bool af = A.dtype == IHSBIN_F32;
+    if (af && y_f32)
+      hipLaunchKernelGGL((csc_gather_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         static_cast<const float*>(csc.val), csc.nchunks,
+                         static_cast<const float*>(Y), w, ldy, G, strips, P);
+    else if (af)
+      hipLaunchKernelGGL((csc_gather_kernel<float, double>), dim3(blocks), dim3(256), 0, st,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         static_cast<const float*>(csc.val), csc.nchunks,
+                         static_cast<const double*>(Y), w, ldy, G, strips, P);
+    else if (y_f32)
+      hipLaunchKernelGGL((csc_gather_kernel<double, float>), dim3(blocks), dim3(256), 0, st,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         static_cast<const double*>(csc.val), csc.nchunks,
+                         static_cast<const float*>(Y), w, ldy, G, strips, P);
+    else
+      hipLaunchKernelGGL((csc_gather_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         static_cast<const double*>(csc.val), csc.nchunks,
+                         static_cast<const double*>(Y), w, ldy, G, strips, P);
+    IHS_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(csc_reduce_kernel, dim3(grid_for(A.d * w)), dim3(256), 0, st, csc.col_chunk,
+                     A.d, w, P, W, ldw);
+  IHS_CHECK_LAUNCH();
+}
+
+}  // namespace ihs

@@ -109,6 +109,27 @@ void launch_alg4_step(double* X, double* Gr, const double* D, const double* W, i
 // X = 0 and Gr = -C.
 void launch_alg4_init(const double* C, double* X, double* Gr, int64_t count, hipStream_t st);
 
+// ------------------------------------------------- CSR column-major copy
+// Entries of every column by increasing row (a stable sort by column), cut
+// into chunks of at most 1024 entries: chunks col_chunk[c] .. col_chunk[c+1]
+// belong to column c, chunk_col[t] names the column of chunk t.
+struct Csc {
+  const int32_t* col_ptr = nullptr;    // d + 1
+  const int32_t* col_chunk = nullptr;  // d + 1
+  const int32_t* row = nullptr;        // nnz
+  const void* val = nullptr;           // nnz, A's dtype
+  const int32_t* chunk_col = nullptr;  // nchunks
+  int64_t nchunks = 0;
+};
+int64_t csc_work_bytes(const MatView& A);
+// Builds the copy inside `work` (csc_work_bytes(A) bytes, kept while used).
+void build_csc(const MatView& A, void* work, Csc& out, hipStream_t st);
+int64_t csc_partial_doubles(const Csc& csc, int64_t w);
+// W (d x w, row stride ldw) = A^T Y for Y (n x w, row stride ldy, FP32 or
+// FP64), gathered column by column; P: csc_partial_doubles(csc, w) doubles.
+void launch_csc_atb(const MatView& A, const Csc& csc, const void* Y, bool y_f32, int64_t w,
+                    int64_t ldy, double* P, double* W, int64_t ldw, hipStream_t st);
+
 // ------------------------------------------------------------ basis kernels
 struct StepParams;  // defined in basis.hip users
 void launch_fill(double* p, int64_t count, double v, hipStream_t st);

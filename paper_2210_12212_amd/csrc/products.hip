@@ -297,6 +297,13 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
         mark();
       }
     } else {
+      if (A.csc) {
+        double* P = static_cast<double*>(
+            ctx.ws_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, csc_partial_doubles(*A.csc, cw))));
+        launch_csc_atb(A, *A.csc, Y, false, cw, cw, P, W + c0, ldw, st);
+        mark();
+        continue;
+      }
       zero_block(W + c0, A.d, cw, ldw, st);
       launch_csr_spmm_t(A, Y, cw, cw, W + c0, ldw, st);
       mark();
@@ -307,6 +314,12 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
 
 void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C) {
   hipStream_t st = ctx.stream;
+  if (A.format == IHSBIN_CSR && A.csc) {
+    double* P = static_cast<double*>(
+        ctx.ws_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, csc_partial_doubles(*A.csc, K))));
+    launch_csc_atb(A, *A.csc, B, A.dtype == IHSBIN_F32, K, ldb, P, C, K, st);
+    return;
+  }
   if (A.format == IHSBIN_CSR) {
     launch_csr_atb(A, B, K, ldb, C, st);
     return;

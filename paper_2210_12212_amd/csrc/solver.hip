@@ -531,9 +531,10 @@ struct Timer {
 struct Form {
   MatView A;
   bool dual = false;
-  PoolBuf At, Cb;
+  PoolBuf At, Cb, cscb;
+  Csc csc;  // CSR: the column-major copy the transposed products gather from
   double* C = nullptr;
-  explicit Form(Pool& p) : At(p), Cb(p) {}
+  explicit Form(Pool& p) : At(p), Cb(p), cscb(p) {}
 };
 
 static void make_form(Ctx& c, const MatView& A0, const void* B, int64_t K, int64_t ldb, Form& f) {
@@ -552,7 +553,11 @@ static void make_form(Ctx& c, const MatView& A0, const void* B, int64_t K, int64
     f.A.ld = A0.n;
     f.A.vals = At;
   }
-  if (f.A.format == IHSBIN_CSR) validate_csr(c, f.A);
+  if (f.A.format == IHSBIN_CSR) {
+    validate_csr(c, f.A);
+    build_csc(f.A, f.cscb.ensure((size_t)csc_work_bytes(f.A)), f.csc, c.stream);
+    f.A.csc = &f.csc;
+  }
   const int64_t d = f.A.d;
   f.C = static_cast<double*>(f.Cb.ensure(sizeof(double) * d * K));
   if (f.dual) launch_widen_rows(B, A0.dtype, d, K, ldb, f.C, c.stream);
@@ -782,6 +787,14 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
     b += 8.0 * L * kcap * A0->d * K + 8.0 * D * cpad + 8.0 * A0->d * cpad;
   }
   if (o.adaptive_m == 2) b += 5 * 8.0 * D * K;
+  if (csr) {
+    // column-major copy (sort scratch bounded by 16 bytes per entry + 4 MiB)
+    const double nnz = (double)std::max<int64_t>(0, A0->nnz);
+    b += 8.0 * (D + 1) + (4.0 + es) * nnz + 4.0 * (nnz / 1024 + D + 1) + 16.0 * nnz +
+         4.0 * (D + 1) + 16.0 * nnz + double(4 << 20);
+    // chunk partials of the gathered products (in the split-K buffer)
+    b += 8.0 * (nnz / 1024 + D + 1) * std::max(wc, K);
+  }
   b += double(16 << 20);  // small buffers and the pool's 64 KiB rounding
   return (int64_t)b;
 }
@@ -1556,9 +1569,15 @@ int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U, i
   if (!ctx) return IHSBIN_EINVAL;
   return guarded(ctx, [&] {
     DeviceGuard g(ctx->c.device);
-    const MatView v = check_matrix(A);
+    MatView v = check_matrix(A);
     if (!U || !W || w < 1 || ldu < w || ldw < w) fail(IHSBIN_EINVAL, "bad U / W");
-    if (v.format == IHSBIN_CSR) validate_csr(ctx->c, v);
+    PoolBuf cscb(ctx->c.pool);
+    Csc csc;
+    if (v.format == IHSBIN_CSR) {
+      validate_csr(ctx->c, v);
+      build_csc(v, cscb.ensure((size_t)csc_work_bytes(v)), csc, ctx->c.stream);
+      v.csc = &csc;
+    }
     ata_apply(ctx->c, v, U, w, ldu, W, ldw, nullptr, ldu);
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
     return IHSBIN_OK;

@@ -70,6 +70,20 @@ def test_ata_ragged_width_ignores_padding(torch, ctx, w, ldu):
     np.testing.assert_allclose(Wg, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n,d,per,w", [(20000, 500, 9, 3), (5000, 64, 20, 70), (3000, 1000, 2, 1),
+                                       (1, 7, 3, 5)])
+def test_ata_csr_skewed_columns(torch, ctx, n, d, per, w):
+    # column 0 holds nearly every row (many gather chunks); w from 1 to 70
+    M = W.csr_zipf(n, d, per, seed=n + w, dtype=np.float64)
+    U = np.random.default_rng(w).standard_normal((d, w))
+    Wg = ctx.ata_apply(csr_dev(torch, M), dev(torch, U)).cpu().numpy()
+    ref = ihs_bin.Operator(M).AtA(U)
+    np.testing.assert_allclose(Wg, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    # the gather sums in a fixed order: the same bits again
+    W2 = ctx.ata_apply(csr_dev(torch, M), dev(torch, U)).cpu().numpy()
+    np.testing.assert_array_equal(Wg, W2)
+
+
 def test_ata_csr(torch, ctx):
     M = W.csr_zipf(2000, 300, 7, seed=3, dtype=np.float32)
     U = np.random.default_rng(1).standard_normal((300, 9))
