@@ -246,7 +246,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs)")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--rate-target", type=float, default=0.5)
-    ap.add_argument("--lanczos-steps", type=int, default=6)
+    ap.add_argument("--lanczos-steps", type=int, default=4)
     ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default="f64",
                     help="sketched Gram precision (the factor and the recursion stay FP64)")
     ap.add_argument("--m-policy", choices=("spectral", "alg4", "fixed"), default="spectral",

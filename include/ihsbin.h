@@ -122,6 +122,10 @@ typedef struct {
                               to BF16 - still a Gaussian-type sketch - and A in
                               three BF16 terms, FP32 sums of <= 2048 rows, then
                               FP64); other sketches ignore it                    */
+  double sigma_d2;         /* >= 0: sigma_d^2 of A (smallest squared singular
+                              value) or an estimate; > 0 centres each interval
+                              [lo, hi] at lam0 = sqrt((lo+s)(hi+s)) - s (the
+                              remark after Theorem 1); 0 (default): sqrt(lo hi) */
 } ihsbin_opts;
 
 /* Arithmetic of the Gaussian sketch product. */

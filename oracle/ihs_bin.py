@@ -54,15 +54,27 @@ def num_intervals(lam_min: float, lam_max: float) -> int:
     return max(1, int(math.floor(2.0 * math.log(beta)))) if beta > 1 else 1
 
 
-def plan(lam_min: float, lam_max: float, L: int | None = None):
-    """Interval boundaries lam^(0..L) and centres lam0^(0..L-1)."""
+def plan(lam_min: float, lam_max: float, L: int | None = None, sigma_d2: float = 0.0):
+    """Interval boundaries lam^(0..L) and centres lam0^(0..L-1).
+
+    With sigma_d2 = sigma_d^2 > 0 (the smallest squared singular value of A,
+    or an estimate) the centre of [lo, hi] follows the remark after Theorem 1:
+    lam0 = sqrt((hi + s)(lo + s)) - s, the shift whose (lam0 + s) is the
+    geometric centre of (lo + s, hi + s); s = 0 gives sqrt(lo hi).  It is
+    evaluated as (lo hi + s (lo + hi)) / (sqrt((lo + s)(hi + s)) + s), the same
+    number without the cancellation of the difference when s >> hi.
+    """
     if not (lam_min > 0 and lam_max >= lam_min):
         raise ValueError("need 0 < lam_min <= lam_max")
+    if not sigma_d2 >= 0:
+        raise ValueError("need sigma_d2 >= 0")
     L = L or num_intervals(lam_min, lam_max)
     beta = lam_max / lam_min
     grid = np.array([lam_min * beta ** (l / L) for l in range(L + 1)])
     grid[-1] = lam_max
-    lam0 = np.sqrt(grid[:-1] * grid[1:])
+    s = float(sigma_d2)
+    lo, hi = grid[:-1], grid[1:]
+    lam0 = (lo * hi + s * (lo + hi)) / (np.sqrt((lo + s) * (hi + s)) + s)
     return grid, lam0
 
 
@@ -249,7 +261,7 @@ def basis_adaptive(op, P, C, tau, rate, lo, hi, ref, tol, k_max):
 
 
 def path(A, B, lambdas, SA, lam_min, lam_max, *, L=None, k=None, tol=1e-10,
-         k_max=200, centred=True, taus=None):
+         k_max=200, centred=True, taus=None, sigma_d2=0.0):
     """IHS-BIN for every lambda: returns (X[T, d, K], list of Interval).
 
     ``SA`` is the sketched matrix (m x d).  With ``k`` given every interval
@@ -258,7 +270,7 @@ def path(A, B, lambdas, SA, lam_min, lam_max, *, L=None, k=None, tol=1e-10,
     """
     op = Operator(A)
     C = op.At(np.asarray(B).reshape(A.shape[0], -1))
-    grid, lam0s = plan(lam_min, lam_max, L)
+    grid, lam0s = plan(lam_min, lam_max, L, sigma_d2)
     ivs = []
     for l in range(len(lam0s)):
         lo, hi, lam0 = grid[l], grid[l + 1], lam0s[l]

@@ -56,7 +56,8 @@ class Opts(C.Structure):
                 ("adaptive_m", C.c_int32), ("rate_target", C.c_double), ("m_max", C.c_int64),
                 ("lanczos_steps", C.c_int32), ("timing", C.c_int32),
                 ("taus", C.POINTER(C.c_double)), ("gram_prec", C.c_int32),
-                ("alg4", C.POINTER(Alg4Opts)), ("sketch_prec", C.c_int32)]
+                ("alg4", C.POINTER(Alg4Opts)), ("sketch_prec", C.c_int32),
+                ("sigma_d2", C.c_double)]
 
 
 class Report(C.Structure):

@@ -814,6 +814,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   if (o.k_fixed < 0 || o.k_fixed > 4096) fail(IHSBIN_EINVAL, "k_fixed out of range");
   if (!(o.tol > 0.0)) fail(IHSBIN_EINVAL, "tol must be positive");
   if (o.adaptive_m < 0 || o.adaptive_m > 2) fail(IHSBIN_EINVAL, "adaptive_m out of range");
+  if (!(o.sigma_d2 >= 0.0) || !std::isfinite(o.sigma_d2)) fail(IHSBIN_EINVAL, "need sigma_d2 >= 0");
   hipStream_t st = c.stream;
   Timer total;
   ihsbin_report r;
@@ -842,7 +843,14 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   std::vector<double> grid(L + 1), lam0(L);
   for (int l = 0; l <= L; ++l) grid[l] = lam_min * std::pow(beta, (double)l / L);
   grid[L] = lam_max;
-  for (int l = 0; l < L; ++l) lam0[l] = std::sqrt(grid[l] * grid[l + 1]);
+  // centre of each interval; with sigma_d^2 known, the shifted geometric
+  // centre of the remark after Theorem 1: (lam0 + s)^2 = (lo + s)(hi + s)
+  // (written without the cancellation of sqrt(...) - s for large s)
+  const double sd2 = o.sigma_d2;
+  for (int l = 0; l < L; ++l) {
+    const double lo = grid[l], hi = grid[l + 1];
+    lam0[l] = (lo * hi + sd2 * (lo + hi)) / (std::sqrt((lo + sd2) * (hi + sd2)) + sd2);
+  }
   const int64_t d = A.d;
 
   // ---- sketch, with adaptive m
@@ -1302,6 +1310,7 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->taus = nullptr;
   o->alg4 = nullptr;
   o->sketch_prec = IHSBIN_SKETCH_F64;
+  o->sigma_d2 = 0.0;
 }
 
 void ihsbin_alg4_opts_default(ihsbin_alg4_opts* a) {

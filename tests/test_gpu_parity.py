@@ -365,3 +365,27 @@ def test_path_with_bf16x3_gram(torch, ctx, kind):
     assert rep["status"] == 0, rep
     err = direct.rel_err(X.cpu().numpy(), direct.ridge_path(A, B, lams))
     assert err.max() <= 1e-6, err
+
+
+def test_path_refined_centres(torch, ctx):
+    # the remark after Theorem 1: centres shifted by sigma_d^2; the same fixed
+    # point, the oracle's centres, and no more steps than the plain centres
+    r = np.random.default_rng(17)
+    n, d = 4000, 120
+    U, _ = np.linalg.qr(r.standard_normal((n, d)))
+    A = (U * np.sqrt(np.geomspace(0.3, 300.0, d))).astype(np.float64)
+    B = A @ r.standard_normal((d, 2)) + 0.1 * r.standard_normal((n, 2))
+    s = float(np.linalg.eigvalsh(A.T @ A)[0])
+    lams = W.lambda_grid(1e-2, 1e2, 25)
+    out = {}
+    for sd2 in (0.0, s):
+        path, rep = ctx.path_build(dev(torch, A), dev(torch, B), lams[0], lams[-1], sketch="srht",
+                                   m=1000, seed=5, sigma_d2=sd2)
+        X = path.eval(lams).cpu().numpy()
+        iv = path.intervals()
+        path.free()
+        _check_path(X, A, B, lams)
+        grid, c = ihs_bin.plan(lams[0], lams[-1], len(iv["lam0"]), sigma_d2=sd2)
+        np.testing.assert_allclose(iv["lam0"], c, rtol=1e-12)
+        out[sd2] = rep["k_sum"]
+    assert out[s] <= out[0.0], out

@@ -202,3 +202,42 @@ def test_matrix_rhs_is_columnwise(prob):
         # one-column product differently, so the tolerance follows the scale of X
         np.testing.assert_allclose(X[:, :, col:col + 1], Xc, rtol=1e-12,
                                    atol=1e-13 * np.abs(X).max())
+
+
+def test_refined_centres_remark():
+    # the remark after Theorem 1: (lam0 + s)^2 = (lo + s)(hi + s); s = 0 is the
+    # geometric centre, s -> infinity the arithmetic one
+    grid, c0 = ihs_bin.plan(1e-3, 1e2, 9)
+    np.testing.assert_allclose(c0, np.sqrt(grid[:-1] * grid[1:]), rtol=1e-14)
+    for s in (1e-3, 0.7, 50.0):
+        g, c = ihs_bin.plan(1e-3, 1e2, 9, sigma_d2=s)
+        np.testing.assert_array_equal(g, grid)
+        np.testing.assert_allclose((c + s) ** 2, (g[:-1] + s) * (g[1:] + s), rtol=1e-13)
+        assert (c >= g[:-1]).all() and (c <= g[1:]).all()
+    g, c = ihs_bin.plan(1e-3, 1e2, 9, sigma_d2=1e9)
+    np.testing.assert_allclose(c, 0.5 * (g[:-1] + g[1:]), rtol=1e-6)
+
+
+def test_refined_centres_lower_the_exact_rate():
+    # with the exact Hessian (S = I) the spectrum of P (A^T A + lam I) over an
+    # interval is {(s_i + lam) / (s_i + lam0)}: with sigma_d^2 comparable to
+    # the lambdas the refined centre gives a smaller worst-case rate
+    r = np.random.default_rng(4)
+    n, d = 400, 30
+    U, _ = np.linalg.qr(r.standard_normal((n, d)))
+    sig2 = np.geomspace(0.5, 50.0, d)
+    A = U * np.sqrt(sig2)
+    op = ihs_bin.Operator(A)
+    s = float(np.linalg.eigvalsh(A.T @ A)[0])
+    g, c_plain = ihs_bin.plan(1e-2, 1e2, 4)
+    _, c_ref = ihs_bin.plan(1e-2, 1e2, 4, sigma_d2=s)
+    for l in range(4):
+        rates = []
+        for c in (c_plain[l], c_ref[l]):
+            P = ihs_bin.Precond(A, c)
+            rates.append(ihs_bin.step_size_from_bounds(*ihs_bin.interval_bounds(op, P, g[l], g[l + 1]))[1])
+        assert rates[1] <= rates[0] + 1e-12, (l, rates)
+        # closed form: the extremes sit at sigma^2 = s, c in [1/k, k] with
+        # k^2 = (hi + s) / (lo + s), so the rate is (k^2 - 1) / (k^2 + 1)
+        k2 = (g[l + 1] + s) / (g[l] + s)
+        assert rates[1] == pytest.approx((k2 - 1) / (k2 + 1), rel=1e-9)
