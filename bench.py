@@ -111,7 +111,7 @@ def serve(args, torch, W):
     """Replay of the serving workload through the request server."""
     from paper_2210_12212_amd import Server
     dev = torch.device("cuda", 0)
-    reqs = W.serving_mix(args.serve_requests, rate=args.serve_rate)
+    reqs = _serve_requests(args, W)
     lams = W.lambda_grid(1e-4, 1e1, 100)
     srv = Server(0, workers=args.serve_workers)
     log(f"[serve] {len(reqs)} requests, {args.serve_rate}/s, {args.serve_workers} workers, "
@@ -166,6 +166,14 @@ def serve(args, torch, W):
     return reqs, done, wall, st, lams
 
 
+def _serve_requests(args, W):
+    if args.serve_small:
+        # many small problems at once: 2048 x 256 dense requests, all arriving at t = 0
+        return [dict(index=i, arrival=0.0, n=2048, d=256, dense=True, K=1, seed=9000 + i)
+                for i in range(args.serve_requests)]
+    return W.serving_mix(args.serve_requests, rate=args.serve_rate)
+
+
 def _serve_opts(req, args):
     return dict(sketch="gaussian" if req["dense"] else "countsketch", seed=req["seed"],
                 adaptive_m={"spectral": 1, "alg4": 2}[args.serve_m_policy], tol=args.tol,
@@ -177,7 +185,7 @@ def _serve_opts(req, args):
 def serve_main(args, torch, W):
     from oracle import direct
     # requests checked against the oracle: the three smallest dense and CSR ones
-    reqs = W.serving_mix(args.serve_requests, rate=args.serve_rate)
+    reqs = _serve_requests(args, W)
     small = sorted(reqs, key=lambda r: r["n"] * r["d"])
     pick = [r["index"] for r in small if r["dense"]][:2] + \
            [r["index"] for r in small if not r["dense"]][:1]
@@ -224,7 +232,8 @@ def serve_main(args, torch, W):
         "higher_is_better": True,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "serving_mix", "rate_per_s": args.serve_rate,
+        "config": {"workload": "small_2048x256_burst" if args.serve_small else "serving_mix",
+                   "rate_per_s": None if args.serve_small else args.serve_rate,
                    "workers": args.serve_workers, "outstanding_cap": args.serve_outstanding,
                    "T": T, "lam": [1e-4, 1e1], "m_policy": args.serve_m_policy,
                    "sketch_prec": args.serve_sketch_prec,
@@ -259,6 +268,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="replay the serving workload (Poisson arrivals) through the server")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-small", action="store_true",
+                    help="serve many 2048 x 256 dense problems submitted at once instead")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-m-policy", choices=("spectral", "alg4"), default="spectral",
