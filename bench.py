@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--lanczos-steps", type=int, default=4)
     ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default="f64",
                     help="sketched Gram precision (the factor and the recursion stay FP64)")
+    ap.add_argument("--sketch-prec", choices=("f64", "bf16"), default="f64",
+                    help="arithmetic of the Gaussian sketch product (other sketches ignore it)")
     ap.add_argument("--m-policy", choices=("spectral", "alg4", "fixed"), default="spectral",
                     help="sketch size: spectral probe (default), Algorithm 4 at lam_min, or m0")
     ap.add_argument("--oracle-lambdas", type=int, default=12,
@@ -326,7 +328,8 @@ def main():
     opts = dict(sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=args.tol,
                 rate_target=args.rate_target, lanczos_steps=args.lanczos_steps, timing=1,
                 gram_prec={"f64": 0, "bf16x3": 1}[args.gram_prec],
-                adaptive_m={"fixed": 0, "spectral": 1, "alg4": 2}[args.m_policy])
+                adaptive_m={"fixed": 0, "spectral": 1, "alg4": 2}[args.m_policy],
+                sketch_prec={"f64": 0, "bf16": 1}[args.sketch_prec])
     X = torch.empty((len(p.lambdas), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
 
     def step():
@@ -455,7 +458,8 @@ def main():
                    "m_used": rep["m_used"], "L": rep["L"], "k_max": rep["k_max_used"],
                    "k_sum": rep["k_sum"], "lam": [p.lam_min, p.lam_max], "tol": args.tol,
                    "rate_target": args.rate_target, "lanczos_steps": args.lanczos_steps,
-                   "gram_prec": args.gram_prec, "m_policy": args.m_policy},
+                   "gram_prec": args.gram_prec, "m_policy": args.m_policy,
+                   "sketch_prec": args.sketch_prec},
         "max_rel_err": max_err,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phase_ms": {k: rep[k] for k in ("ms_sketch", "ms_factor", "ms_spectrum", "ms_basis",
