@@ -5,13 +5,17 @@ Gram, per-interval Cholesky and inverse factors, step-size estimate, basis
 recursion, and evaluation of x(lam) at all T lambdas (the path is freed after).
 The inputs are resident in HBM before the timed region starts.
 
-Default workload: dense A, n = 131072, d = 2048, FP32 storage, singular values
-exp(-i/300), b = A x* + 0.05 noise, SRHT sketch with initial m = 1024, T = 200
-lambdas log-spaced in [1e-4, 1e1].
+Default workload: the matrix-valued problem (Section 5.3), dense A with
+n = 262144, d = 4096, FP32 storage, singular values i^-0.5, B = A X* + 0.05
+noise with K = 64 right-hand sides, Gaussian sketch with initial m = 2048 on
+the BF16 matrix cores, T = 100 lambdas log-spaced in [1e-4, 1e1].
 
 Prints one JSON line.  ``value`` = lambda-solves per second (T per step).
-Outside the timed region the result is checked on sampled lambdas against the
-FP64 CPU oracle, which is also timed on the host as ``cpu_baseline``.
+Outside the timed region every lambda of the last step is checked against the
+FP64 CPU oracle (the eigendecomposition form of Section 2.1 when d <= 4096,
+else one Cholesky solve per lambda); ``value`` is null unless every error is
+<= 1e-6 and every build returned IHSBIN_OK.  The oracle's per-lambda Cholesky
+form is also timed on the host on a sample of lambdas as ``cpu_baseline``.
 """
 from __future__ import annotations
 
@@ -35,17 +39,27 @@ HBM_PEAK = 8.0e12          # bytes/s
 # calibration, recorded in the profile summary below together with the sha256
 # of the GEMM source they were measured on.  When that source has changed
 # since (or for another workload) the figure is stale and reported as null.
-TRAFFIC_WORKLOAD = "dense_exp300_131072x2048"
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_ata_traffic_dense_131072x2048.md")
+TRAFFIC_PROFILES = {
+    "dense_exp300_131072x2048": os.path.join(ROOT, "profiles",
+                                             "gemm_ata_traffic_dense_131072x2048.md"),
+    "dense_invsqrt_262144x4096_k64": os.path.join(ROOT, "profiles",
+                                                  "gemm_ata_traffic_dense_262144x4096_k64.md"),
+}
+DEFAULT_WORKLOAD = "dense_invsqrt_262144x4096_k64"
+# the arithmetic of the Gaussian sketch product per workload when not given:
+# the matrix-valued workload is specified with its sketch on the BF16 matrix cores
+SKETCH_PREC_DEFAULT = {"dense_invsqrt_262144x4096_k64": "bf16"}
 GEMM_SOURCE = os.path.join(ROOT, "paper_2210_12212_amd", "csrc", "gemm.hip")
 
 
-def recorded_traffic(kernel):
+def recorded_traffic(workload, kernel):
     """Measured HBM bytes per launch of `kernel`, or None when stale/absent."""
     import hashlib
     import re
+    if workload not in TRAFFIC_PROFILES:
+        return None
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(TRAFFIC_PROFILES[workload]).read()
         src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -230,7 +244,8 @@ def serve_main(args, torch, W):
         "server": st,
         "max_rel_err_sampled": errs,
         "higher_is_better": True,
-        "dtype": "f64",
+        "dtype": "f64" if args.sketch_prec == "f64" and args.gram_prec == "f64" else
+                 "f64+bf16",
         "data": "synthetic",
         "config": {"workload": "small_2048x256_burst" if args.serve_small else "serving_mix",
                    "rate_per_s": None if args.serve_small else args.serve_rate,
@@ -251,19 +266,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dense_exp300_131072x2048")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs)")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--rate-target", type=float, default=0.5)
     ap.add_argument("--lanczos-steps", type=int, default=4)
     ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default="f64",
                     help="sketched Gram precision (the factor and the recursion stay FP64)")
-    ap.add_argument("--sketch-prec", choices=("f64", "bf16"), default="f64",
-                    help="arithmetic of the Gaussian sketch product (other sketches ignore it)")
+    ap.add_argument("--sketch-prec", choices=("f64", "bf16"), default=None,
+                    help="arithmetic of the Gaussian sketch product (other sketches ignore it); "
+                         "default bf16 for the matrix-valued workload, else f64")
     ap.add_argument("--m-policy", choices=("spectral", "alg4", "fixed"), default="spectral",
                     help="sketch size: spectral probe (default), Algorithm 4 at lam_min, or m0")
     ap.add_argument("--oracle-lambdas", type=int, default=12,
-                    help="lambdas of the sample solved by the CPU oracle")
+                    help="lambdas of the sample the CPU oracle's Cholesky form is timed on")
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration)")
@@ -310,6 +326,8 @@ def main():
         serve_main(args, torch, W)
         return
 
+    if args.sketch_prec is None:
+        args.sketch_prec = SKETCH_PREC_DEFAULT.get(args.workload, "f64")
     t0 = time.time()
     p = W.make(args.workload, n=args.n)
     log(f"[bench] workload {p.name}: n={p.n} d={p.d} K={p.B.shape[1]} T={len(p.lambdas)} "
@@ -343,12 +361,12 @@ def main():
         log(f"[bench] warmup {w}: {rep['ms_total']:.1f} ms  m_used={rep['m_used']} "
             f"k_max={rep['k_max_used']} k_sum={rep['k_sum']} status={rep['status']}")
     lat = []
-    reps = []
+    step_reps = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for s in range(args.steps):
         ts = time.perf_counter()
-        reps.append(step())
+        step_reps.append(step())
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
         log(f"[bench] step {s}: {lat[-1]:.1f} ms")
@@ -357,7 +375,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     T = len(p.lambdas)
     value = T * args.steps / elapsed
-    rep = reps[-1]
+    rep = step_reps[-1]
 
     # dominant kernel: the two products of A^T A U (dense: FP64 MFMA GEMMs of
     # 2*n*d*w flops each)
@@ -377,7 +395,7 @@ def main():
     else:
         dom = "gemm_y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "gemm_w_AtY"
         achieved = (half_flops / launches) / (dom_ms / launches * 1e-3) / 1e12 if dom_ms > 0 else 0.0
-        traffic = recorded_traffic(dom) if p.name == TRAFFIC_WORKLOAD and args.n is None else None
+        traffic = recorded_traffic(p.name, dom) if args.n is None else None
         roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
                     "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                     "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": traffic}
@@ -406,10 +424,12 @@ def main():
     path.free()
     log(f"[bench] eval only: {eval_only} lambda-solves/s")
 
-    # accuracy on sampled lambdas, and the oracle timed on the host (outside the timed region)
+    # accuracy at every lambda, and the oracle timed on the host (outside the
+    # timed region)
     Xh = X.cpu().numpy()
     cpu = None
     max_err = None
+    n_checked = 0
     if not args.no_oracle:
         from oracle import direct
         cores = len(os.sched_getaffinity(0))
@@ -428,8 +448,7 @@ def main():
         else:
             Xo = direct.solve_from_gram(G, C, p.lambdas[idx])
         t_solve = (time.perf_counter() - ts) / len(idx)
-        err = direct.rel_err(Xh[idx], Xo)
-        max_err = float(err.max())
+        err_s = direct.rel_err(Xh[idx], Xo)
         t_full = t_gram + T * t_solve
         cpu = {"value": round(T / t_full, 3), "unit": "lambda-solves/s", "cores": cores,
                "kind": "oracle",
@@ -438,11 +457,35 @@ def main():
                          f"{T} per-lambda Cholesky solves ({t_solve * 1e3:.1f} ms each); the full "
                          f"path time is t_G + T*t_solve = {t_full:.1f}s"}
         log(f"[bench] oracle: gram {t_gram:.1f}s, solve {t_solve * 1e3:.1f} ms/lambda, "
-            f"max rel err on {len(idx)} lambdas = {max_err:.3e}")
+            f"max rel err on the {len(idx)} timed lambdas = {err_s.max():.3e}")
+        # every lambda: the eigendecomposition form (one eigh of the d x d
+        # Gram, then O(d^2 K) per lambda) up to d = 4096, else Cholesky per lambda
+        te = time.perf_counter()
+        if wide:
+            Xall = direct.solve_dual_from_gram(G, p.A, p.B, p.lambdas)
+        elif p.d <= 4096:
+            ev, V = direct.eig_of_gram(G)
+            Xall = direct.solve_from_eig(ev, V, C, p.lambdas)
+        else:
+            Xall = direct.solve_from_gram(G, C, p.lambdas)
+        err = direct.rel_err(Xh, Xall)
+        max_err = float(max(err.max(), err_s.max()))
+        n_checked = T
+        log(f"[bench] oracle: every lambda checked in {time.perf_counter() - te:.1f}s, "
+            f"max rel err {max_err:.3e}")
+    statuses = sorted({int(r_["status"]) for r_ in step_reps})
+    valid = (max_err is not None and max_err <= 1e-6 and statuses == [0])
+    invalid_reason = None
+    if max_err is None:
+        invalid_reason = "accuracy not checked (--no-oracle)"
+    elif max_err > 1e-6:
+        invalid_reason = f"max rel err {max_err:.3e} > 1e-6"
+    elif statuses != [0]:
+        invalid_reason = f"build status {statuses}"
 
     out = {
         "metric": "ridge-path lambda-solves/s at <=1e-6 rel err vs FP64",
-        "value": round(value, 3),
+        "value": round(value, 3) if valid else None,
         "unit": "lambda-solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -451,7 +494,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.sketch_prec == "f64" and args.gram_prec == "f64" else
+                 "f64+bf16",
         "data": "synthetic",
         "config": {"workload": p.name, "n": p.n, "d": p.d, "K": int(p.B.shape[1]), "T": T,
                    "storage": str(p.A.dtype), "sketch": p.sketch, "m0": p.m,
@@ -461,6 +505,11 @@ def main():
                    "gram_prec": args.gram_prec, "m_policy": args.m_policy,
                    "sketch_prec": args.sketch_prec},
         "max_rel_err": max_err,
+        "lambdas_checked": n_checked,
+        "invalid_reason": invalid_reason,
+        "measured_value": round(value, 3),
+        "est_rel_err": rep["est_rel_err"],
+        "bytes_moved_per_step": rep["bytes_moved"],
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phase_ms": {k: rep[k] for k in ("ms_sketch", "ms_factor", "ms_spectrum", "ms_basis",
                                          "ms_total")},

@@ -180,6 +180,19 @@ typedef struct {
   int64_t peak_bytes;      /* device memory held through the context at the
                               build's peak: its pool, workspaces (including those
                               kept from earlier calls) and the path's buffers    */
+  double est_rel_err;      /* the stop test's bound on the relative error left
+                              in x(lam), the largest over every interval and
+                              both of its ends at the step the interval stopped:
+                              ||last increment|| * r / (1 - r) / ||x||, r the
+                              interval's predicted rate (the worst case over an
+                              interval is at its ends, proof of Theorem 1); for
+                              IHSBIN_ENOCONV it is the estimate of the intervals
+                              that hit k_max; n < d: of the dual iterate; NaN
+                              when every interval has one term (k = 1)          */
+  double bytes_moved;      /* algorithmic device-memory bytes of the passes over
+                              A: A read once per product (sketch, A^T B, every
+                              A U and A^T Y), the n x w intermediate Y written
+                              and read once, U read and W written once          */
 } ihsbin_report;
 
 /* Per-interval description of a built path (host arrays of length L). */
@@ -227,8 +240,8 @@ const char* ihsbin_last_error(const ihsbin_ctx* ctx);
  * On success *path owns the basis on the device.  report may be NULL.
  * Errors: EINVAL (0 < lam_min <= lam_max violated, sizes), EUNSUP (n < d
  * with a CSR matrix), ENOTSPD, ENOMEM, EHIP.  ENOCONV: some interval reached
- * k_max; *path is still returned and usable (its error estimate is in the
- * report). */
+ * k_max; *path is still returned and usable, and report->est_rel_err holds
+ * the stop test's bound on its remaining relative error. */
 int ihsbin_path_build(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
                       int64_t K, int64_t ldb, double lam_min, double lam_max,
                       const ihsbin_opts* opts, ihsbin_path** path,
@@ -257,7 +270,10 @@ int ihsbin_path_basis(const ihsbin_path* path, int32_t l, double* out);
 /* Free a path (NULL allowed). */
 int ihsbin_path_free(ihsbin_path* path);
 
-/* Build, evaluate and free in one call. */
+/* Algorithm 3 (Algorithm 6 for K > 1) in one call: build the basis for
+ * [min(lambdas), max(lambdas)], evaluate x(lam_t) for every lambda into X
+ * (layout of ihsbin_path_eval) and free the path.  Errors as for
+ * ihsbin_path_build and ihsbin_path_eval; with ENOCONV X is still written. */
 int ihsbin_solve_path(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
                       int64_t K, int64_t ldb, const double* lambdas, int64_t T,
                       const ihsbin_opts* opts, void* X, int64_t ldx,
@@ -273,6 +289,33 @@ int ihsbin_solve_path(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
 int ihsbin_sketch_draws(ihsbin_ctx* ctx, int32_t sketch, uint64_t seed,
                         int64_t n, int64_t m, int32_t sjlt_s, int32_t* idx,
                         int8_t* sign);
+
+/* The same draws computed on the host, for checking a device copy bit for
+ * bit (Section 4, sketch list; SplitMix64 counter draws).  Layouts as for
+ * ihsbin_sketch_draws: COUNTSKETCH/SJLT fill idx (n*s int32, bucket in
+ * [0, m), SJLT block b of row i in [b*m/s, (b+1)*m/s)) and sign (n*s int8,
+ * +-1); SRHT fills sign (n int8, the diagonal D) and idx (m int32, rows of
+ * the order-n' transform, n' = 2^ceil(log2 n), drawn with replacement).
+ * idx and sign are host buffers owned by the caller.  EINVAL for bad sizes,
+ * null pointers, an SJLT s that does not divide m, or GAUSSIAN (whose
+ * values go through log/cos and are not defined bit for bit). */
+int ihsbin_sketch_indices_host(uint64_t seed, int32_t sketch, int64_t n, int64_t m,
+                               int32_t sjlt_s, int32_t* idx, int8_t* sign);
+
+/* ihsbin_sketch_draws with the argument order of ihsbin_sketch_indices_host
+ * (idx and sign are device buffers). */
+int ihsbin_sketch_indices_device(ihsbin_ctx* ctx, uint64_t seed, int32_t sketch, int64_t n,
+                                 int64_t m, int32_t sjlt_s, int32_t* idx, int8_t* sign);
+
+/* The column-major copy of a CSR matrix that the transposed products A^T Y
+ * gather from (built inside every CSR build).  col_ptr (device int32, d+1),
+ * row (device int32, nnz) and vals (device, nnz elements of A's dtype) receive
+ * it: the entries of column c at positions [col_ptr[c], col_ptr[c+1]) in the
+ * order of their position in the CSR arrays (so by increasing row, and a
+ * row's duplicates in their stored order), which makes it the stable
+ * transpose of A.  EINVAL for a dense or malformed matrix. */
+int ihsbin_csr_transpose(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t* col_ptr,
+                         int32_t* row, void* vals);
 
 /* SA = S A (Section 4, Algorithm 3 first line), FP64, m x d row-major into
  * SA (device, m*d doubles).  ihsbin_sketch_apply_prec selects the Gaussian

@@ -106,9 +106,42 @@ def ridge_path_dual(A, B, lambdas) -> np.ndarray:
     return solve_dual_from_gram(dual_gram(A), A, B, lambdas)
 
 
+def solve_from_eig(evals: np.ndarray, V: np.ndarray, C: np.ndarray, lambdas) -> np.ndarray:
+    """X[t] = V diag(1 / (evals + lambdas[t])) V^T C; returns T x d x K.
+
+    With G = A^T A = V diag(sigma^2) V^T and C = A^T B = V diag(sigma) U^T B
+    this is the closed form x*(lam) = V diag(sigma / (sigma^2 + lam)) U^T b of
+    Section 2.1 (one eigendecomposition of G serves every lambda, O(d^2 K)
+    per lambda afterwards).  ``eig_of_gram`` gives evals, V."""
+    lambdas = np.atleast_1d(np.asarray(lambdas, dtype=np.float64))
+    W = V.T @ np.asarray(C, dtype=np.float64)
+    out = np.empty((len(lambdas), V.shape[0], W.shape[1]))
+    for t, lam in enumerate(lambdas):
+        out[t] = V @ (W / (evals + lam)[:, None])
+    return out
+
+
+def eig_of_gram(G: np.ndarray):
+    """Eigenvalues (clipped at 0: G is PSD) and eigenvectors of G = A^T A."""
+    evals, V = np.linalg.eigh(G)
+    return np.maximum(evals, 0.0), V
+
+
+def ridge_path_eig(A, B, lambdas) -> np.ndarray:
+    """The exact ridge path through the eigendecomposition of G (Section 2.1),
+    T x d x K, FP64; for many lambdas at large d."""
+    evals, V = eig_of_gram(gram(A))
+    return solve_from_eig(evals, V, atb(A, B), lambdas)
+
+
 def rel_err(X_hat, X_ref) -> np.ndarray:
-    """Per-lambda relative Frobenius error ||X_hat - X_ref|| / ||X_ref||."""
+    """Per-lambda relative Frobenius error ||X_hat[t] - X_ref[t]|| / ||X_ref[t]||
+    (each of the T leading blocks is one lambda; a block of zeros in X_ref
+    gives inf or nan, never a small number)."""
+    X_ref = np.asarray(X_ref, dtype=np.float64)
     X_hat = np.asarray(X_hat, dtype=np.float64).reshape(X_ref.shape)
-    num = np.linalg.norm((X_hat - X_ref).reshape(len(X_ref), -1), axis=1)
-    den = np.linalg.norm(X_ref.reshape(len(X_ref), -1), axis=1)
-    return num / den
+    T = X_ref.shape[0]
+    num = np.sqrt(np.sum((X_hat - X_ref).reshape(T, -1) ** 2, axis=1))
+    den = np.sqrt(np.sum(X_ref.reshape(T, -1) ** 2, axis=1))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return num / den

@@ -162,30 +162,45 @@ def step_size(mu_min: float, mu_max: float, lo: float, hi: float, lam0: float):
     return 2.0 / (cmin + cmax), (cmax - cmin) / (cmax + cmin)
 
 
-# --------------------------------------------------- basis (Algorithm 2 / 5)
+# -------------------------------- basis (the Proposition, Eq. (equ:upd))
+def recursion_step(u, P, Hop, tau: float):
+    """One whole step of Eq. (equ:upd): from u_{i,0..i} to u_{i+1,0..i+1}.
+
+    u_{i+1,j} = u_{i,j} - P_S (tau H u_{i,j} + u_{i,j-1}), where a term whose
+    index falls outside 0..i is zero: j = 0 has no u_{i,-1}, and j = i+1 has
+    no u_{i,i+1}, which leaves u_{i+1,i+1} = -P_S u_{i,i}.  Every new vector
+    reads only step-i vectors.  H = A^T A + ref I (``Hop``)."""
+    i = len(u) - 1
+    new = []
+    for j in range(i + 2):
+        prev = u[j] if j <= i else None
+        lower = u[j - 1] if j >= 1 else None
+        rhs = tau * Hop(prev) if prev is not None else 0.0
+        if lower is not None:
+            rhs = rhs + lower
+        step = P(rhs)
+        new.append(prev - step if prev is not None else -step)
+    return new
+
+
+def _accumulate(ut, u):
+    """ut_j += u_{i,j} for the new step (ut grows by one entry)."""
+    ut = list(ut) + [np.zeros_like(u[0])]
+    return [ut[j] + u[j] for j in range(len(u))]
+
+
 def basis(op: Operator, P: Precond, C: np.ndarray, tau: float, k: int,
           ref: float = 0.0):
-    """ut_0 .. ut_{k-1} (each d x K) by the recursion of the Proposition.
-
-    The working vectors u_j are updated in place for j descending, exactly
-    as Algorithm 2 orders them, so u_{j-1} still holds step i-1 when u_j
-    reads it.  H = A^T A + ref I.
-    """
+    """ut_0 .. ut_{k-1} (each d x K) from the Proposition: u_{0,0} = P_S C,
+    k - 1 steps of Eq. (equ:upd), ut_j = sum_i u_{i,j}.  H = A^T A + ref I."""
     def Hop(V):
         return op.AtA(V) + ref * V
 
-    u = [None] * k
-    ut = [None] * k
-    u[0] = P(C)
-    ut[0] = u[0].copy()
-    for i in range(1, k):
-        u[i] = -P(u[i - 1])
-        for j in range(i - 1, 0, -1):
-            u[j] = u[j] - P(tau * Hop(u[j]) + u[j - 1])
-        u[0] = u[0] - P(tau * Hop(u[0]))
-        ut[i] = np.zeros_like(u[0])
-        for j in range(i + 1):
-            ut[j] = ut[j] + u[j]
+    u = [P(C)]
+    ut = [u[0].copy()]
+    for _ in range(1, k):
+        u = recursion_step(u, P, Hop, tau)
+        ut = _accumulate(ut, u)
     return ut
 
 
@@ -229,25 +244,22 @@ def _increment(u_list, tau, lam, ref):
 
 
 def basis_adaptive(op, P, C, tau, rate, lo, hi, ref, tol, k_max):
-    """Algorithm 2 with the step count chosen by the endpoint increment test.
+    """The basis of ``basis`` with the step count chosen by the endpoint
+    increment test.
 
     After step i the increment of x(lam) is tau M^i P_S A^T b; the loop stops
     once its norm times r/(1-r) is below tol * ||x(lam)|| at both interval
     ends (the worst case over the interval, per the proof of Theorem 1).
     """
+    def Hop(V):
+        return op.AtA(V) + ref * V
+
     u = [P(C)]
     ut = [u[0].copy()]
     k = 1
     for i in range(1, k_max):
-        new = [None] * (i + 1)
-        new[i] = -P(u[i - 1])
-        for j in range(i - 1, 0, -1):
-            new[j] = u[j] - P(tau * (op.AtA(u[j]) + ref * u[j]) + u[j - 1])
-        new[0] = u[0] - P(tau * (op.AtA(u[0]) + ref * u[0]))
-        u = new
-        ut.append(np.zeros_like(u[0]))
-        for j in range(i + 1):
-            ut[j] = ut[j] + u[j]
+        u = recursion_step(u, P, Hop, tau)
+        ut = _accumulate(ut, u)
         k = i + 1
         done = True
         for lam in (lo, hi):

@@ -22,7 +22,7 @@ import numpy as np
 from . import _lib as L
 
 __all__ = ["Context", "Path", "Server", "CsrInput", "IhsbinError", "solve_path",
-           "default_opts", "build_footprint"]
+           "default_opts", "build_footprint", "sketch_indices_host"]
 
 
 class IhsbinError(RuntimeError):
@@ -241,6 +241,37 @@ class Context:
                                                 C.c_void_p(idx.data_ptr()), C.c_void_p(sign.data_ptr())))
         return idx, sign
 
+    def sketch_indices_device(self, seed: int, sketch: str, n: int, m: int, sjlt_s: int = 1):
+        """ihsbin_sketch_indices_device -> (idx int32, sign int8) device tensors
+        (the layouts of sketch_draws)."""
+        torch = _torch()
+        code = L.SKETCHES[sketch]
+        dev = torch.device("cuda", self.device)
+        s = sjlt_s if code == L.SJLT else 1
+        idx = torch.empty(m if code == L.SRHT else n * s, dtype=torch.int32, device=dev)
+        sign = torch.empty(n if code == L.SRHT else n * s, dtype=torch.int8, device=dev)
+        self._check(L.lib().ihsbin_sketch_indices_device(
+            self._h, seed, code, n, m, sjlt_s, C.c_void_p(idx.data_ptr()),
+            C.c_void_p(sign.data_ptr())))
+        return idx, sign
+
+    def csr_transpose(self, A):
+        """ihsbin_csr_transpose -> (col_ptr, row, vals) device tensors of the
+        library's column-major copy of the CSR matrix A."""
+        torch = _torch()
+        if not isinstance(A, CsrInput):
+            raise TypeError("csr_transpose needs a CsrInput")
+        nnz = A.vals.numel()
+        col_ptr = torch.empty(A.d + 1, dtype=torch.int32, device=A.vals.device)
+        row = torch.empty(max(nnz, 1), dtype=torch.int32, device=A.vals.device)
+        vals = torch.empty(max(nnz, 1), dtype=A.vals.dtype, device=A.vals.device)
+        mat = _matrix(A)
+        self._check(L.lib().ihsbin_csr_transpose(self._h, C.byref(mat),
+                                                 C.c_void_p(col_ptr.data_ptr()),
+                                                 C.c_void_p(row.data_ptr()),
+                                                 C.c_void_p(vals.data_ptr())))
+        return col_ptr, row[:nnz], vals[:nnz]
+
     def sketch_apply(self, A, sketch: str, m: int, seed: int, sjlt_s: int = 1,
                      prec: str = "f64"):
         """ihsbin_sketch_apply_prec -> SA (m x d float64); prec "f64" or
@@ -287,6 +318,22 @@ class Context:
                                              U.shape[1], U.stride(0), C.c_void_p(W.data_ptr()),
                                              W.stride(0)))
         return W
+
+
+def sketch_indices_host(seed: int, sketch: str, n: int, m: int, sjlt_s: int = 1):
+    """ihsbin_sketch_indices_host -> (idx int32, sign int8) numpy arrays: the
+    library's host computation of the integer sketch draws (CountSketch/SJLT:
+    n*s of each; SRHT: m sampled rows and n signs)."""
+    code = L.SKETCHES[sketch]
+    s = sjlt_s if code == L.SJLT else 1
+    idx = np.zeros(m if code == L.SRHT else n * s, dtype=np.int32)
+    sign = np.zeros(n if code == L.SRHT else n * s, dtype=np.int8)
+    rc = L.lib().ihsbin_sketch_indices_host(int(seed), code, int(n), int(m), int(sjlt_s),
+                                            idx.ctypes.data_as(C.c_void_p),
+                                            sign.ctypes.data_as(C.c_void_p))
+    if rc != L.OK:
+        raise IhsbinError(rc, "ihsbin_sketch_indices_host")
+    return idx, sign
 
 
 def build_footprint(shape, K: int, lam_min: float, lam_max: float, csr: bool = False,
@@ -405,6 +452,16 @@ class Path:
         if out is None:
             out = torch.empty((len(lam), self.d, self.K), dtype=dtype or torch.float64,
                               device=torch.device("cuda", self.device))
+        else:
+            # the library writes T blocks of d rows with row stride ldx and
+            # block stride d * ldx: the tensor must span exactly that
+            if tuple(out.shape) != (len(lam), self.d, self.K):
+                raise ValueError(f"out must have shape {(len(lam), self.d, self.K)}")
+            if not out.is_cuda or out.device.index != self.device:
+                raise ValueError(f"out must be on cuda:{self.device}")
+            if len(lam) and (out.stride(2) != 1 or out.stride(1) < self.K
+                             or out.stride(0) != self.d * out.stride(1)):
+                raise ValueError("out needs unit column stride and block stride d * row stride")
         rc = L.lib().ihsbin_path_eval(self._h, lam.ctypes.data_as(C.POINTER(C.c_double)), len(lam),
                                       C.c_void_p(out.data_ptr()), out.stride(1), _dtype_code(out))
         if rc != L.OK:

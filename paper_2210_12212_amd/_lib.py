@@ -27,6 +27,7 @@ EXPORTED = [
     "ihsbin_build_footprint", "ihsbin_sketch_apply_prec", "ihsbin_path_set_stream", "ihsbin_server_opts_default",
     "ihsbin_server_create", "ihsbin_server_submit", "ihsbin_server_wait",
     "ihsbin_server_get_stats", "ihsbin_server_last_error", "ihsbin_server_destroy",
+    "ihsbin_sketch_indices_host", "ihsbin_sketch_indices_device", "ihsbin_csr_transpose",
 ]
 
 
@@ -68,7 +69,8 @@ class Report(C.Structure):
                 ("ms_spectrum", C.c_double), ("ms_basis", C.c_double), ("ms_total", C.c_double),
                 ("ata_launches", C.c_int64), ("ata_flops", C.c_double), ("ata_ms_y", C.c_double),
                 ("ata_ms_w", C.c_double), ("ata_bytes_a", C.c_double),
-                ("peak_bytes", C.c_int64)]
+                ("peak_bytes", C.c_int64), ("est_rel_err", C.c_double),
+                ("bytes_moved", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -145,6 +147,9 @@ def _declare(lib):
         "ihsbin_server_get_stats": (C.c_int, [vp, C.POINTER(ServerStats)]),
         "ihsbin_server_last_error": (C.c_char_p, [vp]),
         "ihsbin_server_destroy": (C.c_int, [vp]),
+        "ihsbin_sketch_indices_host": (C.c_int, [u64, i32, i64, i64, i32, vp, vp]),
+        "ihsbin_sketch_indices_device": (C.c_int, [vp, u64, i32, i64, i64, i32, vp, vp]),
+        "ihsbin_csr_transpose": (C.c_int, [vp, C.POINTER(Matrix), vp, vp, vp]),
         "ihsbin_sketch_size": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, dbl,
                                          C.POINTER(Opts), C.POINTER(Alg4Opts),
                                          C.POINTER(Alg4Result), vp, i64, pd, i32]),

@@ -185,6 +185,9 @@ struct Ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
   MemStats mem;  // declared before every buffer that reports to it
+  // algorithmic bytes of the passes over A and their n x w intermediates
+  // since the last reset (the build's bytes_moved)
+  double bytes_moved = 0.0;
   Pool pool;     // build-local buffers (declared first: outlives the workspaces below)
   // scratch shared by the step kernels of one call
   DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status;
@@ -260,5 +263,12 @@ struct MatView {  // a validated ihsbin_matrix
 };
 
 MatView check_matrix(const ihsbin_matrix* A);
+
+// Bytes of one read of A's stored values (and CSR indices).
+inline double matrix_bytes(const MatView& A) {
+  const double e = A.dtype == IHSBIN_F32 ? 4.0 : 8.0;
+  return A.format == IHSBIN_DENSE ? (double)A.n * (double)A.d * e
+                                  : (double)A.nnz * (e + 4.0) + 4.0 * (double)(A.n + 1);
+}
 
 }  // namespace ihs

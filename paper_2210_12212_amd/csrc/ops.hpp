@@ -19,6 +19,8 @@ void launch_draw_srht(uint64_t seed, int64_t n, int64_t npad, int64_t m, int8_t*
 void launch_gaussian_fill(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
                           double* S, hipStream_t st);
 // SA += S A for CountSketch / SJLT (SA zeroed by the caller).
+void launch_gaussian_fill_t(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
+                            double* St, hipStream_t st);
 void launch_countsketch_apply(const MatView& A, const int32_t* idx, const int8_t* sign, int s,
                               double* SA, hipStream_t st);
 // Z (npad x d) = D A zero-padded, then the Walsh-Hadamard transform over rows.

@@ -6,8 +6,12 @@
 // over n and a deterministic reduction; A is read in its stored type and
 // widened to FP64 in the GEMM staging.  Columns are processed in chunks so
 // the n x w intermediate stays within a fixed scratch budget.
-// CSR A: row-parallel gather for A U and a row-parallel scatter with FP64
-// atomics for A^T Y.
+// CSR A: row-parallel gather for A U; A^T Y gathers per column from the
+// column-major copy of A (csc.hip) in fixed order, or, without that copy,
+// scatters rows with FP64 atomics.
+// Every pass adds its algorithmic bytes to ctx.bytes_moved: A read once per
+// product, the n x w intermediate written and read once, U read and W
+// written once.
 #include "ops.hpp"
 
 namespace ihs {
@@ -243,6 +247,8 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
     IHS_HIP(hipEventRecord(e, st));
     ev->push_back(e);
   };
+  ctx.bytes_moved += 2.0 * matrix_bytes(A) * (double)cdiv(w, wc) +
+                     8.0 * (double)w * (2.0 * (double)A.n + 2.0 * (double)A.d);
   for (int64_t c0 = 0; c0 < w; c0 += wc) {
     const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
     const ColTiles ct = pick_col_tiles(cw);
@@ -314,6 +320,8 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
 
 void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C) {
   hipStream_t st = ctx.stream;
+  ctx.bytes_moved += matrix_bytes(A) + (double)A.n * (double)K * (A.dtype == IHSBIN_F32 ? 4.0 : 8.0) +
+                     8.0 * (double)A.d * (double)K;
   if (A.format == IHSBIN_CSR && A.csc) {
     double* P = static_cast<double*>(
         ctx.ws_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, csc_partial_doubles(*A.csc, K))));

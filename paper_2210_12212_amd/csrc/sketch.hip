@@ -89,6 +89,32 @@ void launch_gaussian_fill(uint64_t seed, int64_t m, int64_t r0, int64_t rows, in
   IHS_CHECK_LAUNCH();
 }
 
+// The same draws transposed: St[i][r - r0] = S[r][i] for r0 <= r < r0 + rows
+// (row stride `rows`), the layout a product A^T St gathers from.
+__global__ void gaussian_fill_t_kernel(uint64_t key, int64_t r0, int64_t rows, int64_t n,
+                                       double scale, double* St) {
+  const int64_t total = rows * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / rows, r = r0 + (t - i * rows);
+    const uint64_t q = (uint64_t)(r * n + i);
+    const uint64_t x1 = sm_draw(key, 2ull * q);
+    const uint64_t x2 = sm_draw(key, 2ull * q + 1ull);
+    const double u1 = ((double)(x1 >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
+    St[t] = scale * sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+  }
+}
+
+void launch_gaussian_fill_t(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
+                            double* St, hipStream_t st) {
+  int64_t blocks = cdiv(rows * n, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(gaussian_fill_t_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     stream_key(seed, 3), r0, rows, n, 1.0 / std::sqrt((double)m), St);
+  IHS_CHECK_LAUNCH();
+}
+
 // ----------------------------------------------------------- CountSketch
 // One workgroup per row of A: row i is added, with its sign, to row idx of SA.
 template <typename T>

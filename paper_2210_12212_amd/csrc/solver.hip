@@ -127,6 +127,7 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
   hipStream_t st = c.stream;
   if (m <= 0) fail(IHSBIN_EINVAL, "m must be positive");
   if (m > INT32_MAX) fail(IHSBIN_EUNSUP, "m too large");
+  c.bytes_moved += matrix_bytes(A) + 8.0 * (double)m * (double)A.d;
   if (prec != IHSBIN_SKETCH_F64 && prec != IHSBIN_SKETCH_BF16)
     fail(IHSBIN_EINVAL, "unknown sketch precision");
   if (kind == IHSBIN_GAUSSIAN && prec == IHSBIN_SKETCH_BF16) {
@@ -134,8 +135,41 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
     const int64_t pd = gaussian_sketch_bf16_part_doubles(m, A.n, A.d);
     double* part = static_cast<double*>(c.ws_part.ensure(sizeof(double) * (size_t)pd));
     gaussian_sketch_bf16(A, seed, m, SA, work, part, pd, st);
+  } else if (kind == IHSBIN_GAUSSIAN && A.format == IHSBIN_CSR) {
+    // (SA)^T = A^T S^T, O(m nnz(A)): each chunk of rows of S is drawn
+    // transposed (n x rows), gathered through the column-major copy of A in
+    // fixed order (d x rows), and transposed into its rows of SA
+    PoolBuf cb(c.pool);
+    Csc local;
+    const Csc* csc = A.csc;
+    if (!csc) {
+      build_csc(A, cb.ensure((size_t)csc_work_bytes(A)), local, st);
+      csc = &local;
+    }
+    int64_t rows = (int64_t)((size_t(1) << 30) / (sizeof(double) * (size_t)A.n));
+    rows = std::max<int64_t>(1, std::min<int64_t>(rows, 256));
+    if (rows > m) rows = m;
+    double* St = static_cast<double*>(c.ws_sketch.ensure(sizeof(double) * (size_t)rows * A.n));
+    double* Wt = static_cast<double*>(c.ws_tmp.ensure(sizeof(double) * (size_t)rows * A.d));
+    double* part = static_cast<double*>(c.ws_part.ensure(
+        sizeof(double) * (size_t)std::max<int64_t>(1, csc_partial_doubles(*csc, rows))));
+    for (int64_t r0 = 0; r0 < m; r0 += rows) {
+      const int64_t rn = std::min(rows, m - r0);
+      launch_gaussian_fill_t(seed, m, r0, rn, A.n, St, st);
+      launch_csc_atb(A, *csc, St, false, rn, rn, part, Wt, rn, st);
+      MatView wv;
+      wv.format = IHSBIN_DENSE;
+      wv.dtype = IHSBIN_F64;
+      wv.n = A.d;
+      wv.d = rn;
+      wv.ld = rn;
+      wv.nnz = 0;
+      wv.vals = Wt;
+      wv.row_ptr = nullptr;
+      wv.col_idx = nullptr;
+      launch_transpose(wv, SA + r0 * A.d, st);
+    }
   } else if (kind == IHSBIN_GAUSSIAN) {
-    if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "Gaussian sketch of a CSR matrix");
     int64_t rows = (int64_t)((size_t(1) << 30) / (sizeof(double) * (size_t)A.n));
     rows = std::max<int64_t>(64, (rows / 64) * 64);
     if (rows > m) rows = m;
@@ -793,7 +827,10 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
     b += 8.0 * (D + 1) + (4.0 + es) * nnz + 4.0 * (nnz / 1024 + D + 1) + 16.0 * nnz +
          4.0 * (D + 1) + 16.0 * nnz + double(4 << 20);
     // chunk partials of the gathered products (in the split-K buffer)
-    b += 8.0 * (nnz / 1024 + D + 1) * std::max(wc, K);
+    const int64_t gw = o.sketch == IHSBIN_GAUSSIAN ? std::max<int64_t>(wc, 256) : wc;
+    b += 8.0 * (nnz / 1024 + D + 1) * std::max(gw, K);
+    // Gaussian sketch: the d x rows gathered block before its transpose
+    if (o.sketch == IHSBIN_GAUSSIAN) b += 8.0 * 256 * D;
   }
   b += double(16 << 20);  // small buffers and the pool's 64 KiB rounding
   return (int64_t)b;
@@ -820,6 +857,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   ihsbin_report r;
   std::memset(&r, 0, sizeof(r));
   c.mem.peak = c.mem.live;
+  c.bytes_moved = 0.0;
   // path buffers (handed to the caller) count against the context while the
   // build runs
   struct Held {
@@ -1066,6 +1104,8 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   std::vector<hipEvent_t> events;
   std::vector<double> flops_per_launch;
   std::vector<double> host_part;
+  // stop-test bound per interval at its latest step (k = 1: no estimate yet)
+  std::vector<double> est(L, 0.0);
   int unconverged = 0;
   int steps = 0;
   for (int i = 1; i < kcap && !act.empty(); ++i) {
@@ -1104,6 +1144,12 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
       bool stop;
       const bool finite = std::isfinite(sums[0]) && std::isfinite(sums[1]) && std::isfinite(sums[2]) &&
                           std::isfinite(sums[3]);
+      {
+        const double fac = rate[l] / (1.0 - rate[l]);
+        const double e_lo = std::sqrt(sums[0]) * fac / std::sqrt(sums[2]);
+        const double e_hi = std::sqrt(sums[1]) * fac / std::sqrt(sums[3]);
+        est[l] = finite ? std::max(e_lo, e_hi) : INFINITY;
+      }
       if (o.k_fixed > 0) {
         stop = (i + 1 >= o.k_fixed);
       } else if (!finite) {
@@ -1207,6 +1253,9 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     r.k_sum += path->k[l];
   }
   r.n_unconverged = unconverged;
+  for (int l = 0; l < L; ++l) r.est_rel_err = std::max(r.est_rel_err, est[l]);
+  if (kcap == 1) r.est_rel_err = NAN;  // one term: no increment to bound it with
+  r.bytes_moved = c.bytes_moved;
   r.ms_total = total.ms();
   r.peak_bytes = c.mem.peak;
   if (rep) *rep = r;
@@ -1464,6 +1513,63 @@ int ihsbin_sketch_draws(ihsbin_ctx* ctx, int32_t sketch, uint64_t seed, int64_t 
       fail(IHSBIN_EINVAL, "no integer draws for this sketch");
     }
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_sketch_indices_host(uint64_t seed, int32_t sketch, int64_t n, int64_t m,
+                               int32_t sjlt_s, int32_t* idx, int8_t* sign) {
+  if (n <= 0 || m <= 0 || n > INT32_MAX || m > INT32_MAX || !idx || !sign) return IHSBIN_EINVAL;
+  using namespace ihs;
+  if (sketch == IHSBIN_COUNTSKETCH || sketch == IHSBIN_SJLT) {
+    const int64_t s = sketch == IHSBIN_SJLT ? sjlt_s : 1;
+    if (s < 1 || m % s) return IHSBIN_EINVAL;
+    const uint64_t key = stream_key(seed, 0);
+    const uint32_t mb = (uint32_t)(m / s);
+    for (int64_t t = 0; t < n * s; ++t) {
+      const uint64_t x = sm_draw(key, (uint64_t)t);
+      idx[t] = (int32_t)((uint32_t)(t % s) * mb + sm_range(x, mb));
+      sign[t] = (x & 1ull) ? (int8_t)-1 : (int8_t)1;
+    }
+    return IHSBIN_OK;
+  }
+  if (sketch == IHSBIN_SRHT) {
+    const int64_t npad = next_pow2(n);
+    if (npad > INT32_MAX) return IHSBIN_EUNSUP;
+    const uint64_t k1 = stream_key(seed, 1), k2 = stream_key(seed, 2);
+    for (int64_t i = 0; i < n; ++i) sign[i] = (sm_draw(k1, (uint64_t)i) & 1ull) ? (int8_t)-1 : (int8_t)1;
+    for (int64_t r = 0; r < m; ++r) idx[r] = (int32_t)sm_range(sm_draw(k2, (uint64_t)r), (uint32_t)npad);
+    return IHSBIN_OK;
+  }
+  return IHSBIN_EINVAL;
+}
+
+int ihsbin_sketch_indices_device(ihsbin_ctx* ctx, uint64_t seed, int32_t sketch, int64_t n,
+                                 int64_t m, int32_t sjlt_s, int32_t* idx, int8_t* sign) {
+  return ihsbin_sketch_draws(ctx, sketch, seed, n, m, sjlt_s, idx, sign);
+}
+
+int ihsbin_csr_transpose(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t* col_ptr, int32_t* row,
+                         void* vals) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    const MatView v = check_matrix(A);
+    if (v.format != IHSBIN_CSR) fail(IHSBIN_EINVAL, "the column-major copy needs a CSR matrix");
+    if (!col_ptr || (v.nnz > 0 && (!row || !vals))) fail(IHSBIN_EINVAL, "NULL output");
+    validate_csr(ctx->c, v);
+    PoolBuf cscb(ctx->c.pool);
+    Csc csc;
+    build_csc(v, cscb.ensure((size_t)csc_work_bytes(v)), csc, ctx->c.stream);
+    hipStream_t st = ctx->c.stream;
+    const size_t es = v.dtype == IHSBIN_F32 ? 4 : 8;
+    IHS_HIP(hipMemcpyAsync(col_ptr, csc.col_ptr, sizeof(int32_t) * (size_t)(v.d + 1),
+                           hipMemcpyDeviceToDevice, st));
+    if (v.nnz > 0) {
+      IHS_HIP(hipMemcpyAsync(row, csc.row, sizeof(int32_t) * (size_t)v.nnz, hipMemcpyDeviceToDevice, st));
+      IHS_HIP(hipMemcpyAsync(vals, csc.val, es * (size_t)v.nnz, hipMemcpyDeviceToDevice, st));
+    }
+    IHS_HIP(hipStreamSynchronize(st));
     return IHSBIN_OK;
   });
 }

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -96,3 +97,41 @@ def test_footprint_estimate_host_only(lib):
     from paper_2210_12212_amd import IhsbinError
     with pytest.raises(IhsbinError):
         build_footprint((100, 10), 1, 0.0, 1.0)
+
+
+def test_report_layout():
+    from paper_2210_12212_amd import _lib
+    # int64, int32 x6, double x5, int64, double x4, int64, double x2
+    assert C.sizeof(_lib.Report) == 8 + 6 * 4 + 5 * 8 + 8 + 4 * 8 + 8 + 2 * 8
+
+
+@pytest.mark.parametrize("n,m,s", [(1000, 37, 1), (4099, 64, 4), (1, 5, 1), (70000, 4096, 1),
+                                   (3000, 96, 3)])
+def test_host_countsketch_draws_match_oracle(lib, n, m, s):
+    # the library's host draws against the oracle's independent SplitMix64
+    from oracle import rng
+    from paper_2210_12212_amd import sketch_indices_host
+    kind = "sjlt" if s > 1 else "countsketch"
+    idx, sign = sketch_indices_host(2024 + n, kind, n, m, s)
+    h, sg = rng.countsketch_draws(2024 + n, n, m, s)
+    assert np.array_equal(idx.reshape(h.shape), h)
+    assert np.array_equal(sign.reshape(sg.shape), sg)
+
+
+@pytest.mark.parametrize("n,m", [(1000, 100), (4096, 333), (3, 7), (131072, 1024)])
+def test_host_srht_draws_match_oracle(lib, n, m):
+    from oracle import rng
+    from paper_2210_12212_amd import sketch_indices_host
+    rows, sign = sketch_indices_host(99 + m, "srht", n, m)
+    sg, rr, _ = rng.srht_draws(99 + m, n, m)
+    assert np.array_equal(sign, sg)
+    assert np.array_equal(rows, rr)
+
+
+def test_host_draws_reject_bad_arguments(lib):
+    from paper_2210_12212_amd import IhsbinError, sketch_indices_host
+    with pytest.raises(IhsbinError):
+        sketch_indices_host(1, "gaussian", 10, 4)
+    with pytest.raises(IhsbinError):
+        sketch_indices_host(1, "sjlt", 10, 7, 2)     # s does not divide m
+    assert lib.ihsbin_sketch_indices_host(1, 2, 10, 4, 1, None, None) == -1

@@ -1,8 +1,9 @@
 """GPU parity on the configured workloads at their full sizes.
 
-The path is built in the configuration bench.py times; the oracle solves a
-sample of the lambdas (the dense d x d Cholesky per lambda is too slow for all
-of them at d = 8192), which must agree to 1e-6 relative error per lambda.
+The path is built in the configuration bench.py times and every lambda is
+compared with the oracle at 1e-6 relative error: through the
+eigendecomposition of G = A^T A (Section 2.1) up to d = 4096, and by one
+Cholesky solve per lambda at d = 8192.
 """
 import numpy as np
 import pytest
@@ -38,13 +39,21 @@ def _to_dev(torch, p):
     return A, torch.from_numpy(p.B).to(dev)
 
 
-def _sampled_check(p, X, count):
-    idx = np.unique(np.linspace(0, len(p.lambdas) - 1, count).round().astype(int))
+def _reference(p):
     G = direct.gram(p.A)
     C = direct.atb(p.A, p.B)
-    err = direct.rel_err(X[idx], direct.solve_from_gram(G, C, p.lambdas[idx]))
-    print(f"{p.name}: sampled max rel err {err.max():.3e}")
-    assert err.max() <= 1e-6, err
+    if p.d <= 4096:
+        ev, V = direct.eig_of_gram(G)
+        return direct.solve_from_eig(ev, V, C, p.lambdas)
+    return direct.solve_from_gram(G, C, p.lambdas)
+
+
+def _check_every_lambda(p, X, tol=1e-6, ref=None):
+    ref = _reference(p) if ref is None else ref
+    err = direct.rel_err(X, ref)
+    print(f"{p.name}: every lambda, max rel err {err.max():.3e}", flush=True)
+    assert err.max() <= tol, err
+    return err
 
 
 def test_dense_exp300_131072x2048_srht_as_benched(torch, ctx):
@@ -53,15 +62,46 @@ def test_dense_exp300_131072x2048_srht_as_benched(torch, ctx):
     X, rep = ctx.solve_path(A, B, p.lambdas, sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=1e-7,
                             rate_target=0.5, lanczos_steps=4)
     assert rep["status"] == 0 and rep["n_unconverged"] == 0, rep
-    _sampled_check(p, X.cpu().numpy(), 9)
+    _check_every_lambda(p, X.cpu().numpy())
 
 
+@pytest.mark.timeout(600)
 def test_csr_zipf_1048576x8192_countsketch(torch, ctx):
     p = W.make("csr_zipf_1048576x8192")
     A, B = _to_dev(torch, p)
     X, rep = ctx.solve_path(A, B, p.lambdas, sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=1e-7)
     assert rep["status"] == 0, rep
-    _sampled_check(p, X.cpu().numpy(), 3)
+    _check_every_lambda(p, X.cpu().numpy())
+
+
+@pytest.fixture(scope="module")
+def invsqrt_full():
+    p = W.make("dense_invsqrt_262144x4096_k64")
+    cache = {}
+
+    def ref():
+        if "X" not in cache:
+            cache["X"] = _reference(p)
+        return cache["X"]
+    return p, ref
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["bf16", "f64"])
+def test_dense_invsqrt_262144x4096_k64_full_size(torch, ctx, invsqrt_full, prec):
+    # the matrix-valued workload at its full size (Section 5.3, 64 right-hand
+    # sides), Gaussian sketch from m0 = 2048, with the sketch product on the
+    # BF16 matrix cores (as bench.py times it) and in FP64
+    p, ref = invsqrt_full
+    A, B = _to_dev(torch, p)
+    X, rep = ctx.solve_path(A, B, p.lambdas, sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=1e-7,
+                            rate_target=0.5, lanczos_steps=4,
+                            sketch_prec={"f64": 0, "bf16": 1}[prec])
+    assert rep["status"] == 0, rep
+    del A, B
+    print(f"invsqrt {prec}: m_used={rep['m_used']} k_max={rep['k_max_used']} "
+          f"ms={rep['ms_total']:.0f}", flush=True)
+    _check_every_lambda(p, X.cpu().numpy(), ref=ref())
 
 
 def test_dense_invsqrt_k64_reduced_n(torch, ctx):
@@ -70,7 +110,7 @@ def test_dense_invsqrt_k64_reduced_n(torch, ctx):
     A, B = _to_dev(torch, p)
     X, rep = ctx.solve_path(A, B, p.lambdas, sketch=p.sketch, m=p.m // 4, seed=p.sketch_seed, tol=1e-7)
     assert rep["status"] == 0, rep
-    _sampled_check(p, X.cpu().numpy(), 11)
+    _check_every_lambda(p, X.cpu().numpy())
 
 
 def test_strided_rows_and_rhs(torch, ctx):

@@ -125,3 +125,65 @@ def test_dual_form_for_wide_matrices(dt):
     for t, lam in enumerate(lams):
         r = A64.T @ (A64 @ X[t] - B) + lam * X[t]
         assert np.linalg.norm(r) / np.linalg.norm(AtB) < 1e-11
+
+
+# ---- the per-lambda error metric every parity test reads
+def test_rel_err_hand_computed():
+    # two lambdas, d = 2, K = 1: block 0 off by 0.5 in a vector of norm 5,
+    # block 1 exact
+    ref = np.array([[[3.0], [4.0]], [[1.0], [0.0]]])
+    got = np.array([[[3.0], [4.5]], [[1.0], [0.0]]])
+    e = direct.rel_err(got, ref)
+    assert e.shape == (2,)
+    assert e[0] == pytest.approx(0.1, rel=1e-15)
+    assert e[1] == 0.0
+
+
+def test_rel_err_reports_large_errors():
+    rng = np.random.default_rng(11)
+    ref = rng.standard_normal((4, 5, 3))
+    assert np.allclose(direct.rel_err(-ref, ref), 2.0, rtol=1e-14)
+    assert np.allclose(direct.rel_err(np.zeros_like(ref), ref), 1.0, rtol=1e-14)
+    assert np.allclose(direct.rel_err(3.0 * ref, ref), 2.0, rtol=1e-14)
+    # a NaN anywhere in a block is never reported as a small error
+    bad = ref.copy()
+    bad[2, 1, 0] = np.nan
+    e = direct.rel_err(bad, ref)
+    assert not (e[2] <= 1.0)
+    assert np.all(e[[0, 1, 3]] == 0.0)
+
+
+def test_rel_err_is_per_lambda_frobenius():
+    # the norm runs over the whole d x K block of one lambda (all right-hand
+    # sides together), and blocks do not mix
+    ref = np.zeros((3, 2, 2))
+    ref[:, 0, 0] = 1.0
+    ref[:, 1, 1] = 1.0          # every block has Frobenius norm sqrt(2)
+    got = ref.copy()
+    got[1, 0, 1] = 1.0          # only block 1 is wrong, by norm 1
+    got[2, 1, 0] = 2.0          # block 2 is wrong by norm 2
+    e = direct.rel_err(got, ref)
+    assert e[0] == 0.0
+    assert e[1] == pytest.approx(1.0 / np.sqrt(2.0), rel=1e-15)
+    assert e[2] == pytest.approx(2.0 / np.sqrt(2.0), rel=1e-15)
+
+
+def test_rel_err_rejects_mismatched_sizes():
+    with pytest.raises(ValueError):
+        direct.rel_err(np.zeros((2, 3, 1)), np.ones((2, 4, 1)))
+
+
+# ---- the eigendecomposition form used for many lambdas at large d
+def test_eig_form_matches_cholesky_and_svd(small):
+    A, B, lams = small
+    X = direct.ridge_path_eig(A, B, lams)
+    assert direct.rel_err(X, direct.ridge_path(A, B, lams)).max() < 1e-10
+    assert direct.rel_err(X, _svd_path(A, B, lams)).max() < 1e-10
+
+
+def test_eig_form_csr_matches_cholesky():
+    A = W.csr_zipf(3000, 96, 6, seed=21)
+    B, _ = W.rhs(A, 2, 0.1, seed=22)
+    lams = W.lambda_grid(1e-3, 1e2, 7)
+    X = direct.ridge_path_eig(A, B, lams)
+    assert direct.rel_err(X, direct.ridge_path(A, B, lams)).max() < 1e-10

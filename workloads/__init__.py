@@ -180,11 +180,11 @@ def _matvec(A, X):
     return A.astype(np.float64) @ X
 
 
-def rhs(A, K: int, noise: float, seed: int, dtype=None):
-    """B = A X* + noise * N(0,1) with X* ~ N(0, I); returns (B, X*)."""
+def rhs(A, K: int, noise: float, seed: int, dtype=None, x_scale: float = 1.0):
+    """B = A X* + noise * N(0,1) with X* ~ N(0, x_scale^2 I); returns (B, X*)."""
     rng = _rng(seed)
     d = A.shape[1]
-    xs = rng.standard_normal((d, K))
+    xs = x_scale * rng.standard_normal((d, K))
     B = _matvec(A, xs) + noise * rng.standard_normal((A.shape[0], K))
     dt = dtype or (A.dtype if not isinstance(A, CsrMatrix) else A.vals.dtype)
     return np.ascontiguousarray(B.astype(dt)), xs
@@ -205,6 +205,10 @@ WORKLOADS = {
     "dense_invsqrt_262144x4096_k64": dict(kind="dense_spectrum", spectrum="invsqrt",
                                           n=262144, d=4096, K=64, noise=0.05, dtype="f32",
                                           sketch="gaussian", m=2048, lam=(1e-4, 1e1), T=100),
+    # the random over-determined experiment of Section 6.1: AR(1) rows,
+    # x* ~ N(0, I/d), noise sigma = 0.02, SJLT of sparsity 1 (CountSketch)
+    "dense_ar1_20000x4000": dict(kind="ar1", n=20000, d=4000, K=1, noise=0.02, dtype="f64",
+                                 sketch="countsketch", m=1600, lam=(1.0, 100.0), T=50),
     # under-determined (n < d): solved through the dual problem
     "dense_decay_8192x65536_wide": dict(kind="dense_decay", n=8192, d=65536, K=1, noise=0.1,
                                         dtype="f32", sketch="srht", m=4096,
@@ -228,9 +232,12 @@ def make(name: str, seed: int = 1000, n: int = None, d: int = None,
         A = dense_spectrum(n, d, seed, w["spectrum"], dtype=dt)
     elif w["kind"] == "csr_zipf":
         A = csr_zipf(n, d, w["per_row"], seed, dtype=dt)
+    elif w["kind"] == "ar1":
+        A = ar1_rows(n, d, seed, dtype=dt)
     else:
         raise ValueError(w["kind"])
-    B, xs = rhs(A, K, w["noise"], seed + 1)
+    xsc = d ** -0.5 if w["kind"] == "ar1" else 1.0
+    B, xs = rhs(A, K, w["noise"], seed + 1, x_scale=xsc)
     lo, hi = w["lam"]
     return Problem(name, A, B, lambda_grid(lo, hi, T), lo, hi, w["sketch"], m,
                    seed + 1000, xs)
