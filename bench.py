@@ -12,8 +12,8 @@ the BF16 matrix cores, T = 100 lambdas log-spaced in [1e-4, 1e1].
 
 Prints one JSON line.  ``value`` = lambda-solves per second (T per step).
 Outside the timed region every lambda of the last step is checked against the
-FP64 CPU oracle (the eigendecomposition form of Section 2.1 when d <= 4096,
-else one Cholesky solve per lambda); ``value`` is null unless every error is
+FP64 CPU oracle (the eigendecomposition form of Section 2.1); ``value`` is
+null unless every error is
 <= 1e-6 and every build returned IHSBIN_OK.  The oracle's per-lambda Cholesky
 form is also timed on the host on a sample of lambdas as ``cpu_baseline``.
 """
@@ -95,6 +95,57 @@ def ata_sweep(args, torch, W, Context):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / reps
         print(f"| {w} | {ms:.3f} | {4.0 * p.n * p.d * w / ms / 1e9:.1f} |", flush=True)
+    ctx.close()
+
+
+def m_sweep(args, torch, W, Context):
+    """Sketch-size policies on one workload: the spectral probe, Algorithm 4,
+    and fixed m from m0 doubling up to the cap; one build + evaluation each
+    (after one untimed warm-up build), with k, phase times and the error
+    at every lambda against the oracle's eigendecomposition form."""
+    from oracle import direct
+    p = W.make(args.workload, n=args.n)
+    dev = torch.device("cuda", 0)
+    csr = hasattr(p.A, "row_ptr")
+    if csr:
+        from paper_2210_12212_amd import CsrInput
+        A = CsrInput(torch.from_numpy(p.A.row_ptr).to(dev), torch.from_numpy(p.A.col_idx).to(dev),
+                     torch.from_numpy(p.A.vals).to(dev), p.A.n, p.A.d)
+    else:
+        A = torch.from_numpy(p.A).to(dev)
+    B = torch.from_numpy(p.B).to(dev)
+    sp = args.sketch_prec or SKETCH_PREC_DEFAULT.get(p.name, "f64")
+    base = dict(sketch=p.sketch, seed=p.sketch_seed, tol=args.tol, rate_target=args.rate_target,
+                lanczos_steps=args.lanczos_steps, sketch_prec={"f64": 0, "bf16": 1}[sp], k_max=96)
+    ev, V = direct.eig_of_gram(direct.gram(p.A))
+    ref = direct.solve_from_eig(ev, V, direct.atb(p.A, p.B), p.lambdas)
+    log(f"[sweep] {p.name}: oracle ready")
+    cap = min(p.n, 32 * p.d)
+    runs = [("spectral", dict(m=p.m, adaptive_m=1)), ("alg4", dict(m=p.m, adaptive_m=2))]
+    m = p.m
+    while m <= cap:
+        runs.append((f"fixed_{m}", dict(m=m, adaptive_m=0)))
+        m *= 2
+    ctx = Context(0)
+    for name, extra in runs:
+        opts = dict(base, **extra)
+        try:
+            ctx.solve_path(A, B, p.lambdas[:1], **opts)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            X, rep = ctx.solve_path(A, B, p.lambdas, **opts)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3
+            err = float(direct.rel_err(X.cpu().numpy(), ref).max())
+            row = {"policy": name, "m_used": rep["m_used"], "k_max": rep["k_max_used"],
+                   "k_sum": rep["k_sum"], "status": rep["status"], "ms_path": round(ms, 2),
+                   "ms_sketch": round(rep["ms_sketch"], 2), "ms_factor": round(rep["ms_factor"], 2),
+                   "ms_spectrum": round(rep["ms_spectrum"], 2),
+                   "ms_basis": round(rep["ms_basis"], 2), "max_rel_err": err,
+                   "lambda_solves_per_s": round(len(p.lambdas) / ms * 1e3, 2)}
+        except Exception as e:  # noqa: BLE001 - report and go on with the next policy
+            row = {"policy": name, "error": str(e)[:200]}
+        print(json.dumps(row), flush=True)
     ctx.close()
 
 
@@ -296,6 +347,8 @@ def main():
                     help="arithmetic of the Gaussian sketch product of served dense requests")
     ap.add_argument("--serve-outstanding", type=int, default=32,
                     help="client-side cap on submitted, unfinished requests")
+    ap.add_argument("--m-sweep", action="store_true",
+                    help="only compare sketch-size policies (spectral, Algorithm 4, fixed m)")
     ap.add_argument("--ata-sweep", action="store_true",
                     help="only time the A^T A product (ihsbin_ata_apply) at basis-step widths")
     args = ap.parse_args()
@@ -321,6 +374,9 @@ def main():
 
     if args.ata_sweep:
         ata_sweep(args, torch, W, Context)
+        return
+    if args.m_sweep:
+        m_sweep(args, torch, W, Context)
         return
     if args.serve:
         serve_main(args, torch, W)
@@ -459,15 +515,13 @@ def main():
         log(f"[bench] oracle: gram {t_gram:.1f}s, solve {t_solve * 1e3:.1f} ms/lambda, "
             f"max rel err on the {len(idx)} timed lambdas = {err_s.max():.3e}")
         # every lambda: the eigendecomposition form (one eigh of the d x d
-        # Gram, then O(d^2 K) per lambda) up to d = 4096, else Cholesky per lambda
+        # Gram, then O(d^2 K) per lambda; the dual form for n < d)
         te = time.perf_counter()
         if wide:
             Xall = direct.solve_dual_from_gram(G, p.A, p.B, p.lambdas)
-        elif p.d <= 4096:
+        else:
             ev, V = direct.eig_of_gram(G)
             Xall = direct.solve_from_eig(ev, V, C, p.lambdas)
-        else:
-            Xall = direct.solve_from_gram(G, C, p.lambdas)
         err = direct.rel_err(Xh, Xall)
         max_err = float(max(err.max(), err_s.max()))
         n_checked = T

@@ -21,8 +21,11 @@ void launch_gaussian_fill(uint64_t seed, int64_t m, int64_t r0, int64_t rows, in
 // SA += S A for CountSketch / SJLT (SA zeroed by the caller).
 void launch_gaussian_fill_t(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
                             double* St, hipStream_t st);
-void launch_countsketch_apply(const MatView& A, const int32_t* idx, const int8_t* sign, int s,
-                              double* SA, hipStream_t st);
+// SA = S A for CountSketch / SJLT (s blocks), deterministic (bucket-sorted
+// sums); work: countsketch_work_bytes(A, m, s) bytes of device scratch.
+int64_t countsketch_work_bytes(const MatView& A, int64_t m, int s);
+void countsketch_apply(const MatView& A, uint64_t seed, int64_t m, int s, double* SA, void* work,
+                       hipStream_t st);
 // Z (npad x d) = D A zero-padded, then the Walsh-Hadamard transform over rows.
 void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, double* Z,
                            hipStream_t st);
@@ -78,6 +81,8 @@ int64_t gaussian_sketch_bf16_part_doubles(int64_t m, int64_t n, int64_t d);
 // Dual (n < d) helpers: At = A^T (d x n row-major, A's dtype; dense A only)
 // and C = B widened to FP64 (rows x K contiguous).
 void launch_transpose(const MatView& A, void* At, hipStream_t st);
+// D (n x d FP64, contiguous) = the CSR matrix A (duplicates summed in order).
+void launch_csr_densify(const MatView& A, double* D, hipStream_t st);
 void launch_widen_rows(const void* B, int dtype, int64_t rows, int64_t K, int64_t ldb, double* C,
                        hipStream_t st);
 // Z (rows x nb*K, row stride ldz) <- blocks blk[0..nb) of src[blocks][rows][K],

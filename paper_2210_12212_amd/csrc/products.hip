@@ -94,6 +94,32 @@ static void zero_block(double* W, int64_t rows, int64_t cols, int64_t ld, hipStr
   IHS_CHECK_LAUNCH();
 }
 
+// D (n x d, FP64, contiguous) = the CSR matrix, one thread per row adding
+// its entries in stored order (duplicates summed).
+template <typename T>
+__global__ void csr_densify_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                   const T* __restrict__ v, int64_t n, int64_t d,
+                                   double* __restrict__ D) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double* row = D + i * d;
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) row[ci[p]] += (double)v[p];
+  }
+}
+
+void launch_csr_densify(const MatView& A, double* D, hipStream_t st) {
+  zero_block(D, A.n, A.d, A.d, st);
+  int64_t blocks = cdiv(A.n, 256);
+  if (blocks > 16384) blocks = 16384;
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(csr_densify_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       A.row_ptr, A.col_idx, (const float*)A.vals, A.n, A.d, D);
+  else
+    hipLaunchKernelGGL(csr_densify_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       A.row_ptr, A.col_idx, (const double*)A.vals, A.n, A.d, D);
+  IHS_CHECK_LAUNCH();
+}
+
 template <typename T>
 __global__ void csr_atb_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                const T* __restrict__ v, int64_t n, const T* __restrict__ B,

@@ -4,6 +4,8 @@
 // the row index.
 #include <cmath>
 
+#include <hipcub/hipcub.hpp>
+
 #include "ops.hpp"
 
 namespace ihs {
@@ -117,60 +119,208 @@ void launch_gaussian_fill_t(uint64_t seed, int64_t m, int64_t r0, int64_t rows, 
 
 // ----------------------------------------------------------- CountSketch
 // One workgroup per row of A: row i is added, with its sign, to row idx of SA.
-template <typename T>
-__global__ void countsketch_dense_kernel(const T* __restrict__ A, int64_t n, int64_t d,
-                                         int64_t ld, const int32_t* __restrict__ idx,
-                                         const int8_t* __restrict__ sign, int s, double scale,
-                                         double* SA) {
-  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-    for (int b = 0; b < s; ++b) {
-      const int64_t h = idx[i * s + b];
-      const double sg = scale * (double)sign[i * s + b];
-      for (int64_t c = threadIdx.x; c < d; c += blockDim.x)
-        atomicAdd(SA + h * d + c, sg * (double)A[i * ld + c]);
+// Deterministic: the draws are sorted by bucket (a stable radix sort, so the
+// rows of a bucket keep increasing order), and each output entry is summed
+// in that order by one thread.
+//  Dense A: bucket b of SA is the signed sum of the rows drawn into b, one
+//  workgroup per bucket, threads over columns.
+//  CSR A: every entry (row i, column c) of every block bb has the key
+//  idx[i*s+bb] * d + c; after the stable sort, each run of equal keys is one
+//  entry of SA, summed in row order (duplicates in their stored order).
+namespace {
+
+__global__ void iota_kernel(int32_t* __restrict__ v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = (int32_t)i;
+}
+
+// ptr[b] = first sorted position whose key is >= b (b = 0..m)
+__global__ void bucket_ptr_kernel(const int32_t* __restrict__ keys, int64_t count, int64_t m,
+                                  int32_t* __restrict__ ptr) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= m;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = count;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (keys[mid] < b) lo = mid + 1;
+      else hi = mid;
     }
+    ptr[b] = (int32_t)lo;
   }
 }
 
 template <typename T>
-__global__ void countsketch_csr_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                       const T* __restrict__ v, int64_t n, int64_t d,
-                                       const int32_t* __restrict__ idx,
-                                       const int8_t* __restrict__ sign, int s, double scale,
-                                       double* SA) {
+__global__ __launch_bounds__(256) void countsketch_gather_dense_kernel(
+    const T* __restrict__ A, int64_t d, int64_t ld, const int32_t* __restrict__ ptr,
+    const int32_t* __restrict__ perm, const int8_t* __restrict__ sign, int s, double scale,
+    int64_t m, double* __restrict__ SA) {
+  for (int64_t b = blockIdx.x; b < m; b += gridDim.x) {
+    const int32_t q0 = ptr[b], q1 = ptr[b + 1];
+    for (int64_t c = threadIdx.x; c < d; c += blockDim.x) {
+      double acc = 0.0;
+      for (int32_t q = q0; q < q1; ++q) {
+        const int32_t t = perm[q];
+        acc += scale * (double)sign[t] * (double)A[(int64_t)(t / s) * ld + c];
+      }
+      SA[b * d + c] = acc;
+    }
+  }
+}
+
+__global__ void entry_keys_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  int64_t n, int64_t d, const int32_t* __restrict__ idx, int s,
+                                  uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p0 = rp[i], p1 = rp[i + 1];
     for (int b = 0; b < s; ++b) {
-      const int64_t h = idx[i * s + b];
-      const double sg = scale * (double)sign[i * s + b];
-      for (int32_t p = rp[i]; p < rp[i + 1]; ++p) atomicAdd(SA + h * d + ci[p], sg * (double)v[p]);
+      const uint64_t base = (uint64_t)idx[i * s + b] * (uint64_t)d;
+      for (int32_t p = p0; p < p1; ++p) {
+        const int64_t e = (int64_t)p * s + b;
+        keys[e] = base + (uint64_t)ci[p];
+        vals[e] = (int32_t)e;
+      }
     }
   }
 }
 
-void launch_countsketch_apply(const MatView& A, const int32_t* idx, const int8_t* sign, int s,
-                              double* SA, hipStream_t st) {
-  const double scale = 1.0 / std::sqrt((double)s);
-  if (A.format == IHSBIN_DENSE) {
-    const unsigned blocks = (unsigned)(A.n < 65536 ? A.n : 65536);
-    if (A.dtype == IHSBIN_F32)
-      hipLaunchKernelGGL(countsketch_dense_kernel<float>, dim3(blocks), dim3(256), 0, st,
-                         (const float*)A.vals, A.n, A.d, A.ld, idx, sign, s, scale, SA);
-    else
-      hipLaunchKernelGGL(countsketch_dense_kernel<double>, dim3(blocks), dim3(256), 0, st,
-                         (const double*)A.vals, A.n, A.d, A.ld, idx, sign, s, scale, SA);
-  } else {
-    int64_t blocks = cdiv(A.n, 256);
-    if (blocks > 16384) blocks = 16384;
-    if (A.dtype == IHSBIN_F32)
-      hipLaunchKernelGGL(countsketch_csr_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
-                         A.row_ptr, A.col_idx, (const float*)A.vals, A.n, A.d, idx, sign, s, scale,
-                         SA);
-    else
-      hipLaunchKernelGGL(countsketch_csr_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
-                         A.row_ptr, A.col_idx, (const double*)A.vals, A.n, A.d, idx, sign, s,
-                         scale, SA);
+__global__ void row_of_entry_kernel(const int32_t* __restrict__ rp, int64_t n,
+                                    int32_t* __restrict__ row) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) row[p] = (int32_t)i;
+}
+
+template <typename T>
+__global__ void countsketch_runs_kernel(const uint64_t* __restrict__ keys,
+                                        const int32_t* __restrict__ perm, int64_t count,
+                                        const T* __restrict__ v, const int32_t* __restrict__ row_of,
+                                        const int8_t* __restrict__ sign, int s, double scale,
+                                        double* __restrict__ SA) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[q];
+    if (q > 0 && keys[q - 1] == k) continue;  // not the start of a run
+    double acc = 0.0;
+    for (int64_t r = q; r < count && keys[r] == k; ++r) {
+      const int32_t e = perm[r];
+      const int32_t p = e / s, b = e - p * s;
+      acc += scale * (double)sign[(int64_t)row_of[p] * s + b] * (double)v[p];
+    }
+    SA[k] = acc;
   }
+}
+
+__global__ void zero_kernel(double* __restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+unsigned blocks_for(int64_t count, int64_t cap = 16384) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 256), cap));
+}
+
+int bits_for(uint64_t maxval) {
+  int b = 1;
+  while (b < 64 && (uint64_t(1) << b) <= maxval) ++b;
+  return b;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+int64_t countsketch_work_bytes(const MatView& A, int64_t m, int s) {
+  const int64_t ns = A.n * s;
+  size_t tmp = 0;
+  if (A.format == IHSBIN_DENSE) {
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const int32_t*)nullptr,
+                                             (int32_t*)nullptr, (const int32_t*)nullptr,
+                                             (int32_t*)nullptr, (int)ns, 0, 32);
+    // draws (5 ns), sorted keys, iota, perm (4 ns each), bucket pointers
+    return (int64_t)(align256(5 * ns) + 3 * align256(4 * ns) + align256(4 * (m + 1)) +
+                     align256(tmp) + 256);
+  }
+  const int64_t es = A.nnz * s;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint64_t*)nullptr,
+                                           (uint64_t*)nullptr, (const int32_t*)nullptr,
+                                           (int32_t*)nullptr, (int)es, 0, 64);
+  // draws, keys in/out (8 es each), values in/out (4 es each), row of entry
+  return (int64_t)(align256(5 * ns) + 2 * align256(8 * es) + 2 * align256(4 * es) +
+                   align256(4 * A.nnz) + align256(tmp) + 256);
+}
+
+void countsketch_apply(const MatView& A, uint64_t seed, int64_t m, int s, double* SA, void* work,
+                       hipStream_t st) {
+  const double scale = 1.0 / std::sqrt((double)s);
+  const int64_t ns = A.n * s;
+  if (ns >= INT32_MAX) fail(IHSBIN_EUNSUP, "CountSketch: too many rows");
+  char* p = static_cast<char*>(work);
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += align256(bytes);
+    return r;
+  };
+  int32_t* idx = reinterpret_cast<int32_t*>(take(4 * ns));
+  int8_t* sg = reinterpret_cast<int8_t*>(take(ns));
+  launch_draw_countsketch(seed, A.n, m, s, idx, sg, st);
+  if (A.format == IHSBIN_DENSE) {
+    int32_t* keys = reinterpret_cast<int32_t*>(take(4 * ns));
+    int32_t* iota = reinterpret_cast<int32_t*>(take(4 * ns));
+    int32_t* perm = reinterpret_cast<int32_t*>(take(4 * ns));
+    int32_t* ptr = reinterpret_cast<int32_t*>(take(4 * (m + 1)));
+    const int end_bit = bits_for((uint64_t)m);
+    size_t tmp = 0;
+    IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, idx, keys, iota, perm, (int)ns, 0,
+                                               end_bit, st));
+    void* tw = take(tmp);
+    hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(ns)), dim3(256), 0, st, iota, ns);
+    IHS_CHECK_LAUNCH();
+    IHS_HIP(hipcub::DeviceRadixSort::SortPairs(tw, tmp, idx, keys, iota, perm, (int)ns, 0, end_bit,
+                                               st));
+    hipLaunchKernelGGL(bucket_ptr_kernel, dim3(blocks_for(m + 1)), dim3(256), 0, st, keys, ns, m,
+                       ptr);
+    IHS_CHECK_LAUNCH();
+    const unsigned g = (unsigned)std::min<int64_t>(m, 65536);
+    if (A.dtype == IHSBIN_F32)
+      hipLaunchKernelGGL(countsketch_gather_dense_kernel<float>, dim3(g), dim3(256), 0, st,
+                         (const float*)A.vals, A.d, A.ld, ptr, perm, sg, s, scale, m, SA);
+    else
+      hipLaunchKernelGGL(countsketch_gather_dense_kernel<double>, dim3(g), dim3(256), 0, st,
+                         (const double*)A.vals, A.d, A.ld, ptr, perm, sg, s, scale, m, SA);
+    IHS_CHECK_LAUNCH();
+    return;
+  }
+  const int64_t es = A.nnz * s;
+  if (es >= INT32_MAX) fail(IHSBIN_EUNSUP, "CountSketch: too many entries");
+  uint64_t* kin = reinterpret_cast<uint64_t*>(take(8 * es));
+  uint64_t* kout = reinterpret_cast<uint64_t*>(take(8 * es));
+  int32_t* vin = reinterpret_cast<int32_t*>(take(4 * es));
+  int32_t* vout = reinterpret_cast<int32_t*>(take(4 * es));
+  int32_t* row_of = reinterpret_cast<int32_t*>(take(4 * A.nnz));
+  const int end_bit = bits_for((uint64_t)m * (uint64_t)A.d);
+  size_t tmp = 0;
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kin, kout, vin, vout, (int)es, 0, end_bit,
+                                             st));
+  void* tw = take(tmp);
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(m * A.d)), dim3(256), 0, st, SA, m * A.d);
+  IHS_CHECK_LAUNCH();
+  if (es == 0) return;
+  hipLaunchKernelGGL(entry_keys_kernel, dim3(blocks_for(A.n)), dim3(256), 0, st, A.row_ptr,
+                     A.col_idx, A.n, A.d, idx, s, kin, vin);
+  IHS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(row_of_entry_kernel, dim3(blocks_for(A.n)), dim3(256), 0, st, A.row_ptr, A.n,
+                     row_of);
+  IHS_CHECK_LAUNCH();
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(tw, tmp, kin, kout, vin, vout, (int)es, 0, end_bit, st));
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(countsketch_runs_kernel<float>, dim3(blocks_for(es)), dim3(256), 0, st, kout,
+                       vout, es, (const float*)A.vals, row_of, sg, s, scale, SA);
+  else
+    hipLaunchKernelGGL(countsketch_runs_kernel<double>, dim3(blocks_for(es)), dim3(256), 0, st, kout,
+                       vout, es, (const double*)A.vals, row_of, sg, s, scale, SA);
   IHS_CHECK_LAUNCH();
 }
 

@@ -24,19 +24,7 @@
 #include <cstring>
 
 #include "basis.hpp"
-
-struct ihsbin_path {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int64_t d = 0, K = 0, m_used = 0, kcap = 0;
-  int L = 0;
-  double lam_min = 0, lam_max = 0;
-  int centred = 1;
-  int dual = 0;  // built on the dual problem (n < d); the basis is in x-space
-  std::vector<double> grid, lam0, tau, rate, ref;
-  std::vector<int32_t> k;
-  ihs::DevBuf basis, items;
-};
+#include "path.hpp"
 
 #include <cstdarg>
 #include <cstdlib>
@@ -205,12 +193,8 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
   } else if (kind == IHSBIN_COUNTSKETCH || kind == IHSBIN_SJLT) {
     if (kind == IHSBIN_COUNTSKETCH) s = 1;
     if (s < 1 || m % s) fail(IHSBIN_EINVAL, "SJLT needs s >= 1 dividing m");
-    char* base = static_cast<char*>(c.ws_sketch.ensure((size_t)A.n * s * 5 + 256));
-    int32_t* idx = reinterpret_cast<int32_t*>(base);
-    int8_t* sg = reinterpret_cast<int8_t*>(base + (size_t)A.n * s * 4);
-    launch_draw_countsketch(seed, A.n, m, s, idx, sg, st);
-    IHS_HIP(hipMemsetAsync(SA, 0, sizeof(double) * (size_t)m * A.d, st));
-    launch_countsketch_apply(A, idx, sg, s, SA, st);
+    void* work = c.ws_sketch.ensure((size_t)countsketch_work_bytes(A, m, s));
+    countsketch_apply(A, seed, m, s, SA, work, st);
   } else if (kind == IHSBIN_SRHT) {
     const int64_t npad = next_pow2(A.n);
     if (npad > (int64_t(1) << 31)) fail(IHSBIN_EUNSUP, "SRHT order too large");
@@ -542,12 +526,7 @@ static void copy_rows_f64(Ctx& c, const MatView& A, double* SA) {
     launch_widen_rows(A.vals, A.dtype, A.n, A.d, A.ld, SA, c.stream);
     return;
   }
-  char* base = static_cast<char*>(c.ws_sketch.ensure((size_t)A.n * 5 + 256));
-  int32_t* idx = reinterpret_cast<int32_t*>(base);
-  int8_t* sg = reinterpret_cast<int8_t*>(base + (size_t)A.n * 4);
-  launch_identity_draws(A.n, idx, sg, c.stream);
-  IHS_HIP(hipMemsetAsync(SA, 0, sizeof(double) * (size_t)A.n * A.d, c.stream));
-  launch_countsketch_apply(A, idx, sg, 1, SA, c.stream);
+  launch_csr_densify(A, SA, c.stream);
 }
 
 struct Timer {
@@ -786,7 +765,11 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
   } else if (o.sketch == IHSBIN_SRHT) {
     sk = std::max(sk, 8.0 * next_pow2(N) * D + N + 256);
   } else {
-    sk = std::max(sk, 5.0 * N * s + 256);
+    // draws, then the bucket sort: dense 12 bytes per draw (+ sort scratch),
+    // CSR 24 bytes per entry and block (+ sort scratch)
+    const double nnz = csr ? (double)std::max<int64_t>(0, A0->nnz) : 0.0;
+    sk = std::max(sk, 5.0 * N * s + (csr ? 28.0 * nnz * s : 12.0 * N * s + 4.0 * mmax) +
+                          16.0 * (csr ? nnz * s : (double)N * s) + double(8 << 20));
   }
   b += sk + 4.0 * mmax;
   b += 2 * 8.0 * rows * D;  // SA (grown at most geometrically)
@@ -920,17 +903,6 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     return std::min(m_cap, m * mult);
   };
   const bool adapt = o.adaptive_m == 1 && !o.taus;
-  // Sketches whose cost does not grow with m (SRHT: one transform;
-  // CountSketch/SJLT: one pass over A) only pay for m through the 2 m d^2
-  // Gram.  With m < d such a sketch leaves P_S = 1/lam0 on the null space of
-  // SA (dimension >= d - m), plain scaling there, so they start at the cap
-  // without a probe; with m >= d the probe below decides.
-  const bool cheap_sketch = o.sketch != IHSBIN_GAUSSIAN;
-  if (adapt && cheap_sketch && m < d && m < m_cap) {
-    logf("m=%lld < d=%lld: starting at the cap m=%lld", (long long)m, (long long)d,
-         (long long)m_cap);
-    m = m_cap;
-  }
   if (o.adaptive_m == 2) {
     // Algorithm 4 at lam_min from m0 = m (default d / 4); it leaves its
     // final sketch in place
@@ -946,9 +918,10 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   }
   // Probe: factor and estimate the lowest interval only (the Lanczos run stops
   // early once its Ritz values already show a rate above the target).  When m
-  // is too small, cheap sketches go straight to the cap; the Gaussian sketch
-  // costs 2 m n d, so it grows by the measured factor and is probed again.
-  while (adapt && m < m_cap && trials < 6) {
+  // is too small it grows by the factor the measured spectrum implies (a power
+  // of two in [2, 16]) and the sketch is probed again (an SRHT keeps its
+  // transform: only the row sample depends on m).
+  while (adapt && m < m_cap && trials < 8) {
     double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
     factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb);
@@ -959,11 +932,10 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     logf("probe m=%lld: c=[%.4g, %.4g] rate0=%.3f (target %.3f)", (long long)m, sp[0].mu_min,
          sp[0].mu_max, rate_of(sp[0]), o.rate_target);
     if (rate_of(sp[0]) <= o.rate_target) break;
-    const int64_t m_new = cheap_sketch ? m_cap : grow(sp[0]);
+    const int64_t m_new = grow(sp[0]);
     if (m_new <= m) break;
     m = m_new;
     sketch_m(m);
-    if (cheap_sketch) break;
   }
   IHS_HIP(hipStreamSynchronize(st));
   r.ms_sketch = tsk.ms();
@@ -996,7 +968,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     // progress measure can shrink quickly while slow directions stall, e.g.
     // when m < d leaves most directions to the 1/lam0 part of P_S).
     const bool recheck =
-        adapt ? trials < 6 && rate_of(spec[0]) > o.rate_target + 0.1
+        adapt ? trials < 8 && rate_of(spec[0]) > o.rate_target + 0.1
               : o.adaptive_m == 2 && regrows < 4 &&
                     rate_of(spec[0]) > std::exp(std::log(o.tol) / std::max(1, kcap_steps));
     if (recheck && m < m_cap) {

@@ -281,13 +281,26 @@ def test_k_max_reached_reports_noconv(torch, ctx):
     path.free()
 
 
-def test_run_twice_identical(torch, ctx):
-    A = W.dense_decay(700, 50, seed=61)
+@pytest.mark.parametrize("kind,fmt", [("srht", "dense"), ("countsketch", "dense"),
+                                      ("sjlt", "dense"), ("gaussian", "dense"),
+                                      ("countsketch", "csr"), ("sjlt", "csr"), ("gaussian", "csr")])
+def test_run_twice_identical(torch, ctx, kind, fmt):
+    # every sum runs in a fixed order (sketches, products, reductions): the
+    # same inputs give the same bits
+    if fmt == "dense":
+        A = W.dense_decay(3000, 50, seed=61)
+        Ad = dev(torch, A)
+    else:
+        A = W.csr_zipf(6000, 90, 7, seed=61, dtype=np.float32)
+        Ad = csr_dev(torch, A)
     B, _ = W.rhs(A, 2, 0.1, seed=62)
     lams = W.lambda_grid(1e-3, 1e2, 9)
-    X1, _ = ctx.solve_path(dev(torch, A), dev(torch, B), lams, sketch="srht", m=100, seed=5)
-    X2, _ = ctx.solve_path(dev(torch, A), dev(torch, B), lams, sketch="srht", m=100, seed=5)
+    X1, _ = ctx.solve_path(Ad, dev(torch, B), lams, sketch=kind, m=100, seed=5, sjlt_s=2)
+    X2, _ = ctx.solve_path(Ad, dev(torch, B), lams, sketch=kind, m=100, seed=5, sjlt_s=2)
     assert torch.equal(X1, X2)
+    SA1 = ctx.sketch_apply(Ad, kind, 64, 9, sjlt_s=2)
+    SA2 = ctx.sketch_apply(Ad, kind, 64, 9, sjlt_s=2)
+    assert torch.equal(SA1, SA2)
 
 
 def test_step_sizes_close_to_exact_spectrum(torch, ctx):

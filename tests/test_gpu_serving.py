@@ -98,11 +98,8 @@ def test_served_results_match_alone_and_oracle(torch):
     assert st["completed"] == len(REQUESTS) and st["max_concurrent"] >= 2
     assert st["max_inflight_bytes"] <= st["budget"]
     for i, (req, (A, Ad, B, Bd, lams, opts)) in enumerate(zip(REQUESTS, inputs)):
-        atomics = req[0] == "csr" or req[4] in ("countsketch", "sjlt")
-        if atomics:
-            np.testing.assert_allclose(got[i], alone[i], rtol=1e-9, atol=1e-12 * np.abs(alone[i]).max())
-        else:
-            np.testing.assert_array_equal(got[i], alone[i])
+        # every kernel sums in a fixed order: the same bits alone and in the mix
+        np.testing.assert_array_equal(got[i], alone[i])
         if req[1] < req[2]:
             ref = direct.ridge_path_dual(A, B, lams)
         else:

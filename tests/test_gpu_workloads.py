@@ -1,10 +1,12 @@
 """GPU parity on the configured workloads at their full sizes.
 
 The path is built in the configuration bench.py times and every lambda is
-compared with the oracle at 1e-6 relative error: through the
-eigendecomposition of G = A^T A (Section 2.1) up to d = 4096, and by one
-Cholesky solve per lambda at d = 8192.
+compared with the oracle at 1e-6 relative error, through the
+eigendecomposition of G = A^T A (the closed form of Section 2.1; pinned
+against the per-lambda Cholesky solve in the CPU tests).
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -40,12 +42,15 @@ def _to_dev(torch, p):
 
 
 def _reference(p):
+    # one eigendecomposition of G serves every lambda (O(d^3) once, O(d^2 K)
+    # per lambda); progress is printed so a long oracle step is visibly alive
+    t0 = time.time()
     G = direct.gram(p.A)
     C = direct.atb(p.A, p.B)
-    if p.d <= 4096:
-        ev, V = direct.eig_of_gram(G)
-        return direct.solve_from_eig(ev, V, C, p.lambdas)
-    return direct.solve_from_gram(G, C, p.lambdas)
+    print(f"  oracle: G and A^T B in {time.time() - t0:.1f}s", flush=True)
+    ev, V = direct.eig_of_gram(G)
+    print(f"  oracle: eigendecomposition in {time.time() - t0:.1f}s", flush=True)
+    return direct.solve_from_eig(ev, V, C, p.lambdas)
 
 
 def _check_every_lambda(p, X, tol=1e-6, ref=None):
