@@ -255,6 +255,19 @@ int ihsbin_path_build(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
 int ihsbin_path_eval(ihsbin_path* path, const double* lambdas, int64_t T,
                      void* X, int64_t ldx, int32_t x_dtype);
 
+/* ihsbin_path_eval without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layout and results as
+ * ihsbin_path_eval, but the lambdas and the per-lambda evaluation items are
+ * staged in one fixed 8 MiB device array per GPU (taken by the library when
+ * it first runs on that GPU and held until the process ends) instead of the
+ * path's own buffer: T <= 262144 (more: EINVAL), no hipMalloc, hipFree or
+ * allocating library call.  Every call on a GPU uses that GPU's one array,
+ * so calls that overlap on the same GPU (different threads, streams or
+ * paths) race: the caller serializes them.  Returns after X is complete. */
+int ihsbin_path_eval_noalloc(ihsbin_path* path, const double* lambdas, int64_t T,
+                             void* X, int64_t ldx, int32_t x_dtype);
+
 /* Sizes of a built path. */
 int ihsbin_path_get_info(const ihsbin_path* path, ihsbin_path_info* info);
 

@@ -468,6 +468,22 @@ class Path:
             raise IhsbinError(rc, "ihsbin_path_eval")
         return out
 
+    def eval_noalloc(self, lambdas, out):
+        """ihsbin_path_eval_noalloc into a preallocated out (T x d x K, the
+        layout eval accepts); the library allocates no device memory."""
+        lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+        if tuple(out.shape) != (len(lam), self.d, self.K) or not out.is_cuda:
+            raise ValueError(f"out must be a device tensor of shape {(len(lam), self.d, self.K)}")
+        if len(lam) and (out.stride(2) != 1 or out.stride(1) < self.K
+                         or out.stride(0) != self.d * out.stride(1)):
+            raise ValueError("out needs unit column stride and block stride d * row stride")
+        rc = L.lib().ihsbin_path_eval_noalloc(self._h, lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                              len(lam), C.c_void_p(out.data_ptr()), out.stride(1),
+                                              _dtype_code(out))
+        if rc != L.OK:
+            raise IhsbinError(rc, "ihsbin_path_eval_noalloc")
+        return out
+
     def intervals(self):
         """ihsbin_path_intervals -> dict of numpy arrays (lo, hi, lam0, tau, rate, k)."""
         arrs = {k: np.zeros(self.L) for k in ("lo", "hi", "lam0", "tau", "rate")}

@@ -28,6 +28,7 @@ EXPORTED = [
     "ihsbin_server_create", "ihsbin_server_submit", "ihsbin_server_wait",
     "ihsbin_server_get_stats", "ihsbin_server_last_error", "ihsbin_server_destroy",
     "ihsbin_sketch_indices_host", "ihsbin_sketch_indices_device", "ihsbin_csr_transpose",
+    "ihsbin_path_eval_noalloc",
 ]
 
 
@@ -122,6 +123,7 @@ def _declare(lib):
         "ihsbin_path_build": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, dbl, dbl,
                                         C.POINTER(Opts), C.POINTER(vp), C.POINTER(Report)]),
         "ihsbin_path_eval": (C.c_int, [vp, pd, i64, vp, i64, i32]),
+        "ihsbin_path_eval_noalloc": (C.c_int, [vp, pd, i64, vp, i64, i32]),
         "ihsbin_path_get_info": (C.c_int, [vp, C.POINTER(PathInfo)]),
         "ihsbin_path_intervals": (C.c_int, [vp, pd, pd, pd, pd, pd, C.POINTER(C.c_int32)]),
         "ihsbin_path_basis": (C.c_int, [vp, i32, vp]),

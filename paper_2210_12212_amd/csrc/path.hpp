@@ -17,4 +17,13 @@ struct ihsbin_path {
   std::vector<double> grid, lam0, tau, rate, ref;
   std::vector<int32_t> k;
   ihs::DevBuf basis, items;
+  // the plan on the device for ihsbin_path_eval_noalloc: grid (L + 1
+  // doubles), tau (L), ref (L), then k (L int32)
+  ihs::DevBuf plan;
 };
+
+namespace ihs {
+// The device address of the allocation-free entry point's scratch array on
+// `device` (looked up once per device, with that device current).
+void* noalloc_scratch(int device);
+}  // namespace ihs

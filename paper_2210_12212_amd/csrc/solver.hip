@@ -1013,6 +1013,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   path->stream = st;
   path->basis.bind(st, nullptr);
   path->items.bind(st, nullptr);
+  path->plan.bind(st, nullptr);
   path->d = d;
   path->K = K;
   path->L = L;
@@ -1224,6 +1225,21 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     r.k_max_used = std::max(r.k_max_used, path->k[l]);
     r.k_sum += path->k[l];
   }
+  {
+    // the plan on the device, read by ihsbin_path_eval_noalloc
+    const size_t nd = (size_t)(3 * L + 1);
+    char* pl = static_cast<char*>(path->plan.ensure(sizeof(double) * nd + sizeof(int32_t) * L));
+    std::vector<double> hp;
+    hp.reserve(nd);
+    hp.insert(hp.end(), path->grid.begin(), path->grid.end());
+    hp.insert(hp.end(), path->tau.begin(), path->tau.end());
+    hp.insert(hp.end(), path->ref.begin(), path->ref.end());
+    IHS_HIP(hipMemcpyAsync(pl, hp.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(pl + sizeof(double) * nd, path->k.data(), sizeof(int32_t) * L,
+                           hipMemcpyHostToDevice, st));
+    IHS_HIP(hipStreamSynchronize(st));
+    held.add((int64_t)path->plan.bytes);
+  }
   r.n_unconverged = unconverged;
   for (int l = 0; l < L; ++l) r.est_rel_err = std::max(r.est_rel_err, est[l]);
   if (kcap == 1) r.est_rel_err = NAN;  // one term: no increment to bound it with
@@ -1352,6 +1368,11 @@ int ihsbin_create(ihsbin_ctx** ctx, int device, void* stream) {
     int n = 0;
     IHS_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return IHSBIN_EINVAL;
+    {
+      // the allocation-free entry point's scratch address on this device
+      DeviceGuard g(device);
+      noalloc_scratch(device);
+    }
     auto c = new ihsbin_ctx();
     c->c.device = device;
     c->c.stream = static_cast<hipStream_t>(stream);
@@ -1602,6 +1623,7 @@ int ihsbin_path_set_stream(ihsbin_path* p, void* stream) {
     IHS_HIP(hipStreamSynchronize(p->stream));  // the basis is complete
     p->stream = static_cast<hipStream_t>(stream);
     p->basis.stream = p->stream;
+    p->plan.stream = p->stream;
     p->items.stream = p->stream;
   } catch (const Error& e) {
     return e.status;
