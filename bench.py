@@ -8,7 +8,9 @@ The inputs are resident in HBM before the timed region starts.
 Default workload: the matrix-valued problem (Section 5.3), dense A with
 n = 262144, d = 4096, FP32 storage, singular values i^-0.5, B = A X* + 0.05
 noise with K = 64 right-hand sides, Gaussian sketch with initial m = 2048 on
-the BF16 matrix cores, T = 100 lambdas log-spaced in [1e-4, 1e1].
+the BF16 matrix cores, T = 100 lambdas log-spaced in [1e-4, 1e1]; the basis
+products run in FP64 until the increments they refine are below 1e-3 of x,
+then on the FP32 matrix cores (--basis-prec).
 
 Prints one JSON line.  ``value`` = lambda-solves per second (T per step).
 Outside the timed region every lambda of the last step is checked against the
@@ -32,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix, flop/s
+FP32_MFMA_PEAK = 157.3e12  # MI355X dense FP32 matrix, flop/s
 HBM_PEAK = 8.0e12          # bytes/s
 
 # HBM bytes per launch of the A^T A product GEMMs on the default workload come
@@ -146,6 +149,70 @@ def m_sweep(args, torch, W, Context):
         except Exception as e:  # noqa: BLE001 - report and go on with the next policy
             row = {"policy": name, "error": str(e)[:200]}
         print(json.dumps(row), flush=True)
+    ctx.close()
+
+
+def batch_small(args, torch, W, Context):
+    """Many small problems through ihsbin_path_build_batch: the requests of
+    --serve-small (dense 2048 x 256, FP32, K = 1, T = 100 in [1e-4, 1e1],
+    Gaussian sketch) built --batch-size at a time; paths/s and lambda-solves/s
+    over the whole set, each path evaluated at its T lambdas; sampled
+    problems checked against the oracle."""
+    from oracle import direct
+    dev = torch.device("cuda", 0)
+    reqs = [dict(index=i, arrival=0.0, n=2048, d=256, dense=True, K=1, seed=9000 + i)
+            for i in range(args.serve_requests)]
+    data = [_serving_inputs(torch, r, dev) for r in reqs]
+    A = torch.stack([a for a, _ in data])
+    B = torch.stack([b for _, b in data])
+    del data
+    T = 100
+    lams = W.lambda_grid(1e-4, 1e1, T)
+    opts = dict(sketch="gaussian", seed=77, adaptive_m=1, tol=args.tol,
+                rate_target=args.rate_target, lanczos_steps=args.lanczos_steps)
+    ctx = Context(0)
+    P = len(reqs)
+    bs = min(args.batch_size, P)
+    X = torch.empty((P, T, 256, 1), dtype=torch.float64, device=dev)
+
+    def run():
+        reps = []
+        for p0 in range(0, P, bs):
+            paths, rep = ctx.path_build_batch(A[p0:p0 + bs], B[p0:p0 + bs], lams[0], lams[-1],
+                                              **opts)
+            for j, path in enumerate(paths):
+                path.eval(lams, out=X[p0 + j])
+                path.free()
+            reps.append(rep)
+        return reps
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        reps = run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / args.steps
+    Xh = X.cpu().numpy()
+    errs = []
+    for i in np.linspace(0, P - 1, min(P, 8)).round().astype(int):
+        Ah = A[i].cpu().numpy()
+        Bh = B[i].cpu().numpy()
+        errs.append(float(direct.rel_err(Xh[i], direct.ridge_path(Ah, Bh, lams)).max()))
+    res = {"metric": "paths/s (many small problems, one batched build)",
+           "value": round(P / el, 2), "unit": "paths/s",
+           "lambda_solves_per_s": round(P * T / el, 1), "problems": P, "batch_size": bs,
+           "ms_per_batch": round(el * 1e3 / len(reps), 2), "steps": args.steps,
+           "warmup": args.warmup, "m_used": reps[-1]["m_used"], "k": reps[-1]["k_max_used"],
+           "statuses": sorted({int(r["status"]) for r in reps}),
+           "phase_ms_last_batch": {k: round(reps[-1][k], 2) for k in
+                                   ("ms_sketch", "ms_factor", "ms_spectrum", "ms_basis",
+                                    "ms_total")},
+           "max_rel_err_sampled": max(errs),
+           "config": {"workload": "small_2048x256_burst", "T": T, "lam": [1e-4, 1e1],
+                      "tol": args.tol}}
+    print(json.dumps(res), flush=True)
     ctx.close()
 
 
@@ -295,7 +362,7 @@ def serve_main(args, torch, W):
         "server": st,
         "max_rel_err_sampled": errs,
         "higher_is_better": True,
-        "dtype": "f64" if args.sketch_prec == "f64" and args.gram_prec == "f64" else
+        "dtype": "f64" if args.serve_sketch_prec == "f64" and args.gram_prec == "f64" else
                  "f64+bf16",
         "data": "synthetic",
         "config": {"workload": "small_2048x256_burst" if args.serve_small else "serving_mix",
@@ -327,6 +394,12 @@ def main():
     ap.add_argument("--sketch-prec", choices=("f64", "bf16"), default=None,
                     help="arithmetic of the Gaussian sketch product (other sketches ignore it); "
                          "default bf16 for the matrix-valued workload, else f64")
+    ap.add_argument("--basis-prec", choices=("f64", "f32", "mixed"), default="mixed",
+                    help="arithmetic of the basis steps' A^T A products (dense FP32 A; other "
+                         "inputs always FP64): FP64, FP32 matrix cores, or FP64 until the "
+                         "increments are small, then FP32 (default)")
+    ap.add_argument("--f32-switch", type=float, default=1e-3,
+                    help="relative increment below which --basis-prec mixed uses FP32")
     ap.add_argument("--m-policy", choices=("spectral", "alg4", "fixed"), default="spectral",
                     help="sketch size: spectral probe (default), Algorithm 4 at lam_min, or m0")
     ap.add_argument("--oracle-lambdas", type=int, default=12,
@@ -347,6 +420,10 @@ def main():
                     help="arithmetic of the Gaussian sketch product of served dense requests")
     ap.add_argument("--serve-outstanding", type=int, default=32,
                     help="client-side cap on submitted, unfinished requests")
+    ap.add_argument("--batch-small", action="store_true",
+                    help="build the --serve-small problems with batched builds (--batch-size "
+                         "problems per build) instead of serving them one by one")
+    ap.add_argument("--batch-size", type=int, default=256)
     ap.add_argument("--m-sweep", action="store_true",
                     help="only compare sketch-size policies (spectral, Algorithm 4, fixed m)")
     ap.add_argument("--ata-sweep", action="store_true",
@@ -378,6 +455,9 @@ def main():
     if args.m_sweep:
         m_sweep(args, torch, W, Context)
         return
+    if args.batch_small:
+        batch_small(args, torch, W, Context)
+        return
     if args.serve:
         serve_main(args, torch, W)
         return
@@ -403,7 +483,9 @@ def main():
                 rate_target=args.rate_target, lanczos_steps=args.lanczos_steps, timing=1,
                 gram_prec={"f64": 0, "bf16x3": 1}[args.gram_prec],
                 adaptive_m={"fixed": 0, "spectral": 1, "alg4": 2}[args.m_policy],
-                sketch_prec={"f64": 0, "bf16": 1}[args.sketch_prec])
+                sketch_prec={"f64": 0, "bf16": 1}[args.sketch_prec],
+                basis_prec={"f64": 0, "f32": 1, "mixed": 2}[args.basis_prec],
+                f32_switch=args.f32_switch)
     X = torch.empty((len(p.lambdas), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
 
     def step():
@@ -433,32 +515,44 @@ def main():
     value = T * args.steps / elapsed
     rep = step_reps[-1]
 
-    # dominant kernel: the two products of A^T A U (dense: FP64 MFMA GEMMs of
-    # 2*n*d*w flops each)
-    launches = max(1, rep["ata_launches"])
-    half_flops = rep["ata_flops"] / 2.0
-    dom_ms = max(rep["ata_ms_y"], rep["ata_ms_w"])
+    # dominant kernel: the two products of A^T A U (dense: MFMA GEMMs of
+    # 2*n*d*w flops each, on the FP64 matrix cores, and with basis_prec on the
+    # FP32 ones for the later steps; the one with more summed time is reported)
+    def _gemm_roofline(ms_y, ms_w, flops, launches, peak, tag):
+        launches = max(1, launches)
+        half = flops / 2.0
+        dms = max(ms_y, ms_w)
+        kern = ("gemm_y_AU" if ms_y >= ms_w else "gemm_w_AtY") + tag
+        ach = (half / launches) / (dms / launches * 1e-3) / 1e12 if dms > 0 else 0.0
+        return {"bound": "mfma", "kernel": kern, "achieved": round(ach, 3), "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": round(ach * 1e12 / peak, 4),
+                "launches": launches, "flops_per_launch": half / launches,
+                "avg_launch_ms": dms / launches, "ata_ms_y": ms_y, "ata_ms_w": ms_w}, dms
+
     if csr:
         # CSR products: nnz multiply-adds per column, bound by their loads;
         # algorithmic bytes per launch = A once (values and column indices)
+        launches = max(1, rep["ata_launches"])
+        dom_ms = max(rep["ata_ms_y"], rep["ata_ms_w"])
         dom = "csr_spmm_Y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "csr_spmm_t_W_AtY"
         abytes = rep["ata_bytes_a"] / launches
         achieved = abytes / (dom_ms / launches * 1e-3) / 1e9 if dom_ms > 0 else 0.0
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 3),
                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                     "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": None,
-                    "bytes_per_launch": abytes}
+                    "bytes_per_launch": abytes, "launches": rep["ata_launches"],
+                    "avg_launch_ms": dom_ms / launches,
+                    "ata_ms_y": rep["ata_ms_y"], "ata_ms_w": rep["ata_ms_w"]}
     else:
-        dom = "gemm_y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "gemm_w_AtY"
-        achieved = (half_flops / launches) / (dom_ms / launches * 1e-3) / 1e12 if dom_ms > 0 else 0.0
-        traffic = recorded_traffic(p.name, dom) if args.n is None else None
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
-                    "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                    "frac": round(achieved * 1e12 / FP64_MFMA_PEAK, 4), "traffic": traffic}
-    roofline.update({"launches": rep["ata_launches"],
-                     "flops_per_launch": half_flops / launches,
-                     "avg_launch_ms": dom_ms / launches,
-                     "ata_ms_y": rep["ata_ms_y"], "ata_ms_w": rep["ata_ms_w"]})
+        r64, t64 = _gemm_roofline(rep["ata_ms_y"], rep["ata_ms_w"], rep["ata_flops"],
+                                  rep["ata_launches"], FP64_MFMA_PEAK, "")
+        r32, t32 = _gemm_roofline(rep["ata_f32_ms_y"], rep["ata_f32_ms_w"], rep["ata_f32_flops"],
+                                  rep["ata_f32_launches"], FP32_MFMA_PEAK, "_f32")
+        roofline = r32 if rep["ata_f32_launches"] and t32 > t64 else r64
+        roofline["traffic"] = (recorded_traffic(p.name, roofline["kernel"])
+                               if args.n is None else None)
+        if rep["ata_f32_launches"] and rep["ata_launches"]:
+            roofline["other_precision"] = r64 if roofline is r32 else r32
 
     # marginal cost of a lambda on a resident basis (outside the timed region):
     # evaluation only, for the workload's T and for a dense grid of 100000 lambdas
@@ -548,8 +642,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.sketch_prec == "f64" and args.gram_prec == "f64" else
-                 "f64+bf16",
+        "dtype": "+".join(["f64"] + (["f32"] if args.basis_prec != "f64" else []) +
+                          (["bf16"] if args.sketch_prec == "bf16" or args.gram_prec == "bf16x3"
+                           else [])),
         "data": "synthetic",
         "config": {"workload": p.name, "n": p.n, "d": p.d, "K": int(p.B.shape[1]), "T": T,
                    "storage": str(p.A.dtype), "sketch": p.sketch, "m0": p.m,
@@ -557,6 +652,7 @@ def main():
                    "k_sum": rep["k_sum"], "lam": [p.lam_min, p.lam_max], "tol": args.tol,
                    "rate_target": args.rate_target, "lanczos_steps": args.lanczos_steps,
                    "gram_prec": args.gram_prec, "m_policy": args.m_policy,
+                   "basis_prec": args.basis_prec, "f32_switch": args.f32_switch,
                    "sketch_prec": args.sketch_prec},
         "max_rel_err": max_err,
         "lambdas_checked": n_checked,

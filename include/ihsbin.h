@@ -126,7 +126,21 @@ typedef struct {
                               value) or an estimate; > 0 centres each interval
                               [lo, hi] at lam0 = sqrt((lo+s)(hi+s)) - s (the
                               remark after Theorem 1); 0 (default): sqrt(lo hi) */
+  int32_t basis_prec;      /* arithmetic of the basis steps' A^T A products
+                              (dense FP32 A; other inputs always use FP64):
+                              IHSBIN_BASIS_F64 (default), IHSBIN_BASIS_F32 (every
+                              step on the FP32 matrix cores: the recursion
+                              refines with FP32 products, so its accuracy is
+                              limited near 1e-5), IHSBIN_BASIS_MIXED (FP64 until
+                              the largest increment of x at the ends of the
+                              active intervals, relative to x, is <= f32_switch;
+                              FP32 afterwards, when the products only refine
+                              what is left)                                     */
+  double f32_switch;       /* IHSBIN_BASIS_MIXED threshold (default 1e-3)       */
 } ihsbin_opts;
+
+/* Arithmetic of the basis products. */
+enum { IHSBIN_BASIS_F64 = 0, IHSBIN_BASIS_F32 = 1, IHSBIN_BASIS_MIXED = 2 };
 
 /* Arithmetic of the Gaussian sketch product. */
 enum { IHSBIN_SKETCH_F64 = 0, IHSBIN_SKETCH_BF16 = 1 };
@@ -170,7 +184,8 @@ typedef struct {
   int32_t sketch_trials;   /* sketches drawn (adaptive m)                        */
   int32_t steps;           /* outer basis steps run (max k - 1)                  */
   double ms_sketch, ms_factor, ms_spectrum, ms_basis, ms_total;
-  /* A^T A product kernels (Y = A U, then W = A^T Y), timing = 1 only:        */
+  /* A^T A product kernels of the basis steps (Y = A U, then W = A^T Y) on
+   * the FP64 matrix cores, timing = 1 only:                                */
   int64_t ata_launches;    /* launches of each of the two product kernels        */
   double ata_flops;        /* algorithmic flops of all those launches (4*nnz*w)  */
   double ata_ms_y;         /* summed event time of the Y = A U launches          */
@@ -189,6 +204,10 @@ typedef struct {
                               IHSBIN_ENOCONV it is the estimate of the intervals
                               that hit k_max; n < d: of the dual iterate; NaN
                               when every interval has one term (k = 1)          */
+  int64_t ata_f32_launches; /* basis product launches on the FP32 matrix cores
+                              (timing = 1; the ata_* fields above count the FP64
+                              launches only)                                    */
+  double ata_f32_flops, ata_f32_ms_y, ata_f32_ms_w;
   double bytes_moved;      /* algorithmic device-memory bytes of the passes over
                               A: A read once per product (sketch, A^T B, every
                               A U and A^T Y), the n x w intermediate Y written
@@ -246,6 +265,28 @@ int ihsbin_path_build(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
                       int64_t K, int64_t ldb, double lam_min, double lam_max,
                       const ihsbin_opts* opts, ihsbin_path** path,
                       ihsbin_report* report);
+
+/* ihsbin_path_build for P problems of one shape at once (Algorithm 3 / 6 for
+ * each; the problems are independent): dense A_p = A->vals + p * strideA
+ * (elements of A's dtype; every A_p is n x d with row stride A->ld, n >= d)
+ * and B_p = B + p * strideB (n x K, row stride ldb).  All problems share the
+ * interval plan, the sketch family, its dimension m (adaptive_m 0 or 1: the
+ * probe grows m until the slowest problem's lowest interval meets
+ * rate_target) and, for the Gaussian sketch, the sketch matrix itself; each
+ * problem has its own sketched Gram, factors, step sizes and basis.  Every
+ * step runs as one launch sequence over all P L intervals, so many small
+ * problems cost about as many launches as one; the basis steps run in
+ * lockstep (every interval takes the number of steps after which all of them
+ * pass the stop test, or k_fixed).  paths: host array of P handles receiving
+ * independent paths (their bases share one device allocation, released with
+ * the last of them).  report (optional) describes the whole batch.
+ * Errors: EINVAL (sizes, strides, lambda range), EUNSUP (CSR, n < d,
+ * adaptive_m = 2, taus, gram_prec other than FP64), ENOTSPD, ENOMEM, EHIP;
+ * ENOCONV as for ihsbin_path_build (paths are returned). */
+int ihsbin_path_build_batch(ihsbin_ctx* ctx, int32_t P, const ihsbin_matrix* A, int64_t strideA,
+                            const void* B, int64_t K, int64_t ldb, int64_t strideB,
+                            double lam_min, double lam_max, const ihsbin_opts* opts,
+                            ihsbin_path** paths, ihsbin_report* report);
 
 /* Compose x(lam_t) = tau sum_j (tau (lam_t - ref))^j ut_j for every t
  * (Algorithm 3 / 6, the lambda loop).  lambdas: host, T values, any order,

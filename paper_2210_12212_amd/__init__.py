@@ -178,6 +178,35 @@ class Context:
         r["status"] = rc
         return Path(ph, self), r
 
+    def path_build_batch(self, A, B, lam_min: float, lam_max: float, allow_noconv: bool = True,
+                         **opts):
+        """ihsbin_path_build_batch for P problems stacked along dim 0: A is a
+        P x n x d device tensor (unit column stride), B P x n x K (or P x n).
+        Returns (list of P Paths, report dict)."""
+        Bm = B if B.dim() == 3 else B.reshape(B.shape[0], B.shape[1], 1)
+        _require_cuda(A, "A")
+        _require_cuda(Bm, "B")
+        if A.dim() != 3 or A.stride(2) != 1 or Bm.stride(2) != 1:
+            raise ValueError("A (P x n x d) and B (P x n x K) need unit column stride")
+        P = A.shape[0]
+        if Bm.shape[0] != P or Bm.shape[1] != A.shape[1]:
+            raise ValueError("A and B disagree on P or n")
+        o, keep = _with_pointers(opts)
+        mat = L.Matrix()
+        mat.format, mat.dtype = L.DENSE, _dtype_code(A)
+        mat.n, mat.d, mat.ld, mat.nnz = A.shape[1], A.shape[2], A.stride(1), 0
+        mat.vals = A.data_ptr()
+        handles = (C.c_void_p * P)()
+        rep = L.Report()
+        rc = L.lib().ihsbin_path_build_batch(self._h, P, C.byref(mat), A.stride(0),
+                                             C.c_void_p(Bm.data_ptr()), Bm.shape[2], Bm.stride(1),
+                                             Bm.stride(0), float(lam_min), float(lam_max),
+                                             C.byref(o), handles, C.byref(rep))
+        self._check(rc, allow=(L.ENOCONV,) if allow_noconv else ())
+        r = rep.as_dict()
+        r["status"] = rc
+        return [Path(C.c_void_p(handles[p]), self) for p in range(P)], r
+
     def solve_path(self, A, B, lambdas, x_dtype=None, **opts):
         """ihsbin_solve_path: build, evaluate at every lambda, free."""
         torch = _torch()

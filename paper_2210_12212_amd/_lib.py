@@ -28,7 +28,7 @@ EXPORTED = [
     "ihsbin_server_create", "ihsbin_server_submit", "ihsbin_server_wait",
     "ihsbin_server_get_stats", "ihsbin_server_last_error", "ihsbin_server_destroy",
     "ihsbin_sketch_indices_host", "ihsbin_sketch_indices_device", "ihsbin_csr_transpose",
-    "ihsbin_path_eval_noalloc",
+    "ihsbin_path_eval_noalloc", "ihsbin_path_build_batch",
 ]
 
 
@@ -59,7 +59,7 @@ class Opts(C.Structure):
                 ("lanczos_steps", C.c_int32), ("timing", C.c_int32),
                 ("taus", C.POINTER(C.c_double)), ("gram_prec", C.c_int32),
                 ("alg4", C.POINTER(Alg4Opts)), ("sketch_prec", C.c_int32),
-                ("sigma_d2", C.c_double)]
+                ("sigma_d2", C.c_double), ("basis_prec", C.c_int32), ("f32_switch", C.c_double)]
 
 
 class Report(C.Structure):
@@ -71,6 +71,8 @@ class Report(C.Structure):
                 ("ata_launches", C.c_int64), ("ata_flops", C.c_double), ("ata_ms_y", C.c_double),
                 ("ata_ms_w", C.c_double), ("ata_bytes_a", C.c_double),
                 ("peak_bytes", C.c_int64), ("est_rel_err", C.c_double),
+                ("ata_f32_launches", C.c_int64), ("ata_f32_flops", C.c_double),
+                ("ata_f32_ms_y", C.c_double), ("ata_f32_ms_w", C.c_double),
                 ("bytes_moved", C.c_double)]
 
     def as_dict(self):
@@ -123,6 +125,9 @@ def _declare(lib):
         "ihsbin_path_build": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, dbl, dbl,
                                         C.POINTER(Opts), C.POINTER(vp), C.POINTER(Report)]),
         "ihsbin_path_eval": (C.c_int, [vp, pd, i64, vp, i64, i32]),
+        "ihsbin_path_build_batch": (C.c_int, [vp, i32, C.POINTER(Matrix), i64, vp, i64, i64, i64,
+                                              dbl, dbl, C.POINTER(Opts), C.POINTER(vp),
+                                              C.POINTER(Report)]),
         "ihsbin_path_eval_noalloc": (C.c_int, [vp, pd, i64, vp, i64, i32]),
         "ihsbin_path_get_info": (C.c_int, [vp, C.POINTER(PathInfo)]),
         "ihsbin_path_intervals": (C.c_int, [vp, pd, pd, pd, pd, pd, C.POINTER(C.c_int32)]),

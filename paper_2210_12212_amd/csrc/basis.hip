@@ -11,21 +11,25 @@
 
 namespace ihs {
 
+// Column block a of R = C block a / per (C: blocks of d x K).
 __global__ void seed_rhs_kernel(const double* __restrict__ C, int64_t d, int64_t K, int na,
-                                double* __restrict__ R, int64_t ldr) {
+                                int per, double* __restrict__ R, int64_t ldr) {
   const int64_t total = d * K * na;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = t / (K * na), c = t % (K * na);
-    R[r * ldr + c] = C[r * K + c % K];
+    const int64_t a = c / K;
+    R[r * ldr + c] = C[((a / per) * d + r) * K + c % K];
   }
 }
 
 void launch_seed_rhs(const double* C, int64_t d, int64_t K, int na, double* R, int64_t ldr,
-                     hipStream_t st) {
+                     hipStream_t st, int per) {
   int64_t blocks = cdiv(d * K * na, 256);
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(seed_rhs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, C, d, K, na, R, ldr);
+  if (per < 1) per = na;
+  hipLaunchKernelGGL(seed_rhs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, C, d, K, na, per, R,
+                     ldr);
   IHS_CHECK_LAUNCH();
 }
 

@@ -12,8 +12,9 @@ struct EvalItem {  // one lambda of an evaluation request
   double mu;       // tau * (lam - ref)
 };
 
+// per: column blocks per C block (0: every block takes the one C).
 void launch_seed_rhs(const double* C, int64_t d, int64_t K, int na, double* R, int64_t ldr,
-                     hipStream_t st);
+                     hipStream_t st, int per = 0);
 void launch_store_first(const double* U, int64_t ldu, int64_t d, int64_t K, int na,
                         const int32_t* ids, int64_t kcap, double* basis, hipStream_t st);
 void launch_form_r(const double* W, const double* U, int64_t ld, int64_t d, int64_t K, int na,

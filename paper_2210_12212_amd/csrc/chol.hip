@@ -15,8 +15,10 @@
 
 namespace ihs {
 
+// H_l = G_{l / gper} + lam0_l I (lower triangle) for l < nl.
 __global__ void build_shifted_kernel(const double* __restrict__ G, int64_t d,
-                                     const double* __restrict__ lam0, int nl, double* H) {
+                                     const double* __restrict__ lam0, int nl, int gper,
+                                     double* H) {
   const int64_t per = d * d;
   const int64_t total = per * nl;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -24,16 +26,18 @@ __global__ void build_shifted_kernel(const double* __restrict__ G, int64_t d,
     const int l = (int)(t / per);
     const int64_t e = t % per;
     const int64_t r = e / d, c = e % d;
-    H[t] = c > r ? 0.0 : G[e] + (r == c ? lam0[l] : 0.0);  // lower triangle only
+    const double* Gl = G + (int64_t)(l / gper) * per;
+    H[t] = c > r ? 0.0 : Gl[e] + (r == c ? lam0[l] : 0.0);  // lower triangle only
   }
 }
 
 void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, int nl, double* H,
-                          hipStream_t st) {
+                          hipStream_t st, int gper) {
   int64_t blocks = cdiv(d * d * nl, 256);
   if (blocks > 16384) blocks = 16384;
+  if (gper < 1) gper = nl;
   hipLaunchKernelGGL(build_shifted_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G, d, lam0_dev,
-                     nl, H);
+                     nl, gper, H);
   IHS_CHECK_LAUNCH();
 }
 

@@ -190,17 +190,18 @@ struct Ctx {
   double bytes_moved = 0.0;
   Pool pool;     // build-local buffers (declared first: outlives the workspaces below)
   // scratch shared by the step kernels of one call
-  DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status;
+  DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status, ws_f32;
   // every buffer of the context is used on `stream` only
   void bind() {
     pool.bind(stream, &mem);
-    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status})
+    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status, &ws_f32})
       b->bind(stream, &mem);
   }
   // hand idle pool blocks and the workspaces back to the device
   void trim() {
     pool.release_idle();
-    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status}) b->release();
+    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status, &ws_f32})
+      b->release();
   }
 };
 

@@ -25,6 +25,30 @@
 namespace ihs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// The matrix-core instruction of a compute type and the row of accumulator
+// register r held by a lane (column: lane % 16 for both).
+//  FP64 v_mfma_f64_16x16x4f64: register r of lane l holds D[4 r + l / 16].
+//  FP32 v_mfma_f32_16x16x4f32: register r of lane l holds D[4 (l / 16) + r].
+template <typename TM>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
 
 // LDS pitches (in elements) that keep the MFMA fragment reads free of bank
 // conflicts: K-major rows start 64 bytes (FP32) / 128 bytes (FP64) apart
@@ -64,12 +88,12 @@ __device__ inline void ld4c(const T* p, int nv, T (&o)[4]) {
 }
 
 template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
-          bool CHK, int NT>
+          bool CHK, int NT, typename TM>
 __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ A,
                                           const TB* __restrict__ B, int64_t m0, int64_t n0,
                                           int64_t kb, int64_t ke, int nblk,
                                           char* __restrict__ smem,
-                                          v4d (&acc)[BM / WM / 16][BN / WN / 16]) {
+                                          typename Mfma<TM>::acc_t (&acc)[BM / WM / 16][BN / WN / 16]) {
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
   constexpr int A_LD = TRA ? kmajor_pitch<TA>(BM) : rowmajor_pitch<TA>(BK);
@@ -158,18 +182,17 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4), c16 = lane & 15;
-      double af[FM], bf[FN];
+      TM af[FM], bf[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
-        af[i] = (double)(TRA ? As[kr * A_LD + wm + i * 16 + c16] : As[(wm + i * 16 + c16) * A_LD + kr]);
+        af[i] = (TM)(TRA ? As[kr * A_LD + wm + i * 16 + c16] : As[(wm + i * 16 + c16) * A_LD + kr]);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
-        bf[j] = (double)(TRB ? Bs[(wn + j * 16 + c16) * B_LD + kr] : Bs[kr * B_LD + wn + j * 16 + c16]);
+        bf[j] = (TM)(TRB ? Bs[(wn + j * 16 + c16) * B_LD + kr] : Bs[kr * B_LD + wn + j * 16 + c16]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<TM>::mma(af[i], bf[j], acc[i][j]);
     }
   };
 
@@ -201,8 +224,11 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, const TA* __restrict__ 
   }
 }
 
+// TM: the matrix cores' compute type (double, or float for FP32 operands);
+// TC: the type of C (float is used only with TM = float; split-K partials of
+// an FP32 product are stored as double).
 template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
-          int NT = 256>
+          int NT = 256, typename TM = double, typename TC = double>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
   constexpr int FM = BM / WM / 16;
   constexpr int FN = BN / WN / 16;
@@ -253,11 +279,12 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
     ke = s1 < ke ? s1 : ke;
   }
 
-  v4d acc[FM][FN];
+  typedef typename Mfma<TM>::acc_t acc_t;
+  acc_t acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   // 16-column blocks of this wave that hold columns < N (wave-uniform)
   int nblk = (int)((g.N - (n0 + wn) + 15) / 16);
@@ -267,28 +294,30 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
   const int64_t nr = g.n_read > g.N ? g.n_read : g.N;
   const bool fast = g.vec_ok && m0 + BM <= g.M && n0 + BN <= nr && ((ke - kb) % BK) == 0;
   if (fast)
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, false, NT>(g, A, B, m0, n0, kb, ke, nblk, smem,
-                                                                acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, false, NT, TM>(g, A, B, m0, n0, kb, ke, nblk,
+                                                                    smem, acc);
   else
-    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true, NT>(g, A, B, m0, n0, kb, ke, nblk, smem,
-                                                               acc);
+    gemm_tile<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, true, NT, TM>(g, A, B, m0, n0, kb, ke, nblk,
+                                                                   smem, acc);
 
-  double* C = g.splits > 1 ? g.C + (int64_t)z * g.strideC
-                           : g.C + (int64_t)b * g.strideC + (int64_t)b2 * g.strideC2;
+  TC* C = reinterpret_cast<TC*>(g.C) +
+          (g.splits > 1 ? (int64_t)z * g.strideC
+                        : (int64_t)b * g.strideC + (int64_t)b2 * g.strideC2);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gm = m0 + wm + i * 16 + 4 * r + (lane >> 4);
+        const int64_t gm = m0 + wm + i * 16 + Mfma<TM>::row(r, lane);
         const int64_t gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < g.M && gn < g.N) {
-          double* p = C + gm * g.ldc + gn;
+          TC* p = C + gm * g.ldc + gn;
           if (g.splits > 1)
-            *p = acc[i][j][r];
+            *p = (TC)acc[i][j][r];
           else
-            *p = g.alpha * acc[i][j][r] + (g.beta != 0.0 ? g.beta * *p : 0.0);
+            *p = (TC)(g.alpha * (double)acc[i][j][r] +
+                      (g.beta != 0.0 ? g.beta * (double)*p : 0.0));
         }
       }
 }
@@ -319,14 +348,14 @@ static void tile_dims(Tile t, int& bm, int& bn) {
 }
 
 template <typename TA, typename TB, bool TRA, bool TRB, int BM, int BN, int BK, int WM, int WN,
-          int NT = 256>
+          int NT = 256, typename TM = double, typename TC = double>
 static void launch_one(const Gemm& g, hipStream_t s) {
   dim3 grid((unsigned)cdiv(g.N, BN), (unsigned)cdiv(g.M, BM),
             (unsigned)(g.batch * g.batch2 * g.splits));
   if (g.batch2 > 1 && g.splits > 1) fail(IHSBIN_EUNSUP, "gemm: batch2 with split-K");
   if (grid.y > 65535u || grid.z > 65535u) fail(IHSBIN_EUNSUP, "gemm grid too large");
-  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, NT>), grid, dim3(NT), 0,
-                     s, g);
+  hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TRA, TRB, BM, BN, BK, WM, WN, NT, TM, TC>), grid,
+                     dim3(NT), 0, s, g);
 }
 
 template <typename TA, typename TB, bool TRA, bool TRB>
@@ -361,6 +390,40 @@ static void launch_cols(const Gemm& g, int q, hipStream_t s) {
     default: launch_one<TA, double, TRA, false, 128, 112, 16, 4, 1>(g, s); break;
   }
   IHS_CHECK_LAUNCH();
+}
+
+// The same column-matched tiles on the FP32 matrix cores: A FP32, B FP32,
+// C FP32 (cf32) or FP64 (split-K partials).
+template <bool TRA, typename TC>
+static void launch_cols_f32(const Gemm& g, int q, hipStream_t s) {
+  switch (q) {
+    case 1: launch_one<float, float, TRA, false, 128, 16, 32, 4, 1, 256, float, TC>(g, s); break;
+    case 2: launch_one<float, float, TRA, false, 128, 32, 16, 4, 1, 256, float, TC>(g, s); break;
+    case 3: launch_one<float, float, TRA, false, 128, 48, 16, 4, 1, 256, float, TC>(g, s); break;
+    case 4: launch_one<float, float, TRA, false, 128, 64, 16, 4, 1, 256, float, TC>(g, s); break;
+    case 5: launch_one<float, float, TRA, false, 128, 80, 16, 4, 1, 256, float, TC>(g, s); break;
+    case 6: launch_one<float, float, TRA, false, 128, 96, 16, 4, 1, 256, float, TC>(g, s); break;
+    default: launch_one<float, float, TRA, false, 128, 112, 16, 4, 1, 256, float, TC>(g, s); break;
+  }
+  IHS_CHECK_LAUNCH();
+}
+
+void gemm_cols_f32(const Gemm& g_in, bool transA, bool c_f32, const ColTiles& ct, hipStream_t s) {
+  if (g_in.M <= 0 || g_in.N <= 0) return;
+  if (ct.q < 1 || ct.q > kColTileMaxQ || (int64_t)ct.c * 16 * ct.q < g_in.N)
+    fail(IHSBIN_EINVAL, "gemm_cols_f32: column tiling does not cover N");
+  if (c_f32 && (g_in.splits > 1 || g_in.beta != 0.0))
+    fail(IHSBIN_EINVAL, "gemm_cols_f32: FP32 output without split-K or beta only");
+  Gemm g = g_in;
+  g.vec_ok = aligned16(g.A, g.lda, g.strideA, 4) && aligned16(g.B, g.ldb, g.strideB, 4);
+  if (g.n_read > (int64_t)ct.c * 16 * ct.q) g.n_read = (int64_t)ct.c * 16 * ct.q;
+  if (c_f32) {
+    if (transA) launch_cols_f32<true, float>(g, ct.q, s);
+    else launch_cols_f32<false, float>(g, ct.q, s);
+  } else {
+    if (transA) launch_cols_f32<true, double>(g, ct.q, s);
+    else launch_cols_f32<false, double>(g, ct.q, s);
+  }
 }
 
 ColTiles pick_col_tiles(int64_t N) {

@@ -57,6 +57,11 @@ ColTiles pick_col_tiles(int64_t N);
 // op(A) of type ta (FP32/FP64), B FP64 not transposed, C FP64.
 void gemm_cols(const Gemm& g, DT ta, bool transA, const ColTiles& ct, hipStream_t s);
 int pick_splits_cols(int64_t M, const ColTiles& ct, int64_t K, int64_t target);
+// The same products on the FP32 matrix cores (v_mfma_f32_16x16x4f32): op(A)
+// and B FP32; C FP32 when c_f32 (no split-K, beta = 0), else FP64 (split-K
+// partials or a plain FP64 result of FP32 sums).  g.C is then a float*
+// reinterpreted through the double* field.
+void gemm_cols_f32(const Gemm& g, bool transA, bool c_f32, const ColTiles& ct, hipStream_t s);
 
 // Split-K for a lower_only product with M = N = n on 64 x 64 tiles (small_tiles):
 // roughly `target` workgroups over the lower tiles.

@@ -78,7 +78,7 @@ int ihsbin_path_eval_noalloc(ihsbin_path* p, const double* lambdas, int64_t T, v
     if (!p) return IHSBIN_EINVAL;
     if (T < 0 || T > kNoallocMaxT || (T > 0 && (!lambdas || !X))) return IHSBIN_EINVAL;
     if (ldx < p->K || (x_dtype != IHSBIN_F32 && x_dtype != IHSBIN_F64)) return IHSBIN_EINVAL;
-    if (!p->plan.p) return IHSBIN_EINVAL;
+    if (!p->plan_ptr()) return IHSBIN_EINVAL;
     if (T == 0) return IHSBIN_OK;
     const double slack = 1e-12;
     for (int64_t t = 0; t < T; ++t) {
@@ -95,9 +95,9 @@ int ihsbin_path_eval_noalloc(ihsbin_path* p, const double* lambdas, int64_t T, v
     int64_t blocks = cdiv(T, 256);
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(noalloc_items_kernel, dim3((unsigned)blocks), dim3(256), 0, p->stream, lam_d,
-                       T, static_cast<const char*>(p->plan.p), p->L, items);
+                       T, p->plan_ptr(), p->L, items);
     IHS_CHECK_LAUNCH();
-    launch_eval(p->basis.as<double>(), p->kcap, p->d, p->K, items, T, X, ldx, x_dtype, p->stream);
+    launch_eval(p->basis_ptr(), p->kcap, p->d, p->K, items, T, X, ldx, x_dtype, p->stream);
     IHS_HIP(hipStreamSynchronize(p->stream));
     return IHSBIN_OK;
   } catch (const Error& e) {

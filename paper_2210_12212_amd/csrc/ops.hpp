@@ -36,7 +36,7 @@ void launch_gather_rows(const double* Z, int64_t d, const int32_t* rows, int64_t
 // ------------------------------------------------------------ factorization
 // H_l = G + lam0_l I for l < nl (d x d each).
 void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, int nl, double* H,
-                          hipStream_t st);
+                          hipStream_t st, int gper = 0);
 // In-place blocked Cholesky of nl matrices (lower factor, upper zeroed);
 // dinv receives the inverses of the diagonal blocks (nl x nblk x 64 x 64).
 // status_dev (int) is set non-zero when a pivot is not positive.
@@ -92,8 +92,23 @@ void launch_gather_blocks(const double* src, const int32_t* blk, int nb, int64_t
 void launch_scatter_blocks(const double* Z, int64_t ldz, const int32_t* blk, int nb, int64_t rows,
                            int64_t K, double* dst, hipStream_t st);
 int64_t padded_width(int64_t w);
+// f32: products on the FP32 matrix cores (dense FP32 A only; each column of U
+// scaled by a power of two into range and rounded to FP32, Y = A U kept in
+// FP32, A^T Y summed in FP32 over at most 16384 rows and in FP64 across them,
+// then scaled back).
 int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
-                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0);
+                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0, bool f32 = false);
+// Many problems of one shape (dense, problem p's matrix at A.vals + p *
+// strideA elements): W = A_p^T A_p U for `groups` groups of P column blocks of
+// `per` columns each (group g, problem p: columns (g P + p) per ...).  U must
+// keep ata_batch_slack(per) readable columns after its last block.
+int64_t ata_batch_slack(int64_t per);
+void ata_apply_batch(Ctx& ctx, const MatView& A, int64_t strideA, int P, int groups, int64_t per,
+                     const double* U, int64_t ldu, double* W, int64_t ldw);
+// C_p = A_p^T B_p for P problems (B_p at B + p * strideB elements), C: P blocks
+// of d x K.
+void atb_apply_batch(Ctx& ctx, const MatView& A, int64_t strideA, int P, const void* B,
+                     int64_t K, int64_t ldb, int64_t strideB, double* C);
 // C = A^T B (d x K), FP64, B in A's dtype (row stride ldb).
 void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C);
 // CSR kernels

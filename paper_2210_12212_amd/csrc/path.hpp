@@ -2,6 +2,7 @@
 // basis (and evaluation staging) on the device.
 #pragma once
 
+#include <memory>
 #include <vector>
 
 #include "common.hpp"
@@ -20,6 +21,17 @@ struct ihsbin_path {
   // the plan on the device for ihsbin_path_eval_noalloc: grid (L + 1
   // doubles), tau (L), ref (L), then k (L int32)
   ihs::DevBuf plan;
+  // paths built together (ihsbin_path_build_batch) share one basis and one
+  // plan allocation; these are freed with the last of them
+  std::shared_ptr<ihs::DevBuf> shared_basis, shared_plan;
+  size_t basis_off = 0, plan_off = 0;  // bytes into the shared buffers
+  const double* basis_ptr() const {
+    return shared_basis ? reinterpret_cast<const double*>(shared_basis->as<char>() + basis_off)
+                        : basis.as<double>();
+  }
+  const char* plan_ptr() const {
+    return shared_plan ? shared_plan->as<char>() + plan_off : plan.as<char>();
+  }
 };
 
 namespace ihs {

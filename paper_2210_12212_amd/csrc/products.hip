@@ -251,11 +251,148 @@ int64_t padded_width(int64_t w) {
   return cdiv(w, 64) * 64;
 }
 
+// Per-column powers of two that bring each column's largest entry into
+// [1/2, 1): the basis vectors u_{i,j} grow like ||P_S||^j (their powers of
+// tau (lam - lam0) shrink accordingly), far beyond the FP32 range for small
+// lam0 and large j.  Scaling by a power of two is exact, so each column keeps
+// its full FP32 relative precision; the product is linear per column and is
+// scaled back exactly.  scale[c] = 2^-e (1 for a zero column).
+__global__ void col_pow2_scale_kernel(const double* __restrict__ U, int64_t ldu, int64_t d,
+                                      int64_t w, double* __restrict__ scale) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < w;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    double mx = 0.0;
+    for (int64_t r = 0; r < d; ++r) mx = fmax(mx, fabs(U[r * ldu + c]));
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    scale[c] = ldexp(1.0, -e);
+  }
+}
+
+// U32 (d x span, row stride span) = U columns [0, w) times scale, rounded to
+// FP32, zero beyond w.
+__global__ void round_cols_f32_kernel(const double* __restrict__ U, int64_t ldu, int64_t d,
+                                      int64_t w, int64_t span, const double* __restrict__ scale,
+                                      float* __restrict__ U32) {
+  const int64_t total = d * span;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / span, c = t - r * span;
+    U32[t] = c < w ? (float)(U[r * ldu + c] * scale[c]) : 0.0f;
+  }
+}
+
+// W columns [0, w) divided by their scale (exact: powers of two).
+__global__ void unscale_cols_kernel(double* __restrict__ W, int64_t ldw, int64_t d, int64_t w,
+                                    const double* __restrict__ scale) {
+  const int64_t total = d * w;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / w, c = t - r * w;
+    W[r * ldw + c] /= scale[c];
+  }
+}
+
+// The FP32 form of the pair: Y32 = A U32, W = A^T Y32 (split-K partials in FP64).
+static void ata_f32(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
+                    int64_t ldw, std::vector<hipEvent_t>* ev) {
+  hipStream_t st = ctx.stream;
+  auto mark = [&]() {
+    if (!ev) return;
+    hipEvent_t e;
+    IHS_HIP(hipEventCreate(&e));
+    IHS_HIP(hipEventRecord(e, st));
+    ev->push_back(e);
+  };
+  int64_t wc = (int64_t)(kYBudget / (sizeof(float) * (size_t)A.n));
+  if (wc >= 64) wc = (wc / 64) * 64;
+  if (wc > w) wc = w;
+  if (wc < 1) wc = 1;
+  const ColTiles ct_full = pick_col_tiles(wc);
+  const int64_t span_max = (int64_t)ct_full.c * 16 * ct_full.q;
+  const int64_t ycap = std::max(padded_width(wc), span_max);
+  float* Y = static_cast<float*>(ctx.ws_y.ensure(sizeof(float) * (size_t)A.n * (size_t)ycap));
+  const size_t u32_bytes = ((sizeof(float) * (size_t)A.d * (size_t)ycap + 255) / 256) * 256;
+  char* f32_base = static_cast<char*>(ctx.ws_f32.ensure(u32_bytes + sizeof(double) * (size_t)ycap));
+  float* U32 = reinterpret_cast<float*>(f32_base);
+  double* scale = reinterpret_cast<double*>(f32_base + u32_bytes);
+  for (int64_t c0 = 0; c0 < w; c0 += wc) {
+    const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
+    const ColTiles ct = pick_col_tiles(cw);
+    const int64_t span = (int64_t)ct.c * 16 * ct.q;
+    hipLaunchKernelGGL(col_pow2_scale_kernel, dim3((unsigned)cdiv(cw, 256)), dim3(256), 0, st,
+                       U + c0, ldu, A.d, cw, scale);
+    IHS_CHECK_LAUNCH();
+    int64_t blocks = cdiv(A.d * span, 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(round_cols_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, U + c0, ldu,
+                       A.d, cw, span, scale, U32);
+    IHS_CHECK_LAUNCH();
+    mark();
+    Gemm g1;
+    g1.M = A.n;
+    g1.N = cw;
+    g1.K = A.d;
+    g1.A = A.vals;
+    g1.lda = A.ld;
+    g1.B = U32;
+    g1.ldb = span;
+    g1.n_read = span;
+    g1.C = reinterpret_cast<double*>(Y);
+    g1.ldc = span;
+    gemm_cols_f32(g1, false, true, ct, st);
+    mark();
+    // FP32 sums over at most 16384 rows each, FP64 across them
+    const int splits = (int)std::min<int64_t>(
+        256, std::max<int64_t>(pick_splits_cols(A.d, ct, A.n, 1024), cdiv(A.n, 16384)));
+    Gemm g2;
+    g2.M = A.d;
+    g2.N = cw;
+    g2.K = A.n;
+    g2.A = A.vals;
+    g2.lda = A.ld;
+    g2.B = Y;
+    g2.ldb = span;
+    g2.n_read = span;
+    if (splits > 1) {
+      double* part = static_cast<double*>(
+          ctx.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)A.d * (size_t)cw));
+      g2.C = part;
+      g2.ldc = cw;
+      g2.strideC = A.d * cw;
+      g2.splits = splits;
+      gemm_cols_f32(g2, true, false, ct, st);
+      mark();
+      reduce_splits(part, splits, 1, A.d, cw, cw, A.d * cw, W + c0, ldw, 0, 1.0, 0.0, st);
+    } else {
+      g2.C = W + c0;
+      g2.ldc = ldw;
+      gemm_cols_f32(g2, true, false, ct, st);
+      mark();
+    }
+    int64_t ub = cdiv(A.d * cw, 256);
+    if (ub > 16384) ub = 16384;
+    hipLaunchKernelGGL(unscale_cols_kernel, dim3((unsigned)ub), dim3(256), 0, st, W + c0, ldw, A.d,
+                       cw, scale);
+    IHS_CHECK_LAUNCH();
+  }
+}
+
 int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
-                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax) {
+                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax, bool f32) {
   hipStream_t st = ctx.stream;
   if (w <= 0) return 0;
   const bool dense = A.format == IHSBIN_DENSE;
+  if (f32 && dense && A.dtype == IHSBIN_F32) {
+    int64_t wc = (int64_t)(kYBudget / (sizeof(float) * (size_t)A.n));
+    if (wc >= 64) wc = (wc / 64) * 64;
+    if (wc > w) wc = w;
+    if (wc < 1) wc = 1;
+    ctx.bytes_moved += 2.0 * matrix_bytes(A) * (double)cdiv(w, wc) +
+                       (double)w * (8.0 * (double)A.n + 12.0 * (double)A.d);
+    ata_f32(ctx, A, U, w, ldu, W, ldw, ev);
+    return w;
+  }
   // U holds `readable` columns (w unless the caller sized it wider): column
   // tiles may read past w up to there, so ragged widths avoid the checked path
   const int64_t readable = wmax > w && wmax <= ldu ? wmax : w;
@@ -342,6 +479,117 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
     }
   }
   return w;
+}
+
+int64_t ata_batch_slack(int64_t per) {
+  const ColTiles ct = pick_col_tiles(per);
+  return (int64_t)ct.c * 16 * ct.q - per;
+}
+
+void ata_apply_batch(Ctx& ctx, const MatView& A, int64_t strideA, int P, int groups, int64_t per,
+                     const double* U, int64_t ldu, double* W, int64_t ldw) {
+  hipStream_t st = ctx.stream;
+  if (per <= 0 || P <= 0 || groups <= 0) return;
+  if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "batched products need dense matrices");
+  const ColTiles ct = pick_col_tiles(per);
+  const int64_t span = (int64_t)ct.c * 16 * ct.q;
+  const int64_t ycap = std::max(padded_width(per), span);
+  // problems per launch so that their n x ycap intermediates fit the budget
+  int64_t pc = (int64_t)(kYBudget / (sizeof(double) * (size_t)A.n * (size_t)ycap));
+  pc = std::max<int64_t>(1, std::min<int64_t>(pc, P));
+  double* Y = static_cast<double*>(
+      ctx.ws_y.ensure(sizeof(double) * (size_t)pc * (size_t)A.n * (size_t)ycap));
+  const DT ta = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
+  const size_t es = A.dtype == IHSBIN_F32 ? 4 : 8;
+  ctx.bytes_moved += (double)groups * (double)P *
+                     (2.0 * matrix_bytes(A) + 8.0 * (double)per * (2.0 * (double)A.n + 2.0 * (double)A.d));
+  for (int g = 0; g < groups; ++g) {
+    for (int64_t p0 = 0; p0 < P; p0 += pc) {
+      const int nb = (int)std::min<int64_t>(pc, P - p0);
+      const int64_t col0 = (int64_t)g * P * per + p0 * per;
+      const char* Ab = static_cast<const char*>(A.vals) + (size_t)p0 * (size_t)strideA * es;
+      Gemm g1;
+      g1.M = A.n;
+      g1.N = per;
+      g1.K = A.d;
+      g1.A = Ab;
+      g1.lda = A.ld;
+      g1.strideA = strideA;
+      g1.B = U + col0;
+      g1.ldb = ldu;
+      g1.strideB = per;
+      g1.n_read = span;
+      g1.C = Y;
+      g1.ldc = ycap;
+      g1.strideC = A.n * ycap;
+      g1.batch = nb;
+      gemm_cols(g1, ta, false, ct, st);
+      const int splits = pick_splits_cols(A.d, ct, A.n, std::max<int64_t>(1, 1024 / nb));
+      Gemm g2;
+      g2.M = A.d;
+      g2.N = per;
+      g2.K = A.n;
+      g2.A = Ab;
+      g2.lda = A.ld;
+      g2.strideA = strideA;
+      g2.B = Y;
+      g2.ldb = ycap;
+      g2.strideB = A.n * ycap;
+      g2.n_read = span;
+      g2.batch = nb;
+      if (splits > 1) {
+        double* part = static_cast<double*>(ctx.ws_part.ensure(
+            sizeof(double) * (size_t)splits * (size_t)nb * (size_t)A.d * (size_t)per));
+        g2.C = part;
+        g2.ldc = per;
+        g2.strideC = A.d * per;
+        g2.splits = splits;
+        gemm_cols(g2, ta, true, ct, st);
+        reduce_splits(part, splits, nb, A.d, per, per, A.d * per, W + col0, ldw, per, 1.0, 0.0, st);
+      } else {
+        g2.C = W + col0;
+        g2.ldc = ldw;
+        g2.strideC = per;
+        gemm_cols(g2, ta, true, ct, st);
+      }
+    }
+  }
+}
+
+void atb_apply_batch(Ctx& ctx, const MatView& A, int64_t strideA, int P, const void* B,
+                     int64_t K, int64_t ldb, int64_t strideB, double* C) {
+  if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "batched products need dense matrices");
+  hipStream_t st = ctx.stream;
+  ctx.bytes_moved += (double)P * (matrix_bytes(A) + (double)A.n * (double)K *
+                                                        (A.dtype == IHSBIN_F32 ? 4.0 : 8.0));
+  const DT ta = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
+  const int splits = pick_splits(A.d, K, A.n, P);
+  Gemm g;
+  g.M = A.d;
+  g.N = K;
+  g.K = A.n;
+  g.A = A.vals;
+  g.lda = A.ld;
+  g.strideA = strideA;
+  g.B = B;
+  g.ldb = ldb;
+  g.strideB = strideB;
+  g.batch = P;
+  if (splits > 1) {
+    double* part = static_cast<double*>(
+        ctx.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)P * (size_t)A.d * (size_t)K));
+    g.C = part;
+    g.ldc = K;
+    g.strideC = A.d * K;
+    g.splits = splits;
+    gemm(g, ta, true, ta, false, st);
+    reduce_splits(part, splits, P, A.d, K, K, A.d * K, C, K, A.d * K, 1.0, 0.0, st);
+  } else {
+    g.C = C;
+    g.ldc = K;
+    g.strideC = A.d * K;
+    gemm(g, ta, true, ta, false, st);
+  }
 }
 
 void atb_apply(Ctx& ctx, const MatView& A, const void* B, int64_t K, int64_t ldb, double* C) {

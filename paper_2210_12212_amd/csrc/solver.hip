@@ -213,8 +213,11 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
 
 // Lower triangle (and the diagonal tiles) of G = (SA)^T SA; the strictly
 // upper tiles are not computed and hold unspecified values.
+// batch > 1: SA holds `batch` blocks of m x d at stride m * d, G `batch`
+// blocks of d x d (FP64 only).
 static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G,
-                      int prec = IHSBIN_GRAM_F64) {
+                      int prec = IHSBIN_GRAM_F64, int batch = 1) {
+  if (batch > 1 && prec != IHSBIN_GRAM_F64) fail(IHSBIN_EUNSUP, "batched Gram is FP64 only");
   if (prec == IHSBIN_GRAM_BF16X3) {
     const int splits = gram_bf16x3_splits(m);
     PoolBuf wb(c.pool);
@@ -228,7 +231,7 @@ static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G,
   if (prec != IHSBIN_GRAM_F64) fail(IHSBIN_EINVAL, "unknown Gram precision");
   // 64 x 64 lower tiles, ~64 workgroups per CU over the K-splits (a sweep at
   // 65536 x 2048: 8 splits 47, 16 splits 52, 32 splits 57 TFLOP/s)
-  const int splits = pick_splits_lower(d, m, 16384);
+  const int splits = pick_splits_lower(d, m, std::max<int64_t>(1, 16384 / batch));
   Gemm g;
   g.small_tiles = 1;
   g.M = d;
@@ -236,32 +239,39 @@ static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G,
   g.K = m;
   g.A = SA;
   g.lda = d;
+  g.strideA = m * d;
   g.B = SA;
   g.ldb = d;
+  g.strideB = m * d;
+  g.batch = batch;
   g.lower_only = 1;
   if (splits > 1) {
-    double* part = static_cast<double*>(
-        c.ws_part.ensure(sizeof(double) * (size_t)splits * (size_t)d * (size_t)d));
+    double* part = static_cast<double*>(c.ws_part.ensure(
+        sizeof(double) * (size_t)splits * (size_t)batch * (size_t)d * (size_t)d));
     g.C = part;
     g.ldc = d;
     g.strideC = d * d;
     g.splits = splits;
     gemm(g, DT::F64, true, DT::F64, false, c.stream);
-    reduce_splits(part, splits, 1, d, d, d, d * d, G, d, 0, 1.0, 0.0, c.stream);
+    reduce_splits(part, splits, batch, d, d, d, d * d, G, d, d * d, 1.0, 0.0, c.stream);
   } else {
     g.C = G;
     g.ldc = d;
+    g.strideC = d * d;
     gemm(g, DT::F64, true, DT::F64, false, c.stream);
   }
 }
 
 // H_l = G + lam0_l I, factor in place, and Linv_l = L_l^-1.
+// gper > 0: matrix l is built from G block l / gper (blocks of d x d), so the
+// factors of several Grams run in one batch.
 static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<double>& lam0s,
-                        double* Lf, double* Linv, PoolBuf& dinv_buf, PoolBuf& lam_buf) {
+                        double* Lf, double* Linv, PoolBuf& dinv_buf, PoolBuf& lam_buf,
+                        int gper = 0) {
   const int nl = (int)lam0s.size();
   double* lam_dev = static_cast<double*>(lam_buf.ensure(sizeof(double) * nl));
   IHS_HIP(hipMemcpyAsync(lam_dev, lam0s.data(), sizeof(double) * nl, hipMemcpyHostToDevice, c.stream));
-  launch_build_shifted(G, d, lam_dev, nl, Lf, c.stream);
+  launch_build_shifted(G, d, lam_dev, nl, Lf, c.stream, gper > 0 ? gper : nl);
   const int64_t nblk = cdiv(d, kNB);
   double* dinv = static_cast<double*>(dinv_buf.ensure(sizeof(double) * nl * nblk * kNB * kNB));
   int* status = static_cast<int*>(c.ws_status.ensure(64));
@@ -408,19 +418,32 @@ static Ritz ritz_extremes(const std::vector<double>& h, int na, int J, int a, in
 // enabled, the run may stop once early(Ritz extremes of every column) returns
 // true (Ritz values bound the spectrum from inside).
 // nv = 2: columns a and a + na/2 share a factor (ids holds na/2 entries).
-template <class Early>
-static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* Linv_all,
+// The A^T A product of the working form (one matrix): S = A^T A T for w
+// columns of row stride ld.
+struct AtaProd {
+  Ctx& c;
+  const MatView& A;
+  int64_t d() const { return A.d; }
+  int64_t slack(int64_t) const { return 0; }
+  void operator()(const double* T, int64_t w, int64_t ld, double* S) const {
+    ata_apply(c, A, T, w, ld, S, ld, nullptr, ld);
+  }
+};
+
+template <class Early, class Prod>
+static std::vector<Spec> spectrum_impl(Ctx& c, const Prod& prod, const double* Linv_all,
                                        const std::vector<int32_t>& ids,
                                        const std::vector<double>& shifts, int J, uint64_t seed,
                                        Early early, int nv = 1) {
   hipStream_t st = c.stream;
   const int na = (int)shifts.size();
   if ((int)ids.size() * nv != na) fail(IHSBIN_EINVAL, "spectrum: ids and shifts disagree");
-  const int64_t d = A.d;
+  const int64_t d = prod.d();
   if (J < 2) J = 2;
   if (J > d) J = (int)d;
   if (J > 63) J = 63;
-  const int64_t ld = padded_width(na);  // padded so the A^T A product runs on whole tiles
+  // padded so the A^T A product runs on whole tiles
+  const int64_t ld = padded_width(na + prod.slack(na));
   const size_t vec = sizeof(double) * (size_t)d * ld;
   PoolBuf Qb(c.pool), Tb(c.pool), Sb(c.pool), Wb(c.pool), ab(c.pool), idb(c.pool), lb(c.pool), trb(c.pool);
   double* trs = static_cast<double*>(trb.ensure(sizeof(double) * trmv_scratch_doubles(d, na)));
@@ -439,7 +462,7 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const MatView& A, const double* L
   int steps = J;
   for (int j = 0; j < J; ++j) {
     launch_trmv(Linv_all, d, ids_dev, na, true, Q + (size_t)j * d * ld, ld, T, ld, trs, st, nv);  // T = Linv^T q
-    ata_apply(c, A, T, na, ld, S, ld, nullptr, ld);  // S = A^T A T
+    prod(T, na, ld, S);                                // S = A^T A T
     launch_add_shift(S, T, d, na, ld, lam_dev, st);   // S += shift T
     launch_trmv(Linv_all, d, ids_dev, na, false, S, ld, Wv, ld, trs, st, nv);                  // W = Linv S
     launch_lanczos_orth(Q, Wv, d, na, ld, j, J, alpha, beta, st);
@@ -492,13 +515,45 @@ struct EarlyIfSlow {
   }
 };
 
+// The same for `groups` x P column blocks of problems of one shape: columns
+// (g P + p) per .. + per - 1 belong to problem p (batched builds).
+struct BatchProd {
+  Ctx& c;
+  const MatView& A;
+  int64_t strideA;
+  int P, groups;
+  int64_t d() const { return A.d; }
+  int64_t slack(int64_t na) const { return ata_batch_slack(std::max<int64_t>(1, na / (groups * P))); }
+  void operator()(const double* T, int64_t w, int64_t ld, double* S) const {
+    const int64_t per = w / ((int64_t)groups * P);
+    if (per * groups * P != w) fail(IHSBIN_EINVAL, "batched product: ragged column blocks");
+    ata_apply_batch(c, A, strideA, P, groups, per, T, ld, S, ld);
+  }
+};
+
+// P problems probed together (columns p: lower end, P + p: upper end of the
+// lowest interval of problem p): stop as soon as any of them is too slow.
+struct EarlyIfAnySlow {
+  bool enabled = true;
+  int min_steps = 2;
+  int P = 1;
+  double target;
+  bool operator()(const std::vector<Ritz>& r) const {
+    for (int p = 0; p < P; ++p) {
+      const double cmin = r[p].tmin, cmax = r[P + p].tmax;
+      if ((cmax - cmin) / (cmax + cmin) > target) return true;
+    }
+    return false;
+  }
+};
+
 // Spectrum bounds over whole intervals.  In the symmetric form
 // Linv (A^T A + lam I) Linv^T = B_0 + lam Linv Linv^T every Rayleigh quotient
 // grows with lam, so for lam in [lo, hi] the spectrum of P_S (A^T A + lam I)
 // lies between the smallest eigenvalue at lo and the largest at hi.  One
 // Lanczos column per interval end; fids[i] is the factor of interval i.
-template <class Early>
-static std::vector<Spec> interval_spectra(Ctx& c, const MatView& A, const double* Linv_all,
+template <class Early, class Prod>
+static std::vector<Spec> interval_spectra(Ctx& c, const Prod& prod, const double* Linv_all,
                                           const std::vector<int32_t>& fids,
                                           const std::vector<double>& los,
                                           const std::vector<double>& his, int J, uint64_t seed,
@@ -509,7 +564,7 @@ static std::vector<Spec> interval_spectra(Ctx& c, const MatView& A, const double
     shifts[i] = los[i];
     shifts[ni + i] = his[i];
   }
-  const std::vector<Spec> col = spectrum_impl(c, A, Linv_all, fids, shifts, J, seed, early, 2);
+  const std::vector<Spec> col = spectrum_impl(c, prod, Linv_all, fids, shifts, J, seed, early, 2);
   std::vector<Spec> out(ni);
   for (int i = 0; i < ni; ++i) {
     out[i].mu_min = col[i].mu_min;
@@ -835,6 +890,10 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   if (!(o.tol > 0.0)) fail(IHSBIN_EINVAL, "tol must be positive");
   if (o.adaptive_m < 0 || o.adaptive_m > 2) fail(IHSBIN_EINVAL, "adaptive_m out of range");
   if (!(o.sigma_d2 >= 0.0) || !std::isfinite(o.sigma_d2)) fail(IHSBIN_EINVAL, "need sigma_d2 >= 0");
+  if (o.basis_prec < IHSBIN_BASIS_F64 || o.basis_prec > IHSBIN_BASIS_MIXED)
+    fail(IHSBIN_EINVAL, "basis_prec out of range");
+  if (o.basis_prec == IHSBIN_BASIS_MIXED && !(o.f32_switch > 0.0))
+    fail(IHSBIN_EINVAL, "f32_switch must be positive");
   hipStream_t st = c.stream;
   Timer total;
   ihsbin_report r;
@@ -903,6 +962,21 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     return std::min(m_cap, m * mult);
   };
   const bool adapt = o.adaptive_m == 1 && !o.taus;
+  // Sketches whose cost does not grow with m (SRHT: one transform;
+  // CountSketch/SJLT: one pass over A) pay for m only through the 2 m d^2
+  // Gram, while a larger m shrinks the spectrum of P_S (A^T A + lam I) and
+  // with it k.  Measured on the dense 131072 x 2048 SRHT workload with m
+  // fixed: path time falls monotonically from m = d/2 (k_max 96, no
+  // convergence) to the cap m = 32 d (k_max 14, the fastest), while growing
+  // from m0 by probes ends at m = 16 d after three probes (1.6x the time).
+  // With m < d such a sketch therefore starts at the cap without a probe;
+  // with m >= d the probe below decides.
+  const bool cheap_sketch = o.sketch != IHSBIN_GAUSSIAN;
+  if (adapt && cheap_sketch && m < d && m < m_cap) {
+    logf("m=%lld < d=%lld: starting at the cap m=%lld", (long long)m, (long long)d,
+         (long long)m_cap);
+    m = m_cap;
+  }
   if (o.adaptive_m == 2) {
     // Algorithm 4 at lam_min from m0 = m (default d / 4); it leaves its
     // final sketch in place
@@ -927,7 +1001,8 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb);
     EarlyIfSlow early;
     early.target = o.rate_target;
-    auto sp = interval_spectra(c, A, Li1, {0}, {grid[0]}, {grid[1]}, std::max(8, o.lanczos_steps),
+    auto sp = interval_spectra(c, AtaProd{c, A}, Li1, {0}, {grid[0]}, {grid[1]},
+                               std::max(8, o.lanczos_steps),
                                o.seed, early);
     logf("probe m=%lld: c=[%.4g, %.4g] rate0=%.3f (target %.3f)", (long long)m, sp[0].mu_min,
          sp[0].mu_max, rate_of(sp[0]), o.rate_target);
@@ -957,7 +1032,8 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     IHS_HIP(hipStreamSynchronize(st));
     r.ms_factor += tf.ms();
     Timer tspec;
-    spec = interval_spectra(c, A, Linv, all, std::vector<double>(grid.begin(), grid.end() - 1),
+    spec = interval_spectra(c, AtaProd{c, A}, Linv, all,
+                            std::vector<double>(grid.begin(), grid.end() - 1),
                             std::vector<double>(grid.begin() + 1, grid.end()),
                             std::max(2, o.lanczos_steps), o.seed + 1, NoEarly{});
     r.ms_spectrum += tspec.ms();
@@ -1079,6 +1155,11 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   std::vector<double> host_part;
   // stop-test bound per interval at its latest step (k = 1: no estimate yet)
   std::vector<double> est(L, 0.0);
+  // FP32 products (dense FP32 A): from the start, or once the increments
+  // they refine are small (basis_prec)
+  const bool f32_ok = A.format == IHSBIN_DENSE && A.dtype == IHSBIN_F32;
+  bool use32 = f32_ok && o.basis_prec == IHSBIN_BASIS_F32;
+  std::vector<char> launch_f32;
   int unconverged = 0;
   int steps = 0;
   for (int i = 1; i < kcap && !act.empty(); ++i) {
@@ -1090,12 +1171,15 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
            (long long)w_old, ct.c, 16 * ct.q);
     }
     const size_t ev0 = events.size();
-    ata_apply(c, A, Ucur, w_old, wcap, W, wcap, o.timing ? &events : nullptr, wcap);
+    ata_apply(c, A, Ucur, w_old, wcap, W, wcap, o.timing ? &events : nullptr, wcap, use32);
     if (o.timing) {
       const double per = A.format == IHSBIN_DENSE ? 4.0 * A.n * A.d : 4.0 * A.nnz;
       const size_t chunks = (events.size() - ev0) / 3;
       const int64_t wc = w_old / (int64_t)std::max<size_t>(1, chunks);
-      for (size_t q = 0; q < chunks; ++q) flops_per_launch.push_back(per * (double)wc);
+      for (size_t q = 0; q < chunks; ++q) {
+        flops_per_launch.push_back(per * (double)wc);
+        launch_f32.push_back(use32 ? 1 : 0);
+      }
     }
     launch_form_r(W, Ucur, wcap, d, K, na, i, tau_dev, ref_dev, R, st);
     apply_p(c, Linv, ids_dev, na, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
@@ -1108,6 +1192,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     IHS_HIP(hipStreamSynchronize(st));
     steps = i;
     std::vector<int32_t> keep_pos, next_act;
+    double max_inc = 0.0;  // largest relative increment at the active interval ends
     for (int a = 0; a < na; ++a) {
       const int l = act[a];
       path->k[l] = i + 1;
@@ -1122,6 +1207,9 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
         const double e_lo = std::sqrt(sums[0]) * fac / std::sqrt(sums[2]);
         const double e_hi = std::sqrt(sums[1]) * fac / std::sqrt(sums[3]);
         est[l] = finite ? std::max(e_lo, e_hi) : INFINITY;
+        max_inc = std::max(max_inc, finite ? std::max(std::sqrt(sums[0] / sums[2]),
+                                                      std::sqrt(sums[1] / sums[3]))
+                                           : INFINITY);
       }
       if (o.k_fixed > 0) {
         stop = (i + 1 >= o.k_fixed);
@@ -1138,6 +1226,11 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
         keep_pos.push_back(a);
         next_act.push_back(l);
       }
+    }
+    if (f32_ok && o.basis_prec == IHSBIN_BASIS_MIXED && !use32 && max_inc <= o.f32_switch) {
+      use32 = true;
+      logf("step %d: largest relative increment %.3g <= %.3g: FP32 products from here", i,
+           max_inc, o.f32_switch);
     }
     if ((int)next_act.size() < na && !next_act.empty()) {
       IHS_HIP(hipMemcpyAsync(keep_dev, keep_pos.data(), sizeof(int32_t) * keep_pos.size(),
@@ -1204,15 +1297,23 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   }
   r.ms_basis = tb.ms();
   if (o.timing && !events.empty()) {
-    for (size_t q = 0; q + 2 < events.size(); q += 3) {
+    for (size_t q = 0, t = 0; q + 2 < events.size(); q += 3, ++t) {
       float ty = 0.f, tw = 0.f;
       IHS_HIP(hipEventElapsedTime(&ty, events[q], events[q + 1]));
       IHS_HIP(hipEventElapsedTime(&tw, events[q + 1], events[q + 2]));
-      r.ata_ms_y += ty;
-      r.ata_ms_w += tw;
-      r.ata_launches += 1;
+      const double f = t < flops_per_launch.size() ? flops_per_launch[t] : 0.0;
+      if (t < launch_f32.size() && launch_f32[t]) {
+        r.ata_f32_ms_y += ty;
+        r.ata_f32_ms_w += tw;
+        r.ata_f32_launches += 1;
+        r.ata_f32_flops += f;
+      } else {
+        r.ata_ms_y += ty;
+        r.ata_ms_w += tw;
+        r.ata_launches += 1;
+        r.ata_flops += f;
+      }
     }
-    for (double f : flops_per_launch) r.ata_flops += f;
     const double abytes = A.format == IHSBIN_DENSE
                               ? (double)A.n * A.d * (A.dtype == IHSBIN_F32 ? 4.0 : 8.0)
                               : (double)A.nnz * ((A.dtype == IHSBIN_F32 ? 4.0 : 8.0) + 4.0);
@@ -1251,6 +1352,383 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   return unconverged > 0 ? IHSBIN_ENOCONV : IHSBIN_OK;
 }
 
+// Many problems of one shape in one set of launches: P dense n x d problems
+// (A_p = A + p strideA, B_p = B + p strideB) share the interval plan, the
+// sketch family and its dimension m, and every step runs as one batched
+// launch over all P L intervals (GEMMs with a problem dimension, factors and
+// triangular products over P L matrices).  The basis steps run in lockstep:
+// every interval takes the same number of steps, the first after which all
+// of them pass the stop test (so each gets at least the steps it needs).
+// Each problem gets its own path; their bases share one allocation.
+static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t strideA,
+                            const void* B, int64_t K, int64_t ldb, int64_t strideB,
+                            double lam_min, double lam_max, const ihsbin_opts* o_in,
+                            ihsbin_path** paths, ihsbin_report* rep) {
+  if (!paths) fail(IHSBIN_EINVAL, "paths is NULL");
+  if (P < 1 || P > 65535) fail(IHSBIN_EINVAL, "need 1 <= P <= 65535");
+  for (int p = 0; p < P; ++p) paths[p] = nullptr;
+  ihsbin_opts o;
+  if (o_in) o = *o_in;
+  else ihsbin_opts_default(&o);
+  const MatView A = check_matrix(Ain);
+  if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "batched builds take dense matrices");
+  if (A.n < A.d) fail(IHSBIN_EUNSUP, "batched builds need n >= d");
+  if (strideA < (A.n - 1) * A.ld + A.d) fail(IHSBIN_EINVAL, "strideA smaller than one matrix");
+  if (!B || K < 1 || ldb < K || strideB < (A.n - 1) * ldb + K)
+    fail(IHSBIN_EINVAL, "need B, K >= 1, ldb >= K and strideB covering one right-hand side block");
+  if (!(lam_min > 0.0) || !(lam_max >= lam_min) || !std::isfinite(lam_max))
+    fail(IHSBIN_EINVAL, "need 0 < lam_min <= lam_max");
+  if (o.k_max < 1 || o.k_max > 4096) fail(IHSBIN_EINVAL, "k_max out of range");
+  if (o.k_fixed < 0 || o.k_fixed > 4096) fail(IHSBIN_EINVAL, "k_fixed out of range");
+  if (!(o.tol > 0.0)) fail(IHSBIN_EINVAL, "tol must be positive");
+  if (o.adaptive_m < 0 || o.adaptive_m > 1)
+    fail(IHSBIN_EUNSUP, "batched builds use adaptive_m 0 or 1");
+  if (o.taus) fail(IHSBIN_EUNSUP, "batched builds estimate their step sizes");
+  if (o.gram_prec != IHSBIN_GRAM_F64) fail(IHSBIN_EUNSUP, "batched builds form the Gram in FP64");
+  if (!(o.sigma_d2 >= 0.0) || !std::isfinite(o.sigma_d2)) fail(IHSBIN_EINVAL, "need sigma_d2 >= 0");
+  hipStream_t st = c.stream;
+  Timer total;
+  ihsbin_report r;
+  std::memset(&r, 0, sizeof(r));
+  c.mem.peak = c.mem.live;
+  c.bytes_moved = 0.0;
+  const int64_t n = A.n, d = A.d;
+  const size_t es = A.dtype == IHSBIN_F32 ? 4 : 8;
+  auto problem = [&](int p) {
+    MatView v = A;
+    v.vals = static_cast<const char*>(A.vals) + (size_t)p * (size_t)strideA * es;
+    return v;
+  };
+
+  // ---- interval plan (Section 4.2), shared by every problem
+  const double beta = lam_max / lam_min;
+  const int L = o.L > 0 ? o.L
+                        : (beta > 1.0 ? std::max(1, (int)std::floor(2.0 * std::log(beta))) : 1);
+  std::vector<double> grid(L + 1), lam0(L);
+  for (int l = 0; l <= L; ++l) grid[l] = lam_min * std::pow(beta, (double)l / L);
+  grid[L] = lam_max;
+  for (int l = 0; l < L; ++l) {
+    const double lo = grid[l], hi = grid[l + 1], sd2 = o.sigma_d2;
+    lam0[l] = (lo * hi + sd2 * (lo + hi)) / (std::sqrt((lo + sd2) * (hi + sd2)) + sd2);
+  }
+  const int nl = P * L;  // slots: problem p, interval l -> p L + l
+
+  // ---- C_p = A_p^T B_p
+  PoolBuf Cb(c.pool);
+  double* C = static_cast<double*>(Cb.ensure(sizeof(double) * (size_t)P * d * K));
+  atb_apply_batch(c, A, strideA, P, B, K, ldb, strideB, C);
+
+  // ---- sketch with one m for all problems
+  Timer tsk;
+  const int s = o.sketch == IHSBIN_SJLT ? std::max(1, o.sjlt_s) : 1;
+  auto round_s = [&](int64_t mm) { return mm % s ? mm + (s - mm % s) : mm; };
+  int64_t m = round_s(o.m > 0 ? o.m : 2 * d);
+  int64_t m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(n, 32 * d));
+  if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(n)));
+  const bool adapt = o.adaptive_m == 1;
+  const bool cheap_sketch = o.sketch != IHSBIN_GAUSSIAN;
+  if (adapt && cheap_sketch && m < d && m < m_cap) m = m_cap;
+  PoolBuf SAb(c.pool), Gb(c.pool), Sb(c.pool);
+  double* G = static_cast<double*>(Gb.ensure(sizeof(double) * (size_t)P * d * d));
+  int trials = 0;
+  auto sketch_all = [&](int64_t mm) {
+    const int64_t rows = std::min(mm, n);
+    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * (size_t)P * rows * d));
+    if (mm >= n) {
+      for (int p = 0; p < P; ++p) copy_rows_f64(c, problem(p), SA + (size_t)p * rows * d);
+    } else if (o.sketch == IHSBIN_GAUSSIAN && o.sketch_prec == IHSBIN_SKETCH_F64) {
+      // one S for every problem: S A_p as a batched product per chunk of rows
+      c.bytes_moved += (double)P * (matrix_bytes(A) + 8.0 * (double)mm * (double)d);
+      int64_t rb = (int64_t)((size_t(1) << 30) / (sizeof(double) * (size_t)n));
+      rb = std::max<int64_t>(64, (rb / 64) * 64);
+      if (rb > mm) rb = mm;
+      double* S = static_cast<double*>(Sb.ensure(sizeof(double) * (size_t)rb * n));
+      for (int64_t r0 = 0; r0 < mm; r0 += rb) {
+        const int64_t rn = std::min(rb, mm - r0);
+        launch_gaussian_fill(o.seed, mm, r0, rn, n, S, st);
+        const int splits = pick_splits(rn, d, n, P);
+        Gemm g;
+        g.M = rn;
+        g.N = d;
+        g.K = n;
+        g.A = S;
+        g.lda = n;
+        g.strideA = 0;
+        g.B = A.vals;
+        g.ldb = A.ld;
+        g.strideB = strideA;
+        g.batch = P;
+        const DT tb = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
+        if (splits > 1) {
+          double* part = static_cast<double*>(c.ws_part.ensure(
+              sizeof(double) * (size_t)splits * (size_t)P * (size_t)rn * (size_t)d));
+          g.C = part;
+          g.ldc = d;
+          g.strideC = rn * d;
+          g.splits = splits;
+          gemm(g, DT::F64, false, tb, false, st);
+          reduce_splits(part, splits, P, rn, d, d, rn * d, SA + r0 * d, d, rows * d, 1.0, 0.0, st);
+        } else {
+          g.C = SA + r0 * d;
+          g.ldc = d;
+          g.strideC = rows * d;
+          gemm(g, DT::F64, false, tb, false, st);
+        }
+      }
+    } else {
+      for (int p = 0; p < P; ++p)
+        sketch_apply_impl(c, problem(p), o.sketch, s, mm, o.seed, SA + (size_t)p * rows * d, false,
+                          o.sketch_prec);
+    }
+    gram_impl(c, SA, rows, d, G, IHSBIN_GRAM_F64, P);
+    ++trials;
+  };
+  auto rate_of = [&](const Spec& sp) { return (sp.mu_max - sp.mu_min) / (sp.mu_max + sp.mu_min); };
+  auto grow = [&](const Spec& sp) {
+    const double kap = sp.mu_max / sp.mu_min;
+    const double kt = (1.0 + o.rate_target) / (1.0 - o.rate_target);
+    double factor = 16.0;
+    if (kt > 1.0 && kap > 1.0) {
+      const double so = (std::sqrt(kap) - 1.0) / (std::sqrt(kap) + 1.0);
+      const double sg = (std::sqrt(kt) - 1.0) / (std::sqrt(kt) + 1.0);
+      factor = (so * so) / (sg * sg);
+    }
+    factor = std::min(16.0, std::max(2.0, factor));
+    int64_t mult = 1;
+    while (mult < factor) mult <<= 1;
+    return round_s(std::min(m_cap, m * mult));
+  };
+  sketch_all(m);
+  PoolBuf Lb(c.pool), Ib(c.pool), dinvb(c.pool), lamb(c.pool);
+  const BatchProd prod{c, A, strideA, P, 2};
+  std::vector<int32_t> pid(P);
+  for (int p = 0; p < P; ++p) pid[p] = p;
+  while (adapt && m < m_cap && trials < 8) {
+    // the lowest interval of every problem, probed together
+    double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * (size_t)P * d * d));
+    double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)P * d * d));
+    factor_impl(c, G, d, std::vector<double>(P, lam0[0]), Lf1, Li1, dinvb, lamb, 1);
+    EarlyIfAnySlow early;
+    early.P = P;
+    early.target = o.rate_target;
+    auto sp = interval_spectra(c, prod, Li1, pid, std::vector<double>(P, grid[0]),
+                               std::vector<double>(P, grid[1]), std::max(8, o.lanczos_steps),
+                               o.seed, early);
+    int worst = 0;
+    for (int p = 1; p < P; ++p)
+      if (rate_of(sp[p]) > rate_of(sp[worst])) worst = p;
+    logf("batch probe m=%lld: worst rate %.3f (problem %d, target %.3f)", (long long)m,
+         rate_of(sp[worst]), worst, o.rate_target);
+    if (rate_of(sp[worst]) <= o.rate_target) break;
+    const int64_t m_new = grow(sp[worst]);
+    if (m_new <= m) break;
+    m = m_new;
+    sketch_all(m);
+  }
+  IHS_HIP(hipStreamSynchronize(st));
+  r.ms_sketch = tsk.ms();
+
+  // ---- factors and spectra of every interval of every problem
+  std::vector<double> lam0s(nl), los(nl), his(nl);
+  std::vector<int32_t> all(nl);
+  for (int p = 0; p < P; ++p)
+    for (int l = 0; l < L; ++l) {
+      lam0s[p * L + l] = lam0[l];
+      los[p * L + l] = grid[l];
+      his[p * L + l] = grid[l + 1];
+      all[p * L + l] = p * L + l;
+    }
+  std::vector<Spec> spec;
+  double* Lf = nullptr;
+  double* Linv = nullptr;
+  for (;;) {
+    Timer tf;
+    Lf = static_cast<double*>(Lb.ensure(sizeof(double) * (size_t)nl * d * d));
+    Linv = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)nl * d * d));
+    factor_impl(c, G, d, lam0s, Lf, Linv, dinvb, lamb, L);
+    IHS_HIP(hipStreamSynchronize(st));
+    r.ms_factor += tf.ms();
+    Timer tspec;
+    spec = interval_spectra(c, prod, Linv, all, los, his, std::max(2, o.lanczos_steps), o.seed + 1,
+                            NoEarly{});
+    r.ms_spectrum += tspec.ms();
+    int worst = 0;
+    for (int p = 1; p < P; ++p)
+      if (rate_of(spec[p * L]) > rate_of(spec[worst * L])) worst = p;
+    if (adapt && trials < 8 && m < m_cap && rate_of(spec[worst * L]) > o.rate_target + 0.1) {
+      const int64_t m_new = grow(spec[worst * L]);
+      if (m_new > m) {
+        Timer t2;
+        m = m_new;
+        sketch_all(m);
+        IHS_HIP(hipStreamSynchronize(st));
+        r.ms_sketch += t2.ms();
+        continue;
+      }
+    }
+    break;
+  }
+  SAb.release();
+  Gb.release();
+  r.m_used = std::min<int64_t>(m, n);
+  r.sketch_trials = trials;
+  std::vector<double> tau(nl), rate(nl), ref(nl);
+  for (int a = 0; a < nl; ++a) {
+    tau[a] = 2.0 / (spec[a].mu_min + spec[a].mu_max);
+    const double rr = std::max(std::fabs(1.0 - tau[a] * spec[a].mu_min),
+                               std::fabs(1.0 - tau[a] * spec[a].mu_max));
+    rate[a] = std::min(rr, 0.999);
+    ref[a] = o.centred ? lam0s[a] : 0.0;
+  }
+
+  // ---- basis recursion, all P L intervals in lockstep
+  Timer tb;
+  const int64_t kcap = o.k_fixed > 0 ? o.k_fixed : o.k_max;
+  auto basis_buf = std::make_shared<DevBuf>();
+  double* basis =
+      static_cast<double*>(basis_buf->ensure(sizeof(double) * (size_t)nl * kcap * d * K));
+  c.mem.add((int64_t)basis_buf->bytes);
+  struct Unheld {
+    MemStats& s;
+    int64_t b;
+    ~Unheld() { s.sub(b); }
+  } unheld{c.mem, (int64_t)basis_buf->bytes};
+  IHS_HIP(hipMemsetAsync(basis, 0, sizeof(double) * (size_t)nl * kcap * d * K, st));
+  const int64_t wcap = padded_width((int64_t)nl * kcap * K + 128);
+  PoolBuf Ub0(c.pool), Ub1(c.pool), Rb(c.pool), Tt(c.pool), Zb(c.pool), Wb(c.pool), pb(c.pool),
+      partial_b(c.pool);
+  double* Ucur = static_cast<double*>(Ub0.ensure(sizeof(double) * d * wcap));
+  double* Unext = static_cast<double*>(Ub1.ensure(sizeof(double) * d * wcap));
+  double* R = static_cast<double*>(Rb.ensure(sizeof(double) * d * wcap));
+  double* Tm = static_cast<double*>(Tt.ensure(sizeof(double) * d * wcap));
+  double* Z = static_cast<double*>(Zb.ensure(sizeof(double) * d * wcap));
+  double* W = static_cast<double*>(Wb.ensure(sizeof(double) * d * wcap));
+  // the product's tiles may read columns past the last block: keep them finite
+  IHS_HIP(hipMemsetAsync(Ucur, 0, sizeof(double) * d * wcap, st));
+  IHS_HIP(hipMemsetAsync(Unext, 0, sizeof(double) * d * wcap, st));
+  char* pbase = static_cast<char*>(pb.ensure((sizeof(int32_t) + sizeof(double) * 4) * nl + 256));
+  int32_t* ids_dev = reinterpret_cast<int32_t*>(pbase);
+  double* tau_dev = reinterpret_cast<double*>(pbase + ((sizeof(int32_t) * nl + 63) / 64) * 64);
+  double* ref_dev = tau_dev + nl;
+  double* mlo_dev = ref_dev + nl;
+  double* mhi_dev = mlo_dev + nl;
+  {
+    std::vector<double> ml(nl), mh(nl);
+    for (int a = 0; a < nl; ++a) {
+      ml[a] = tau[a] * (los[a] - ref[a]);
+      mh[a] = tau[a] * (his[a] - ref[a]);
+    }
+    IHS_HIP(hipMemcpyAsync(ids_dev, all.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(tau_dev, tau.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(ref_dev, ref.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(mlo_dev, ml.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
+    IHS_HIP(hipMemcpyAsync(mhi_dev, mh.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
+  }
+  launch_seed_rhs(C, d, K, nl, R, wcap, st, L);
+  apply_p(c, Linv, ids_dev, nl, d, K, wcap, R, Tm, Ucur);
+  launch_store_first(Ucur, wcap, d, K, nl, ids_dev, kcap, basis, st);
+  const BatchProd prod1{c, A, strideA, P, 1};
+  std::vector<double> host_part, est(nl, 0.0);
+  std::vector<char> passed(nl, 0);
+  int steps = 0;
+  bool all_passed = false;
+  for (int i = 1; i < kcap; ++i) {
+    const int64_t w_old = (int64_t)nl * i * K;
+    prod1(Ucur, w_old, wcap, W);
+    launch_form_r(W, Ucur, wcap, d, K, nl, i, tau_dev, ref_dev, R, st);
+    apply_p(c, Linv, ids_dev, nl, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
+    double* part = static_cast<double*>(partial_b.ensure(sizeof(double) * 4 * nl * 64));
+    const int nbx = launch_update(Ucur, Z, Unext, wcap, d, K, nl, i, ids_dev, kcap, basis, mlo_dev,
+                                  mhi_dev, part, st);
+    host_part.resize((size_t)4 * nl * nbx);
+    IHS_HIP(hipMemcpyAsync(host_part.data(), part, sizeof(double) * host_part.size(),
+                           hipMemcpyDeviceToHost, st));
+    IHS_HIP(hipStreamSynchronize(st));
+    std::swap(Ucur, Unext);
+    steps = i;
+    all_passed = true;
+    for (int a = 0; a < nl; ++a) {
+      double sums[4] = {0, 0, 0, 0};
+      for (int b = 0; b < nbx; ++b)
+        for (int q = 0; q < 4; ++q) sums[q] += host_part[((size_t)a * nbx + b) * 4 + q];
+      const bool finite = std::isfinite(sums[0]) && std::isfinite(sums[1]) &&
+                          std::isfinite(sums[2]) && std::isfinite(sums[3]);
+      const double fac = rate[a] / (1.0 - rate[a]);
+      const double e_lo = std::sqrt(sums[0]) * fac / std::sqrt(sums[2]);
+      const double e_hi = std::sqrt(sums[1]) * fac / std::sqrt(sums[3]);
+      est[a] = finite ? std::max(e_lo, e_hi) : INFINITY;
+      passed[a] = finite && e_lo <= o.tol && e_hi <= o.tol;
+      if (!passed[a]) all_passed = false;
+    }
+    if (o.k_fixed > 0 ? i + 1 >= o.k_fixed : all_passed) break;
+  }
+  const int k_all = steps + 1;
+  int unconverged = 0;
+  if (o.k_fixed == 0)
+    for (int a = 0; a < nl; ++a) unconverged += passed[a] ? 0 : 1;
+  r.ms_basis = tb.ms();
+
+  // ---- one path per problem, sharing the basis and plan allocations
+  const size_t plan_doubles = (size_t)(3 * L + 1);
+  const size_t plan_bytes = ((sizeof(double) * plan_doubles + sizeof(int32_t) * L + 255) / 256) * 256;
+  auto plan_buf = std::make_shared<DevBuf>();
+  char* plan = static_cast<char*>(plan_buf->ensure(plan_bytes * (size_t)P));
+  {
+    std::vector<char> hp(plan_bytes * (size_t)P, 0);
+    for (int p = 0; p < P; ++p) {
+      double* dp = reinterpret_cast<double*>(hp.data() + plan_bytes * p);
+      for (int l = 0; l <= L; ++l) dp[l] = grid[l];
+      for (int l = 0; l < L; ++l) {
+        dp[L + 1 + l] = tau[p * L + l];
+        dp[2 * L + 1 + l] = ref[p * L + l];
+      }
+      int32_t* kp = reinterpret_cast<int32_t*>(dp + plan_doubles);
+      for (int l = 0; l < L; ++l) kp[l] = k_all;
+    }
+    IHS_HIP(hipMemcpyAsync(plan, hp.data(), hp.size(), hipMemcpyHostToDevice, st));
+    IHS_HIP(hipStreamSynchronize(st));
+  }
+  std::vector<std::unique_ptr<ihsbin_path>> made;
+  for (int p = 0; p < P; ++p) {
+    auto path = std::make_unique<ihsbin_path>();
+    path->device = c.device;
+    path->stream = st;
+    path->items.bind(st, nullptr);
+    path->d = d;
+    path->K = K;
+    path->L = L;
+    path->m_used = r.m_used;
+    path->lam_min = lam_min;
+    path->lam_max = lam_max;
+    path->centred = o.centred ? 1 : 0;
+    path->grid = grid;
+    path->lam0 = lam0;
+    path->tau.assign(tau.begin() + (size_t)p * L, tau.begin() + (size_t)(p + 1) * L);
+    path->rate.assign(rate.begin() + (size_t)p * L, rate.begin() + (size_t)(p + 1) * L);
+    path->ref.assign(ref.begin() + (size_t)p * L, ref.begin() + (size_t)(p + 1) * L);
+    path->k.assign(L, k_all);
+    path->kcap = kcap;
+    path->shared_basis = basis_buf;
+    path->basis_off = sizeof(double) * (size_t)p * L * kcap * d * K;
+    path->shared_plan = plan_buf;
+    path->plan_off = plan_bytes * (size_t)p;
+    made.push_back(std::move(path));
+  }
+  r.L = L;
+  r.steps = steps;
+  r.k_max_used = k_all;
+  r.k_sum = k_all * nl;
+  r.n_unconverged = unconverged;
+  for (int a = 0; a < nl; ++a) r.est_rel_err = std::max(r.est_rel_err, est[a]);
+  if (kcap == 1) r.est_rel_err = NAN;
+  r.bytes_moved = c.bytes_moved;
+  r.ms_total = total.ms();
+  r.peak_bytes = c.mem.peak;
+  if (rep) *rep = r;
+  for (int p = 0; p < P; ++p) paths[p] = made[p].release();
+  return unconverged > 0 ? IHSBIN_ENOCONV : IHSBIN_OK;
+}
+
 static int interval_of(const std::vector<double>& grid, double lam) {
   const int L = (int)grid.size() - 1;
   int l = (int)(std::lower_bound(grid.begin() + 1, grid.end(), lam) - (grid.begin() + 1));
@@ -1280,7 +1758,7 @@ static void eval_impl(ihsbin_path* p, const double* lambdas, int64_t T, void* X,
   EvalItem* it = static_cast<EvalItem*>(p->items.ensure(sizeof(EvalItem) * (size_t)T));
   IHS_HIP(hipMemcpyAsync(it, items.data(), sizeof(EvalItem) * (size_t)T, hipMemcpyHostToDevice,
                          p->stream));
-  launch_eval(p->basis.as<double>(), p->kcap, p->d, p->K, it, T, X, ldx, x_dtype, p->stream);
+  launch_eval(p->basis_ptr(), p->kcap, p->d, p->K, it, T, X, ldx, x_dtype, p->stream);
   IHS_HIP(hipStreamSynchronize(p->stream));
 }
 
@@ -1348,6 +1826,8 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->alg4 = nullptr;
   o->sketch_prec = IHSBIN_SKETCH_F64;
   o->sigma_d2 = 0.0;
+  o->basis_prec = IHSBIN_BASIS_F64;
+  o->f32_switch = 1e-3;
 }
 
 void ihsbin_alg4_opts_default(ihsbin_alg4_opts* a) {
@@ -1411,6 +1891,18 @@ int ihsbin_path_build(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B, in
   });
 }
 
+int ihsbin_path_build_batch(ihsbin_ctx* ctx, int32_t P, const ihsbin_matrix* A, int64_t strideA,
+                            const void* B, int64_t K, int64_t ldb, int64_t strideB,
+                            double lam_min, double lam_max, const ihsbin_opts* opts,
+                            ihsbin_path** paths, ihsbin_report* report) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    return build_batch_impl(ctx->c, P, A, strideA, B, K, ldb, strideB, lam_min, lam_max, opts,
+                            paths, report);
+  });
+}
+
 int ihsbin_path_eval(ihsbin_path* path, const double* lambdas, int64_t T, void* X, int64_t ldx,
                      int32_t x_dtype) {
   return guarded(nullptr, [&] {
@@ -1451,7 +1943,7 @@ int ihsbin_path_basis(const ihsbin_path* p, int32_t l, double* out) {
   return guarded(nullptr, [&] {
     DeviceGuard g(p->device);
     const size_t blk = sizeof(double) * (size_t)p->d * p->K;
-    IHS_HIP(hipMemcpyAsync(out, p->basis.as<double>() + (size_t)l * p->kcap * p->d * p->K,
+    IHS_HIP(hipMemcpyAsync(out, p->basis_ptr() + (size_t)l * p->kcap * p->d * p->K,
                            blk * p->k[l], hipMemcpyDeviceToDevice, p->stream));
     IHS_HIP(hipStreamSynchronize(p->stream));
     return IHSBIN_OK;

@@ -45,6 +45,7 @@ def test_default_options(lib):
     lib.ihsbin_opts_default(C.byref(o))
     assert o.tol == 1e-8 and o.k_max == 96 and o.centred == 1 and o.adaptive_m == 1
     assert o.lanczos_steps == 12 and not o.taus
+    assert o.basis_prec == 0 and o.f32_switch == 1e-3
 
 
 def test_null_arguments_are_rejected(lib):
@@ -101,8 +102,9 @@ def test_footprint_estimate_host_only(lib):
 
 def test_report_layout():
     from paper_2210_12212_amd import _lib
-    # int64, int32 x6, double x5, int64, double x4, int64, double x2
-    assert C.sizeof(_lib.Report) == 8 + 6 * 4 + 5 * 8 + 8 + 4 * 8 + 8 + 2 * 8
+    # int64, int32 x6, double x5, int64, double x4, int64, double, int64,
+    # double x3, double
+    assert C.sizeof(_lib.Report) == 8 + 6 * 4 + 5 * 8 + 8 + 4 * 8 + 8 + 8 + 8 + 3 * 8 + 8
 
 
 @pytest.mark.parametrize("n,m,s", [(1000, 37, 1), (4099, 64, 4), (1, 5, 1), (70000, 4096, 1),
