@@ -136,7 +136,12 @@ typedef struct {
                               active intervals, relative to x, is <= f32_switch;
                               FP32 afterwards, when the products only refine
                               what is left)                                     */
-  double f32_switch;       /* IHSBIN_BASIS_MIXED threshold (default 1e-3)       */
+  double f32_switch;       /* IHSBIN_BASIS_MIXED threshold (default 1e-2)       */
+  int32_t graph_steps;     /* ihsbin_path_build_batch: > 0 captures that many
+                              basis steps at a time into one HIP graph (on a
+                              private stream of the context) and launches it
+                              as one unit, reading the stop test once per
+                              graph; 0 (default): step by step                  */
 } ihsbin_opts;
 
 /* Arithmetic of the basis products. */
@@ -418,6 +423,16 @@ int ihsbin_sketch_size(ihsbin_ctx* ctx, const ihsbin_matrix* A, const void* B,
  * only columns [0, w) are written. */
 int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U,
                      int64_t w, int64_t ldu, double* W, int64_t ldw);
+
+/* The same product (dense A) with a chosen column tiling, for tuning: prec
+ * IHSBIN_BASIS_F64 or IHSBIN_BASIS_F32 (FP32 matrix cores, FP32 A only), q in
+ * [1, 7] the tile width in 16-column blocks and splits in [1, 256] the split-K
+ * count of W = A^T Y (0 for either: the library's choice, from its tuned
+ * table or its cost model).  Results equal ihsbin_ata_apply's up to the
+ * summation order. */
+int ihsbin_ata_apply_tiled(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U, int64_t w,
+                           int64_t ldu, double* W, int64_t ldw, int32_t prec, int32_t q,
+                           int32_t splits);
 
 /* ----------------------------------------------------------------- serving
  * Independent path builds on one device, run concurrently by worker slots

@@ -338,6 +338,16 @@ class Context:
                                         C.c_void_p(G.data_ptr())))
         return G
 
+    def ata_apply_tiled(self, A, U, prec: str = "f64", q: int = 0, splits: int = 0):
+        """ihsbin_ata_apply_tiled -> W = A^T A U with a chosen tiling (tuning)."""
+        U = U if U.dim() == 2 else U.reshape(-1, 1)
+        W = _torch().empty_like(U)
+        mat = _matrix(A)
+        self._check(L.lib().ihsbin_ata_apply_tiled(
+            self._h, C.byref(mat), C.c_void_p(U.data_ptr()), U.shape[1], U.stride(0),
+            C.c_void_p(W.data_ptr()), W.stride(0), {"f64": 0, "f32": 1}[prec], int(q), int(splits)))
+        return W
+
     def ata_apply(self, A, U):
         """ihsbin_ata_apply -> W = A^T A U (d x w float64)."""
         U = U if U.dim() == 2 else U.reshape(-1, 1)

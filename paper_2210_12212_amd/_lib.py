@@ -28,7 +28,7 @@ EXPORTED = [
     "ihsbin_server_create", "ihsbin_server_submit", "ihsbin_server_wait",
     "ihsbin_server_get_stats", "ihsbin_server_last_error", "ihsbin_server_destroy",
     "ihsbin_sketch_indices_host", "ihsbin_sketch_indices_device", "ihsbin_csr_transpose",
-    "ihsbin_path_eval_noalloc", "ihsbin_path_build_batch",
+    "ihsbin_path_eval_noalloc", "ihsbin_path_build_batch", "ihsbin_ata_apply_tiled",
 ]
 
 
@@ -59,7 +59,8 @@ class Opts(C.Structure):
                 ("lanczos_steps", C.c_int32), ("timing", C.c_int32),
                 ("taus", C.POINTER(C.c_double)), ("gram_prec", C.c_int32),
                 ("alg4", C.POINTER(Alg4Opts)), ("sketch_prec", C.c_int32),
-                ("sigma_d2", C.c_double), ("basis_prec", C.c_int32), ("f32_switch", C.c_double)]
+                ("sigma_d2", C.c_double), ("basis_prec", C.c_int32), ("f32_switch", C.c_double),
+                ("graph_steps", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -141,6 +142,8 @@ def _declare(lib):
         "ihsbin_precond_factor": (C.c_int, [vp, vp, i64, i64, pd, i32, vp, vp]),
         "ihsbin_ata_apply": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64]),
         "ihsbin_gram": (C.c_int, [vp, vp, i64, i64, i32, vp]),
+        "ihsbin_ata_apply_tiled": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64, i32,
+                                             i32, i32]),
         "ihsbin_alg4_opts_default": (None, [C.POINTER(Alg4Opts)]),
         "ihsbin_build_footprint": (C.c_int, [C.POINTER(Matrix), i64, dbl, dbl, C.POINTER(Opts),
                                              C.POINTER(C.c_int64)]),

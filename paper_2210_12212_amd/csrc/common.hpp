@@ -191,6 +191,9 @@ struct Ctx {
   Pool pool;     // build-local buffers (declared first: outlives the workspaces below)
   // scratch shared by the step kernels of one call
   DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status, ws_f32;
+  // a private stream (default priority) that work is captured on into HIP
+  // graphs, created on first use and destroyed with the context
+  hipStream_t capture_stream = nullptr;
   // every buffer of the context is used on `stream` only
   void bind() {
     pool.bind(stream, &mem);

@@ -96,13 +96,22 @@ int64_t padded_width(int64_t w);
 // scaled by a power of two into range and rounded to FP32, Y = A U kept in
 // FP32, A^T Y summed in FP32 over at most 16384 rows and in FP64 across them,
 // then scaled back).
+// A forced tiling for tuning: q (16q-column tiles) and the split-K count of
+// W = A^T Y (0: the library's choice).
+struct TileForce {
+  int q = 0, splits = 0;
+};
 int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
-                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0, bool f32 = false);
+                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax = 0, bool f32 = false,
+                  const TileForce* force = nullptr);
 // Many problems of one shape (dense, problem p's matrix at A.vals + p *
 // strideA elements): W = A_p^T A_p U for `groups` groups of P column blocks of
 // `per` columns each (group g, problem p: columns (g P + p) per ...).  U must
 // keep ata_batch_slack(per) readable columns after its last block.
 int64_t ata_batch_slack(int64_t per);
+// Grow the workspaces of ata_apply_batch to what `per` columns per problem need
+// (so that calls captured into a graph allocate nothing).
+void ata_batch_reserve(Ctx& ctx, const MatView& A, int P, int64_t per);
 void ata_apply_batch(Ctx& ctx, const MatView& A, int64_t strideA, int P, int groups, int64_t per,
                      const double* U, int64_t ldu, double* W, int64_t ldw);
 // C_p = A_p^T B_p for P problems (B_p at B + p * strideB elements), C: P blocks

@@ -18,6 +18,40 @@ namespace ihs {
 
 static constexpr size_t kYBudget = size_t(6) << 30;  // bytes for the n x w intermediate
 
+// Tuned column tilings (autotune.py); see choose_tiles.
+struct TunedTile {
+  int64_t n, d;
+  int32_t dtype, prec, nb, q, splits;
+};
+#include "tuned_tiles.inc"
+
+// Column tiling and split-K count of the W = A^T Y product for a chunk of cw
+// columns: forced (tuning calls), else the tuned table for this shape and
+// width class, else the cost model of pick_col_tiles / pick_splits_cols.
+static void choose_tiles(const MatView& A, bool f32, int64_t cw, const TileForce* force,
+                         ColTiles& ct, int& splits) {
+  const int64_t nb = cdiv(cw, 16);
+  ct = pick_col_tiles(cw);
+  splits = pick_splits_cols(A.d, ct, A.n, 1024);
+  bool tuned = false;
+  for (int i = 0; i < kNumTunedTiles && !(force && force->q > 0); ++i) {
+    const TunedTile& e = kTunedTiles[i];
+    if (e.n == A.n && e.d == A.d && e.dtype == A.dtype && e.prec == (f32 ? 1 : 0) && e.nb == nb &&
+        e.q >= 1 && e.q <= kColTileMaxQ) {
+      ct = ColTiles{(int)cdiv(nb, e.q), e.q};
+      splits = e.splits > 0 ? e.splits : pick_splits_cols(A.d, ct, A.n, 1024);
+      tuned = true;
+      break;
+    }
+  }
+  if (force && force->q > 0) {
+    ct = ColTiles{(int)cdiv(nb, force->q), std::min(force->q, kColTileMaxQ)};
+    if (!tuned) splits = pick_splits_cols(A.d, ct, A.n, 1024);
+  }
+  if (force && force->splits > 0) splits = force->splits;
+  if (splits > 256) splits = 256;
+}
+
 template <typename T>
 __global__ void csr_spmm_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                 const T* __restrict__ v, int64_t n, const double* __restrict__ U,
@@ -295,7 +329,7 @@ __global__ void unscale_cols_kernel(double* __restrict__ W, int64_t ldw, int64_t
 
 // The FP32 form of the pair: Y32 = A U32, W = A^T Y32 (split-K partials in FP64).
 static void ata_f32(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
-                    int64_t ldw, std::vector<hipEvent_t>* ev) {
+                    int64_t ldw, std::vector<hipEvent_t>* ev, const TileForce* force) {
   hipStream_t st = ctx.stream;
   auto mark = [&]() {
     if (!ev) return;
@@ -308,7 +342,9 @@ static void ata_f32(Ctx& ctx, const MatView& A, const double* U, int64_t w, int6
   if (wc >= 64) wc = (wc / 64) * 64;
   if (wc > w) wc = w;
   if (wc < 1) wc = 1;
-  const ColTiles ct_full = pick_col_tiles(wc);
+  ColTiles ct_full;
+  int sp_full = 1;
+  choose_tiles(A, true, wc, force, ct_full, sp_full);
   const int64_t span_max = (int64_t)ct_full.c * 16 * ct_full.q;
   const int64_t ycap = std::max(padded_width(wc), span_max);
   float* Y = static_cast<float*>(ctx.ws_y.ensure(sizeof(float) * (size_t)A.n * (size_t)ycap));
@@ -318,8 +354,10 @@ static void ata_f32(Ctx& ctx, const MatView& A, const double* U, int64_t w, int6
   double* scale = reinterpret_cast<double*>(f32_base + u32_bytes);
   for (int64_t c0 = 0; c0 < w; c0 += wc) {
     const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
-    const ColTiles ct = pick_col_tiles(cw);
-    const int64_t span = (int64_t)ct.c * 16 * ct.q;
+    ColTiles ct;
+    int tuned_splits = 1;
+    choose_tiles(A, true, cw, force, ct, tuned_splits);
+    const int64_t span = std::min<int64_t>((int64_t)ct.c * 16 * ct.q, ycap);
     hipLaunchKernelGGL(col_pow2_scale_kernel, dim3((unsigned)cdiv(cw, 256)), dim3(256), 0, st,
                        U + c0, ldu, A.d, cw, scale);
     IHS_CHECK_LAUNCH();
@@ -343,8 +381,8 @@ static void ata_f32(Ctx& ctx, const MatView& A, const double* U, int64_t w, int6
     gemm_cols_f32(g1, false, true, ct, st);
     mark();
     // FP32 sums over at most 16384 rows each, FP64 across them
-    const int splits = (int)std::min<int64_t>(
-        256, std::max<int64_t>(pick_splits_cols(A.d, ct, A.n, 1024), cdiv(A.n, 16384)));
+    const int splits =
+        (int)std::min<int64_t>(256, std::max<int64_t>(tuned_splits, cdiv(A.n, 16384)));
     Gemm g2;
     g2.M = A.d;
     g2.N = cw;
@@ -379,7 +417,8 @@ static void ata_f32(Ctx& ctx, const MatView& A, const double* U, int64_t w, int6
 }
 
 int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_t ldu, double* W,
-                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax, bool f32) {
+                  int64_t ldw, std::vector<hipEvent_t>* ev, int64_t wmax, bool f32,
+                  const TileForce* force) {
   hipStream_t st = ctx.stream;
   if (w <= 0) return 0;
   const bool dense = A.format == IHSBIN_DENSE;
@@ -390,7 +429,7 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
     if (wc < 1) wc = 1;
     ctx.bytes_moved += 2.0 * matrix_bytes(A) * (double)cdiv(w, wc) +
                        (double)w * (8.0 * (double)A.n + 12.0 * (double)A.d);
-    ata_f32(ctx, A, U, w, ldu, W, ldw, ev);
+    ata_f32(ctx, A, U, w, ldu, W, ldw, ev, force);
     return w;
   }
   // U holds `readable` columns (w unless the caller sized it wider): column
@@ -414,7 +453,9 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
                      8.0 * (double)w * (2.0 * (double)A.n + 2.0 * (double)A.d);
   for (int64_t c0 = 0; c0 < w; c0 += wc) {
     const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
-    const ColTiles ct = pick_col_tiles(cw);
+    ColTiles ct;
+    int tuned_splits = 1;
+    choose_tiles(A, false, cw, force, ct, tuned_splits);
     const int64_t span = (int64_t)ct.c * 16 * ct.q;  // columns the tiles cover
     int64_t nread = readable - c0;
     if (nread > span) nread = span;
@@ -439,7 +480,7 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
     if (dense) {
       // Y columns [cw, span) are never written; the W tiles read them (their
       // results land in columns >= cw, which are not stored)
-      const int splits = pick_splits_cols(A.d, ct, A.n, 1024);
+      const int splits = tuned_splits;
       Gemm g2;
       g2.M = A.d;
       g2.N = cw;
@@ -486,19 +527,50 @@ int64_t ata_batch_slack(int64_t per) {
   return (int64_t)ct.c * 16 * ct.q - per;
 }
 
+// Workspace of one batched product: the n x ycap intermediates of pc
+// problems per launch, and the split-K partials of the widest launch.
+struct BatchPlan {
+  ColTiles ct;
+  int64_t span, ycap, pc;
+  size_t y_bytes, part_bytes;
+};
+static BatchPlan batch_plan(const MatView& A, int P, int64_t per) {
+  BatchPlan b;
+  b.ct = pick_col_tiles(per);
+  b.span = (int64_t)b.ct.c * 16 * b.ct.q;
+  b.ycap = std::max(padded_width(per), b.span);
+  // problems per launch so that their n x ycap intermediates fit the budget
+  b.pc = (int64_t)(kYBudget / (sizeof(double) * (size_t)A.n * (size_t)b.ycap));
+  b.pc = std::max<int64_t>(1, std::min<int64_t>(b.pc, P));
+  b.y_bytes = sizeof(double) * (size_t)b.pc * (size_t)A.n * (size_t)b.ycap;
+  b.part_bytes = 0;
+  for (int64_t p0 = 0; p0 < P; p0 += b.pc) {
+    const int64_t nb = std::min<int64_t>(b.pc, P - p0);
+    const int splits = pick_splits_cols(A.d, b.ct, A.n, std::max<int64_t>(1, 1024 / nb));
+    if (splits > 1)
+      b.part_bytes = std::max(b.part_bytes, sizeof(double) * (size_t)splits * (size_t)nb *
+                                                (size_t)A.d * (size_t)per);
+  }
+  return b;
+}
+
+void ata_batch_reserve(Ctx& ctx, const MatView& A, int P, int64_t per) {
+  const BatchPlan b = batch_plan(A, P, per);
+  ctx.ws_y.ensure(b.y_bytes);
+  if (b.part_bytes) ctx.ws_part.ensure(b.part_bytes);
+}
+
 void ata_apply_batch(Ctx& ctx, const MatView& A, int64_t strideA, int P, int groups, int64_t per,
                      const double* U, int64_t ldu, double* W, int64_t ldw) {
   hipStream_t st = ctx.stream;
   if (per <= 0 || P <= 0 || groups <= 0) return;
   if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "batched products need dense matrices");
-  const ColTiles ct = pick_col_tiles(per);
-  const int64_t span = (int64_t)ct.c * 16 * ct.q;
-  const int64_t ycap = std::max(padded_width(per), span);
-  // problems per launch so that their n x ycap intermediates fit the budget
-  int64_t pc = (int64_t)(kYBudget / (sizeof(double) * (size_t)A.n * (size_t)ycap));
-  pc = std::max<int64_t>(1, std::min<int64_t>(pc, P));
-  double* Y = static_cast<double*>(
-      ctx.ws_y.ensure(sizeof(double) * (size_t)pc * (size_t)A.n * (size_t)ycap));
+  const BatchPlan bp = batch_plan(A, P, per);
+  const ColTiles ct = bp.ct;
+  const int64_t span = bp.span;
+  const int64_t ycap = bp.ycap;
+  const int64_t pc = bp.pc;
+  double* Y = static_cast<double*>(ctx.ws_y.ensure(bp.y_bytes));
   const DT ta = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
   const size_t es = A.dtype == IHSBIN_F32 ? 4 : 8;
   ctx.bytes_moved += (double)groups * (double)P *

@@ -292,11 +292,22 @@ static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<do
 // Z = P R for every active position: P_a = Linv_{ids[a]}^T Linv_{ids[a]}.
 // Each product reads a whole triangular factor for a few columns, so it is
 // bound by that read: K is split until ~2048 workgroups stream the factors.
-static void apply_p(Ctx& c, const double* Linv_all, const int32_t* ids_dev, int na, int64_t d,
-                    int64_t cw, int64_t ld, const double* R, double* T, double* Z) {
+static int apply_p_splits(int na, int64_t d, int64_t cw) {
   const int64_t tiles = (int64_t)na * cdiv(d, 256) * cdiv(cw, cw <= 16 ? 16 : 32);
   int splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, cdiv(2048, tiles)));
   if (d < 1024 || cw > 32) splits = 1;
+  return splits;
+}
+
+// Grow the split-K workspace of apply_p for na positions of cw columns.
+static void apply_p_reserve(Ctx& c, int na, int64_t d, int64_t cw) {
+  const int splits = apply_p_splits(na, d, cw);
+  if (splits > 1) c.ws_part.ensure(sizeof(double) * (size_t)splits * na * (size_t)d * (size_t)cw);
+}
+
+static void apply_p(Ctx& c, const double* Linv_all, const int32_t* ids_dev, int na, int64_t d,
+                    int64_t cw, int64_t ld, const double* R, double* T, double* Z) {
+  const int splits = apply_p_splits(na, d, cw);
   double* part = splits > 1 ? static_cast<double*>(c.ws_part.ensure(
                                   sizeof(double) * (size_t)splits * na * (size_t)d * (size_t)cw))
                             : nullptr;
@@ -1385,6 +1396,7 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     fail(IHSBIN_EUNSUP, "batched builds use adaptive_m 0 or 1");
   if (o.taus) fail(IHSBIN_EUNSUP, "batched builds estimate their step sizes");
   if (o.gram_prec != IHSBIN_GRAM_F64) fail(IHSBIN_EUNSUP, "batched builds form the Gram in FP64");
+  if (o.graph_steps < 0 || o.graph_steps > 64) fail(IHSBIN_EINVAL, "graph_steps in [0, 64]");
   if (!(o.sigma_d2 >= 0.0) || !std::isfinite(o.sigma_d2)) fail(IHSBIN_EINVAL, "need sigma_d2 >= 0");
   hipStream_t st = c.stream;
   Timer total;
@@ -1632,20 +1644,71 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
   std::vector<char> passed(nl, 0);
   int steps = 0;
   bool all_passed = false;
-  for (int i = 1; i < kcap; ++i) {
+  double* part = static_cast<double*>(partial_b.ensure(sizeof(double) * 4 * nl * 64));
+  // one basis step of every interval on stream s (the context's own stream
+  // or the capture stream); returns the blocks of partial norms it wrote
+  auto step = [&](int i, hipStream_t s) {
     const int64_t w_old = (int64_t)nl * i * K;
     prod1(Ucur, w_old, wcap, W);
-    launch_form_r(W, Ucur, wcap, d, K, nl, i, tau_dev, ref_dev, R, st);
+    launch_form_r(W, Ucur, wcap, d, K, nl, i, tau_dev, ref_dev, R, s);
     apply_p(c, Linv, ids_dev, nl, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
-    double* part = static_cast<double*>(partial_b.ensure(sizeof(double) * 4 * nl * 64));
     const int nbx = launch_update(Ucur, Z, Unext, wcap, d, K, nl, i, ids_dev, kcap, basis, mlo_dev,
-                                  mhi_dev, part, st);
+                                  mhi_dev, part, s);
+    std::swap(Ucur, Unext);
+    return nbx;
+  };
+  const int gsteps = o.graph_steps;
+  int graphs = 0;
+  for (int i = 1; i < kcap;) {
+    int chunk = 1, nbx = 0;
+    if (gsteps > 0) {
+      // steps i .. i + chunk - 1 captured into one HIP graph and launched as
+      // one unit (the stop test reads the last step's norms): nothing may
+      // allocate while capturing, so the workspaces are grown first
+      chunk = std::min<int>(gsteps, (int)(kcap - i));
+      for (int j = 0; j < chunk; ++j) {
+        ata_batch_reserve(c, A, P, (int64_t)L * (i + j) * K);
+        apply_p_reserve(c, nl, d, (int64_t)(i + j + 1) * K);
+      }
+      if (!c.capture_stream)
+        IHS_HIP(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+      hipEvent_t ready;
+      IHS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      IHS_HIP(hipEventRecord(ready, st));
+      IHS_HIP(hipStreamWaitEvent(c.capture_stream, ready, 0));
+      (void)hipEventDestroy(ready);
+      hipGraph_t graph = nullptr;
+      c.stream = c.capture_stream;
+      IHS_HIP(hipStreamBeginCapture(c.capture_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int j = 0; j < chunk; ++j) nbx = step(i + j, c.capture_stream);
+      } catch (...) {
+        (void)hipStreamEndCapture(c.capture_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        c.stream = st;
+        throw;
+      }
+      const hipError_t ec = hipStreamEndCapture(c.capture_stream, &graph);
+      c.stream = st;
+      IHS_HIP(ec);
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      IHS_HIP(ei);
+      const hipError_t el = hipGraphLaunch(exec, st);
+      if (el == hipSuccess) IHS_HIP(hipStreamSynchronize(st));
+      (void)hipGraphExecDestroy(exec);
+      IHS_HIP(el);
+      ++graphs;
+    } else {
+      nbx = step(i, st);
+    }
     host_part.resize((size_t)4 * nl * nbx);
     IHS_HIP(hipMemcpyAsync(host_part.data(), part, sizeof(double) * host_part.size(),
                            hipMemcpyDeviceToHost, st));
     IHS_HIP(hipStreamSynchronize(st));
-    std::swap(Ucur, Unext);
-    steps = i;
+    i += chunk;
+    steps = i - 1;
     all_passed = true;
     for (int a = 0; a < nl; ++a) {
       double sums[4] = {0, 0, 0, 0};
@@ -1660,8 +1723,9 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
       passed[a] = finite && e_lo <= o.tol && e_hi <= o.tol;
       if (!passed[a]) all_passed = false;
     }
-    if (o.k_fixed > 0 ? i + 1 >= o.k_fixed : all_passed) break;
+    if (o.k_fixed > 0 ? steps + 1 >= o.k_fixed : all_passed) break;
   }
+  if (graphs) logf("batch basis: %d steps in %d HIP graphs", steps, graphs);
   const int k_all = steps + 1;
   int unconverged = 0;
   if (o.k_fixed == 0)
@@ -1827,7 +1891,8 @@ void ihsbin_opts_default(ihsbin_opts* o) {
   o->sketch_prec = IHSBIN_SKETCH_F64;
   o->sigma_d2 = 0.0;
   o->basis_prec = IHSBIN_BASIS_F64;
-  o->f32_switch = 1e-3;
+  o->f32_switch = 1e-2;
+  o->graph_steps = 0;
 }
 
 void ihsbin_alg4_opts_default(ihsbin_alg4_opts* a) {
@@ -1871,6 +1936,10 @@ int ihsbin_destroy(ihsbin_ctx* ctx) {
   try {
     DeviceGuard g(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.capture_stream) {
+      (void)hipStreamSynchronize(ctx->c.capture_stream);
+      (void)hipStreamDestroy(ctx->c.capture_stream);
+    }
     delete ctx;
   } catch (...) {
     delete ctx;
@@ -2160,6 +2229,29 @@ int ihsbin_gram(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d, int32_t
     DeviceGuard g(ctx->c.device);
     if (!SA || !G || m <= 0 || d <= 0) fail(IHSBIN_EINVAL, "bad arguments");
     gram_impl(ctx->c, SA, m, d, G, prec);
+    IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_ata_apply_tiled(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U, int64_t w,
+                           int64_t ldu, double* W, int64_t ldw, int32_t prec, int32_t q,
+                           int32_t splits) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    const MatView v = check_matrix(A);
+    if (v.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "tiled products are dense only");
+    if (!U || !W || w < 1 || ldu < w || ldw < w) fail(IHSBIN_EINVAL, "bad U / W");
+    if (prec != IHSBIN_BASIS_F64 && prec != IHSBIN_BASIS_F32) fail(IHSBIN_EINVAL, "bad prec");
+    if (q < 0 || q > kColTileMaxQ || splits < 0 || splits > 256)
+      fail(IHSBIN_EINVAL, "q in [0, 7], splits in [0, 256]");
+    if (prec == IHSBIN_BASIS_F32 && v.dtype != IHSBIN_F32)
+      fail(IHSBIN_EUNSUP, "FP32 products need an FP32 matrix");
+    TileForce f;
+    f.q = q;
+    f.splits = splits;
+    ata_apply(ctx->c, v, U, w, ldu, W, ldw, nullptr, ldu, prec == IHSBIN_BASIS_F32, &f);
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
     return IHSBIN_OK;
   });

@@ -45,7 +45,7 @@ def test_default_options(lib):
     lib.ihsbin_opts_default(C.byref(o))
     assert o.tol == 1e-8 and o.k_max == 96 and o.centred == 1 and o.adaptive_m == 1
     assert o.lanczos_steps == 12 and not o.taus
-    assert o.basis_prec == 0 and o.f32_switch == 1e-3
+    assert o.basis_prec == 0 and o.f32_switch == 1e-2 and o.graph_steps == 0
 
 
 def test_null_arguments_are_rejected(lib):

@@ -83,3 +83,27 @@ def test_batch_of_one_matches_oracle_and_rejects_csr(torch, ctx):
     with pytest.raises(IhsbinError) as e:
         ctx.path_build_batch(At, Bt, 1e-3, 1e2, adaptive_m=2)
     assert e.value.status == -7
+
+
+@pytest.mark.parametrize("graph_steps", [1, 3, 5])
+def test_batch_basis_steps_in_hip_graphs(torch, ctx, graph_steps):
+    # the basis steps captured into HIP graphs a few at a time give paths of
+    # the same accuracy (the stop test runs once per graph, so the step count
+    # can only grow)
+    P, n, d = 6, 2048, 128
+    As, Bs, At, Bt = stack(torch, P, n, d, 2, seed=500, dtype=np.float32)
+    lams = W.lambda_grid(1e-3, 1e2, 30)
+    p0, r0 = ctx.path_build_batch(At, Bt, 1e-3, 1e2, sketch="gaussian", m=128, seed=2)
+    pg, rg = ctx.path_build_batch(At, Bt, 1e-3, 1e2, sketch="gaussian", m=128, seed=2,
+                                  graph_steps=graph_steps)
+    assert rg["status"] == 0 and rg["k_max_used"] >= r0["k_max_used"]
+    assert rg["k_max_used"] <= r0["k_max_used"] + graph_steps - 1
+    for p in range(P):
+        X = pg[p].eval(lams).cpu().numpy()
+        err = direct.rel_err(X, direct.ridge_path(As[p], Bs[p], lams))
+        assert err.max() <= 1e-6, (p, err.max())
+        if rg["k_max_used"] == r0["k_max_used"]:
+            # same steps in the same order: the same bits
+            assert torch.equal(pg[p].eval(lams), p0[p].eval(lams))
+        pg[p].free()
+        p0[p].free()

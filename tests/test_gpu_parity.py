@@ -402,3 +402,22 @@ def test_path_refined_centres(torch, ctx):
         np.testing.assert_allclose(iv["lam0"], c, rtol=1e-12)
         out[sd2] = rep["k_sum"]
     assert out[s] <= out[0.0], out
+
+
+@pytest.mark.parametrize("prec,q,splits", [("f64", 1, 1), ("f64", 3, 4), ("f64", 7, 16),
+                                           ("f64", 0, 0), ("f32", 2, 8), ("f32", 5, 1),
+                                           ("f32", 0, 0)])
+@pytest.mark.parametrize("w", [5, 40, 161])
+def test_ata_forced_tilings(torch, ctx, prec, q, splits, w):
+    # every tiling the tuner may pick computes the same product: FP64 to
+    # rounding, FP32 (columns scaled by powers of two) to FP32 accuracy; the
+    # columns differ in scale by 2^200 to exercise the scaling
+    r = np.random.default_rng(w + q)
+    A = r.standard_normal((5000, 120)).astype(np.float32)
+    U = r.standard_normal((120, w)) * (2.0 ** (200 * (np.arange(w) % 3 - 1)))[None, :]
+    Wg = ctx.ata_apply_tiled(dev(torch, A), dev(torch, U), prec, q, splits).cpu().numpy()
+    A64 = A.astype(np.float64)
+    ref = A64.T @ (A64 @ U)
+    tol = 1e-12 if prec == "f64" else 2e-5
+    colmax = np.abs(ref).max(axis=0)
+    assert np.all(np.abs(Wg - ref) <= tol * colmax[None, :]), np.abs((Wg - ref) / colmax).max()

@@ -61,12 +61,13 @@ def test_fp32_products_every_step(torch, ctx, problem, K):
     assert err.max() <= 1e-4, err
 
 
-def test_mixed_products_keep_1e6(torch, ctx, problem):
+@pytest.mark.parametrize("switch", [1e-3, 1e-2])
+def test_mixed_products_keep_1e6(torch, ctx, problem, switch):
     p, ref = problem
     X64, rep64 = ctx.solve_path(dev(torch, p.A), dev(torch, p.B), p.lambdas, sketch="srht", m=1024,
                                 seed=3, tol=1e-7, timing=1)
     X, rep = ctx.solve_path(dev(torch, p.A), dev(torch, p.B), p.lambdas, sketch="srht", m=1024,
-                            seed=3, tol=1e-7, basis_prec=2, f32_switch=1e-3, timing=1)
+                            seed=3, tol=1e-7, basis_prec=2, f32_switch=switch, timing=1)
     e64 = direct.rel_err(X64.cpu().numpy(), ref)
     err = direct.rel_err(X.cpu().numpy(), ref)
     print(f"mixed: max rel err {err.max():.3e} (FP64 path {e64.max():.3e}), "
