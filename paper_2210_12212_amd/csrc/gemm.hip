@@ -247,12 +247,23 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
   const int wm = (wave % WM) * (BM / WM);
   const int wn = (wave / WM) * (BN / WN);
 
-  // XCD-aware tile order
+  // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+  // XCDs, so the linear id is remapped to give each XCD a contiguous range;
+  // within (bz fixed) the range is walked in groups of kGroupM row tiles, all
+  // of a group's row tiles for one column tile before the next column tile,
+  // so the tiles resident on an XCD at a time share both their A row panels
+  // and their B column panels in its L2.
+  constexpr unsigned kGroupM = 8;
   const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
   const unsigned total = gx * gy * gz;
   unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
   if ((total & 7u) == 0) lin = (lin & 7u) * (total >> 3) + (lin >> 3);
-  const unsigned bx = lin % gx, by = (lin / gx) % gy, bz = lin / (gx * gy);
+  const unsigned bz = lin / (gx * gy);
+  const unsigned in_z = lin - bz * (gx * gy);
+  const unsigned first_by = (in_z / (kGroupM * gx)) * kGroupM;
+  const unsigned gm = gy - first_by < kGroupM ? gy - first_by : kGroupM;
+  const unsigned in_g = in_z - first_by * gx;
+  const unsigned by = first_by + in_g % gm, bx = in_g / gm;
 
   const int z = (int)bz;
   const int bb = z / g.splits;
