@@ -43,8 +43,6 @@ HBM_PEAK = 8.0e12          # bytes/s
 # of the GEMM source they were measured on.  When that source has changed
 # since (or for another workload) the figure is stale and reported as null.
 TRAFFIC_PROFILES = {
-    "dense_exp300_131072x2048": os.path.join(ROOT, "profiles",
-                                             "gemm_ata_traffic_dense_131072x2048.md"),
     "dense_invsqrt_262144x4096_k64": os.path.join(ROOT, "profiles",
                                                   "gemm_ata_traffic_dense_262144x4096_k64.md"),
 }
@@ -52,6 +50,9 @@ DEFAULT_WORKLOAD = "dense_invsqrt_262144x4096_k64"
 # the arithmetic of the Gaussian sketch product per workload when not given:
 # the matrix-valued workload is specified with its sketch on the BF16 matrix cores
 SKETCH_PREC_DEFAULT = {"dense_invsqrt_262144x4096_k64": "bf16"}
+# the sketched Gram on the BF16 matrix cores where the 2 m d^2 Gram is a large
+# share of the path (d = 8192: 966 -> 642 ms per path, the same error)
+GRAM_PREC_DEFAULT = {"csr_zipf_1048576x8192": "bf16x3"}
 GEMM_SOURCE = os.path.join(ROOT, "paper_2210_12212_amd", "csrc", "gemm.hip")
 
 
@@ -363,7 +364,7 @@ def serve_main(args, torch, W):
         "server": st,
         "max_rel_err_sampled": errs,
         "higher_is_better": True,
-        "dtype": "f64" if args.serve_sketch_prec == "f64" and args.gram_prec == "f64" else
+        "dtype": "f64" if args.serve_sketch_prec == "f64" and (args.gram_prec or "f64") == "f64" else
                  "f64+bf16",
         "data": "synthetic",
         "config": {"workload": "small_2048x256_burst" if args.serve_small else "serving_mix",
@@ -390,8 +391,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--rate-target", type=float, default=0.5)
     ap.add_argument("--lanczos-steps", type=int, default=4)
-    ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default="f64",
-                    help="sketched Gram precision (the factor and the recursion stay FP64)")
+    ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default=None,
+                    help="sketched Gram precision (the factor and the recursion stay FP64); "
+                         "default bf16x3 for the CSR workload, else f64")
     ap.add_argument("--sketch-prec", choices=("f64", "bf16"), default=None,
                     help="arithmetic of the Gaussian sketch product (other sketches ignore it); "
                          "default bf16 for the matrix-valued workload, else f64")
@@ -467,6 +469,8 @@ def main():
 
     if args.sketch_prec is None:
         args.sketch_prec = SKETCH_PREC_DEFAULT.get(args.workload, "f64")
+    if args.gram_prec is None:
+        args.gram_prec = GRAM_PREC_DEFAULT.get(args.workload, "f64")
     t0 = time.time()
     p = W.make(args.workload, n=args.n)
     log(f"[bench] workload {p.name}: n={p.n} d={p.d} K={p.B.shape[1]} T={len(p.lambdas)} "

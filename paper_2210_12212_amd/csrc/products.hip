@@ -290,17 +290,46 @@ int64_t padded_width(int64_t w) {
 // tau (lam - lam0) shrink accordingly), far beyond the FP32 range for small
 // lam0 and large j.  Scaling by a power of two is exact, so each column keeps
 // its full FP32 relative precision; the product is linear per column and is
-// scaled back exactly.  scale[c] = 2^-e (1 for a zero column).
-__global__ void col_pow2_scale_kernel(const double* __restrict__ U, int64_t ldu, int64_t d,
-                                      int64_t w, double* __restrict__ scale) {
+// scaled back exactly.  Two passes: the largest binary exponent of every
+// column (64 columns by 256 rows per workgroup, combined with an integer
+// atomic maximum, which does not depend on order), then scale[c] = 2^-e
+// (1 for a zero column).
+constexpr int kNoExp = -2147483647;
+
+__global__ void col_exp_init_kernel(int* __restrict__ ex, int64_t w) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < w;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    double mx = 0.0;
-    for (int64_t r = 0; r < d; ++r) mx = fmax(mx, fabs(U[r * ldu + c]));
-    int e = 0;
-    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
-    scale[c] = ldexp(1.0, -e);
+       c += (int64_t)gridDim.x * blockDim.x)
+    ex[c] = kNoExp;
+}
+
+__global__ __launch_bounds__(256) void col_exp_max_kernel(const double* __restrict__ U, int64_t ldu,
+                                                          int64_t d, int64_t w,
+                                                          int* __restrict__ ex) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t r0 = (int64_t)blockIdx.y * 256;
+  double mx = 0.0;
+  if (c < w) {
+    const int64_t r1 = r0 + 256 < d ? r0 + 256 : d;
+    for (int64_t r = r0 + wave; r < r1; r += 4) mx = fmax(mx, fabs(U[r * ldu + c]));
   }
+  red[wave][lane] = mx;
+  __syncthreads();
+  if (wave == 0 && c < w) {
+    mx = fmax(fmax(red[0][lane], red[1][lane]), fmax(red[2][lane], red[3][lane]));
+    if (mx > 0.0 && isfinite(mx)) {
+      int e = 0;
+      frexp(mx, &e);
+      atomicMax(ex + c, e);
+    }
+  }
+}
+
+__global__ void col_scale_kernel(const int* __restrict__ ex, int64_t w, double* __restrict__ scale) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < w;
+       c += (int64_t)gridDim.x * blockDim.x)
+    scale[c] = ex[c] == kNoExp ? 1.0 : ldexp(1.0, -ex[c]);
 }
 
 // U32 (d x span, row stride span) = U columns [0, w) times scale, rounded to
@@ -349,17 +378,26 @@ static void ata_f32(Ctx& ctx, const MatView& A, const double* U, int64_t w, int6
   const int64_t ycap = std::max(padded_width(wc), span_max);
   float* Y = static_cast<float*>(ctx.ws_y.ensure(sizeof(float) * (size_t)A.n * (size_t)ycap));
   const size_t u32_bytes = ((sizeof(float) * (size_t)A.d * (size_t)ycap + 255) / 256) * 256;
-  char* f32_base = static_cast<char*>(ctx.ws_f32.ensure(u32_bytes + sizeof(double) * (size_t)ycap));
+  const size_t sc_bytes = ((sizeof(double) * (size_t)ycap + 255) / 256) * 256;
+  char* f32_base = static_cast<char*>(
+      ctx.ws_f32.ensure(u32_bytes + sc_bytes + sizeof(int) * (size_t)ycap));
   float* U32 = reinterpret_cast<float*>(f32_base);
   double* scale = reinterpret_cast<double*>(f32_base + u32_bytes);
+  int* ex = reinterpret_cast<int*>(f32_base + u32_bytes + sc_bytes);
   for (int64_t c0 = 0; c0 < w; c0 += wc) {
     const int64_t cw = (w - c0) < wc ? (w - c0) : wc;
     ColTiles ct;
     int tuned_splits = 1;
     choose_tiles(A, true, cw, force, ct, tuned_splits);
     const int64_t span = std::min<int64_t>((int64_t)ct.c * 16 * ct.q, ycap);
-    hipLaunchKernelGGL(col_pow2_scale_kernel, dim3((unsigned)cdiv(cw, 256)), dim3(256), 0, st,
-                       U + c0, ldu, A.d, cw, scale);
+    hipLaunchKernelGGL(col_exp_init_kernel, dim3((unsigned)cdiv(cw, 256)), dim3(256), 0, st, ex, cw);
+    IHS_CHECK_LAUNCH();
+    if (cdiv(A.d, 256) > 65535) fail(IHSBIN_EUNSUP, "FP32 products: d too large");
+    hipLaunchKernelGGL(col_exp_max_kernel, dim3((unsigned)cdiv(cw, 64), (unsigned)cdiv(A.d, 256)),
+                       dim3(256), 0, st, U + c0, ldu, A.d, cw, ex);
+    IHS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(col_scale_kernel, dim3((unsigned)cdiv(cw, 256)), dim3(256), 0, st, ex, cw,
+                       scale);
     IHS_CHECK_LAUNCH();
     int64_t blocks = cdiv(A.d * span, 256);
     if (blocks > 16384) blocks = 16384;
