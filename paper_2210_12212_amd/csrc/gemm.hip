@@ -419,6 +419,22 @@ static void launch_cols_f32(const Gemm& g, int q, hipStream_t s) {
   IHS_CHECK_LAUNCH();
 }
 
+// 256-row tiles with eight waves for tall products: each operand panel is
+// re-read by half as many tiles as with 128 rows.
+template <bool TRA, typename TC>
+static void launch_cols_f32_tall(const Gemm& g, int q, hipStream_t s) {
+  switch (q) {
+    case 1: launch_one<float, float, TRA, false, 256, 16, 32, 8, 1, 512, float, TC>(g, s); break;
+    case 2: launch_one<float, float, TRA, false, 256, 32, 16, 8, 1, 512, float, TC>(g, s); break;
+    case 3: launch_one<float, float, TRA, false, 256, 48, 16, 8, 1, 512, float, TC>(g, s); break;
+    case 4: launch_one<float, float, TRA, false, 256, 64, 16, 8, 1, 512, float, TC>(g, s); break;
+    case 5: launch_one<float, float, TRA, false, 256, 80, 16, 8, 1, 512, float, TC>(g, s); break;
+    case 6: launch_one<float, float, TRA, false, 256, 96, 16, 8, 1, 512, float, TC>(g, s); break;
+    default: launch_one<float, float, TRA, false, 256, 112, 16, 8, 1, 512, float, TC>(g, s); break;
+  }
+  IHS_CHECK_LAUNCH();
+}
+
 void gemm_cols_f32(const Gemm& g_in, bool transA, bool c_f32, const ColTiles& ct, hipStream_t s) {
   if (g_in.M <= 0 || g_in.N <= 0) return;
   if (ct.q < 1 || ct.q > kColTileMaxQ || (int64_t)ct.c * 16 * ct.q < g_in.N)
@@ -428,12 +444,23 @@ void gemm_cols_f32(const Gemm& g_in, bool transA, bool c_f32, const ColTiles& ct
   Gemm g = g_in;
   g.vec_ok = aligned16(g.A, g.lda, g.strideA, 4) && aligned16(g.B, g.ldb, g.strideB, 4);
   if (g.n_read > (int64_t)ct.c * 16 * ct.q) g.n_read = (int64_t)ct.c * 16 * ct.q;
+  const bool tall = g.M >= 4096 && !g.lower_only && g.tri == 0;
   if (c_f32) {
-    if (transA) launch_cols_f32<true, float>(g, ct.q, s);
-    else launch_cols_f32<false, float>(g, ct.q, s);
+    if (tall) {
+      if (transA) launch_cols_f32_tall<true, float>(g, ct.q, s);
+      else launch_cols_f32_tall<false, float>(g, ct.q, s);
+    } else {
+      if (transA) launch_cols_f32<true, float>(g, ct.q, s);
+      else launch_cols_f32<false, float>(g, ct.q, s);
+    }
   } else {
-    if (transA) launch_cols_f32<true, double>(g, ct.q, s);
-    else launch_cols_f32<false, double>(g, ct.q, s);
+    if (tall) {
+      if (transA) launch_cols_f32_tall<true, double>(g, ct.q, s);
+      else launch_cols_f32_tall<false, double>(g, ct.q, s);
+    } else {
+      if (transA) launch_cols_f32<true, double>(g, ct.q, s);
+      else launch_cols_f32<false, double>(g, ct.q, s);
+    }
   }
 }
 

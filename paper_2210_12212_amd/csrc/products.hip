@@ -52,20 +52,56 @@ static void choose_tiles(const MatView& A, bool f32, int64_t cw, const TileForce
   if (splits > 256) splits = 256;
 }
 
+// Y = A U: one wave per row, lanes over columns of U.  The row's entries (64
+// at a time) are loaded once, one per lane, and broadcast with shuffles, so
+// the loop over entries issues only the loads of U's rows (four in flight);
+// each output sums its entries in stored order.
 template <typename T>
-__global__ void csr_spmm_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                const T* __restrict__ v, int64_t n, const double* __restrict__ U,
-                                int64_t w, int64_t ldu, double* __restrict__ Y, int64_t ldy) {
-  // one wave per row, lanes over columns
+__global__ __launch_bounds__(256) void csr_spmm_kernel(const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       const T* __restrict__ v, int64_t n,
+                                                       const double* __restrict__ U, int64_t w,
+                                                       int64_t ldu, double* __restrict__ Y,
+                                                       int64_t ldy) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = wave; i < n; i += nwaves) {
     const int32_t p0 = rp[i], p1 = rp[i + 1];
-    for (int64_t c = lane; c < w; c += 64) {
+    for (int64_t c0 = 0; c0 < w; c0 += 64) {
+      const int64_t c = c0 + lane;
+      const bool live = c < w;
       double acc = 0.0;
-      for (int32_t p = p0; p < p1; ++p) acc += (double)v[p] * U[(int64_t)ci[p] * ldu + c];
-      Y[i * ldy + c] = acc;
+      for (int32_t q0 = p0; q0 < p1; q0 += 64) {
+        const int cnt = p1 - q0 < 64 ? p1 - q0 : 64;
+        int32_t my_col = 0;
+        double my_val = 0.0;
+        if (lane < cnt) {
+          my_col = ci[q0 + lane];
+          my_val = (double)v[q0 + lane];
+        }
+        int t = 0;
+        for (; t + 4 <= cnt; t += 4) {
+          const int64_t k0 = __shfl(my_col, t), k1 = __shfl(my_col, t + 1),
+                        k2 = __shfl(my_col, t + 2), k3 = __shfl(my_col, t + 3);
+          const double a0 = __shfl(my_val, t), a1 = __shfl(my_val, t + 1),
+                       a2 = __shfl(my_val, t + 2), a3 = __shfl(my_val, t + 3);
+          if (live) {
+            const double u0 = U[k0 * ldu + c], u1 = U[k1 * ldu + c], u2 = U[k2 * ldu + c],
+                         u3 = U[k3 * ldu + c];
+            acc += a0 * u0;
+            acc += a1 * u1;
+            acc += a2 * u2;
+            acc += a3 * u3;
+          }
+        }
+        for (; t < cnt; ++t) {
+          const int64_t k = __shfl(my_col, t);
+          const double a = __shfl(my_val, t);
+          if (live) acc += a * U[k * ldu + c];
+        }
+      }
+      if (live) Y[i * ldy + c] = acc;
     }
   }
 }
