@@ -45,6 +45,8 @@ HBM_PEAK = 8.0e12          # bytes/s
 TRAFFIC_PROFILES = {
     "dense_invsqrt_262144x4096_k64": os.path.join(ROOT, "profiles",
                                                   "gemm_ata_traffic_dense_262144x4096_k64.md"),
+    "csr_zipf_1048576x8192": os.path.join(ROOT, "profiles",
+                                          "csr_products_traffic_csr_1048576x8192.md"),
 }
 DEFAULT_WORKLOAD = "dense_invsqrt_262144x4096_k64"
 # the arithmetic of the Gaussian sketch product per workload when not given:
@@ -53,23 +55,32 @@ SKETCH_PREC_DEFAULT = {"dense_invsqrt_262144x4096_k64": "bf16"}
 # the sketched Gram on the BF16 matrix cores where the 2 m d^2 Gram is a large
 # share of the path (d = 8192: 966 -> 642 ms per path, the same error)
 GRAM_PREC_DEFAULT = {"csr_zipf_1048576x8192": "bf16x3"}
-GEMM_SOURCE = os.path.join(ROOT, "paper_2210_12212_amd", "csrc", "gemm.hip")
+CSRC = os.path.join(ROOT, "paper_2210_12212_amd", "csrc")
 
 
 def recorded_traffic(workload, kernel):
-    """Measured HBM bytes per launch of `kernel`, or None when stale/absent."""
+    """Measured HBM bytes per launch of `kernel`, or None when stale/absent.
+
+    The profile names the kernel sources it was measured on with their sha256
+    ("<file>.hip sha256: <hash>"); a changed source makes the figure stale."""
     import hashlib
     import re
     if workload not in TRAFFIC_PROFILES:
         return None
     try:
         text = open(TRAFFIC_PROFILES[workload]).read()
-        src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
-    m = re.search(r"gemm\.hip sha256: ([0-9a-f]{64})", text)
-    if not m or m.group(1) != src:
+    pinned = re.findall(r"(\w+\.hip) sha256: ([0-9a-f]{64})", text)
+    if not pinned:
         return None
+    for fname, digest in pinned:
+        try:
+            src = hashlib.sha256(open(os.path.join(CSRC, fname), "rb").read()).hexdigest()
+        except OSError:
+            return None
+        if src != digest:
+            return None
     m = re.search(r"bytes per launch %s: ([0-9.eE+]+)" % re.escape(kernel), text)
     return float(m.group(1)) if m else None
 
@@ -119,16 +130,25 @@ def m_sweep(args, torch, W, Context):
         A = torch.from_numpy(p.A).to(dev)
     B = torch.from_numpy(p.B).to(dev)
     sp = args.sketch_prec or SKETCH_PREC_DEFAULT.get(p.name, "f64")
+    gp = args.gram_prec or GRAM_PREC_DEFAULT.get(p.name, "f64")
     base = dict(sketch=p.sketch, seed=p.sketch_seed, tol=args.tol, rate_target=args.rate_target,
-                lanczos_steps=args.lanczos_steps, sketch_prec={"f64": 0, "bf16": 1}[sp], k_max=96)
+                lanczos_steps=args.lanczos_steps, sketch_prec={"f64": 0, "bf16": 1}[sp], k_max=96,
+                gram_prec={"f64": 0, "bf16x3": 1}[gp],
+                basis_prec={"f64": 0, "f32": 1, "mixed": 2}[args.basis_prec],
+                f32_switch=args.f32_switch)
     ev, V = direct.eig_of_gram(direct.gram(p.A))
     ref = direct.solve_from_eig(ev, V, direct.atb(p.A, p.B), p.lambdas)
     log(f"[sweep] {p.name}: oracle ready")
     cap = min(p.n, 32 * p.d)
-    runs = [("spectral", dict(m=p.m, adaptive_m=1)), ("alg4", dict(m=p.m, adaptive_m=2))]
+    runs = [("spectral", dict(m=p.m, adaptive_m=1))]
+    for r in args.sweep_rates:
+        runs.append((f"spectral_rate{r:g}", dict(m=p.m, adaptive_m=1, rate_target=r)))
+    if not args.sweep_no_alg4:
+        runs.append(("alg4", dict(m=p.m, adaptive_m=2)))
     m = p.m
     while m <= cap:
-        runs.append((f"fixed_{m}", dict(m=m, adaptive_m=0)))
+        if m >= args.sweep_m_min:
+            runs.append((f"fixed_{m}", dict(m=m, adaptive_m=0)))
         m *= 2
     ctx = Context(0)
     for name, extra in runs:
@@ -429,6 +449,11 @@ def main():
     ap.add_argument("--batch-size", type=int, default=256)
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="batched builds: basis steps captured per HIP graph (0: none)")
+    ap.add_argument("--sweep-rates", type=lambda v: [float(x) for x in v.split(",") if x],
+                    default=[], help="--m-sweep: also the spectral policy at these rate targets")
+    ap.add_argument("--sweep-m-min", type=int, default=0,
+                    help="--m-sweep: fixed sketch sizes from this one up")
+    ap.add_argument("--sweep-no-alg4", action="store_true")
     ap.add_argument("--m-sweep", action="store_true",
                     help="only compare sketch-size policies (spectral, Algorithm 4, fixed m)")
     ap.add_argument("--ata-sweep", action="store_true",
@@ -537,18 +562,30 @@ def main():
                 "avg_launch_ms": dms / launches, "ata_ms_y": ms_y, "ata_ms_w": ms_w}, dms
 
     if csr:
-        # CSR products: nnz multiply-adds per column, bound by their loads;
-        # algorithmic bytes per launch = A once (values and column indices)
+        # CSR products: 2 nnz w multiply-adds each, bound by their loads.
+        # Algorithmic bytes of a launch of width w: Y = A U reads A (column
+        # index and value, 8 B per entry, plus the row pointers) and U once and
+        # writes Y once (8 n w + 8 d w); W = A^T Y reads the column-major copy
+        # (row index and value, 8 B per entry, plus the column pointers) and Y
+        # once and writes W once.  The summed width follows from the launches'
+        # flop count (4 nnz w each).
         launches = max(1, rep["ata_launches"])
-        dom_ms = max(rep["ata_ms_y"], rep["ata_ms_w"])
-        dom = "csr_spmm_Y_AU" if rep["ata_ms_y"] >= rep["ata_ms_w"] else "csr_spmm_t_W_AtY"
-        abytes = rep["ata_bytes_a"] / launches
+        nnz = int(p.A.col_idx.size)
+        sum_w = rep["ata_flops"] / (4.0 * nnz) if nnz else 0.0
+        vec = 8.0 * (p.n + p.d) * sum_w / launches
+        by = 8.0 * nnz + 4.0 * (p.n + 1) + vec
+        bw = 8.0 * nnz + 4.0 * (p.d + 1) + vec
+        if rep["ata_ms_y"] >= rep["ata_ms_w"]:
+            dom, dom_ms, abytes = "csr_Y_AU", rep["ata_ms_y"], by
+        else:
+            dom, dom_ms, abytes = "csc_gather_W_AtY", rep["ata_ms_w"], bw
         achieved = abytes / (dom_ms / launches * 1e-3) / 1e9 if dom_ms > 0 else 0.0
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 3),
                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                    "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": None,
-                    "bytes_per_launch": abytes, "launches": rep["ata_launches"],
-                    "avg_launch_ms": dom_ms / launches,
+                    "frac": round(achieved * 1e9 / HBM_PEAK, 4),
+                    "traffic": recorded_traffic(p.name, dom) if args.n is None else None,
+                    "bytes_per_launch": abytes, "mean_width": sum_w / launches,
+                    "launches": rep["ata_launches"], "avg_launch_ms": dom_ms / launches,
                     "ata_ms_y": rep["ata_ms_y"], "ata_ms_w": rep["ata_ms_w"]}
     else:
         r64, t64 = _gemm_roofline(rep["ata_ms_y"], rep["ata_ms_w"], rep["ata_flops"],

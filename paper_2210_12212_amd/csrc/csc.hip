@@ -73,6 +73,20 @@ __global__ void chunk_table_kernel(const int32_t* __restrict__ col_chunk, int64_
     for (int32_t t = col_chunk[c]; t < col_chunk[c + 1]; ++t) chunk_col[t] = (int32_t)c;
 }
 
+// key[t] = first row of chunk t, idx[t] = t
+__global__ void chunk_first_row_kernel(const int32_t* __restrict__ col_ptr,
+                                       const int32_t* __restrict__ col_chunk,
+                                       const int32_t* __restrict__ chunk_col,
+                                       const int32_t* __restrict__ row, int64_t nch,
+                                       int32_t* __restrict__ key, int32_t* __restrict__ idx) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nch;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = chunk_col[t];
+    key[t] = row[col_ptr[c] + (int32_t)(t - col_chunk[c]) * kCscChunk];
+    idx[t] = (int32_t)t;
+  }
+}
+
 unsigned grid_for(int64_t count) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 256), 16384));
 }
@@ -93,10 +107,16 @@ int64_t csc_work_bytes(const MatView& A) {
                                            (int32_t*)nullptr, (int)nnz, 0, 32);
   (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (const int32_t*)nullptr,
                                          (int32_t*)nullptr, (int)(d + 1));
-  // kept: col_ptr, col_chunk (d+1 each), row, val (nnz), chunk_col (<= nnz/chunk + d)
+  size_t order_tmp = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, order_tmp, (const int32_t*)nullptr,
+                                           (int32_t*)nullptr, (const int32_t*)nullptr,
+                                           (int32_t*)nullptr, (int)std::max<int64_t>(nnz, 1), 0, 32);
+  // kept: col_ptr, col_chunk (d+1 each), row, val (nnz), chunk_col and order
+  // (<= nnz/chunk + d each)
   // transient: row_of, keys_out, perm in/out (nnz each), counts, sort/scan scratch
-  const int64_t kept = 4 * 2 * (d + 1) + (4 + es) * nnz + 4 * (nnz / kCscChunk + d + 1);
-  const int64_t transient = 4 * 4 * nnz + 4 * (d + 1) + (int64_t)std::max(sort_tmp, scan_tmp);
+  const int64_t kept = 4 * 2 * (d + 1) + (4 + es) * nnz + 2 * 4 * (nnz / kCscChunk + d + 1);
+  const int64_t transient =
+      4 * 4 * nnz + 4 * (d + 1) + (int64_t)std::max(std::max(sort_tmp, scan_tmp), order_tmp);
   return kept + transient + 16 * 256;
 }
 
@@ -116,6 +136,7 @@ void build_csc(const MatView& A, void* work, Csc& out, hipStream_t st) {
   int32_t* row = reinterpret_cast<int32_t*>(take(4 * nnz));
   void* val = take(es * nnz);
   int32_t* chunk_col = reinterpret_cast<int32_t*>(take(4 * (nnz / kCscChunk + d + 1)));
+  int32_t* order = reinterpret_cast<int32_t*>(take(4 * (nnz / kCscChunk + d + 1)));
   int32_t* row_of = reinterpret_cast<int32_t*>(take(4 * nnz));
   int32_t* keys_out = reinterpret_cast<int32_t*>(take(4 * nnz));
   int32_t* perm_in = reinterpret_cast<int32_t*>(take(4 * nnz));
@@ -123,11 +144,14 @@ void build_csc(const MatView& A, void* work, Csc& out, hipStream_t st) {
   int32_t* cnt = reinterpret_cast<int32_t*>(take(4 * (d + 1)));
   int end_bit = 1;
   while ((int64_t(1) << end_bit) < d) ++end_bit;
-  size_t sort_tmp = 0, scan_tmp = 0;
+  size_t sort_tmp = 0, scan_tmp = 0, order_tmp = 0;
   IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, A.col_idx, keys_out, perm_in,
                                              perm_out, (int)nnz, 0, end_bit, st));
   IHS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, cnt, col_chunk, (int)(d + 1), st));
-  void* tmp = take((int64_t)std::max(sort_tmp, scan_tmp));
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, order_tmp, keys_out, perm_in, perm_out,
+                                             order, (int)std::max<int64_t>(nnz, 1), 0, 32, st));
+  const size_t tmp_bytes = std::max(std::max(sort_tmp, scan_tmp), order_tmp);
+  void* tmp = take((int64_t)tmp_bytes);
 
   hipLaunchKernelGGL(row_of_entry_kernel, dim3(grid_for(n)), dim3(256), 0, st, A.row_ptr, n, row_of);
   IHS_CHECK_LAUNCH();
@@ -158,54 +182,90 @@ void build_csc(const MatView& A, void* work, Csc& out, hipStream_t st) {
   int32_t nch = 0;
   IHS_HIP(hipMemcpyAsync(&nch, col_chunk + d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   IHS_HIP(hipStreamSynchronize(st));
+  // processing order of the chunks: by their first row (stable, so ties keep
+  // chunk order).  Chunks that start near each other read nearby rows of the
+  // gathered matrix while they run together; every chunk still writes its
+  // own partial, so the order does not change any result.  The nnz-sized
+  // transient arrays hold the keys (nch <= nnz: every chunk has an entry).
+  if (nch > 0) {
+    int nbits = 1;
+    while ((int64_t(1) << nbits) < n) ++nbits;
+    hipLaunchKernelGGL(chunk_first_row_kernel, dim3(grid_for(nch)), dim3(256), 0, st, col_ptr,
+                       col_chunk, chunk_col, row, (int64_t)nch, row_of, perm_in);
+    IHS_CHECK_LAUNCH();
+    size_t need = 0;
+    IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, row_of, keys_out, perm_in, order,
+                                               (int)nch, 0, nbits, st));
+    if (need > tmp_bytes) fail(IHSBIN_EUNSUP, "CSC copy: chunk sort scratch");
+    bytes = tmp_bytes;
+    IHS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, bytes, row_of, keys_out, perm_in, order,
+                                               (int)nch, 0, nbits, st));
+  }
   out.col_ptr = col_ptr;
   out.col_chunk = col_chunk;
   out.row = row;
   out.val = val;
   out.chunk_col = chunk_col;
+  out.order = order;
   out.nchunks = nch;
 }
 
 // P[t][j] = sum over the entries of chunk t of val * Y[row][j].  Lanes form
 // groups of G = min(64, pow2ceil(w)) columns; the 64 / G groups of a wave take
-// every (64/G)-th entry of the chunk and are added by a fixed butterfly.
+// every (64/G)-th entry of the chunk and are added by a fixed butterfly.  The
+// chunk's (row, val) pairs are loaded 64 at a time, one per lane, and handed
+// to the groups with shuffles, so the loop issues only the loads of Y's rows
+// (kGatherBatch in flight per lane); every lane adds its entries in
+// increasing order.  Waves take the chunks in the order of `order`.
+constexpr int kGatherBatch = 16;
 template <typename T, typename TY>
 __global__ __launch_bounds__(256) void csc_gather_kernel(
     const int32_t* __restrict__ col_ptr, const int32_t* __restrict__ col_chunk,
-    const int32_t* __restrict__ chunk_col, const int32_t* __restrict__ row,
-    const T* __restrict__ val, int64_t nchunks, const TY* __restrict__ Y, int64_t w, int64_t ldy,
-    int G, int strips, double* __restrict__ P) {
+    const int32_t* __restrict__ chunk_col, const int32_t* __restrict__ order,
+    const int32_t* __restrict__ row, const T* __restrict__ val, int64_t nchunks,
+    const TY* __restrict__ Y, int64_t w, int64_t ldy, int G, int strips, double* __restrict__ P) {
   const int lane = threadIdx.x & 63;
   const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (item >= nchunks * strips) return;
-  const int64_t t = item / strips;
-  const int strip = (int)(item - t * strips);
+  const int64_t k = item / strips;
+  const int strip = (int)(item - k * strips);
+  const int64_t t = order ? order[k] : k;
   const int c = chunk_col[t];
   const int32_t q0 = col_ptr[c] + (int32_t)(t - col_chunk[c]) * kCscChunk;
   const int32_t q1 = min(q0 + kCscChunk, col_ptr[c + 1]);
   const int groups = 64 / G;
   const int grp = lane / G, cl = lane - grp * G;
   const int64_t j = (int64_t)strip * G + cl;
+  const bool live = j < w;
+  const int per = G;  // entries of a 64-entry block per group
   double acc = 0.0;
-  if (j < w) {
-    int32_t q = q0 + grp;
-    // four entries in flight per lane
-    for (; q + 3 * groups < q1; q += 4 * groups) {
-      const int32_t r0 = row[q], r1 = row[q + groups], r2 = row[q + 2 * groups],
-                    r3 = row[q + 3 * groups];
-      const double v0 = (double)val[q], v1 = (double)val[q + groups],
-                   v2 = (double)val[q + 2 * groups], v3 = (double)val[q + 3 * groups];
-      const double y0 = (double)Y[(int64_t)r0 * ldy + j], y1 = (double)Y[(int64_t)r1 * ldy + j],
-                   y2 = (double)Y[(int64_t)r2 * ldy + j], y3 = (double)Y[(int64_t)r3 * ldy + j];
-      acc += v0 * y0;
-      acc += v1 * y1;
-      acc += v2 * y2;
-      acc += v3 * y3;
+  for (int32_t b0 = q0; b0 < q1; b0 += 64) {
+    const int cnt = q1 - b0 < 64 ? q1 - b0 : 64;
+    int32_t my_row = 0;
+    double my_val = 0.0;
+    if (lane < cnt) {
+      my_row = row[b0 + lane];
+      my_val = (double)val[b0 + lane];
     }
-    for (; q < q1; q += groups) acc += (double)val[q] * (double)Y[(int64_t)row[q] * ldy + j];
+    // group grp takes block entries grp, grp + groups, grp + 2 groups, ...
+    for (int s0 = 0; s0 < per && s0 * groups < cnt; s0 += kGatherBatch) {
+      double yv[kGatherBatch];
+#pragma unroll
+      for (int u = 0; u < kGatherBatch; ++u) {
+        const int e = (s0 + u) * groups + grp;
+        const int64_t r = __shfl(my_row, e & 63);
+        yv[u] = (live && s0 + u < per && e < cnt) ? (double)Y[r * ldy + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kGatherBatch; ++u) {
+        const int e = (s0 + u) * groups + grp;
+        const double v = __shfl(my_val, e & 63);
+        if (s0 + u < per && e < cnt) acc += v * yv[u];
+      }
+    }
   }
   for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
-  if (grp == 0 && j < w) P[t * w + j] = acc;
+  if (grp == 0 && live) P[t * w + j] = acc;
 }
 
 // W[c][j] = sum of the chunk partials of column c in chunk order (0 if none)
@@ -236,22 +296,22 @@ void launch_csc_atb(const MatView& A, const Csc& csc, const void* Y, bool y_f32,
     const bool af = A.dtype == IHSBIN_F32;
     if (af && y_f32)
       hipLaunchKernelGGL((csc_gather_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
                          static_cast<const float*>(csc.val), csc.nchunks,
                          static_cast<const float*>(Y), w, ldy, G, strips, P);
     else if (af)
       hipLaunchKernelGGL((csc_gather_kernel<float, double>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
                          static_cast<const float*>(csc.val), csc.nchunks,
                          static_cast<const double*>(Y), w, ldy, G, strips, P);
     else if (y_f32)
       hipLaunchKernelGGL((csc_gather_kernel<double, float>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
                          static_cast<const double*>(csc.val), csc.nchunks,
                          static_cast<const float*>(Y), w, ldy, G, strips, P);
     else
       hipLaunchKernelGGL((csc_gather_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.row,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
                          static_cast<const double*>(csc.val), csc.nchunks,
                          static_cast<const double*>(Y), w, ldy, G, strips, P);
     IHS_CHECK_LAUNCH();

@@ -143,13 +143,15 @@ void launch_alg4_init(const double* C, double* X, double* Gr, int64_t count, hip
 // ------------------------------------------------- CSR column-major copy
 // Entries of every column by increasing row (a stable sort by column), cut
 // into chunks of at most 1024 entries: chunks col_chunk[c] .. col_chunk[c+1]
-// belong to column c, chunk_col[t] names the column of chunk t.
+// belong to column c, chunk_col[t] names the column of chunk t, and order
+// lists the chunks by their first row (the order the gathers process them).
 struct Csc {
   const int32_t* col_ptr = nullptr;    // d + 1
   const int32_t* col_chunk = nullptr;  // d + 1
   const int32_t* row = nullptr;        // nnz
   const void* val = nullptr;           // nnz, A's dtype
   const int32_t* chunk_col = nullptr;  // nchunks
+  const int32_t* order = nullptr;      // nchunks
   int64_t nchunks = 0;
 };
 int64_t csc_work_bytes(const MatView& A);

@@ -52,7 +52,7 @@ static void choose_tiles(const MatView& A, bool f32, int64_t cw, const TileForce
   if (splits > 256) splits = 256;
 }
 
-// Y = A U: one wave per row, lanes over columns of U.  The row's entries (64
+// Y = A U (w > 32): one wave per row, lanes over columns of U.  The row's entries (64
 // at a time) are loaded once, one per lane, and broadcast with shuffles, so
 // the loop over entries issues only the loads of U's rows (four in flight);
 // each output sums its entries in stored order.
@@ -106,6 +106,54 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(const int32_t* __restrict
   }
 }
 
+// Y = A U for narrow U (w <= 32): 64 / G rows per wave, G = pow2ceil(w) lanes
+// per row over its columns.  Each group loads its row's entries G at a time
+// (one per lane) and broadcasts them with shuffles; eight loads of U's rows
+// are in flight per lane, and each output sums its entries in stored order
+// (the same sums as csr_spmm_kernel).
+template <typename T>
+__global__ __launch_bounds__(256) void csr_spmm_narrow_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const T* __restrict__ v,
+    int64_t n, const double* __restrict__ U, int64_t w, int64_t ldu, double* __restrict__ Y,
+    int64_t ldy, int G) {
+  constexpr int NB = 8;
+  const int lane = threadIdx.x & 63;
+  const int rows_per_wave = 64 / G;
+  const int grp = lane / G, cl = lane - grp * G;
+  const int64_t i = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * rows_per_wave + grp;
+  const bool rlive = i < n;
+  const bool live = rlive && cl < w;
+  const int32_t p0 = rlive ? rp[i] : 0, p1 = rlive ? rp[i + 1] : 0;
+  int len = p1 - p0;  // the longest row of the wave bounds its (uniform) loop
+  for (int off = 1; off < 64; off <<= 1) len = max(len, __shfl_xor(len, off, 64));
+  double acc = 0.0;
+  for (int q = 0; q < len; q += G) {
+    int32_t my_col = 0;
+    double my_val = 0.0;
+    if (p0 + q + cl < p1) {
+      my_col = ci[p0 + q + cl];
+      my_val = (double)v[p0 + q + cl];
+    }
+    const int cnt = p1 - p0 - q;  // this group's entries left (may be <= 0)
+    for (int t0 = 0; t0 < G && t0 < len - q; t0 += NB) {
+      double uv[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int t = t0 + u;
+        const int64_t k = __shfl(my_col, grp * G + (t < G ? t : 0));
+        uv[u] = (live && t < G && t < cnt) ? U[k * ldu + cl] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int t = t0 + u;
+        const double a = __shfl(my_val, grp * G + (t < G ? t : 0));
+        if (t < G && t < cnt) acc += a * uv[u];
+      }
+    }
+  }
+  if (live) Y[i * ldy + cl] = acc;
+}
+
 template <typename T>
 __global__ void csr_spmm_t_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                   const T* __restrict__ v, int64_t n, const double* __restrict__ Y,
@@ -125,6 +173,22 @@ __global__ void csr_spmm_t_kernel(const int32_t* __restrict__ rp, const int32_t*
 
 void launch_csr_spmm(const MatView& A, const double* U, int64_t w, int64_t ldu, double* Y,
                      int64_t ldy, hipStream_t st) {
+  if (w <= 0 || A.n <= 0) return;
+  if (w <= 32) {
+    int G = 1;
+    while (G < w) G <<= 1;
+    const int64_t waves = cdiv(A.n, 64 / G);
+    const int64_t nblk = cdiv(waves, 4);
+    if (nblk > INT32_MAX) fail(IHSBIN_EUNSUP, "CSR product: too many rows");
+    if (A.dtype == IHSBIN_F32)
+      hipLaunchKernelGGL(csr_spmm_narrow_kernel<float>, dim3((unsigned)nblk), dim3(256), 0, st,
+                         A.row_ptr, A.col_idx, (const float*)A.vals, A.n, U, w, ldu, Y, ldy, G);
+    else
+      hipLaunchKernelGGL(csr_spmm_narrow_kernel<double>, dim3((unsigned)nblk), dim3(256), 0, st,
+                         A.row_ptr, A.col_idx, (const double*)A.vals, A.n, U, w, ldu, Y, ldy, G);
+    IHS_CHECK_LAUNCH();
+    return;
+  }
   int64_t blocks = cdiv(A.n * 64, 256);
   if (blocks > 65536) blocks = 65536;
   if (A.dtype == IHSBIN_F32)
