@@ -18,7 +18,8 @@ void launch_draw_srht(uint64_t seed, int64_t n, int64_t npad, int64_t m, int8_t*
 // S (rows x n, FP64) holding Gaussian rows [r0, r0 + rows) of the m x n sketch.
 void launch_gaussian_fill(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
                           double* S, hipStream_t st);
-// SA += S A for CountSketch / SJLT (SA zeroed by the caller).
+// Y[i] = f * X[i] for i < count.
+void launch_scale_copy(const double* X, int64_t count, double f, double* Y, hipStream_t st);
 void launch_gaussian_fill_t(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
                             double* St, hipStream_t st);
 // SA = S A for CountSketch / SJLT (s blocks), deterministic (bucket-sorted
@@ -74,8 +75,10 @@ void launch_split3_transpose(const void* X, bool f32, int64_t m, int64_t d, int6
 // A is split into three BF16 terms.  FP32 sums over at most kMaxSplitRows
 // rows of A, then FP64.  work: sketch_bf16_work_bytes(m, n, d) bytes.
 int64_t sketch_bf16_work_bytes(int64_t m, int64_t n, int64_t d);
+// Rows [r_begin, m) only (earlier rows of SA are left alone).
 void gaussian_sketch_bf16(const MatView& A, uint64_t seed, int64_t m, double* SA, void* work,
-                          double* part, int64_t part_doubles, hipStream_t st);
+                          double* part, int64_t part_doubles, hipStream_t st,
+                          int64_t r_begin = 0);
 int64_t gaussian_sketch_bf16_part_doubles(int64_t m, int64_t n, int64_t d);
 
 // Dual (n < d) helpers: At = A^T (d x n row-major, A's dtype; dense A only)

@@ -91,6 +91,21 @@ void launch_gaussian_fill(uint64_t seed, int64_t m, int64_t r0, int64_t rows, in
   IHS_CHECK_LAUNCH();
 }
 
+__global__ void scale_copy_kernel(const double* __restrict__ X, int64_t count, double f,
+                                  double* __restrict__ Y) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * blockDim.x)
+    Y[t] = f * X[t];
+}
+
+void launch_scale_copy(const double* X, int64_t count, double f, double* Y, hipStream_t st) {
+  if (count <= 0) return;
+  int64_t blocks = cdiv(count, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(scale_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, count, f, Y);
+  IHS_CHECK_LAUNCH();
+}
+
 // The same draws transposed: St[i][r - r0] = S[r][i] for r0 <= r < r0 + rows
 // (row stride `rows`), the layout a product A^T St gathers from.
 __global__ void gaussian_fill_t_kernel(uint64_t key, int64_t r0, int64_t rows, int64_t n,

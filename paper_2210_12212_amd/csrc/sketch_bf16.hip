@@ -205,7 +205,7 @@ int64_t sketch_bf16_work_bytes(int64_t m, int64_t n, int64_t d) {
 int64_t gaussian_sketch_bf16_part_doubles(int64_t, int64_t, int64_t) { return kPartDoubles; }
 
 void gaussian_sketch_bf16(const MatView& A, uint64_t seed, int64_t m, double* SA, void* work,
-                          double* part, int64_t part_doubles, hipStream_t st) {
+                          double* part, int64_t part_doubles, hipStream_t st, int64_t r_begin) {
   if (A.format != IHSBIN_DENSE) fail(IHSBIN_EUNSUP, "BF16 Gaussian sketch of a CSR matrix");
   const int64_t n = A.n, d = A.d, npad = pad_rows(n);
   char* base = static_cast<char*>(work);
@@ -217,7 +217,7 @@ void gaussian_sketch_bf16(const MatView& A, uint64_t seed, int64_t m, double* SA
   const uint64_t key = stream_key(seed, 3);
   const unsigned nt = (unsigned)cdiv(d, kT);
   if (nt > 65535u) fail(IHSBIN_EUNSUP, "sketch: too many columns");
-  for (int64_t r0 = 0; r0 < m; r0 += rows) {
+  for (int64_t r0 = r_begin; r0 < m; r0 += rows) {
     const int64_t rn = std::min(rows, m - r0);
     {
       const unsigned gx = (unsigned)std::min<int64_t>(cdiv(npad, 256), 64);

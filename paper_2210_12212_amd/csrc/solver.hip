@@ -109,20 +109,25 @@ static int64_t next_pow2(int64_t n) {
 // ------------------------------------------------------------------ sketch
 // reuse_transform: the SRHT transform D-signs + Walsh-Hadamard of A for this
 // seed is still in the context's sketch scratch (only the row sample depends on m).
+// r_begin (Gaussian only): rows [r_begin, m) of SA are formed and earlier
+// rows are left as they are (a Gaussian row depends on its index alone, so
+// a grown sketch keeps the rows already formed, rescaled by the caller).
 static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t m, uint64_t seed,
                               double* SA, bool reuse_transform = false,
-                              int prec = IHSBIN_SKETCH_F64) {
+                              int prec = IHSBIN_SKETCH_F64, int64_t r_begin = 0) {
   hipStream_t st = c.stream;
   if (m <= 0) fail(IHSBIN_EINVAL, "m must be positive");
   if (m > INT32_MAX) fail(IHSBIN_EUNSUP, "m too large");
-  c.bytes_moved += matrix_bytes(A) + 8.0 * (double)m * (double)A.d;
+  if (r_begin < 0 || r_begin >= m || (r_begin > 0 && kind != IHSBIN_GAUSSIAN))
+    fail(IHSBIN_EINVAL, "sketch rows out of range");
+  c.bytes_moved += matrix_bytes(A) + 8.0 * (double)(m - r_begin) * (double)A.d;
   if (prec != IHSBIN_SKETCH_F64 && prec != IHSBIN_SKETCH_BF16)
     fail(IHSBIN_EINVAL, "unknown sketch precision");
   if (kind == IHSBIN_GAUSSIAN && prec == IHSBIN_SKETCH_BF16) {
     void* work = c.ws_sketch.ensure((size_t)sketch_bf16_work_bytes(m, A.n, A.d));
     const int64_t pd = gaussian_sketch_bf16_part_doubles(m, A.n, A.d);
     double* part = static_cast<double*>(c.ws_part.ensure(sizeof(double) * (size_t)pd));
-    gaussian_sketch_bf16(A, seed, m, SA, work, part, pd, st);
+    gaussian_sketch_bf16(A, seed, m, SA, work, part, pd, st, r_begin);
   } else if (kind == IHSBIN_GAUSSIAN && A.format == IHSBIN_CSR) {
     // (SA)^T = A^T S^T, O(m nnz(A)): each chunk of rows of S is drawn
     // transposed (n x rows), gathered through the column-major copy of A in
@@ -141,7 +146,7 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
     double* Wt = static_cast<double*>(c.ws_tmp.ensure(sizeof(double) * (size_t)rows * A.d));
     double* part = static_cast<double*>(c.ws_part.ensure(
         sizeof(double) * (size_t)std::max<int64_t>(1, csc_partial_doubles(*csc, rows))));
-    for (int64_t r0 = 0; r0 < m; r0 += rows) {
+    for (int64_t r0 = r_begin; r0 < m; r0 += rows) {
       const int64_t rn = std::min(rows, m - r0);
       launch_gaussian_fill_t(seed, m, r0, rn, A.n, St, st);
       launch_csc_atb(A, *csc, St, false, rn, rn, part, Wt, rn, st);
@@ -163,7 +168,7 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
     if (rows > m) rows = m;
     double* S = static_cast<double*>(c.ws_sketch.ensure(sizeof(double) * (size_t)rows * A.n));
     const DT tb = A.dtype == IHSBIN_F32 ? DT::F32 : DT::F64;
-    for (int64_t r0 = 0; r0 < m; r0 += rows) {
+    for (int64_t r0 = r_begin; r0 < m; r0 += rows) {
       const int64_t rn = std::min(rows, m - r0);
       launch_gaussian_fill(seed, m, r0, rn, A.n, S, st);
       const int splits = pick_splits(rn, A.d, A.n, 1);
@@ -669,17 +674,35 @@ struct Sketcher {
     if (m % s) m += s - m % s;
     return m;
   }
+  // Rows of a Gaussian sketch already formed (0: none): row r of S depends
+  // on r alone up to the common factor 1 / sqrt(m), so growing m keeps them,
+  // rescaled by sqrt(m_old / m), and draws only the new rows.
+  int64_t gauss_rows = 0;
   void operator()(int64_t mm) {
     const int64_t rows = mm >= A.n ? A.n : mm;
-    double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * A.d));
     if (mm >= A.n) {
+      double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * A.d));
       logf("m=%lld >= n=%lld: exact Hessian (S = I)", (long long)mm, (long long)A.n);
       copy_rows_f64(c, A, SA);
+      gauss_rows = 0;
+    } else if (o.sketch == IHSBIN_GAUSSIAN && gauss_rows > 0 && mm > gauss_rows) {
+      PoolBuf grown(c.pool);
+      double* SA = static_cast<double*>(grown.ensure(sizeof(double) * rows * A.d));
+      launch_scale_copy(static_cast<const double*>(SAb.p), gauss_rows * A.d,
+                        std::sqrt((double)gauss_rows / (double)mm), SA, c.stream);
+      std::swap(SAb.p, grown.p);  // the old rows go back to the pool (stream-ordered)
+      std::swap(SAb.bytes, grown.bytes);
+      logf("m=%lld: keeps the %lld Gaussian rows formed, draws %lld", (long long)mm,
+           (long long)gauss_rows, (long long)(mm - gauss_rows));
+      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, false, o.sketch_prec, gauss_rows);
+      gauss_rows = mm;
     } else {
+      double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * A.d));
       sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT,
                         o.sketch_prec);
+      gauss_rows = o.sketch == IHSBIN_GAUSSIAN ? mm : 0;
     }
-    gram_impl(c, SA, rows, A.d, G, o.gram_prec);
+    gram_impl(c, static_cast<const double*>(SAb.p), rows, A.d, G, o.gram_prec);
     ++trials;
   }
   void release() {

@@ -225,6 +225,31 @@ def test_path_each_sketch_matrix_rhs(torch, ctx, kind):
     _check_path(X.cpu().numpy(), A, B, lams)
 
 
+@pytest.mark.parametrize("prec,fmt", [("f64", "dense"), ("bf16", "dense"), ("f64", "csr")])
+def test_gaussian_growth_keeps_rows(torch, ctx, prec, fmt):
+    # a Gaussian sketch grown by the probes keeps the rows it has formed
+    # (rescaled); the path must equal, up to rounding, the one built with the
+    # final m drawn at once, and both must match the oracle
+    if fmt == "csr":
+        A = W.csr_zipf(6000, 150, 10, seed=41, dtype=np.float32)
+        Ad = csr_dev(torch, A)
+    else:
+        A = W.dense_decay(6000, 150, seed=41, dtype=np.float32)
+        Ad = dev(torch, A)
+    B, _ = W.rhs(A, 2, 0.1, seed=42)
+    lams = W.lambda_grid(1e-3, 1e2, 21)
+    sp = {"f64": 0, "bf16": 1}[prec]
+    X1, r1 = ctx.solve_path(Ad, dev(torch, B), lams, sketch="gaussian", m=16, seed=5,
+                            adaptive_m=1, sketch_prec=sp, rate_target=0.3)
+    assert r1["status"] == 0 and r1["sketch_trials"] >= 2, r1
+    X2, r2 = ctx.solve_path(Ad, dev(torch, B), lams, sketch="gaussian", m=r1["m_used"], seed=5,
+                            adaptive_m=0, sketch_prec=sp, rate_target=0.3)
+    assert r2["status"] == 0 and r2["m_used"] == r1["m_used"], (r1, r2)
+    X1, X2 = X1.cpu().numpy(), X2.cpu().numpy()
+    assert direct.rel_err(X1, X2).max() <= 1e-9
+    _check_path(X1, A, B, lams)
+
+
 def test_path_csr(torch, ctx):
     M = W.csr_zipf(6000, 200, 8, seed=31, dtype=np.float32)
     B, _ = W.rhs(M, 1, 0.1, seed=32)
