@@ -52,9 +52,10 @@ DEFAULT_WORKLOAD = "dense_invsqrt_262144x4096_k64"
 # the arithmetic of the Gaussian sketch product per workload when not given:
 # the matrix-valued workload is specified with its sketch on the BF16 matrix cores
 SKETCH_PREC_DEFAULT = {"dense_invsqrt_262144x4096_k64": "bf16"}
-# the sketched Gram on the BF16 matrix cores where the 2 m d^2 Gram is a large
-# share of the path (d = 8192: 966 -> 642 ms per path, the same error)
-GRAM_PREC_DEFAULT = {"csr_zipf_1048576x8192": "bf16x3"}
+# the sketched Gram on the BF16 matrix cores per workload when not given (none
+# by default: the CSR workload's CountSketch keeps SA sparse and forms its
+# Gram from the entries in FP64, which gram_prec does not change)
+GRAM_PREC_DEFAULT = {}
 CSRC = os.path.join(ROOT, "paper_2210_12212_amd", "csrc")
 
 
@@ -502,6 +503,9 @@ def main():
         f"sketch={p.sketch} m0={p.m} (generated in {time.time() - t0:.1f}s)")
     dev = torch.device("cuda", 0)
     csr = hasattr(p.A, "row_ptr")
+    # CountSketch / SJLT of a CSR matrix with d <= 8192: the library keeps SA
+    # sparse (its Gram from the entries, FP64)
+    sparse_gram = csr and p.sketch in ("countsketch", "sjlt") and p.d <= 8192
     if csr:
         from paper_2210_12212_amd import CsrInput
         A = CsrInput(torch.from_numpy(p.A.row_ptr).to(dev), torch.from_numpy(p.A.col_idx).to(dev),
@@ -686,9 +690,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "+".join(["f64"] + (["f32"] if args.basis_prec != "f64" else []) +
-                          (["bf16"] if args.sketch_prec == "bf16" or args.gram_prec == "bf16x3"
-                           else [])),
+        # arithmetic types the build ran: FP32 products only for dense FP32 A
+        # after the switch, BF16 only where a dense sketch or Gram used it (a
+        # CountSketch of a CSR matrix keeps SA sparse, its Gram in FP64)
+        "dtype": "+".join(["f64"] + (["f32"] if rep.get("ata_f32_launches") else []) +
+                          (["bf16"] if args.sketch_prec == "bf16" or
+                           (args.gram_prec == "bf16x3" and not sparse_gram) else [])),
         "data": "synthetic",
         "config": {"workload": p.name, "n": p.n, "d": p.d, "K": int(p.B.shape[1]), "T": T,
                    "storage": str(p.A.dtype), "sketch": p.sketch, "m0": p.m,

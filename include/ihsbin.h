@@ -401,6 +401,19 @@ int ihsbin_precond_factor(ihsbin_ctx* ctx, const double* SA, int64_t m,
 int ihsbin_gram(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d, int32_t prec,
                 double* G);
 
+/* The sketched Gram G = (SA)^T SA exactly as a path build forms it for a
+ * sketch of m rows (Section 4: the Gram P_S is built from): the sketch
+ * (sketch, sjlt_s, seed, sketch_prec as in ihsbin_opts), then the Gram
+ * (gram_prec).  For CountSketch / SJLT of a CSR matrix with d <= 8192 the
+ * sketch is kept sparse and G is formed from its entries in FP64 (gram_prec
+ * does not apply); m >= n gives G = A^T A.  A: device matrix; G: device d x d
+ * doubles (row-major), of which the lower triangle and the diagonal 64 x 64
+ * tiles are written.  EINVAL on bad arguments (SJLT: sjlt_s must divide m),
+ * EUNSUP as ihsbin_sketch_apply_prec. */
+int ihsbin_sketch_gram(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch, int32_t sjlt_s,
+                       int64_t m, uint64_t seed, int32_t sketch_prec, int32_t gram_prec,
+                       double* G);
+
 /* Adaptive sketch dimension (Section 5.1, Algorithm 4) for the problem at
  * lam (the path's lam_min): runs the search from m0 = opts->m (0: max(16, d / 4),
  * rounded up to a multiple of sjlt_s) with opts->sketch, sjlt_s, seed,

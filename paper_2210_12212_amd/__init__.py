@@ -338,6 +338,21 @@ class Context:
                                         C.c_void_p(G.data_ptr())))
         return G
 
+    def sketch_gram(self, A, sketch: str, m: int, seed: int, sjlt_s: int = 1,
+                    sketch_prec: str = "f64", gram_prec: str = "f64"):
+        """ihsbin_sketch_gram -> G = (SA)^T SA as a path build forms it (d x d
+        float64; lower triangle and the diagonal tiles written)."""
+        torch = _torch()
+        d = A.shape[1]
+        dev = A.vals.device if isinstance(A, CsrInput) else A.device
+        G = torch.zeros((d, d), dtype=torch.float64, device=dev)
+        mat = _matrix(A)
+        self._check(L.lib().ihsbin_sketch_gram(
+            self._h, C.byref(mat), L.SKETCHES[sketch], sjlt_s, m, seed,
+            {"f64": 0, "bf16": 1}[sketch_prec], {"f64": 0, "bf16x3": 1}[gram_prec],
+            C.c_void_p(G.data_ptr())))
+        return G
+
     def ata_apply_tiled(self, A, U, prec: str = "f64", q: int = 0, splits: int = 0):
         """ihsbin_ata_apply_tiled -> W = A^T A U with a chosen tiling (tuning)."""
         U = U if U.dim() == 2 else U.reshape(-1, 1)

@@ -23,7 +23,7 @@ EXPORTED = [
     "ihsbin_path_get_info", "ihsbin_path_intervals", "ihsbin_path_basis", "ihsbin_path_free",
     "ihsbin_solve_path", "ihsbin_sketch_draws", "ihsbin_sketch_apply", "ihsbin_precond_factor",
     "ihsbin_ata_apply",
-    "ihsbin_gram", "ihsbin_alg4_opts_default", "ihsbin_sketch_size",
+    "ihsbin_gram", "ihsbin_sketch_gram", "ihsbin_alg4_opts_default", "ihsbin_sketch_size",
     "ihsbin_build_footprint", "ihsbin_sketch_apply_prec", "ihsbin_path_set_stream", "ihsbin_server_opts_default",
     "ihsbin_server_create", "ihsbin_server_submit", "ihsbin_server_wait",
     "ihsbin_server_get_stats", "ihsbin_server_last_error", "ihsbin_server_destroy",
@@ -142,6 +142,7 @@ def _declare(lib):
         "ihsbin_precond_factor": (C.c_int, [vp, vp, i64, i64, pd, i32, vp, vp]),
         "ihsbin_ata_apply": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64]),
         "ihsbin_gram": (C.c_int, [vp, vp, i64, i64, i32, vp]),
+        "ihsbin_sketch_gram": (C.c_int, [vp, C.POINTER(Matrix), i32, i32, i64, u64, i32, i32, vp]),
         "ihsbin_ata_apply_tiled": (C.c_int, [vp, C.POINTER(Matrix), vp, i64, i64, vp, i64, i32,
                                              i32, i32]),
         "ihsbin_alg4_opts_default": (None, [C.POINTER(Alg4Opts)]),

@@ -27,6 +27,28 @@ void launch_gaussian_fill_t(uint64_t seed, int64_t m, int64_t r0, int64_t rows, 
 int64_t countsketch_work_bytes(const MatView& A, int64_t m, int s);
 void countsketch_apply(const MatView& A, uint64_t seed, int64_t m, int s, double* SA, void* work,
                        hipStream_t st);
+// A sketch held as a CSR matrix (m x d; FP64 values, columns increasing
+// within a row).
+struct SparseRows {
+  int32_t* row_ptr = nullptr;        // m + 1
+  int32_t* col = nullptr;            // nnz
+  double* val = nullptr;             // nnz
+  int64_t m = 0, d = 0, nnz = 0;
+};
+// SA = S A for CountSketch / SJLT of a CSR matrix, kept sparse: the entries
+// of SA are the runs of the bucket-sorted entries of A (the same sums as
+// countsketch_apply).  work: countsketch_sparse_work_bytes; out:
+// countsketch_sparse_out_bytes (holds sa's arrays).  Returns nnz(SA).
+int64_t countsketch_sparse_work_bytes(const MatView& A, int64_t m, int s);
+int64_t countsketch_sparse_out_bytes(const MatView& A, int64_t m, int s);
+int64_t countsketch_apply_sparse(const MatView& A, uint64_t seed, int64_t m, int s, void* work,
+                                 void* out, SparseRows& sa, hipStream_t st);
+// Lower triangle and diagonal 64 x 64 tiles of G = (SA)^T SA (d x d, FP64)
+// for a sparse SA with d <= kSparseGramMaxD: each column c of SA (from its
+// column-major copy, chunked) accumulates row c of G in LDS, entry by entry
+// in row order.  Scratch from ctx's pool; returns when G is written.
+constexpr int64_t kSparseGramMaxD = 8192;
+void sparse_gram(Ctx& ctx, const SparseRows& sa, double* G);
 // Z (npad x d) = D A zero-padded, then the Walsh-Hadamard transform over rows.
 void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, double* Z,
                            hipStream_t st);

@@ -227,6 +227,59 @@ __global__ void countsketch_runs_kernel(const uint64_t* __restrict__ keys,
   }
 }
 
+// flag[q] = 1 where a run of equal keys starts
+__global__ void run_start_kernel(const uint64_t* __restrict__ keys, int64_t count,
+                                 int32_t* __restrict__ flag) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
+       q += (int64_t)gridDim.x * blockDim.x)
+    flag[q] = (q == 0 || keys[q - 1] != keys[q]) ? 1 : 0;
+}
+
+// The runs as a CSR matrix: run j (j = run_idx[q] at its first position q)
+// holds the column key % d and the signed sum of its entries in row order
+// (the same sums as countsketch_runs_kernel); rkey[j] = its key.
+template <typename T>
+__global__ void countsketch_runs_csr_kernel(const uint64_t* __restrict__ keys,
+                                            const int32_t* __restrict__ perm,
+                                            const int32_t* __restrict__ run_idx, int64_t count,
+                                            const T* __restrict__ v,
+                                            const int32_t* __restrict__ row_of,
+                                            const int8_t* __restrict__ sign, int s, double scale,
+                                            int64_t d, uint64_t* __restrict__ rkey,
+                                            int32_t* __restrict__ col, double* __restrict__ val) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[q];
+    if (q > 0 && keys[q - 1] == k) continue;  // not the start of a run
+    double acc = 0.0;
+    for (int64_t r = q; r < count && keys[r] == k; ++r) {
+      const int32_t e = perm[r];
+      const int32_t p = e / s, b = e - p * s;
+      acc += scale * (double)sign[(int64_t)row_of[p] * s + b] * (double)v[p];
+    }
+    const int32_t j = run_idx[q];
+    rkey[j] = k;
+    col[j] = (int32_t)(k % (uint64_t)d);
+    val[j] = acc;
+  }
+}
+
+// row_ptr[b] = first run whose key is >= b d (b = 0..m)
+__global__ void run_row_ptr_kernel(const uint64_t* __restrict__ rkey, int64_t nrun, int64_t m,
+                                   int64_t d, int32_t* __restrict__ row_ptr) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= m;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = (uint64_t)b * (uint64_t)d;
+    int64_t lo = 0, hi = nrun;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (rkey[mid] < key) lo = mid + 1;
+      else hi = mid;
+    }
+    row_ptr[b] = (int32_t)lo;
+  }
+}
+
 __global__ void zero_kernel(double* __restrict__ p, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -337,6 +390,99 @@ void countsketch_apply(const MatView& A, uint64_t seed, int64_t m, int s, double
     hipLaunchKernelGGL(countsketch_runs_kernel<double>, dim3(blocks_for(es)), dim3(256), 0, st, kout,
                        vout, es, (const double*)A.vals, row_of, sg, s, scale, SA);
   IHS_CHECK_LAUNCH();
+}
+
+int64_t countsketch_sparse_work_bytes(const MatView& A, int64_t m, int s) {
+  const int64_t es = A.nnz * s;
+  size_t scan = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                         (int)std::max<int64_t>(es, 1));
+  // the sort's arrays, then the run index (4 es) and its scan scratch
+  return countsketch_work_bytes(A, m, s) + (int64_t)(align256(4 * es) + align256(scan) + 256);
+}
+
+int64_t countsketch_sparse_out_bytes(const MatView& A, int64_t m, int s) {
+  const int64_t es = A.nnz * s;
+  return (int64_t)(align256(4 * (m + 1)) + align256(4 * std::max<int64_t>(es, 1)) +
+                   align256(8 * std::max<int64_t>(es, 1)) + 256);
+}
+
+int64_t countsketch_apply_sparse(const MatView& A, uint64_t seed, int64_t m, int s, void* work,
+                                 void* out, SparseRows& sa, hipStream_t st) {
+  if (A.format != IHSBIN_CSR) fail(IHSBIN_EINVAL, "sparse CountSketch of a dense matrix");
+  const double scale = 1.0 / std::sqrt((double)s);
+  const int64_t ns = A.n * s, es = A.nnz * s;
+  if (ns >= INT32_MAX || es >= INT32_MAX) fail(IHSBIN_EUNSUP, "CountSketch: too many entries");
+  char* p = static_cast<char*>(work);
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += align256(bytes);
+    return r;
+  };
+  char* o = static_cast<char*>(out);
+  sa.row_ptr = reinterpret_cast<int32_t*>(o);
+  o += align256(4 * (m + 1));
+  sa.col = reinterpret_cast<int32_t*>(o);
+  o += align256(4 * std::max<int64_t>(es, 1));
+  sa.val = reinterpret_cast<double*>(o);
+  sa.m = m;
+  sa.d = A.d;
+  int32_t* idx = reinterpret_cast<int32_t*>(take(4 * ns));
+  int8_t* sg = reinterpret_cast<int8_t*>(take(ns));
+  launch_draw_countsketch(seed, A.n, m, s, idx, sg, st);
+  uint64_t* kin = reinterpret_cast<uint64_t*>(take(8 * es));
+  uint64_t* kout = reinterpret_cast<uint64_t*>(take(8 * es));
+  int32_t* vin = reinterpret_cast<int32_t*>(take(4 * es));
+  int32_t* vout = reinterpret_cast<int32_t*>(take(4 * es));
+  int32_t* row_of = reinterpret_cast<int32_t*>(take(4 * A.nnz));
+  const int end_bit = bits_for((uint64_t)m * (uint64_t)A.d);
+  size_t tmp = 0;
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kin, kout, vin, vout, (int)es, 0, end_bit,
+                                             st));
+  void* tw = take(tmp);
+  int32_t* run_idx = reinterpret_cast<int32_t*>(take(4 * es));
+  size_t scan = 0;
+  IHS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan, vin, run_idx,
+                                           (int)std::max<int64_t>(es, 1), st));
+  void* sw = take(scan);
+  if (es == 0) {
+    hipLaunchKernelGGL(run_row_ptr_kernel, dim3(blocks_for(m + 1)), dim3(256), 0, st,
+                       (const uint64_t*)kin, (int64_t)0, m, A.d, sa.row_ptr);
+    IHS_CHECK_LAUNCH();
+    sa.nnz = 0;
+    return 0;
+  }
+  hipLaunchKernelGGL(entry_keys_kernel, dim3(blocks_for(A.n)), dim3(256), 0, st, A.row_ptr,
+                     A.col_idx, A.n, A.d, idx, s, kin, vin);
+  IHS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(row_of_entry_kernel, dim3(blocks_for(A.n)), dim3(256), 0, st, A.row_ptr, A.n,
+                     row_of);
+  IHS_CHECK_LAUNCH();
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(tw, tmp, kin, kout, vin, vout, (int)es, 0, end_bit, st));
+  // vin is free after the sort: it holds the run-start flags
+  hipLaunchKernelGGL(run_start_kernel, dim3(blocks_for(es)), dim3(256), 0, st, kout, es, vin);
+  IHS_CHECK_LAUNCH();
+  IHS_HIP(hipcub::DeviceScan::ExclusiveSum(sw, scan, vin, run_idx, (int)es, st));
+  int32_t last[2] = {0, 0};
+  IHS_HIP(hipMemcpyAsync(&last[0], run_idx + es - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  IHS_HIP(hipMemcpyAsync(&last[1], vin + es - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  // kin is free too: it receives the key of every run
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(countsketch_runs_csr_kernel<float>, dim3(blocks_for(es)), dim3(256), 0, st,
+                       kout, vout, run_idx, es, (const float*)A.vals, row_of, sg, s, scale, A.d,
+                       kin, sa.col, sa.val);
+  else
+    hipLaunchKernelGGL(countsketch_runs_csr_kernel<double>, dim3(blocks_for(es)), dim3(256), 0, st,
+                       kout, vout, run_idx, es, (const double*)A.vals, row_of, sg, s, scale, A.d,
+                       kin, sa.col, sa.val);
+  IHS_CHECK_LAUNCH();
+  IHS_HIP(hipStreamSynchronize(st));
+  const int64_t nrun = (int64_t)last[0] + last[1];
+  hipLaunchKernelGGL(run_row_ptr_kernel, dim3(blocks_for(m + 1)), dim3(256), 0, st,
+                     (const uint64_t*)kin, nrun, m, A.d, sa.row_ptr);
+  IHS_CHECK_LAUNCH();
+  sa.nnz = nrun;
+  return nrun;
 }
 
 // ----------------------------------------------------------------- SRHT

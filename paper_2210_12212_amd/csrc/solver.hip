@@ -678,8 +678,27 @@ struct Sketcher {
   // on r alone up to the common factor 1 / sqrt(m), so growing m keeps them,
   // rescaled by sqrt(m_old / m), and draws only the new rows.
   int64_t gauss_rows = 0;
+  // CountSketch / SJLT of a CSR matrix: SA is kept sparse and its Gram is
+  // formed from its entries (gram_prec does not apply)
+  bool sparse_sketch() const {
+    return A.format == IHSBIN_CSR &&
+           (o.sketch == IHSBIN_COUNTSKETCH || o.sketch == IHSBIN_SJLT) && A.d <= kSparseGramMaxD;
+  }
   void operator()(int64_t mm) {
     const int64_t rows = mm >= A.n ? A.n : mm;
+    if (mm < A.n && sparse_sketch()) {
+      if (mm > INT32_MAX || mm % s) fail(IHSBIN_EINVAL, "sketch size");
+      void* work = c.ws_sketch.ensure((size_t)countsketch_sparse_work_bytes(A, mm, s));
+      void* out = SAb.ensure((size_t)countsketch_sparse_out_bytes(A, mm, s));
+      SparseRows sa;
+      const int64_t nnz_s = countsketch_apply_sparse(A, o.seed, mm, s, work, out, sa, c.stream);
+      c.bytes_moved += matrix_bytes(A) + 12.0 * (double)nnz_s;
+      logf("m=%lld: sparse sketch with %lld entries", (long long)mm, (long long)nnz_s);
+      sparse_gram(c, sa, G);
+      gauss_rows = 0;
+      ++trials;
+      return;
+    }
     if (mm >= A.n) {
       double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * A.d));
       logf("m=%lld >= n=%lld: exact Hessian (S = I)", (long long)mm, (long long)A.n);
@@ -2252,6 +2271,33 @@ int ihsbin_gram(ihsbin_ctx* ctx, const double* SA, int64_t m, int64_t d, int32_t
     DeviceGuard g(ctx->c.device);
     if (!SA || !G || m <= 0 || d <= 0) fail(IHSBIN_EINVAL, "bad arguments");
     gram_impl(ctx->c, SA, m, d, G, prec);
+    IHS_HIP(hipStreamSynchronize(ctx->c.stream));
+    return IHSBIN_OK;
+  });
+}
+
+int ihsbin_sketch_gram(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch, int32_t sjlt_s,
+                       int64_t m, uint64_t seed, int32_t sketch_prec, int32_t gram_prec,
+                       double* G) {
+  if (!ctx) return IHSBIN_EINVAL;
+  return guarded(ctx, [&] {
+    DeviceGuard g(ctx->c.device);
+    const MatView v = check_matrix(A);
+    if (!G || m <= 0) fail(IHSBIN_EINVAL, "bad arguments");
+    if (v.format == IHSBIN_CSR) validate_csr(ctx->c, v);
+    ihsbin_opts o;
+    ihsbin_opts_default(&o);
+    o.sketch = sketch;
+    o.sjlt_s = sjlt_s;
+    o.m = m;
+    o.seed = seed;
+    o.sketch_prec = sketch_prec;
+    o.gram_prec = gram_prec;
+    if (sketch == IHSBIN_SJLT && (sjlt_s < 1 || m % sjlt_s)) fail(IHSBIN_EINVAL, "SJLT needs s | m");
+    Sketcher sk(ctx->c, v, o);
+    sk(m);
+    IHS_HIP(hipMemcpyAsync(G, sk.G, sizeof(double) * (size_t)v.d * (size_t)v.d,
+                           hipMemcpyDeviceToDevice, ctx->c.stream));
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
     return IHSBIN_OK;
   });

@@ -132,6 +132,54 @@ def test_gaussian_sketch_of_csr(torch, ctx, m):
     np.testing.assert_allclose(SA, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
 
 
+# ------------------------------------- Gram of a sparse (CSR) sketch
+def _gram_parts_close(G, ref, d, tol=1e-12):
+    """The lower triangle and the diagonal 64 x 64 tiles of G against ref."""
+    scale = np.abs(ref).max()
+    low = np.tril_indices(d)
+    np.testing.assert_allclose(G[low], ref[low], rtol=tol, atol=tol * scale)
+    for t0 in range(0, d, 64):
+        t1 = min(d, t0 + 64)
+        np.testing.assert_allclose(G[t0:t1, t0:t1], ref[t0:t1, t0:t1], rtol=tol, atol=tol * scale)
+
+
+@pytest.mark.parametrize("kind,n,d,per,m,s", [
+    ("countsketch", 20000, 3000, 9, 4000, 1),   # heavy columns (several chunks), three LDS ranges
+    ("sjlt", 12000, 700, 6, 1200, 3),
+    ("countsketch", 3000, 150, 5, 64, 1),       # m < d: every bucket holds many rows
+])
+def test_sketch_gram_of_csr_is_sparse_and_exact(torch, ctx, kind, n, d, per, m, s):
+    # CountSketch / SJLT of a CSR matrix: the build keeps SA sparse and forms
+    # (SA)^T SA from its entries; it must equal the Gram of the oracle's sketch
+    M = messy_csr(n, d, per, seed=n % 97)
+    G = ctx.sketch_gram(csr_dev(torch, M), kind, m, 123, sjlt_s=s).cpu().numpy()
+    SA = sketch.apply(kind, M, 123, m, s=s)
+    _gram_parts_close(G, SA.T @ SA, d)
+
+
+def test_sketch_gram_dense_matches_gram_of_sketch(torch, ctx):
+    # the dense path of the same call: the Gram of the library's own SA
+    A = W.dense_decay(3000, 200, seed=8, dtype=np.float32)
+    G = ctx.sketch_gram(dev(torch, A), "countsketch", 400, 5).cpu().numpy()
+    SA = sketch.apply("countsketch", A, 5, 400)
+    _gram_parts_close(G, SA.T @ SA, 200)
+
+
+def test_sketch_gram_empty_columns(torch, ctx):
+    # columns of A without entries give zero rows and columns of G
+    M = W.csr_zipf(4000, 300, 4, seed=12, dtype=np.float32)
+    keep = M.col_idx < 250           # columns 250.. have no entries
+    rp = np.concatenate([[0], np.cumsum([keep[M.row_ptr[i]:M.row_ptr[i + 1]].sum()
+                                         for i in range(M.n)])]).astype(np.int32)
+    M2 = W.CsrMatrix(M.n, M.d, rp, M.col_idx[keep].copy(), M.vals[keep].copy())
+    G = ctx.sketch_gram(csr_dev(torch, M2), "countsketch", 500, 9).cpu().numpy()
+    SA = sketch.apply("countsketch", M2, 9, 500)
+    ref = SA.T @ SA
+    _gram_parts_close(G, ref, 300)
+    for c in range(250, 300):        # their rows of the lower triangle are exactly zero
+        assert not G[c, :c + 1].any()
+
+
 # --------------------------------------------------------------- report
 def test_report_estimate_and_bytes(torch, ctx):
     A = W.dense_decay(3000, 100, seed=5, dtype=np.float32)
