@@ -5,9 +5,10 @@
 // factored (and inverted) inside LDS by one workgroup per matrix, the panel
 // below it is multiplied by the inverted block, and the trailing lower
 // triangle is updated with the MFMA GEMM.  All nl matrices advance together,
-// one launch per stage.  The inverse factor L^-1 is then built row block by
-// row block with the same GEMM, so that applying P_S = L^-T L^-1 to many
-// vectors is two triangular matrix products.
+// one launch per stage.  When the inverse factor L^-1 is wanted too (so that
+// applying P_S = L^-T L^-1 to many vectors is two triangular matrix
+// products), both are built together by halves (factor_inverse_batched).
+#include <algorithm>
 #include <cmath>
 #include <utility>
 
@@ -174,7 +175,8 @@ __device__ __forceinline__ void trinv_panel(std::integer_sequence<int, I...>, do
 }  // namespace
 
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, int p,
-                                                         double* dinv, int nblk, int* status) {
+                                                         double* dinv, int nblk, int* status,
+                                                         double* X) {
   constexpr int NB = kNB;
   static_assert(NB == 64, "register layout assumes 64 x 64 blocks and 256 threads");
   __shared__ double colbuf[2][NB];
@@ -221,6 +223,31 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* H, int64_t d, i
     const int c = q + 4 * s;
     Di[r * NB + c] = c <= r ? x[s] : 0.0;
   }
+  if (X) {  // the inverse block in place on the diagonal of X (upper part zero)
+    double* Xl = X + (int64_t)l * d * d;
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      const int c = q + 4 * s;
+      if (r < nb && c < nb) Xl[(o + r) * d + o + c] = c <= r ? x[s] : 0.0;
+    }
+  }
+}
+
+// The trailing updates compute whole GEMM tiles that touch the lower
+// triangle, so entries right of the diagonal, within the widest tile's
+// BM + BN (at most 288) columns, receive partial sums: the strict upper
+// triangle is cleared within that band at the end.
+constexpr int kUpperBand = 384;
+
+__global__ void zero_upper_band_kernel(double* H, int64_t d, int nl) {
+  const int64_t per = d * kUpperBand;
+  const int64_t total = per * nl;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = t / per, e = t - l * per;
+    const int64_t r = e / kUpperBand, c = r + 1 + (e - r * kUpperBand);
+    if (c < d) H[l * d * d + r * d + c] = 0.0;
+  }
 }
 
 // Two-level right-looking order: 64-column steps inside 256-column outer
@@ -259,7 +286,7 @@ void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_de
     for (int64_t o = O; o < oe; o += NB) {
       const int p = (int)(o / NB);
       hipLaunchKernelGGL(potrf_diag_kernel, dim3(nl), dim3(256), 0, st, H, d, p, dinv, nblk,
-                         status_dev);
+                         status_dev, (double*)nullptr);
       IHS_CHECK_LAUNCH();
       const int64_t below = d - o - NB;
       if (below <= 0) break;
@@ -286,109 +313,159 @@ void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_de
     const int64_t rest = d - oe;
     if (rest > 0) syrk_lower(oe, oe, rest, rest, O, oe - O);
   }
+  if (d > NB) {
+    int64_t blocks = cdiv(d * kUpperBand * nl, 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(zero_upper_band_kernel, dim3((unsigned)blocks), dim3(256), 0, st, H, d, nl);
+    IHS_CHECK_LAUNCH();
+  }
 }
 
-// X <- block diagonal of the 64 x 64 inverses dinv, zero elsewhere.
-__global__ void init_inverse_kernel(double* X, int64_t d, int nl, const double* __restrict__ dinv,
-                                    int nblk) {
-  const int64_t per = d * d;
+// ------------------------------------------------ recursive factor + inverse
+// Both factors of every H_l at once, by halves: for H = [H11 .; H21 H22],
+//   L11, X11 = L11^-1           (the first half, recursively)
+//   L21 = H21 X11^T             (X11 triangular: its zero K-slices skipped)
+//   H22 <- H22 - L21 L21^T      (the Schur complement, lower tiles)
+//   L22, X22 = L22^-1           (recursively)
+//   X21 = -X22 (L21 X11)
+// down to 64 x 64 diagonal blocks, which one workgroup per matrix factors
+// and inverts in LDS.  The same flops as a right-looking factorization
+// followed by a triangular inverse, but the large levels are single GEMMs
+// with K = n / 2 (a right-looking order updates the trailing matrix with
+// K = 256 slices, each output tile loaded and stored per slice).
+namespace {
+__global__ void copy_blocks_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                   int64_t d, int64_t rows, int64_t cols, int nl) {
+  const int64_t per = rows * cols;
   const int64_t total = per * nl;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int l = (int)(t / per);
-    const int64_t e = t % per;
-    const int64_t r = e / d, c = e % d;
-    const int64_t p = r / kNB;
-    double v = 0.0;
-    if (c / kNB == p && c <= r)
-      v = dinv[((int64_t)l * nblk + p) * kNB * kNB + (r - p * kNB) * kNB + (c - p * kNB)];
-    X[t] = v;
+    const int64_t l = t / per, e = t - l * per;
+    const int64_t r = e / cols, c = e - r * cols;
+    dst[l * d * d + r * d + c] = src[l * d * d + r * d + c];
   }
 }
 
-// Doubling levels b = 64, 128, ...: diagonal blocks of size b already hold
-// their inverses; neighbouring pairs (P, Q) are joined by
-//   X_QP = -X_QQ (L_QP X_PP),
-// two batched products per level (over pairs and matrices).
-static int64_t level_pairs(int64_t d, int64_t b, int64_t& part_rows) {
-  const int64_t full = d / (2 * b);
-  const int64_t rem = d - full * 2 * b;
-  part_rows = rem > b ? rem - b : 0;  // a last pair with a short second block
-  return full;
+__global__ void zero_matrices_kernel(double* __restrict__ X, int64_t count) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * blockDim.x)
+    X[t] = 0.0;
 }
 
-int64_t tri_inverse_work_doubles(int64_t d, int nl) {
-  int64_t mx = 0;
-  for (int64_t b = kNB; b < d; b *= 2) {
-    int64_t pr = 0;
-    const int64_t full = level_pairs(d, b, pr);
-    const int64_t need = full * b * b + pr * b;
-    mx = need > mx ? need : mx;
+struct RecFactor {
+  double* H;
+  double* X;
+  int64_t d;
+  int nl;
+  double* dinv;
+  int nblk;
+  int* status;
+  double* work;  // n2 x n1 per matrix at the top split
+  hipStream_t st;
+
+  Gemm base(int64_t M, int64_t N, int64_t K) const {
+    Gemm g;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.lda = d;
+    g.ldb = d;
+    g.ldc = d;
+    g.strideA = d * d;
+    g.strideB = d * d;
+    g.strideC = d * d;
+    g.batch = nl;
+    return g;
   }
-  return mx * nl;
+
+  int64_t work_doubles;  // capacity of work
+
+  void run(int64_t o, int64_t n) {
+    if (n <= kNB) {
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(nl), dim3(256), 0, st, H, d, (int)(o / kNB), dinv,
+                         nblk, status, X);
+      IHS_CHECK_LAUNCH();
+      return;
+    }
+    const int64_t n1 = cdiv(cdiv(n, 2), kNB) * kNB, n2 = n - n1;
+    if (n2 * n1 * nl > work_doubles) fail(IHSBIN_EINVAL, "factor: work buffer too small");
+    run(o, n1);
+    double* H21 = H + (o + n1) * d + o;
+    double* X21 = X + (o + n1) * d + o;
+    const double* X11 = X + o * d + o;
+    // L21 = H21 X11^T, first into X21's place (H21 is its input)
+    Gemm g1 = base(n2, n1, n1);
+    g1.A = H21;
+    g1.B = X11;  // op(B) = X11^T: upper triangular
+    g1.C = X21;
+    g1.tri = 4;
+    gemm(g1, DT::F64, false, DT::F64, true, st);
+    int64_t blocks = cdiv(n2 * n1 * nl, 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(copy_blocks_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X21, H21, d,
+                       n2, n1, nl);
+    IHS_CHECK_LAUNCH();
+    // H22 -= L21 L21^T (tiles touching the lower triangle)
+    Gemm g2 = base(n2, n2, n1);
+    g2.A = H21;
+    g2.B = H21;
+    g2.C = H + (o + n1) * d + o + n1;
+    g2.alpha = -1.0;
+    g2.beta = 1.0;
+    g2.lower_only = 1;
+    gemm(g2, DT::F64, false, DT::F64, true, st);
+    run(o + n1, n2);
+    // T = L21 X11 (X11 lower triangular), then X21 = -X22 T (X22 lower)
+    Gemm g3 = base(n2, n1, n1);
+    g3.A = H21;
+    g3.B = X11;
+    g3.C = work;
+    g3.ldc = n1;
+    g3.strideC = n2 * n1;
+    g3.tri = 3;
+    gemm(g3, DT::F64, false, DT::F64, false, st);
+    Gemm g4 = base(n2, n1, n2);
+    g4.A = X + (o + n1) * d + o + n1;
+    g4.B = work;
+    g4.ldb = n1;
+    g4.strideB = n2 * n1;
+    g4.C = X21;
+    g4.alpha = -1.0;
+    g4.tri = 1;
+    gemm(g4, DT::F64, false, DT::F64, false, st);
+  }
+};
+}  // namespace
+
+// largest n2 x n1 over every split of the recursion (a ragged top split can
+// be smaller than the splits below it)
+static int64_t largest_split(int64_t n) {
+  if (n <= kNB) return 0;
+  const int64_t n1 = cdiv(cdiv(n, 2), kNB) * kNB, n2 = n - n1;
+  return std::max(n2 * n1, std::max(largest_split(n1), largest_split(n2)));
 }
 
-void tri_inverse_batched(const double* Lf, int64_t d, int nl, const double* dinv, double* Linv,
-                         double* work, hipStream_t st) {
-  const int nblk = (int)cdiv(d, kNB);
+int64_t factor_inverse_work_doubles(int64_t d, int nl) {
+  return std::max<int64_t>(1, largest_split(d) * nl);
+}
+
+void factor_inverse_batched(double* H, double* X, int64_t d, int nl, double* dinv,
+                            int* status_dev, double* work, hipStream_t st) {
   {
     int64_t blocks = cdiv(d * d * nl, 256);
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(init_inverse_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Linv, d, nl,
-                       dinv, nblk);
+    hipLaunchKernelGGL(zero_matrices_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X,
+                       d * d * nl);
     IHS_CHECK_LAUNCH();
   }
-  for (int64_t b = kNB; b < d; b *= 2) {
-    int64_t pr = 0;
-    const int64_t full = level_pairs(d, b, pr);
-    // pairs start at diagonal offset o = 2 t b; P = [o, o + b), Q = [o + b, o + b + bq)
-    auto join = [&](int64_t o, int64_t bq, int npairs, double* T, int64_t strideT) {
-      // T = L_QP X_PP   (X_PP lower triangular)
-      Gemm g1;
-      g1.M = bq;
-      g1.N = b;
-      g1.K = b;
-      g1.A = Lf + (o + b) * d + o;
-      g1.lda = d;
-      g1.strideA = d * d;
-      g1.strideA2 = 2 * b * (d + 1);
-      g1.B = Linv + o * d + o;
-      g1.ldb = d;
-      g1.strideB = d * d;
-      g1.strideB2 = 2 * b * (d + 1);
-      g1.C = T;
-      g1.ldc = b;
-      g1.strideC = strideT * npairs;
-      g1.strideC2 = strideT;
-      g1.batch = nl;
-      g1.batch2 = npairs;
-      g1.tri = 3;
-      gemm(g1, DT::F64, false, DT::F64, false, st);
-      // X_QP = -X_QQ T   (X_QQ lower triangular)
-      Gemm g2;
-      g2.M = bq;
-      g2.N = b;
-      g2.K = bq;
-      g2.A = Linv + (o + b) * d + o + b;
-      g2.lda = d;
-      g2.strideA = d * d;
-      g2.strideA2 = 2 * b * (d + 1);
-      g2.B = T;
-      g2.ldb = b;
-      g2.strideB = strideT * npairs;
-      g2.strideB2 = strideT;
-      g2.C = Linv + (o + b) * d + o;
-      g2.ldc = d;
-      g2.strideC = d * d;
-      g2.strideC2 = 2 * b * (d + 1);
-      g2.alpha = -1.0;
-      g2.batch = nl;
-      g2.batch2 = npairs;
-      g2.tri = 1;
-      gemm(g2, DT::F64, false, DT::F64, false, st);
-    };
-    if (full > 0) join(0, b, (int)full, work, b * b);
-    if (pr > 0) join(full * 2 * b, pr, 1, work, pr * b);
+  RecFactor rf{H, X, d, nl, dinv, (int)cdiv(d, kNB), status_dev, work, st,
+               factor_inverse_work_doubles(d, nl)};
+  rf.run(0, d);
+  if (d > kNB) {
+    int64_t blocks = cdiv(d * kUpperBand * nl, 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(zero_upper_band_kernel, dim3((unsigned)blocks), dim3(256), 0, st, H, d, nl);
+    IHS_CHECK_LAUNCH();
   }
 }
 

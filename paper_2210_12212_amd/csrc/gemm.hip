@@ -281,6 +281,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
   if (g.tri == 1) ke = ke < m0 + BM ? ke : m0 + BM;
   if (g.tri == 2) kb = (m0 / BK) * BK;
   if (g.tri == 3) kb = (n0 / BK) * BK;
+  if (g.tri == 4) ke = ke < n0 + BN ? ke : n0 + BN;
   if (g.splits > 1) {
     const int64_t tiles = (ke - kb + BK - 1) / BK;
     const int64_t per = (tiles + g.splits - 1) / g.splits;

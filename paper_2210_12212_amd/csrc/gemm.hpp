@@ -25,7 +25,8 @@ struct Gemm {
   int64_t strideA2 = 0, strideB2 = 0, strideC2 = 0;
   int splits = 1;        // split-K: partial sums of (b, s) go to C + (b*splits+s)*strideC
   int tri = 0;           // 1: op(A) lower triangular, 2: op(A) upper triangular,
-                         // 3: op(B) lower triangular (zero K-slices are skipped)
+                         // 3: op(B) lower triangular, 4: op(B) upper triangular
+                         // (zero K-slices are skipped)
   int lower_only = 0;    // compute only C tiles touching the lower triangle
   const int32_t* amap = nullptr;  // optional device map: problem b uses A + amap[b]*strideA
   int small_tiles = 0;   // 1: 64 x 64 tiles even for large M (FP64 x FP64 products

@@ -65,11 +65,12 @@ void launch_build_shifted(const double* G, int64_t d, const double* lam0_dev, in
 // status_dev (int) is set non-zero when a pivot is not positive.
 void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_dev,
                       hipStream_t st);
-// Linv = L^-1 for nl factors, using the diagonal-block inverses from above.
-// work: tri_inverse_work_doubles(d, nl) doubles of device scratch.
-void tri_inverse_batched(const double* Lf, int64_t d, int nl, const double* dinv, double* Linv,
-                         double* work, hipStream_t st);
-int64_t tri_inverse_work_doubles(int64_t d, int nl);
+// The factor and its inverse together, by halves (recursive: L and
+// X = L^-1 of every H_l; H's upper triangle zeroed, X's upper triangle zero).  status_dev as cholesky_batched;
+// work: factor_inverse_work_doubles(d, nl) doubles.
+void factor_inverse_batched(double* H, double* X, int64_t d, int nl, double* dinv,
+                            int* status_dev, double* work, hipStream_t st);
+int64_t factor_inverse_work_doubles(int64_t d, int nl);
 constexpr int kNB = 64;
 
 // ------------------------------------------------------------ products with A

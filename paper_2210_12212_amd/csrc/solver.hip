@@ -281,17 +281,19 @@ static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<do
   double* dinv = static_cast<double*>(dinv_buf.ensure(sizeof(double) * nl * nblk * kNB * kNB));
   int* status = static_cast<int*>(c.ws_status.ensure(64));
   IHS_HIP(hipMemsetAsync(status, 0, sizeof(int), c.stream));
-  cholesky_batched(Lf, d, nl, dinv, status, c.stream);
+  PoolBuf work(c.pool);
+  if (Linv) {
+    // factor and inverse together, by halves
+    double* wk = static_cast<double*>(work.ensure(
+        sizeof(double) * (size_t)std::max<int64_t>(1, factor_inverse_work_doubles(d, nl))));
+    factor_inverse_batched(Lf, Linv, d, nl, dinv, status, wk, c.stream);
+  } else {
+    cholesky_batched(Lf, d, nl, dinv, status, c.stream);
+  }
   int h = 0;
   IHS_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
   IHS_HIP(hipStreamSynchronize(c.stream));
   if (h) fail(IHSBIN_ENOTSPD, "sketched Hessian not positive definite");
-  if (Linv) {
-    PoolBuf work(c.pool);
-    double* wk = static_cast<double*>(
-        work.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, tri_inverse_work_doubles(d, nl))));
-    tri_inverse_batched(Lf, d, nl, dinv, Linv, wk, c.stream);
-  }
 }
 
 // Z = P R for every active position: P_a = Linv_{ids[a]}^T Linv_{ids[a]}.
@@ -885,7 +887,7 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
   if (o.gram_prec == IHSBIN_GRAM_BF16X3) b += (double)gram_bf16x3_work_bytes(rows, D);
   b += 2 * 8.0 * D * D + 8.0 * cdiv(D, kNB) * kNB * kNB;  // probe or Algorithm 4 factor
   b += 2 * 8.0 * L * D * D + 8.0 * L * cdiv(D, kNB) * kNB * kNB +
-       8.0 * tri_inverse_work_doubles(D, (int)L);
+       8.0 * factor_inverse_work_doubles(D, (int)L);
   // Lanczos at both ends of every interval
   const int64_t na = 2 * L, ld = padded_width(na);
   const int64_t J = std::min<int64_t>(63, std::max<int64_t>(8, o.lanczos_steps));

@@ -140,7 +140,7 @@ def test_srht_large_order_three_passes(torch, ctx):
 
 
 # ---------------------------------------------------------------- factor
-@pytest.mark.parametrize("d", [40, 64, 200, 300, 1000])
+@pytest.mark.parametrize("d", [40, 64, 200, 300, 1000, 2100])
 def test_precond_factor(torch, ctx, d):
     r = np.random.default_rng(d)
     SA = r.standard_normal((d // 2 + 3, d))
