@@ -257,6 +257,7 @@ bool log_enabled();
 void logf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
 struct Csc;
+struct HeadTail;
 struct MatView {  // a validated ihsbin_matrix
   int format, dtype;
   int64_t n, d, ld, nnz;
@@ -264,6 +265,7 @@ struct MatView {  // a validated ihsbin_matrix
   const int32_t* row_ptr;
   const int32_t* col_idx;
   const Csc* csc = nullptr;  // CSR only, optional: its column-major copy
+  const HeadTail* ht = nullptr;  // CSR only, optional: its dense head columns
 };
 
 MatView check_matrix(const ihsbin_matrix* A);

@@ -10,6 +10,9 @@
 // column in chunk order.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+#include <vector>
+
 #include "ops.hpp"
 
 namespace ihs {
@@ -210,6 +213,170 @@ void build_csc(const MatView& A, void* work, Csc& out, hipStream_t st) {
   out.nchunks = nch;
 }
 
+// ---------------------------------------------------------- head / tail
+namespace {
+template <typename T>
+__global__ void head_fill_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const T* __restrict__ v, int64_t n,
+                                 const int32_t* __restrict__ head_pos, int64_t ldh,
+                                 T* __restrict__ AH) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+      const int32_t pos = head_pos[ci[p]];
+      if (pos >= 0) AH[i * ldh + pos] += v[p];  // duplicates in stored order
+    }
+}
+
+__global__ void tail_count_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  int64_t n, const int32_t* __restrict__ head_pos,
+                                  int32_t* __restrict__ cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t c = 0;
+    if (i < n)
+      for (int32_t p = rp[i]; p < rp[i + 1]; ++p) c += head_pos[ci[p]] < 0 ? 1 : 0;
+    cnt[i] = c;
+  }
+}
+
+template <typename T>
+__global__ void tail_fill_kernel(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const T* __restrict__ v, int64_t n,
+                                 const int32_t* __restrict__ head_pos,
+                                 const int32_t* __restrict__ trp, int32_t* __restrict__ tci,
+                                 T* __restrict__ tv) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t q = trp[i];
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+      if (head_pos[ci[p]] < 0) {
+        tci[q] = ci[p];
+        tv[q] = v[p];
+        ++q;
+      }
+  }
+}
+
+__global__ void zero_bytes_kernel(uint32_t* __restrict__ p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+}  // namespace
+
+void build_head_tail(const MatView& A, const Csc& csc, PoolBuf& buf, HeadTail& out,
+                     hipStream_t st) {
+  out = HeadTail();
+  if (A.format != IHSBIN_CSR) return;
+  const int64_t n = A.n, d = A.d, nnz = A.nnz;
+  constexpr int64_t kMaxHead = 256;
+  std::vector<int32_t> cp(d + 1);
+  IHS_HIP(hipMemcpyAsync(cp.data(), csc.col_ptr, sizeof(int32_t) * (size_t)(d + 1),
+                         hipMemcpyDeviceToHost, st));
+  IHS_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> head, pos(d, -1);
+  const int64_t need = std::max<int64_t>(1, n / 16);
+  // the densest columns first when more than kMaxHead qualify
+  std::vector<int32_t> cand;
+  for (int64_t c = 0; c < d; ++c)
+    if (cp[c + 1] - cp[c] >= need) cand.push_back((int32_t)c);
+  if ((int64_t)cand.size() > kMaxHead) {
+    std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+      return cp[a + 1] - cp[a] > cp[b + 1] - cp[b];
+    });
+    cand.resize(kMaxHead);
+    std::sort(cand.begin(), cand.end());
+  }
+  head = cand;
+  const int64_t h = (int64_t)head.size();
+  if (h == 0) return;
+  for (int64_t k = 0; k < h; ++k) pos[head[k]] = (int32_t)k;
+  const int64_t ldh = cdiv(h, 4) * 4;
+  const size_t es = A.dtype == IHSBIN_F32 ? 4 : 8;
+  size_t scan_tmp = 0;
+  IHS_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (const int32_t*)nullptr,
+                                           (int32_t*)nullptr, (int)(n + 1), st));
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t bytes = al(4 * h) + al(4 * d) + al(es * (size_t)n * ldh) + al(4 * (n + 1)) +
+                       al(4 * std::max<int64_t>(nnz, 1)) + al(es * std::max<int64_t>(nnz, 1)) +
+                       al(4 * std::max<int64_t>(csc.nchunks, 1)) + al(4 * (n + 1)) + al(scan_tmp);
+  char* p = static_cast<char*>(buf.ensure(bytes));
+  auto take = [&](size_t b) {
+    char* r = p;
+    p += al(b);
+    return r;
+  };
+  int32_t* head_d = reinterpret_cast<int32_t*>(take(4 * h));
+  int32_t* pos_d = reinterpret_cast<int32_t*>(take(4 * d));
+  void* AH = take(es * (size_t)n * ldh);
+  int32_t* trp = reinterpret_cast<int32_t*>(take(4 * (n + 1)));
+  int32_t* tci = reinterpret_cast<int32_t*>(take(4 * std::max<int64_t>(nnz, 1)));
+  void* tv = take(es * std::max<int64_t>(nnz, 1));
+  int32_t* torder = reinterpret_cast<int32_t*>(take(4 * std::max<int64_t>(csc.nchunks, 1)));
+  int32_t* cnt = reinterpret_cast<int32_t*>(take(4 * (n + 1)));
+  void* tmp = take(scan_tmp);
+  IHS_HIP(hipMemcpyAsync(head_d, head.data(), 4 * (size_t)h, hipMemcpyHostToDevice, st));
+  IHS_HIP(hipMemcpyAsync(pos_d, pos.data(), 4 * (size_t)d, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(zero_bytes_kernel, dim3(grid_for(es * n * ldh / 4)), dim3(256), 0, st,
+                     static_cast<uint32_t*>(AH), (int64_t)(es * n * ldh / 4));
+  IHS_CHECK_LAUNCH();
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(head_fill_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, static_cast<const float*>(A.vals), n, pos_d, ldh,
+                       static_cast<float*>(AH));
+  else
+    hipLaunchKernelGGL(head_fill_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, static_cast<const double*>(A.vals), n, pos_d, ldh,
+                       static_cast<double*>(AH));
+  IHS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(tail_count_kernel, dim3(grid_for(n + 1)), dim3(256), 0, st, A.row_ptr,
+                     A.col_idx, n, pos_d, cnt);
+  IHS_CHECK_LAUNCH();
+  size_t sb = scan_tmp;
+  IHS_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, sb, cnt, trp, (int)(n + 1), st));
+  if (A.dtype == IHSBIN_F32)
+    hipLaunchKernelGGL(tail_fill_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, static_cast<const float*>(A.vals), n, pos_d, trp, tci,
+                       static_cast<float*>(tv));
+  else
+    hipLaunchKernelGGL(tail_fill_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st, A.row_ptr,
+                       A.col_idx, static_cast<const double*>(A.vals), n, pos_d, trp, tci,
+                       static_cast<double*>(tv));
+  IHS_CHECK_LAUNCH();
+  // tail chunks in the copy's first-row order
+  std::vector<int32_t> ord(std::max<int64_t>(csc.nchunks, 1)), ccol(std::max<int64_t>(csc.nchunks, 1));
+  int32_t tnnz = 0;
+  if (csc.nchunks > 0) {
+    IHS_HIP(hipMemcpyAsync(ord.data(), csc.order, 4 * (size_t)csc.nchunks, hipMemcpyDeviceToHost,
+                           st));
+    IHS_HIP(hipMemcpyAsync(ccol.data(), csc.chunk_col, 4 * (size_t)csc.nchunks,
+                           hipMemcpyDeviceToHost, st));
+  }
+  IHS_HIP(hipMemcpyAsync(&tnnz, trp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  IHS_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> tord;
+  for (int64_t k = 0; k < csc.nchunks; ++k)
+    if (pos[ccol[ord[k]]] < 0) tord.push_back(ord[k]);
+  if (!tord.empty())
+    IHS_HIP(hipMemcpyAsync(torder, tord.data(), 4 * tord.size(), hipMemcpyHostToDevice, st));
+  out.h = h;
+  out.ldh = ldh;
+  out.head_cols = head_d;
+  out.head_pos = pos_d;
+  out.AH = AH;
+  out.tail = A;
+  out.tail.row_ptr = trp;
+  out.tail.col_idx = tci;
+  out.tail.vals = tv;
+  out.tail.nnz = tnnz;
+  out.tail.csc = nullptr;
+  out.tail.ht = nullptr;
+  out.torder = torder;
+  out.tnchunks = (int64_t)tord.size();
+  IHS_HIP(hipStreamSynchronize(st));  // the host vectors above go out of scope
+}
+
 // P[t][j] = sum over the entries of chunk t of val * Y[row][j].  Lanes form
 // groups of G = min(64, pow2ceil(w)) columns; the 64 / G groups of a wave take
 // every (64/G)-th entry of the chunk and are added by a fixed butterfly.  The
@@ -271,11 +438,12 @@ __global__ __launch_bounds__(256) void csc_gather_kernel(
 // W[c][j] = sum of the chunk partials of column c in chunk order (0 if none)
 __global__ void csc_reduce_kernel(const int32_t* __restrict__ col_chunk, int64_t d, int64_t w,
                                   const double* __restrict__ P, double* __restrict__ W,
-                                  int64_t ldw) {
+                                  int64_t ldw, const int32_t* __restrict__ skip) {
   const int64_t total = d * w;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e / w, j = e - c * w;
+    if (skip && skip[c] >= 0) continue;  // a head column (written by its GEMM)
     double s = 0.0;
     for (int32_t t = col_chunk[c]; t < col_chunk[c + 1]; ++t) s += P[(int64_t)t * w + j];
     W[c * ldw + j] = s;
@@ -285,39 +453,43 @@ __global__ void csc_reduce_kernel(const int32_t* __restrict__ col_chunk, int64_t
 int64_t csc_partial_doubles(const Csc& csc, int64_t w) { return csc.nchunks * w; }
 
 void launch_csc_atb(const MatView& A, const Csc& csc, const void* Y, bool y_f32, int64_t w,
-                    int64_t ldy, double* P, double* W, int64_t ldw, hipStream_t st) {
+                    int64_t ldy, double* P, double* W, int64_t ldw, hipStream_t st,
+                    const HeadTail* ht) {
   if (w <= 0) return;
   const int G = pow2ceil(w);
   const int strips = (int)cdiv(w, G);
-  const int64_t items = csc.nchunks * strips;
+  const bool split = ht && ht->h > 0;
+  const int32_t* order = split ? ht->torder : csc.order;
+  const int64_t nchunks = split ? ht->tnchunks : csc.nchunks;
+  const int64_t items = nchunks * strips;
   if (items > 0) {
     const unsigned blocks = (unsigned)cdiv(items, 4);
     if (cdiv(items, 4) > INT32_MAX) fail(IHSBIN_EUNSUP, "CSC product: grid too large");
     const bool af = A.dtype == IHSBIN_F32;
     if (af && y_f32)
       hipLaunchKernelGGL((csc_gather_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
-                         static_cast<const float*>(csc.val), csc.nchunks,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, order, csc.row,
+                         static_cast<const float*>(csc.val), nchunks,
                          static_cast<const float*>(Y), w, ldy, G, strips, P);
     else if (af)
       hipLaunchKernelGGL((csc_gather_kernel<float, double>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
-                         static_cast<const float*>(csc.val), csc.nchunks,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, order, csc.row,
+                         static_cast<const float*>(csc.val), nchunks,
                          static_cast<const double*>(Y), w, ldy, G, strips, P);
     else if (y_f32)
       hipLaunchKernelGGL((csc_gather_kernel<double, float>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
-                         static_cast<const double*>(csc.val), csc.nchunks,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, order, csc.row,
+                         static_cast<const double*>(csc.val), nchunks,
                          static_cast<const float*>(Y), w, ldy, G, strips, P);
     else
       hipLaunchKernelGGL((csc_gather_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
-                         csc.col_ptr, csc.col_chunk, csc.chunk_col, csc.order, csc.row,
-                         static_cast<const double*>(csc.val), csc.nchunks,
+                         csc.col_ptr, csc.col_chunk, csc.chunk_col, order, csc.row,
+                         static_cast<const double*>(csc.val), nchunks,
                          static_cast<const double*>(Y), w, ldy, G, strips, P);
     IHS_CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(csc_reduce_kernel, dim3(grid_for(A.d * w)), dim3(256), 0, st, csc.col_chunk,
-                     A.d, w, P, W, ldw);
+                     A.d, w, P, W, ldw, split ? ht->head_pos : (const int32_t*)nullptr);
   IHS_CHECK_LAUNCH();
 }
 

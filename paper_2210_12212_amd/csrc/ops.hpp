@@ -180,14 +180,37 @@ struct Csc {
   const int32_t* order = nullptr;      // nchunks
   int64_t nchunks = 0;
 };
+// The columns of a CSR matrix that hold at least n / 16 entries (at most
+// 256 of them, increasing column order) kept as a dense n x h block AH (A's
+// type, row stride ldh, zero where a row has no entry; duplicates summed in
+// stored order), the other entries as a tail CSR matrix, and the column
+// chunks of the tail columns in first-row order.  The products then run the
+// head as dense GEMMs (one streaming pass over the n x w intermediate
+// instead of one gather of its row per entry) and gather the tail.
+struct HeadTail {
+  int64_t h = 0, ldh = 0;
+  const int32_t* head_cols = nullptr;  // h
+  const int32_t* head_pos = nullptr;   // d: position in the head or -1
+  const void* AH = nullptr;            // n x ldh
+  MatView tail;                        // the tail entries (CSR, same n, d)
+  const int32_t* torder = nullptr;     // tail chunks of the column-major copy
+  int64_t tnchunks = 0;
+};
+// Builds `out` for A (CSR) and its column-major copy; device memory from
+// `buf` (kept while used).  h = 0 (nothing allocated) when no column is
+// dense enough.  Synchronizes the stream.
+void build_head_tail(const MatView& A, const Csc& csc, PoolBuf& buf, HeadTail& out,
+                     hipStream_t st);
 int64_t csc_work_bytes(const MatView& A);
 // Builds the copy inside `work` (csc_work_bytes(A) bytes, kept while used).
 void build_csc(const MatView& A, void* work, Csc& out, hipStream_t st);
 int64_t csc_partial_doubles(const Csc& csc, int64_t w);
 // W (d x w, row stride ldw) = A^T Y for Y (n x w, row stride ldy, FP32 or
 // FP64), gathered column by column; P: csc_partial_doubles(csc, w) doubles.
+// ht: gather only the tail chunks and leave W's head rows untouched.
 void launch_csc_atb(const MatView& A, const Csc& csc, const void* Y, bool y_f32, int64_t w,
-                    int64_t ldy, double* P, double* W, int64_t ldw, hipStream_t st);
+                    int64_t ldy, double* P, double* W, int64_t ldw, hipStream_t st,
+                    const HeadTail* ht = nullptr);
 
 // ------------------------------------------------------------ basis kernels
 struct StepParams;  // defined in basis.hip users

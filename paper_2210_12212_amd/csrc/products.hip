@@ -213,6 +213,29 @@ void launch_csr_spmm_t(const MatView& A, const double* Y, int64_t w, int64_t ldy
   IHS_CHECK_LAUNCH();
 }
 
+// UH[k][j] = U[cols[k]][j] (k < h, j < w), and the inverse scatter of WH.
+__global__ void gather_rows_by_index_kernel(const double* __restrict__ U, int64_t ldu,
+                                            const int32_t* __restrict__ cols, int64_t h,
+                                            int64_t w, double* __restrict__ UH) {
+  const int64_t total = h * w;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = t / w, j = t - k * w;
+    UH[t] = U[(int64_t)cols[k] * ldu + j];
+  }
+}
+
+__global__ void scatter_rows_by_index_kernel(const double* __restrict__ WH,
+                                             const int32_t* __restrict__ cols, int64_t h,
+                                             int64_t w, double* __restrict__ W, int64_t ldw) {
+  const int64_t total = h * w;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = t / w, j = t - k * w;
+    W[(int64_t)cols[k] * ldw + j] = WH[t];
+  }
+}
+
 __global__ void zero_rows_kernel(double* W, int64_t rows, int64_t cols, int64_t ld) {
   const int64_t total = rows * cols;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -611,6 +634,31 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
       g1.C = Y;
       g1.ldc = ycap;
       gemm_cols(g1, ta, false, ct, st);
+    } else if (A.ht && A.ht->h > 0) {
+      // Y = A_tail U + AH U_head: the tail rows gathered, the head columns
+      // one dense product added onto them
+      const HeadTail& ht = *A.ht;
+      launch_csr_spmm(ht.tail, U + c0, cw, ldu, Y, cw, st);
+      double* UH = static_cast<double*>(ctx.ws_tmp.ensure(sizeof(double) * (size_t)(ht.h * cw)));
+      {
+        int64_t b = cdiv(ht.h * cw, 256);
+        if (b > 16384) b = 16384;
+        hipLaunchKernelGGL(gather_rows_by_index_kernel, dim3((unsigned)b), dim3(256), 0, st,
+                           U + c0, ldu, ht.head_cols, ht.h, cw, UH);
+        IHS_CHECK_LAUNCH();
+      }
+      Gemm gh;
+      gh.M = A.n;
+      gh.N = cw;
+      gh.K = ht.h;
+      gh.A = ht.AH;
+      gh.lda = ht.ldh;
+      gh.B = UH;
+      gh.ldb = cw;
+      gh.C = Y;
+      gh.ldc = cw;
+      gh.beta = 1.0;
+      gemm(gh, ta, false, DT::F64, false, st);
     } else {
       launch_csr_spmm(A, U + c0, cw, ldu, Y, cw, st);
     }
@@ -646,9 +694,38 @@ int64_t ata_apply(Ctx& ctx, const MatView& A, const double* U, int64_t w, int64_
       }
     } else {
       if (A.csc) {
-        double* P = static_cast<double*>(
-            ctx.ws_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, csc_partial_doubles(*A.csc, cw))));
-        launch_csc_atb(A, *A.csc, Y, false, cw, cw, P, W + c0, ldw, st);
+        const bool split = A.ht && A.ht->h > 0;
+        const HeadTail* ht = split ? A.ht : nullptr;
+        const int64_t pd = std::max<int64_t>(1, csc_partial_doubles(*A.csc, cw));
+        int hs = 1;
+        if (split) hs = pick_splits(ht->h, cw, A.n, 1, 2048);
+        const int64_t hd = split ? ht->h * cw * (1 + hs) : 0;  // WH and its split partials
+        double* P = static_cast<double*>(ctx.ws_part.ensure(sizeof(double) * (size_t)(pd + hd)));
+        launch_csc_atb(A, *A.csc, Y, false, cw, cw, P, W + c0, ldw, st, ht);
+        if (split) {
+          // W's head rows: AH^T Y, split over n, reduced in fixed order
+          double* WH = P + pd;
+          double* part = WH + ht->h * cw;
+          Gemm gw;
+          gw.M = ht->h;
+          gw.N = cw;
+          gw.K = A.n;
+          gw.A = ht->AH;
+          gw.lda = ht->ldh;
+          gw.B = Y;
+          gw.ldb = cw;
+          gw.C = part;
+          gw.ldc = cw;
+          gw.strideC = ht->h * cw;
+          gw.splits = hs;
+          gemm(gw, ta, true, DT::F64, false, st);
+          reduce_splits(part, hs, 1, ht->h, cw, cw, ht->h * cw, WH, cw, 0, 1.0, 0.0, st);
+          int64_t b = cdiv(ht->h * cw, 256);
+          if (b > 16384) b = 16384;
+          hipLaunchKernelGGL(scatter_rows_by_index_kernel, dim3((unsigned)b), dim3(256), 0, st, WH,
+                             ht->head_cols, ht->h, cw, W + c0, ldw);
+          IHS_CHECK_LAUNCH();
+        }
         mark();
         continue;
       }

@@ -617,10 +617,11 @@ struct Timer {
 struct Form {
   MatView A;
   bool dual = false;
-  PoolBuf At, Cb, cscb;
-  Csc csc;  // CSR: the column-major copy the transposed products gather from
+  PoolBuf At, Cb, cscb, htb;
+  Csc csc;     // CSR: the column-major copy the transposed products gather from
+  HeadTail ht;  // CSR: its dense head columns and sparse tail
   double* C = nullptr;
-  explicit Form(Pool& p) : At(p), Cb(p), cscb(p) {}
+  explicit Form(Pool& p) : At(p), Cb(p), cscb(p), htb(p) {}
 };
 
 static void make_form(Ctx& c, const MatView& A0, const void* B, int64_t K, int64_t ldb, Form& f) {
@@ -643,6 +644,8 @@ static void make_form(Ctx& c, const MatView& A0, const void* B, int64_t K, int64
     validate_csr(c, f.A);
     build_csc(f.A, f.cscb.ensure((size_t)csc_work_bytes(f.A)), f.csc, c.stream);
     f.A.csc = &f.csc;
+    build_head_tail(f.A, f.csc, f.htb, f.ht, c.stream);
+    if (f.ht.h > 0) f.A.ht = &f.ht;
   }
   const int64_t d = f.A.d;
   f.C = static_cast<double*>(f.Cb.ensure(sizeof(double) * d * K));
@@ -864,6 +867,13 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
   double b = 0;
   if (dual) b += (double)es * N * D;
   b += 8.0 * D * K;  // C
+  if (csr) {
+    // the column-major copy and the dense head block (<= 256 columns) with
+    // the tail entries
+    const double nz = (double)std::max<int64_t>(0, A0->nnz);
+    b += (8.0 + es + 16.0) * nz + 16.0 * D + double(8 << 20) +  // copy and its sort scratch
+         (double)es * N * 256.0 + (4.0 + es) * nz + 8.0 * N;
+  }
   // sketch scratch (also the identity draws of S = I for CSR)
   double sk = 5.0 * N + 256;
   if (o.sketch == IHSBIN_GAUSSIAN && o.sketch_prec == IHSBIN_SKETCH_BF16) {
@@ -2335,12 +2345,15 @@ int ihsbin_ata_apply(ihsbin_ctx* ctx, const ihsbin_matrix* A, const double* U, i
     DeviceGuard g(ctx->c.device);
     MatView v = check_matrix(A);
     if (!U || !W || w < 1 || ldu < w || ldw < w) fail(IHSBIN_EINVAL, "bad U / W");
-    PoolBuf cscb(ctx->c.pool);
+    PoolBuf cscb(ctx->c.pool), htb(ctx->c.pool);
     Csc csc;
+    HeadTail ht;
     if (v.format == IHSBIN_CSR) {
       validate_csr(ctx->c, v);
       build_csc(v, cscb.ensure((size_t)csc_work_bytes(v)), csc, ctx->c.stream);
       v.csc = &csc;
+      build_head_tail(v, csc, htb, ht, ctx->c.stream);
+      if (ht.h > 0) v.ht = &ht;
     }
     ata_apply(ctx->c, v, U, w, ldu, W, ldw, nullptr, ldu);
     IHS_HIP(hipStreamSynchronize(ctx->c.stream));
