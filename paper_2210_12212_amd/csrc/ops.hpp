@@ -50,8 +50,19 @@ int64_t countsketch_apply_sparse(const MatView& A, uint64_t seed, int64_t m, int
 constexpr int64_t kSparseGramMaxD = 8192;
 void sparse_gram(Ctx& ctx, const SparseRows& sa, double* G);
 // Z (npad x d) = D A zero-padded, then the Walsh-Hadamard transform over rows.
-void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, double* Z,
-                           hipStream_t st);
+// With SA given (and rstart, rk from build_row_sample), the last pass writes
+// scale * row rows[k] of the transform to row k of SA for every k instead of
+// storing its rows in Z (Z then holds an intermediate pass); returns whether
+// it did (false: Z holds the whole transform, gather it).
+bool launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, double* Z,
+                           hipStream_t st, const int32_t* rstart = nullptr,
+                           const int32_t* rk = nullptr, double scale = 0.0,
+                           double* SA = nullptr);
+// The m sampled rows grouped by row: rk lists the positions k by rows[k]
+// (stable), rstart (npad + 1) points into it.  work: row_sample_work_bytes.
+int64_t row_sample_work_bytes(int64_t m, int64_t npad);
+void build_row_sample(const int32_t* rows, int64_t m, int64_t npad, void* work,
+                      const int32_t** rstart, const int32_t** rk, hipStream_t st);
 // SA[k] = scale * Z[rows[k]].
 void launch_gather_rows(const double* Z, int64_t d, const int32_t* rows, int64_t m, double scale,
                         double* SA, hipStream_t st);

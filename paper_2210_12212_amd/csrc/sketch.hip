@@ -551,11 +551,21 @@ __global__ __launch_bounds__(256) void fwht_pass_kernel(const T* __restrict__ A,
 // (128 bytes) are read and written per thread group.
 constexpr int kFwhtRC = 16;
 
+// With `sample` (the last pass of a sampled transform) a finished row r is
+// not stored in Z but written, times scale, to every row k of SA with
+// rows[k] = r (sample->rk[sample->rstart[r] .. sample->rstart[r + 1]]).
+struct RowSample {
+  const int32_t* rstart;  // npad + 1
+  const int32_t* rk;      // m: sample positions ordered by their row
+  double scale;
+  double* SA;
+};
+
 template <typename T, bool LOAD, int V>
 __global__ __launch_bounds__(256) void fwht_reg_kernel(const T* __restrict__ A, int64_t n,
                                                        int64_t ld, const int8_t* __restrict__ sign,
                                                        double* Z, int64_t npad, int64_t d,
-                                                       int64_t stride) {
+                                                       int64_t stride, RowSample sample) {
   constexpr int LEN = 16 * V;
   constexpr int PER = V >= 16 ? V / 16 : 1;  // row sets of 16 per thread in phase 2
   __shared__ double buf[LEN][kFwhtRC + 1];
@@ -614,8 +624,17 @@ __global__ __launch_bounds__(256) void fwht_reg_kernel(const T* __restrict__ A, 
               w[j + hh] = a - b;
             }
         if (cok) {
+          if (!sample.SA) {
 #pragma unroll
-          for (int j = 0; j < 16; ++j) Z[row_of(16 * kk + j) * d + col] = w[j];
+            for (int j = 0; j < 16; ++j) Z[row_of(16 * kk + j) * d + col] = w[j];
+          } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+              const int64_t row = row_of(16 * kk + j);
+              for (int32_t q = sample.rstart[row]; q < sample.rstart[row + 1]; ++q)
+                sample.SA[(int64_t)sample.rk[q] * d + col] = sample.scale * w[j];
+            }
+          }
         }
       }
     }
@@ -625,12 +644,12 @@ __global__ __launch_bounds__(256) void fwht_reg_kernel(const T* __restrict__ A, 
 template <typename T, bool LOAD>
 static void launch_fwht_reg(int dg, unsigned blocks, hipStream_t st, const T* A, int64_t n,
                             int64_t ld, const int8_t* sign, double* Z, int64_t npad, int64_t d,
-                            int64_t stride) {
+                            int64_t stride, const RowSample& sample) {
   switch (dg) {
 #define IHS_FWHT_CASE(DG, V)                                                                   \
   case DG:                                                                                     \
     hipLaunchKernelGGL((fwht_reg_kernel<T, LOAD, V>), dim3(blocks), dim3(256), 0, st, A, n, ld, \
-                       sign, Z, npad, d, stride);                                              \
+                       sign, Z, npad, d, stride, sample);                                      \
     break;
     IHS_FWHT_CASE(4, 1)
     IHS_FWHT_CASE(5, 2)
@@ -656,8 +675,11 @@ __global__ void csr_signed_scatter_kernel(const int32_t* __restrict__ rp, const 
   }
 }
 
-void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, double* Z,
-                           hipStream_t st) {
+bool launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, double* Z,
+                           hipStream_t st, const int32_t* rstart, const int32_t* rk,
+                           double scale, double* SA) {
+  const RowSample none{nullptr, nullptr, 0.0, nullptr};
+  bool fused = false;
   int p = 0;
   while ((int64_t(1) << p) < npad) ++p;
   // digits of at most 9 bits, lowest first
@@ -685,21 +707,26 @@ void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, d
     IHS_CHECK_LAUNCH();
     first = false;
   }
-  for (int dg : digits) {
+  for (size_t di = 0; di < digits.size(); ++di) {
+    const int dg = digits[di];
     const int len = 1 << dg;
     if (dg >= 4) {
       const int64_t rjobs = (npad / ((int64_t)len * stride)) * stride * cdiv(A.d, kFwhtRC);
       const unsigned rblocks = (unsigned)(rjobs < 32768 ? rjobs : 32768);
+      // the last pass writes the sampled rows straight into SA
+      const bool last = di + 1 == digits.size() && SA != nullptr;
+      const RowSample rs = last ? RowSample{rstart, rk, scale, SA} : none;
+      fused = fused || last;
       if (first && A.format == IHSBIN_DENSE) {
         if (A.dtype == IHSBIN_F32)
           launch_fwht_reg<float, true>(dg, rblocks, st, (const float*)A.vals, A.n, A.ld, sign, Z,
-                                       npad, A.d, stride);
+                                       npad, A.d, stride, rs);
         else
           launch_fwht_reg<double, true>(dg, rblocks, st, (const double*)A.vals, A.n, A.ld, sign,
-                                        Z, npad, A.d, stride);
+                                        Z, npad, A.d, stride, rs);
       } else {
         launch_fwht_reg<double, false>(dg, rblocks, st, (const double*)nullptr, A.n, A.ld, sign, Z,
-                                       npad, A.d, stride);
+                                       npad, A.d, stride, rs);
       }
       IHS_CHECK_LAUNCH();
       first = false;
@@ -723,6 +750,63 @@ void launch_srht_transform(const MatView& A, const int8_t* sign, int64_t npad, d
     first = false;
     stride *= len;
   }
+  return fused;
+}
+
+// rk = the sample positions k ordered by rows[k] (stable), rstart[r] = the
+// first of them whose row is >= r (r = 0..npad)
+__global__ void row_start_kernel(const int32_t* __restrict__ sorted_rows, int64_t m, int64_t npad,
+                                 int32_t* __restrict__ rstart) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= npad;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (sorted_rows[mid] < r) lo = mid + 1;
+      else hi = mid;
+    }
+    rstart[r] = (int32_t)lo;
+  }
+}
+
+int64_t row_sample_work_bytes(int64_t m, int64_t npad) {
+  size_t tmp = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)m, 0,
+                                           32);
+  return (int64_t)(4 * align256(4 * (size_t)m) + align256(4 * (size_t)(npad + 1)) + align256(tmp) +
+                   256);
+}
+
+void build_row_sample(const int32_t* rows, int64_t m, int64_t npad, void* work,
+                      const int32_t** rstart, const int32_t** rk, hipStream_t st) {
+  if (m >= INT32_MAX || npad >= INT32_MAX) fail(IHSBIN_EUNSUP, "SRHT sample too large");
+  char* p = static_cast<char*>(work);
+  auto take = [&](size_t b) {
+    char* r = p;
+    p += align256(b);
+    return r;
+  };
+  int32_t* keys = reinterpret_cast<int32_t*>(take(4 * (size_t)m));
+  int32_t* iota = reinterpret_cast<int32_t*>(take(4 * (size_t)m));
+  int32_t* sk = reinterpret_cast<int32_t*>(take(4 * (size_t)m));
+  int32_t* sv = reinterpret_cast<int32_t*>(take(4 * (size_t)m));
+  int32_t* rs = reinterpret_cast<int32_t*>(take(4 * (size_t)(npad + 1)));
+  int end_bit = 1;
+  while ((int64_t(1) << end_bit) < npad) ++end_bit;
+  size_t tmp = 0;
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, keys, sk, iota, sv, (int)m, 0, end_bit,
+                                             st));
+  void* tw = take(tmp);
+  IHS_HIP(hipMemcpyAsync(keys, rows, 4 * (size_t)m, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(m)), dim3(256), 0, st, iota, m);
+  IHS_CHECK_LAUNCH();
+  IHS_HIP(hipcub::DeviceRadixSort::SortPairs(tw, tmp, keys, sk, iota, sv, (int)m, 0, end_bit, st));
+  hipLaunchKernelGGL(row_start_kernel, dim3(blocks_for(npad + 1)), dim3(256), 0, st, sk, m, npad,
+                     rs);
+  IHS_CHECK_LAUNCH();
+  *rstart = rs;
+  *rk = sv;
 }
 
 __global__ void gather_rows_kernel(const double* __restrict__ Z, int64_t d,

@@ -112,9 +112,13 @@ static int64_t next_pow2(int64_t n) {
 // r_begin (Gaussian only): rows [r_begin, m) of SA are formed and earlier
 // rows are left as they are (a Gaussian row depends on its index alone, so
 // a grown sketch keeps the rows already formed, rescaled by the caller).
+// SRHT: reuse_transform gathers from the transform a previous call kept
+// whole; keep_transform keeps this call's transform whole for such reuse
+// (otherwise its last pass writes the sampled rows straight into SA).
 static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t m, uint64_t seed,
                               double* SA, bool reuse_transform = false,
-                              int prec = IHSBIN_SKETCH_F64, int64_t r_begin = 0) {
+                              int prec = IHSBIN_SKETCH_F64, int64_t r_begin = 0,
+                              bool keep_transform = false) {
   hipStream_t st = c.stream;
   if (m <= 0) fail(IHSBIN_EINVAL, "m must be positive");
   if (m > INT32_MAX) fail(IHSBIN_EUNSUP, "m too large");
@@ -209,8 +213,18 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
     int8_t* sg = reinterpret_cast<int8_t*>(base + sizeof(double) * (size_t)npad * A.d);
     int32_t* rows = static_cast<int32_t*>(c.ws_tmp.ensure(sizeof(int32_t) * (size_t)m));
     launch_draw_srht(seed, A.n, npad, m, sg, rows, st);
-    if (!reuse_transform) launch_srht_transform(A, sg, npad, Z, st);
-    launch_gather_rows(Z, A.d, rows, m, 1.0 / std::sqrt((double)m), SA, st);
+    const double scale = 1.0 / std::sqrt((double)m);
+    if (reuse_transform || keep_transform) {
+      if (!reuse_transform) launch_srht_transform(A, sg, npad, Z, st);
+      launch_gather_rows(Z, A.d, rows, m, scale, SA, st);
+    } else {
+      PoolBuf wb(c.pool);
+      const int32_t *rstart = nullptr, *rk = nullptr;
+      build_row_sample(rows, m, npad, wb.ensure((size_t)row_sample_work_bytes(m, npad)), &rstart,
+                       &rk, st);
+      if (!launch_srht_transform(A, sg, npad, Z, st, rstart, rk, scale, SA))
+        launch_gather_rows(Z, A.d, rows, m, scale, SA, st);
+    }
   } else {
     fail(IHSBIN_EINVAL, "unknown sketch type");
   }
@@ -683,6 +697,7 @@ struct Sketcher {
   // on r alone up to the common factor 1 / sqrt(m), so growing m keeps them,
   // rescaled by sqrt(m_old / m), and draws only the new rows.
   int64_t gauss_rows = 0;
+  bool srht_whole = false;  // the SRHT transform of the last call is complete
   // CountSketch / SJLT of a CSR matrix: SA is kept sparse and its Gram is
   // formed from its entries (gram_prec does not apply)
   bool sparse_sketch() const {
@@ -722,8 +737,13 @@ struct Sketcher {
       gauss_rows = mm;
     } else {
       double* SA = static_cast<double*>(SAb.ensure(sizeof(double) * rows * A.d));
-      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && o.sketch == IHSBIN_SRHT,
-                        o.sketch_prec);
+      // an SRHT keeps its whole transform only while a later probe could
+      // sample it again (m below the cap)
+      const bool srht = o.sketch == IHSBIN_SRHT;
+      const bool keep = srht && o.adaptive_m != 0 && mm < m_cap;
+      sketch_apply_impl(c, A, o.sketch, s, mm, o.seed, SA, trials > 0 && srht && srht_whole,
+                        o.sketch_prec, 0, keep);
+      if (srht) srht_whole = keep || (trials > 0 && srht_whole);
       gauss_rows = o.sketch == IHSBIN_GAUSSIAN ? mm : 0;
     }
     gram_impl(c, static_cast<const double*>(SAb.p), rows, A.d, G, o.gram_prec);
