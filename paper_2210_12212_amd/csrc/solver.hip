@@ -452,13 +452,17 @@ static Ritz ritz_extremes(const std::vector<double>& h, int na, int J, int a, in
 // nv = 2: columns a and a + na/2 share a factor (ids holds na/2 entries).
 // The A^T A product of the working form (one matrix): S = A^T A T for w
 // columns of row stride ld.
+// f32: the products on the FP32 matrix cores (dense FP32 A; ignored
+// otherwise).  The spectrum estimates take them when the basis may: their
+// Ritz values move by ~1e-7 relative, far inside the bounds' 2 % slack.
 struct AtaProd {
   Ctx& c;
   const MatView& A;
+  bool f32 = false;
   int64_t d() const { return A.d; }
   int64_t slack(int64_t) const { return 0; }
   void operator()(const double* T, int64_t w, int64_t ld, double* S) const {
-    ata_apply(c, A, T, w, ld, S, ld, nullptr, ld);
+    ata_apply(c, A, T, w, ld, S, ld, nullptr, ld, f32);
   }
 };
 
@@ -1047,6 +1051,10 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     return std::min(m_cap, m * mult);
   };
   const bool adapt = o.adaptive_m == 1 && !o.taus;
+  // spectrum estimates on the FP32 matrix cores when the basis products may
+  // run there (dense FP32 A)
+  const bool spec32 = o.basis_prec != IHSBIN_BASIS_F64 && A.format == IHSBIN_DENSE &&
+                      A.dtype == IHSBIN_F32;
   // Sketches whose cost does not grow with m (SRHT: one transform;
   // CountSketch/SJLT: one pass over A) pay for m only through the 2 m d^2
   // Gram, while a larger m shrinks the spectrum of P_S (A^T A + lam I) and
@@ -1086,7 +1094,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb);
     EarlyIfSlow early;
     early.target = o.rate_target;
-    auto sp = interval_spectra(c, AtaProd{c, A}, Li1, {0}, {grid[0]}, {grid[1]},
+    auto sp = interval_spectra(c, AtaProd{c, A, spec32}, Li1, {0}, {grid[0]}, {grid[1]},
                                std::max(8, o.lanczos_steps),
                                o.seed, early);
     logf("probe m=%lld: c=[%.4g, %.4g] rate0=%.3f (target %.3f)", (long long)m, sp[0].mu_min,
@@ -1117,7 +1125,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     IHS_HIP(hipStreamSynchronize(st));
     r.ms_factor += tf.ms();
     Timer tspec;
-    spec = interval_spectra(c, AtaProd{c, A}, Linv, all,
+    spec = interval_spectra(c, AtaProd{c, A, spec32}, Linv, all,
                             std::vector<double>(grid.begin(), grid.end() - 1),
                             std::vector<double>(grid.begin() + 1, grid.end()),
                             std::max(2, o.lanczos_steps), o.seed + 1, NoEarly{});
