@@ -331,6 +331,7 @@ void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int64_t ld, i
 // y_b = L_{map[b]} x_b (lower triangular, row-major d x d): one wave per row
 // (general fallback for d above the LDS staging limit).
 __global__ __launch_bounds__(256) void trmv_lower_kernel(const double* __restrict__ L, int64_t d,
+                                                         int64_t ldl, int64_t ms,
                                                          const int32_t* __restrict__ map, int nb,
                                                          const double* __restrict__ X, int64_t ldx,
                                                          double* __restrict__ Y, int64_t ldy) {
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(256) void trmv_lower_kernel(const double* __restric
   for (int64_t t = wave; t < d * nb; t += nwaves) {
     const int b = (int)(t / d);
     const int64_t r = t % d;
-    const double* row = L + (int64_t)map[b] * d * d + r * d;
+    const double* row = L + (int64_t)map[b] * ms + r * ldl;
     double s0 = 0.0, s1 = 0.0;
     for (int64_t k = lane; k <= r; k += 128) {
       s0 += row[k] * X[k * ldx + b];
@@ -359,7 +360,7 @@ constexpr int64_t kTrmvLdsMax = 8192;
 
 template <int NV>
 __global__ __launch_bounds__(256) void trmv_lower_lds_kernel(const double* __restrict__ L,
-                                                             int64_t d,
+                                                             int64_t d, int64_t ldl, int64_t ms,
                                                              const int32_t* __restrict__ map,
                                                              int nm, const double* __restrict__ X,
                                                              int64_t ldx, double* __restrict__ Y,
@@ -373,10 +374,11 @@ __global__ __launch_bounds__(256) void trmv_lower_lds_kernel(const double* __res
     for (int v = 0; v < NV; ++v) xs[v][k] = X[k * ldx + b + v * nm];
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double* Lb = L + (int64_t)map[b] * d * d;
-  const bool vec = (d & 1) == 0;
+  const double* Lb = L + (int64_t)map[b] * ms;
+  // 16-byte loads need every row start 16-byte aligned
+  const bool vec = (ldl & 1) == 0 && ((reinterpret_cast<uintptr_t>(Lb) & 15) == 0);
   for (int64_t r = r0 + w; r < rend; r += 4) {
-    const double* row = Lb + r * d;
+    const double* row = Lb + r * ldl;
     double s[NV][2];
 #pragma unroll
     for (int v = 0; v < NV; ++v) s[v][0] = s[v][1] = 0.0;
@@ -414,8 +416,9 @@ constexpr int kTrmvRows = 256;
 
 template <int NV>
 __global__ __launch_bounds__(256) void trmv_upper_t_partial_kernel(
-    const double* __restrict__ L, int64_t d, const int32_t* __restrict__ map, int nm,
-    const double* __restrict__ X, int64_t ldx, double* __restrict__ part) {
+    const double* __restrict__ L, int64_t d, int64_t ldl, int64_t ms,
+    const int32_t* __restrict__ map, int nm, const double* __restrict__ X, int64_t ldx,
+    double* __restrict__ part) {
   __shared__ double red[NV][4][64];
   const int64_t panels = (d + 63) / 64, chunks = (d + kTrmvRows - 1) / kTrmvRows;
   const int64_t job = blockIdx.x;
@@ -423,7 +426,7 @@ __global__ __launch_bounds__(256) void trmv_upper_t_partial_kernel(
   const int64_t pc = job % (panels * chunks);
   const int64_t c0 = (pc / chunks) * 64, r0 = (pc % chunks) * kTrmvRows;
   const int cc = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const double* Lb = L + (int64_t)map[b] * d * d;
+  const double* Lb = L + (int64_t)map[b] * ms;
   const int64_t c = c0 + cc;
   double s[NV];
 #pragma unroll
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(256) void trmv_upper_t_partial_kernel(
   if (c < d && r0 + kTrmvRows > c0) {
     const int64_t rs = r0 > c0 ? r0 : c0, re = (r0 + kTrmvRows) < d ? (r0 + kTrmvRows) : d;
     for (int64_t r = rs + g; r < re; r += 4) {
-      const double a = Lb[r * d + c];
+      const double a = Lb[r * ldl + c];
 #pragma unroll
       for (int v = 0; v < NV; ++v) s[v] += a * X[r * ldx + b + v * nm];
     }
@@ -463,35 +466,41 @@ __global__ void trmv_upper_t_sum_kernel(const double* __restrict__ part, int64_t
 void launch_trmv(const double* L, int64_t d, const int32_t* map, int nb, bool transpose,
                  const double* X, int64_t ldx, double* Y, int64_t ldy, double* scratch,
                  hipStream_t st, int nv) {
+  launch_trmv_block(L, d, d, d * d, map, nb, transpose, X, ldx, Y, ldy, scratch, st, nv);
+}
+
+void launch_trmv_block(const double* L, int64_t d, int64_t ldl, int64_t ms, const int32_t* map,
+                       int nb, bool transpose, const double* X, int64_t ldx, double* Y,
+                       int64_t ldy, double* scratch, hipStream_t st, int nv) {
   if (nv != 1 && nv != 2) fail(IHSBIN_EINVAL, "trmv: nv must be 1 or 2");
   if (nb % nv) fail(IHSBIN_EINVAL, "trmv: columns not a multiple of nv");
   const int nm = nb / nv;
   if (!transpose) {
     if (nv == 2 && d <= kTrmvLdsMax / 2 && nm <= 65535) {
       hipLaunchKernelGGL(trmv_lower_lds_kernel<2>, dim3((unsigned)cdiv(d, kTrmvLRows), (unsigned)nm),
-                         dim3(256), 0, st, L, d, map, nm, X, ldx, Y, ldy);
+                         dim3(256), 0, st, L, d, ldl, ms, map, nm, X, ldx, Y, ldy);
     } else if (d <= kTrmvLdsMax && nb <= 65535) {
       // one vector per block; the second half of a paired layout reuses map
       for (int v = 0; v < nv; ++v)
         hipLaunchKernelGGL(trmv_lower_lds_kernel<1>,
                            dim3((unsigned)cdiv(d, kTrmvLRows), (unsigned)nm), dim3(256), 0, st, L,
-                           d, map, nm, X + v * nm, ldx, Y + v * nm, ldy);
+                           d, ldl, ms, map, nm, X + v * nm, ldx, Y + v * nm, ldy);
     } else {
       int64_t blocks = cdiv(d * nm * 64, 256);
       if (blocks > 65536) blocks = 65536;
       for (int v = 0; v < nv; ++v)
-        hipLaunchKernelGGL(trmv_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, d, map,
-                           nm, X + v * nm, ldx, Y + v * nm, ldy);
+        hipLaunchKernelGGL(trmv_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, d, ldl,
+                           ms, map, nm, X + v * nm, ldx, Y + v * nm, ldy);
     }
   } else {
     const int64_t chunks = cdiv(d, kTrmvRows);
     const dim3 grid((unsigned)(cdiv(d, 64) * chunks * nm));
     if (nv == 2)
-      hipLaunchKernelGGL(trmv_upper_t_partial_kernel<2>, grid, dim3(256), 0, st, L, d, map, nm, X,
-                         ldx, scratch);
+      hipLaunchKernelGGL(trmv_upper_t_partial_kernel<2>, grid, dim3(256), 0, st, L, d, ldl, ms, map,
+                         nm, X, ldx, scratch);
     else
-      hipLaunchKernelGGL(trmv_upper_t_partial_kernel<1>, grid, dim3(256), 0, st, L, d, map, nm, X,
-                         ldx, scratch);
+      hipLaunchKernelGGL(trmv_upper_t_partial_kernel<1>, grid, dim3(256), 0, st, L, d, ldl, ms, map,
+                         nm, X, ldx, scratch);
     IHS_CHECK_LAUNCH();
     int64_t blocks = cdiv(d * nb, 256);
     if (blocks > 4096) blocks = 4096;

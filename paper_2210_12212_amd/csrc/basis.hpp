@@ -40,6 +40,11 @@ void launch_lanczos_orth(double* Q, double* Wv, int64_t d, int na, int64_t ld, i
 void launch_trmv(const double* L, int64_t d, const int32_t* map, int nb, bool transpose,
                  const double* X, int64_t ldx, double* Y, int64_t ldy, double* scratch,
                  hipStream_t st, int nv = 1);
+// The same on the n x n diagonal block of each factor that starts at L (row
+// stride ldl, factor b at L + map[b] * ms): X and Y hold the block's rows.
+void launch_trmv_block(const double* L, int64_t n, int64_t ldl, int64_t ms, const int32_t* map,
+                       int nb, bool transpose, const double* X, int64_t ldx, double* Y,
+                       int64_t ldy, double* scratch, hipStream_t st, int nv = 1);
 int64_t trmv_scratch_doubles(int64_t d, int nb);
 
 }  // namespace ihs

@@ -379,6 +379,7 @@ struct RecFactor {
   }
 
   int64_t work_doubles;  // capacity of work
+  bool top_inverse = true;  // form X21 at the top split as well
 
   void run(int64_t o, int64_t n) {
     if (n <= kNB) {
@@ -415,6 +416,9 @@ struct RecFactor {
     g2.lower_only = 1;
     gemm(g2, DT::F64, false, DT::F64, true, st);
     run(o + n1, n2);
+    // without the top split's X21, L^-1 is applied through its blocks
+    // (X11, L21, X22): 3/4 of the inverse's flops are in this split
+    if (o == 0 && n == d && !top_inverse) return;
     // T = L21 X11 (X11 lower triangular), then X21 = -X22 T (X22 lower)
     Gemm g3 = base(n2, n1, n1);
     g3.A = H21;
@@ -449,8 +453,10 @@ int64_t factor_inverse_work_doubles(int64_t d, int nl) {
   return std::max<int64_t>(1, largest_split(d) * nl);
 }
 
+int64_t factor_top_split(int64_t d) { return d <= kNB ? 0 : cdiv(cdiv(d, 2), kNB) * kNB; }
+
 void factor_inverse_batched(double* H, double* X, int64_t d, int nl, double* dinv,
-                            int* status_dev, double* work, hipStream_t st) {
+                            int* status_dev, double* work, hipStream_t st, bool full) {
   {
     int64_t blocks = cdiv(d * d * nl, 256);
     if (blocks > 16384) blocks = 16384;
@@ -459,7 +465,7 @@ void factor_inverse_batched(double* H, double* X, int64_t d, int nl, double* din
     IHS_CHECK_LAUNCH();
   }
   RecFactor rf{H, X, d, nl, dinv, (int)cdiv(d, kNB), status_dev, work, st,
-               factor_inverse_work_doubles(d, nl)};
+               factor_inverse_work_doubles(d, nl), full};
   rf.run(0, d);
   if (d > kNB) {
     int64_t blocks = cdiv(d * kUpperBand * nl, 256);

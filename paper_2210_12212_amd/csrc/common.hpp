@@ -190,20 +190,20 @@ struct Ctx {
   double bytes_moved = 0.0;
   Pool pool;     // build-local buffers (declared first: outlives the workspaces below)
   // scratch shared by the step kernels of one call
-  DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status, ws_f32;
+  DevBuf ws_y, ws_part, ws_small, ws_sketch, ws_tmp, ws_status, ws_f32, ws_ps;
   // a private stream (default priority) that work is captured on into HIP
   // graphs, created on first use and destroyed with the context
   hipStream_t capture_stream = nullptr;
   // every buffer of the context is used on `stream` only
   void bind() {
     pool.bind(stream, &mem);
-    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status, &ws_f32})
+    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status, &ws_f32, &ws_ps})
       b->bind(stream, &mem);
   }
   // hand idle pool blocks and the workspaces back to the device
   void trim() {
     pool.release_idle();
-    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status, &ws_f32})
+    for (DevBuf* b : {&ws_y, &ws_part, &ws_small, &ws_sketch, &ws_tmp, &ws_status, &ws_f32, &ws_ps})
       b->release();
   }
 };

@@ -79,9 +79,14 @@ void cholesky_batched(double* H, int64_t d, int nl, double* dinv, int* status_de
 // The factor and its inverse together, by halves (recursive: L and
 // X = L^-1 of every H_l; H's upper triangle zeroed, X's upper triangle zero).  status_dev as cholesky_batched;
 // work: factor_inverse_work_doubles(d, nl) doubles.
+// full = false: the top split's lower-left block of X is not formed (it
+// holds L21 instead); L^-1 is then [X11 0; -X22 L21 X11  X22] with
+// n1 = factor_top_split(d), X11 = X[0:n1, 0:n1], X22 = X[n1:, n1:] and L21
+// from H.
 void factor_inverse_batched(double* H, double* X, int64_t d, int nl, double* dinv,
-                            int* status_dev, double* work, hipStream_t st);
+                            int* status_dev, double* work, hipStream_t st, bool full = true);
 int64_t factor_inverse_work_doubles(int64_t d, int nl);
+int64_t factor_top_split(int64_t d);
 constexpr int kNB = 64;
 
 // ------------------------------------------------------------ products with A
@@ -129,6 +134,9 @@ void launch_gather_blocks(const double* src, const int32_t* blk, int nb, int64_t
 void launch_scatter_blocks(const double* Z, int64_t ldz, const int32_t* blk, int nb, int64_t rows,
                            int64_t K, double* dst, hipStream_t st);
 int64_t padded_width(int64_t w);
+// dst (rows x cols, row stride ldd) = src (row stride lds).
+void launch_copy_rect(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst,
+                      int64_t ldd, hipStream_t st);
 // f32: products on the FP32 matrix cores (dense FP32 A only; each column of U
 // scaled by a power of two into range and rounded to FP32, Y = A U kept in
 // FP32, A^T Y summed in FP32 over at most 16384 rows and in FP64 across them,

@@ -402,6 +402,26 @@ void launch_scatter_blocks(const double* Z, int64_t ldz, const int32_t* blk, int
   IHS_CHECK_LAUNCH();
 }
 
+__global__ void copy_rect_kernel(const double* __restrict__ src, int64_t lds, int64_t rows,
+                                 int64_t cols, double* __restrict__ dst, int64_t ldd) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / cols, c = t - r * cols;
+    dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+
+void launch_copy_rect(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst,
+                      int64_t ldd, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  int64_t blocks = cdiv(rows * cols, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(copy_rect_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, lds, rows,
+                     cols, dst, ldd);
+  IHS_CHECK_LAUNCH();
+}
+
 int64_t padded_width(int64_t w) {
   if (w <= 16) return 16;
   if (w <= 32) return 32;

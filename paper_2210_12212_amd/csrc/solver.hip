@@ -284,9 +284,12 @@ static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G,
 // H_l = G + lam0_l I, factor in place, and Linv_l = L_l^-1.
 // gper > 0: matrix l is built from G block l / gper (blocks of d x d), so the
 // factors of several Grams run in one batch.
-static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<double>& lam0s,
-                        double* Lf, double* Linv, PoolBuf& dinv_buf, PoolBuf& lam_buf,
-                        int gper = 0) {
+// split: leave out the top split's lower-left block of L^-1 (applied through
+// X11, L21, X22 instead, see PsFactors); returns that split (0: Linv is the
+// whole inverse).
+static int64_t factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<double>& lam0s,
+                           double* Lf, double* Linv, PoolBuf& dinv_buf, PoolBuf& lam_buf,
+                           int gper = 0, bool split = false) {
   const int nl = (int)lam0s.size();
   double* lam_dev = static_cast<double*>(lam_buf.ensure(sizeof(double) * nl));
   IHS_HIP(hipMemcpyAsync(lam_dev, lam0s.data(), sizeof(double) * nl, hipMemcpyHostToDevice, c.stream));
@@ -300,7 +303,7 @@ static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<do
     // factor and inverse together, by halves
     double* wk = static_cast<double*>(work.ensure(
         sizeof(double) * (size_t)std::max<int64_t>(1, factor_inverse_work_doubles(d, nl))));
-    factor_inverse_batched(Lf, Linv, d, nl, dinv, status, wk, c.stream);
+    factor_inverse_batched(Lf, Linv, d, nl, dinv, status, wk, c.stream, !split);
   } else {
     cholesky_batched(Lf, d, nl, dinv, status, c.stream);
   }
@@ -308,7 +311,21 @@ static void factor_impl(Ctx& c, const double* G, int64_t d, const std::vector<do
   IHS_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
   IHS_HIP(hipStreamSynchronize(c.stream));
   if (h) fail(IHSBIN_ENOTSPD, "sketched Hessian not positive definite");
+  return Linv && split ? factor_top_split(d) : 0;
 }
+
+// The preconditioner P_S = L^-T L^-1 of every interval: X holds L^-1 whole
+// (n1 == 0) or only its diagonal blocks X11 = L11^-1 (n1 x n1) and
+// X22 = L22^-1, with L21 read from the Cholesky factor Lf; then
+//   L^-1 [v1; v2] = [X11 v1; X22 (v2 - L21 X11 v1)],
+//   L^-T [y1; y2] = [X11^T (y1 - L21^T X22^T y2); X22^T y2],
+// which reads the same bytes as the whole inverse (X11, L21, X22 are its
+// quarters) without the two GEMMs that would form its lower-left block.
+struct PsFactors {
+  const double* X = nullptr;
+  const double* Lf = nullptr;
+  int64_t n1 = 0;
+};
 
 // Z = P R for every active position: P_a = Linv_{ids[a]}^T Linv_{ids[a]}.
 // Each product reads a whole triangular factor for a few columns, so it is
@@ -320,14 +337,89 @@ static int apply_p_splits(int na, int64_t d, int64_t cw) {
   return splits;
 }
 
-// Grow the split-K workspace of apply_p for na positions of cw columns.
+// Grow the workspaces of apply_p for na positions of cw columns (the split-K
+// partials at most 16 splits, the split factors' block temporary), so that
+// calls captured into a graph allocate nothing.
 static void apply_p_reserve(Ctx& c, int na, int64_t d, int64_t cw) {
   const int splits = apply_p_splits(na, d, cw);
-  if (splits > 1) c.ws_part.ensure(sizeof(double) * (size_t)splits * na * (size_t)d * (size_t)cw);
+  if (splits > 1) c.ws_part.ensure(sizeof(double) * (size_t)16 * na * (size_t)d * (size_t)cw);
+  c.ws_ps.ensure(sizeof(double) * (size_t)d * na * (size_t)cw);
 }
 
-static void apply_p(Ctx& c, const double* Linv_all, const int32_t* ids_dev, int na, int64_t d,
+// C_a = alpha op(A_a) B_a + beta C_a for na positions: A_a = A0 + ids[a] d^2
+// (row stride d), op(A_a) M x K; B_a, C_a = N columns from column a N of B, C
+// (row strides ldb, ldc).  Skinny products split K over the factor's read
+// (fixed-order reduction).
+static void ps_product(Ctx& c, const double* A0, int64_t d, const int32_t* ids, int na, bool trans,
+                       int tri, int64_t M, int64_t N, int64_t K, const double* B, int64_t ldb,
+                       double* C, int64_t ldc, double alpha, double beta) {
+  if (M <= 0 || N <= 0) return;
+  const int splits = apply_p_splits(na, std::max(M, K), N);
+  Gemm g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A0;
+  g.lda = d;
+  g.strideA = d * d;
+  g.amap = ids;
+  g.B = B;
+  g.ldb = ldb;
+  g.strideB = N;
+  g.batch = na;
+  g.tri = tri;
+  if (splits > 1) {
+    double* part = static_cast<double*>(
+        c.ws_part.ensure(sizeof(double) * (size_t)splits * na * (size_t)M * (size_t)N));
+    g.C = part;
+    g.ldc = N;
+    g.strideC = M * N;
+    g.splits = splits;
+    gemm(g, DT::F64, trans, DT::F64, false, c.stream);
+    reduce_splits(part, splits, na, M, N, N, M * N, C, ldc, N, alpha, beta, c.stream);
+  } else {
+    g.C = C;
+    g.ldc = ldc;
+    g.strideC = N;
+    g.alpha = alpha;
+    g.beta = beta;
+    gemm(g, DT::F64, trans, DT::F64, false, c.stream);
+  }
+}
+
+// Y = L^-1 X (lower) or L^-T X (upper) for the split factors, na positions of
+// N columns (row stride ld); tmp: max(n1, n2) x (na N) doubles.
+static void ps_split_apply(Ctx& c, const PsFactors& F, const int32_t* ids, int na, int64_t d,
+                           int64_t N, int64_t ld, bool upper, const double* X, double* Y,
+                           double* tmp) {
+  const int64_t n1 = F.n1, n2 = d - n1, ldt = (int64_t)na * N;
+  const double* X11 = F.X;
+  const double* X22 = F.X + n1 * d + n1;
+  const double* L21 = F.Lf + n1 * d;
+  hipStream_t st = c.stream;
+  if (!upper) {
+    ps_product(c, X11, d, ids, na, false, 1, n1, N, n1, X, ld, Y, ld, 1.0, 0.0);
+    launch_copy_rect(X + n1 * ld, ld, n2, ldt, tmp, ldt, st);
+    ps_product(c, L21, d, ids, na, false, 0, n2, N, n1, Y, ld, tmp, ldt, -1.0, 1.0);
+    ps_product(c, X22, d, ids, na, false, 1, n2, N, n2, tmp, ldt, Y + n1 * ld, ld, 1.0, 0.0);
+  } else {
+    ps_product(c, X22, d, ids, na, true, 2, n2, N, n2, X + n1 * ld, ld, Y + n1 * ld, ld, 1.0, 0.0);
+    launch_copy_rect(X, ld, n1, ldt, tmp, ldt, st);
+    ps_product(c, L21, d, ids, na, true, 0, n1, N, n2, Y + n1 * ld, ld, tmp, ldt, -1.0, 1.0);
+    ps_product(c, X11, d, ids, na, true, 2, n1, N, n1, tmp, ldt, Y, ld, 1.0, 0.0);
+  }
+}
+
+static void apply_p(Ctx& c, const PsFactors& F, const int32_t* ids_dev, int na, int64_t d,
                     int64_t cw, int64_t ld, const double* R, double* T, double* Z) {
+  if (F.n1 > 0) {
+    double* tmp = static_cast<double*>(
+        c.ws_ps.ensure(sizeof(double) * (size_t)std::max(F.n1, d - F.n1) * na * (size_t)cw));
+    ps_split_apply(c, F, ids_dev, na, d, cw, ld, false, R, T, tmp);
+    ps_split_apply(c, F, ids_dev, na, d, cw, ld, true, T, Z, tmp);
+    return;
+  }
+  const double* Linv_all = F.X;
   const int splits = apply_p_splits(na, d, cw);
   double* part = splits > 1 ? static_cast<double*>(c.ws_part.ensure(
                                   sizeof(double) * (size_t)splits * na * (size_t)d * (size_t)cw))
@@ -467,7 +559,7 @@ struct AtaProd {
 };
 
 template <class Early, class Prod>
-static std::vector<Spec> spectrum_impl(Ctx& c, const Prod& prod, const double* Linv_all,
+static std::vector<Spec> spectrum_impl(Ctx& c, const Prod& prod, const PsFactors& F,
                                        const std::vector<int32_t>& ids,
                                        const std::vector<double>& shifts, int J, uint64_t seed,
                                        Early early, int nv = 1) {
@@ -491,16 +583,49 @@ static std::vector<Spec> spectrum_impl(Ctx& c, const Prod& prod, const double* L
   double* beta = alpha + (size_t)na * J;
   int32_t* ids_dev = static_cast<int32_t*>(idb.ensure(sizeof(int32_t) * na));
   double* lam_dev = static_cast<double*>(lb.ensure(sizeof(double) * na));
-  IHS_HIP(hipMemcpyAsync(ids_dev, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, st));
+  // one id per column (column b + v nm takes ids[b]): the triangular
+  // products read the first nm, the L21 products all na
+  std::vector<int32_t> col_ids((size_t)na);
+  for (int a = 0; a < na; ++a) col_ids[a] = ids[a % ids.size()];
+  IHS_HIP(hipMemcpyAsync(ids_dev, col_ids.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
   IHS_HIP(hipMemcpyAsync(lam_dev, shifts.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
   launch_lanczos_start(seed, d, na, ld, Q, st);
   std::vector<double> h(2 * (size_t)na * J);
   int steps = J;
+  // Y = L^-1 X or L^-T X for every column (its interval's factor); the
+  // split factors go through their diagonal blocks and L21 (PsFactors)
+  PoolBuf tmb(c.pool);
+  double* tmv = F.n1 > 0 ? static_cast<double*>(tmb.ensure(
+                               sizeof(double) * (size_t)std::max(F.n1, d - F.n1) * ld))
+                         : nullptr;
+  auto linv = [&](bool transpose, const double* X, double* Y) {
+    if (F.n1 == 0) {
+      launch_trmv(F.X, d, ids_dev, na, transpose, X, ld, Y, ld, trs, st, nv);
+      return;
+    }
+    const int64_t n1 = F.n1, n2 = d - n1;
+    const double* X11 = F.X;
+    const double* X22 = F.X + n1 * d + n1;
+    const double* L21 = F.Lf + n1 * d;
+    if (!transpose) {
+      launch_trmv_block(X11, n1, d, d * d, ids_dev, na, false, X, ld, Y, ld, trs, st, nv);
+      launch_copy_rect(X + n1 * ld, ld, n2, na, tmv, ld, st);
+      ps_product(c, L21, d, ids_dev, na, false, 0, n2, 1, n1, Y, ld, tmv, ld, -1.0, 1.0);
+      launch_trmv_block(X22, n2, d, d * d, ids_dev, na, false, tmv, ld, Y + n1 * ld, ld, trs, st,
+                        nv);
+    } else {
+      launch_trmv_block(X22, n2, d, d * d, ids_dev, na, true, X + n1 * ld, ld, Y + n1 * ld, ld,
+                        trs, st, nv);
+      launch_copy_rect(X, ld, n1, na, tmv, ld, st);
+      ps_product(c, L21, d, ids_dev, na, true, 0, n1, 1, n2, Y + n1 * ld, ld, tmv, ld, -1.0, 1.0);
+      launch_trmv_block(X11, n1, d, d * d, ids_dev, na, true, tmv, ld, Y, ld, trs, st, nv);
+    }
+  };
   for (int j = 0; j < J; ++j) {
-    launch_trmv(Linv_all, d, ids_dev, na, true, Q + (size_t)j * d * ld, ld, T, ld, trs, st, nv);  // T = Linv^T q
+    linv(true, Q + (size_t)j * d * ld, T);           // T = Linv^T q
     prod(T, na, ld, S);                                // S = A^T A T
     launch_add_shift(S, T, d, na, ld, lam_dev, st);   // S += shift T
-    launch_trmv(Linv_all, d, ids_dev, na, false, S, ld, Wv, ld, trs, st, nv);                  // W = Linv S
+    linv(false, S, Wv);                                // W = Linv S
     launch_lanczos_orth(Q, Wv, d, na, ld, j, J, alpha, beta, st);
     // checked after every step from early.min_steps on (a sketch far too small
     // shows within two or three steps; converged extremes stop the run)
@@ -589,7 +714,7 @@ struct EarlyIfAnySlow {
 // lies between the smallest eigenvalue at lo and the largest at hi.  One
 // Lanczos column per interval end; fids[i] is the factor of interval i.
 template <class Early, class Prod>
-static std::vector<Spec> interval_spectra(Ctx& c, const Prod& prod, const double* Linv_all,
+static std::vector<Spec> interval_spectra(Ctx& c, const Prod& prod, const PsFactors& F,
                                           const std::vector<int32_t>& fids,
                                           const std::vector<double>& los,
                                           const std::vector<double>& his, int J, uint64_t seed,
@@ -600,7 +725,7 @@ static std::vector<Spec> interval_spectra(Ctx& c, const Prod& prod, const double
     shifts[i] = los[i];
     shifts[ni + i] = his[i];
   }
-  const std::vector<Spec> col = spectrum_impl(c, prod, Linv_all, fids, shifts, J, seed, early, 2);
+  const std::vector<Spec> col = spectrum_impl(c, prod, F, fids, shifts, J, seed, early, 2);
   std::vector<Spec> out(ni);
   for (int i = 0; i < ni; ++i) {
     out[i].mu_min = col[i].mu_min;
@@ -799,13 +924,16 @@ static ihsbin_alg4_result alg4_impl(Ctx& c, const MatView& A, const double* C, i
     IHS_HIP(hipMemcpyAsync(h, dev_out, sizeof(h), hipMemcpyDeviceToHost, st));
     IHS_HIP(hipStreamSynchronize(st));
   };
+  PsFactors F;
   auto redraw = [&](int64_t m) {
     sk(m);
-    factor_impl(c, sk.G, d, {lam}, Lf, Li, dinvb, lamb);
+    F.n1 = factor_impl(c, sk.G, d, {lam}, Lf, Li, dinvb, lamb, 0, true);
+    F.X = Li;
+    F.Lf = Lf;
   };
   // D = P_S Gr and delta = <D, Gr>
   auto direction = [&]() {
-    apply_p(c, Li, ids, 1, d, K, K, Gr, T, D);
+    apply_p(c, F, ids, 1, d, K, K, Gr, T, D);
     dots(nullptr);
     return h[0];
   };
@@ -1091,10 +1219,13 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   while (adapt && m < m_cap && trials < 8) {
     double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
-    factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb);
+    PsFactors F1;
+    F1.n1 = factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb, 0, true);
+    F1.X = Li1;
+    F1.Lf = Lf1;
     EarlyIfSlow early;
     early.target = o.rate_target;
-    auto sp = interval_spectra(c, AtaProd{c, A, spec32}, Li1, {0}, {grid[0]}, {grid[1]},
+    auto sp = interval_spectra(c, AtaProd{c, A, spec32}, F1, {0}, {grid[0]}, {grid[1]},
                                std::max(8, o.lanczos_steps),
                                o.seed, early);
     logf("probe m=%lld: c=[%.4g, %.4g] rate0=%.3f (target %.3f)", (long long)m, sp[0].mu_min,
@@ -1115,17 +1246,20 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   for (int l = 0; l < L; ++l) all[l] = l;
   double* Lf = nullptr;
   double* Linv = nullptr;
+  PsFactors PF;
   int regrows = 0;
   const int kcap_steps = o.k_fixed > 0 ? o.k_fixed : o.k_max;
   for (;;) {
     Timer tf;
     Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d * L));
     Linv = static_cast<double*>(Ib.ensure(sizeof(double) * d * d * L));
-    factor_impl(c, G, d, lam0, Lf, Linv, dinvb, lamb);
+    PF.n1 = factor_impl(c, G, d, lam0, Lf, Linv, dinvb, lamb, 0, true);
+    PF.X = Linv;
+    PF.Lf = Lf;
     IHS_HIP(hipStreamSynchronize(st));
     r.ms_factor += tf.ms();
     Timer tspec;
-    spec = interval_spectra(c, AtaProd{c, A, spec32}, Linv, all,
+    spec = interval_spectra(c, AtaProd{c, A, spec32}, PF, all,
                             std::vector<double>(grid.begin(), grid.end() - 1),
                             std::vector<double>(grid.begin() + 1, grid.end()),
                             std::max(2, o.lanczos_steps), o.seed + 1, NoEarly{});
@@ -1240,7 +1374,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   upload();
   // u_{0,0} = P_S C for every interval
   launch_seed_rhs(C, d, K, L, R, wcap, st);
-  apply_p(c, Linv, ids_dev, L, d, K, wcap, R, Tm, Ucur);
+  apply_p(c, PF, ids_dev, L, d, K, wcap, R, Tm, Ucur);
   launch_store_first(Ucur, wcap, d, K, L, ids_dev, kcap, basis, st);
 
   std::vector<hipEvent_t> events;
@@ -1275,7 +1409,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
       }
     }
     launch_form_r(W, Ucur, wcap, d, K, na, i, tau_dev, ref_dev, R, st);
-    apply_p(c, Linv, ids_dev, na, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
+    apply_p(c, PF, ids_dev, na, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
     double* part = static_cast<double*>(partial_b.ensure(sizeof(double) * 4 * na * 64));
     const int nbx = launch_update(Ucur, Z, Unext, wcap, d, K, na, i, ids_dev, kcap, basis, mlo_dev,
                                   mhi_dev, part, st);
@@ -1601,11 +1735,14 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     // the lowest interval of every problem, probed together
     double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * (size_t)P * d * d));
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)P * d * d));
-    factor_impl(c, G, d, std::vector<double>(P, lam0[0]), Lf1, Li1, dinvb, lamb, 1);
+    PsFactors F1;
+    F1.n1 = factor_impl(c, G, d, std::vector<double>(P, lam0[0]), Lf1, Li1, dinvb, lamb, 1, true);
+    F1.X = Li1;
+    F1.Lf = Lf1;
     EarlyIfAnySlow early;
     early.P = P;
     early.target = o.rate_target;
-    auto sp = interval_spectra(c, prod, Li1, pid, std::vector<double>(P, grid[0]),
+    auto sp = interval_spectra(c, prod, F1, pid, std::vector<double>(P, grid[0]),
                                std::vector<double>(P, grid[1]), std::max(8, o.lanczos_steps),
                                o.seed, early);
     int worst = 0;
@@ -1635,15 +1772,18 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
   std::vector<Spec> spec;
   double* Lf = nullptr;
   double* Linv = nullptr;
+  PsFactors PF;
   for (;;) {
     Timer tf;
     Lf = static_cast<double*>(Lb.ensure(sizeof(double) * (size_t)nl * d * d));
     Linv = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)nl * d * d));
-    factor_impl(c, G, d, lam0s, Lf, Linv, dinvb, lamb, L);
+    PF.n1 = factor_impl(c, G, d, lam0s, Lf, Linv, dinvb, lamb, L, true);
+    PF.X = Linv;
+    PF.Lf = Lf;
     IHS_HIP(hipStreamSynchronize(st));
     r.ms_factor += tf.ms();
     Timer tspec;
-    spec = interval_spectra(c, prod, Linv, all, los, his, std::max(2, o.lanczos_steps), o.seed + 1,
+    spec = interval_spectra(c, prod, PF, all, los, his, std::max(2, o.lanczos_steps), o.seed + 1,
                             NoEarly{});
     r.ms_spectrum += tspec.ms();
     int worst = 0;
@@ -1719,7 +1859,7 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     IHS_HIP(hipMemcpyAsync(mhi_dev, mh.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
   }
   launch_seed_rhs(C, d, K, nl, R, wcap, st, L);
-  apply_p(c, Linv, ids_dev, nl, d, K, wcap, R, Tm, Ucur);
+  apply_p(c, PF, ids_dev, nl, d, K, wcap, R, Tm, Ucur);
   launch_store_first(Ucur, wcap, d, K, nl, ids_dev, kcap, basis, st);
   const BatchProd prod1{c, A, strideA, P, 1};
   std::vector<double> host_part, est(nl, 0.0);
@@ -1733,7 +1873,7 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     const int64_t w_old = (int64_t)nl * i * K;
     prod1(Ucur, w_old, wcap, W);
     launch_form_r(W, Ucur, wcap, d, K, nl, i, tau_dev, ref_dev, R, s);
-    apply_p(c, Linv, ids_dev, nl, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
+    apply_p(c, PF, ids_dev, nl, d, (int64_t)(i + 1) * K, wcap, R, Tm, Z);
     const int nbx = launch_update(Ucur, Z, Unext, wcap, d, K, nl, i, ids_dev, kcap, basis, mlo_dev,
                                   mhi_dev, part, s);
     std::swap(Ucur, Unext);
