@@ -42,9 +42,10 @@ __device__ __forceinline__ void split3(double x, __bf16& a, __bf16& b, __bf16& c
 }
 }  // namespace
 
-// XS[p][c][k] = term p of X[k][c]; rows k >= m are zero (32 x 32 tiles via LDS;
-// the row tiles are strided over gridDim.y).  FP32 input splits exactly.
-template <typename T>
+// XS[p][c][k] = term p < NT of X[k][c]; rows k >= m are zero (32 x 32 tiles
+// via LDS; the row tiles are strided over gridDim.y).  Three terms split an
+// FP32 input exactly.
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void split_transpose_kernel(const T* __restrict__ X, int64_t m,
                                                               int64_t d, int64_t ldx, int64_t mpad,
                                                               __bf16* __restrict__ XS) {
@@ -65,25 +66,33 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const T* __restric
         const int64_t o = c * mpad + k;
         XS[o] = a;
         XS[d * mpad + o] = b;
-        XS[2 * d * mpad + o] = e;
+        if (NT == 3) XS[2 * d * mpad + o] = e;
       }
     }
     __syncthreads();
   }
 }
 
-void launch_split3_transpose(const void* X, bool f32, int64_t m, int64_t d, int64_t ldx,
-                             int64_t mpad, void* XS, hipStream_t st) {
+void launch_split_transpose(const void* X, bool f32, int64_t m, int64_t d, int64_t ldx,
+                            int64_t mpad, void* XS, int terms, hipStream_t st) {
   if (m <= 0 || d <= 0) return;
+  if (terms != 2 && terms != 3) fail(IHSBIN_EINVAL, "split: 2 or 3 terms");
   const unsigned gx = (unsigned)cdiv(d, 32);
   const unsigned gy = (unsigned)std::min<int64_t>(cdiv(mpad, 32), 32768);
   if (gx > 65535u) fail(IHSBIN_EUNSUP, "split: too many columns");
-  if (f32)
-    hipLaunchKernelGGL(split_transpose_kernel<float>, dim3(gx, gy), dim3(256), 0, st,
-                       static_cast<const float*>(X), m, d, ldx, mpad, static_cast<__bf16*>(XS));
+  __bf16* out = static_cast<__bf16*>(XS);
+  if (f32 && terms == 3)
+    hipLaunchKernelGGL((split_transpose_kernel<float, 3>), dim3(gx, gy), dim3(256), 0, st,
+                       static_cast<const float*>(X), m, d, ldx, mpad, out);
+  else if (f32)
+    hipLaunchKernelGGL((split_transpose_kernel<float, 2>), dim3(gx, gy), dim3(256), 0, st,
+                       static_cast<const float*>(X), m, d, ldx, mpad, out);
+  else if (terms == 3)
+    hipLaunchKernelGGL((split_transpose_kernel<double, 3>), dim3(gx, gy), dim3(256), 0, st,
+                       static_cast<const double*>(X), m, d, ldx, mpad, out);
   else
-    hipLaunchKernelGGL(split_transpose_kernel<double>, dim3(gx, gy), dim3(256), 0, st,
-                       static_cast<const double*>(X), m, d, ldx, mpad, static_cast<__bf16*>(XS));
+    hipLaunchKernelGGL((split_transpose_kernel<double, 2>), dim3(gx, gy), dim3(256), 0, st,
+                       static_cast<const double*>(X), m, d, ldx, mpad, out);
   IHS_CHECK_LAUNCH();
 }
 
@@ -198,7 +207,7 @@ void gram_bf16x3(const double* X, int64_t m, int64_t d, int64_t ldx, void* work,
   if (m <= 0 || d <= 0) return;
   const int64_t mpad = cdiv(m, kBK) * kBK;
   __bf16* XS = static_cast<__bf16*>(work);
-  launch_split3_transpose(X, false, m, d, ldx, mpad, XS, st);
+  launch_split_transpose(X, false, m, d, ldx, mpad, XS, 3, st);
   int64_t rows_per = cdiv(mpad, splits);
   rows_per = cdiv(rows_per, kBK) * kBK;
   const unsigned nt = (unsigned)cdiv(d, kT);

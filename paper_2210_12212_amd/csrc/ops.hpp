@@ -105,14 +105,17 @@ int64_t gram_bf16x3_work_bytes(int64_t m, int64_t d);
 void gram_bf16x3(const double* X, int64_t m, int64_t d, int64_t ldx, void* work, double* part,
                  int splits, hipStream_t st);
 
-// XS[p][c][k] (3 x d x mpad BF16, rows k >= m zero) = term p of the
-// three-term BF16 split of X[k][c] (X: m x d, FP32 or FP64, row stride ldx).
-void launch_split3_transpose(const void* X, bool f32, int64_t m, int64_t d, int64_t ldx,
-                             int64_t mpad, void* XS, hipStream_t st);
+// XS[p][c][k] (terms x d x mpad BF16, rows k >= m zero) = term p of the
+// BF16 split x = x0 + x1 + x2 + ... of X[k][c] (each term the BF16 rounding of
+// what the earlier ones leave; X: m x d, FP32 or FP64, row stride ldx);
+// terms = 2 or 3.
+void launch_split_transpose(const void* X, bool f32, int64_t m, int64_t d, int64_t ldx,
+                            int64_t mpad, void* XS, int terms, hipStream_t st);
 // Gaussian sketch on the BF16 matrix cores: SA = (1/sqrt(m)) G16 A where
 // G16 = BF16(FP32(z)) of the same N(0,1) draws z as launch_gaussian_fill and
-// A is split into three BF16 terms.  FP32 sums over at most kMaxSplitRows
-// rows of A, then FP64.  work: sketch_bf16_work_bytes(m, n, d) bytes.
+// A is split into two BF16 terms (what they leave is at most 2^-18 |a|).
+// FP32 sums over at most kMaxSplitRows rows of A, then FP64.  work:
+// sketch_bf16_work_bytes(m, n, d) bytes.
 int64_t sketch_bf16_work_bytes(int64_t m, int64_t n, int64_t d);
 // Rows [r_begin, m) only (earlier rows of SA are left alone).
 void gaussian_sketch_bf16(const MatView& A, uint64_t seed, int64_t m, double* SA, void* work,

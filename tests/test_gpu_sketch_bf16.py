@@ -38,9 +38,9 @@ def test_bf16_gaussian_sketch_matches_oracle(torch, ctx, n, d, m, dt):
     S16 = rng.gaussian_matrix_bf16(9, m, n)
     A64 = A.astype(np.float64)
     ref = S16 @ A64
-    # FP32 sums of at most 2048 products (each exact in FP32 for FP32 A; the
-    # three-term split keeps 24 bits of an FP64 A): error within a few
-    # 2^-24 * sqrt(2048) of sum |s||a| per entry
+    # two BF16 terms leave at most 2^-18 |a| of each entry; FP32 sums of at
+    # most 2048 exact products lose a few 2^-24 * sqrt(2048): together within
+    # 2e-5 of sum |s||a| per entry
     bound = 2e-5 * (np.abs(S16) @ np.abs(A64)) + 1e-300
     err = np.abs(SA - ref)
     assert (err <= bound).all(), (err / bound).max()
