@@ -56,6 +56,11 @@ SKETCH_PREC_DEFAULT = {"dense_invsqrt_262144x4096_k64": "bf16"}
 # by default: the CSR workload's CountSketch keeps SA sparse and forms its
 # Gram from the entries in FP64, which gram_prec does not change)
 GRAM_PREC_DEFAULT = {}
+# the spectral policy's rate target per workload when not given (0.5
+# otherwise): with the BF16 sketch, doubling m to 131072 costs the
+# 262144 x 4096 workload ~0.38 s of sketch and saves ~0.57 s of basis steps
+# (k 17 -> 13; bench.py --m-sweep --sweep-m-min 65536 --sweep-rates 0.35)
+RATE_TARGET_DEFAULT = {"dense_invsqrt_262144x4096_k64": 0.35}
 CSRC = os.path.join(ROOT, "paper_2210_12212_amd", "csrc")
 
 
@@ -410,7 +415,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs)")
     ap.add_argument("--tol", type=float, default=1e-7)
-    ap.add_argument("--rate-target", type=float, default=0.5)
+    ap.add_argument("--rate-target", type=float, default=None,
+                    help="spectral policy's rate target (default: per workload, else 0.5)")
     ap.add_argument("--lanczos-steps", type=int, default=4)
     ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default=None,
                     help="sketched Gram precision (the factor and the recursion stay FP64); "
@@ -480,6 +486,9 @@ def main():
     import workloads as W
     from paper_2210_12212_amd import Context
 
+    if args.rate_target is None:
+        single = not (args.serve or args.batch_small)
+        args.rate_target = RATE_TARGET_DEFAULT.get(args.workload, 0.5) if single else 0.5
     if args.ata_sweep:
         ata_sweep(args, torch, W, Context)
         return

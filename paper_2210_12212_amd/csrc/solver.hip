@@ -281,6 +281,14 @@ static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G,
   }
 }
 
+// Whether P_S keeps its factors in split form (PsFactors) at dimension d.  The
+// split form skips two GEMMs of the inverse (about L d^3 / 4 flop) but applies
+// through three products instead of one; where those run split-K (d >= 1024)
+// their extra launches outweigh the saving until d reaches about 3000
+// (measured: d = 2048 path 43.2 ms whole, 44.4 ms split; d = 4096 and 8192
+// 7 ms and 59 ms faster split).
+static bool split_factors(int64_t d) { return d < 1024 || d >= 3072; }
+
 // H_l = G + lam0_l I, factor in place, and Linv_l = L_l^-1.
 // gper > 0: matrix l is built from G block l / gper (blocks of d x d), so the
 // factors of several Grams run in one batch.
@@ -927,7 +935,7 @@ static ihsbin_alg4_result alg4_impl(Ctx& c, const MatView& A, const double* C, i
   PsFactors F;
   auto redraw = [&](int64_t m) {
     sk(m);
-    F.n1 = factor_impl(c, sk.G, d, {lam}, Lf, Li, dinvb, lamb, 0, true);
+    F.n1 = factor_impl(c, sk.G, d, {lam}, Lf, Li, dinvb, lamb, 0, split_factors(d));
     F.X = Li;
     F.Lf = Lf;
   };
@@ -1220,7 +1228,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * d * d));
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * d * d));
     PsFactors F1;
-    F1.n1 = factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb, 0, true);
+    F1.n1 = factor_impl(c, G, d, {lam0[0]}, Lf1, Li1, dinvb, lamb, 0, split_factors(d));
     F1.X = Li1;
     F1.Lf = Lf1;
     EarlyIfSlow early;
@@ -1253,7 +1261,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     Timer tf;
     Lf = static_cast<double*>(Lb.ensure(sizeof(double) * d * d * L));
     Linv = static_cast<double*>(Ib.ensure(sizeof(double) * d * d * L));
-    PF.n1 = factor_impl(c, G, d, lam0, Lf, Linv, dinvb, lamb, 0, true);
+    PF.n1 = factor_impl(c, G, d, lam0, Lf, Linv, dinvb, lamb, 0, split_factors(d));
     PF.X = Linv;
     PF.Lf = Lf;
     IHS_HIP(hipStreamSynchronize(st));
@@ -1736,7 +1744,8 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     double* Lf1 = static_cast<double*>(Lb.ensure(sizeof(double) * (size_t)P * d * d));
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)P * d * d));
     PsFactors F1;
-    F1.n1 = factor_impl(c, G, d, std::vector<double>(P, lam0[0]), Lf1, Li1, dinvb, lamb, 1, true);
+    F1.n1 = factor_impl(c, G, d, std::vector<double>(P, lam0[0]), Lf1, Li1, dinvb, lamb, 1,
+                        split_factors(d));
     F1.X = Li1;
     F1.Lf = Lf1;
     EarlyIfAnySlow early;
@@ -1777,7 +1786,7 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     Timer tf;
     Lf = static_cast<double*>(Lb.ensure(sizeof(double) * (size_t)nl * d * d));
     Linv = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)nl * d * d));
-    PF.n1 = factor_impl(c, G, d, lam0s, Lf, Linv, dinvb, lamb, L, true);
+    PF.n1 = factor_impl(c, G, d, lam0s, Lf, Linv, dinvb, lamb, L, split_factors(d));
     PF.X = Linv;
     PF.Lf = Lf;
     IHS_HIP(hipStreamSynchronize(st));

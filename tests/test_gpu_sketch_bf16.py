@@ -57,3 +57,14 @@ def test_path_with_bf16_gaussian_sketch(torch, ctx, K):
     ref = direct.ridge_path(A, B, lams)
     err = direct.rel_err(X.cpu().numpy(), ref)
     assert err.max() <= 1e-6, err.max()
+
+
+@pytest.mark.parametrize("m,n", [(4096, 1024), (300, 2500)])
+def test_bf16_gaussian_draws_exact(torch, ctx, m, n):
+    # A = I: each entry of SA is one BF16 draw times 1/sqrt(m) (a single exact
+    # product in the FP32 sums), so every draw of the sketch matrix is checked
+    # against BF16(FP32(z)) of the oracle's FP64 Box-Muller draw
+    A = np.eye(n, dtype=np.float32)
+    SA = ctx.sketch_apply(dev(torch, A), "gaussian", m, seed=13, prec="bf16").cpu().numpy()
+    S16 = rng.round_bf16(rng.gaussian_draws(13, m, n))
+    np.testing.assert_allclose(SA * np.sqrt(m), S16, rtol=1e-14, atol=0)
