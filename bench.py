@@ -138,7 +138,7 @@ def m_sweep(args, torch, W, Context):
     sp = args.sketch_prec or SKETCH_PREC_DEFAULT.get(p.name, "f64")
     gp = args.gram_prec or GRAM_PREC_DEFAULT.get(p.name, "f64")
     base = dict(sketch=p.sketch, seed=p.sketch_seed, tol=args.tol, rate_target=args.rate_target,
-                lanczos_steps=args.lanczos_steps, sketch_prec={"f64": 0, "bf16": 1}[sp], k_max=96,
+                lanczos_steps=args.lanczos_steps, sketch_prec={"f64": 0, "bf16": 1, "fp8": 2}[sp], k_max=96,
                 gram_prec={"f64": 0, "bf16x3": 1}[gp],
                 basis_prec={"f64": 0, "f32": 1, "mixed": 2}[args.basis_prec],
                 f32_switch=args.f32_switch)
@@ -337,7 +337,7 @@ def _serve_requests(args, W):
 def _serve_opts(req, args):
     return dict(sketch="gaussian" if req["dense"] else "countsketch", seed=req["seed"],
                 adaptive_m={"spectral": 1, "alg4": 2}[args.serve_m_policy], tol=args.tol,
-                sketch_prec={"f64": 0, "bf16": 1}[args.serve_sketch_prec],
+                sketch_prec={"f64": 0, "bf16": 1, "fp8": 2}[args.serve_sketch_prec],
                 rate_target=args.rate_target,
                 lanczos_steps=args.lanczos_steps)
 
@@ -390,8 +390,10 @@ def serve_main(args, torch, W):
         "server": st,
         "max_rel_err_sampled": errs,
         "higher_is_better": True,
-        "dtype": "f64" if args.serve_sketch_prec == "f64" and (args.gram_prec or "f64") == "f64" else
-                 "f64+bf16",
+        "dtype": "+".join(["f64"] + ([args.serve_sketch_prec] if args.serve_sketch_prec != "f64"
+                                      else []) +
+                          (["bf16"] if (args.gram_prec or "f64") == "bf16x3" and
+                           args.serve_sketch_prec != "bf16" else [])),
         "data": "synthetic",
         "config": {"workload": "small_2048x256_burst" if args.serve_small else "serving_mix",
                    "rate_per_s": None if args.serve_small else args.serve_rate,
@@ -421,7 +423,7 @@ def main():
     ap.add_argument("--gram-prec", choices=("f64", "bf16x3"), default=None,
                     help="sketched Gram precision (the factor and the recursion stay FP64); "
                          "default bf16x3 for the CSR workload, else f64")
-    ap.add_argument("--sketch-prec", choices=("f64", "bf16"), default=None,
+    ap.add_argument("--sketch-prec", choices=("f64", "bf16", "fp8"), default=None,
                     help="arithmetic of the Gaussian sketch product (other sketches ignore it); "
                          "default bf16 for the matrix-valued workload, else f64")
     ap.add_argument("--basis-prec", choices=("f64", "f32", "mixed"), default="mixed",
@@ -446,7 +448,7 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-m-policy", choices=("spectral", "alg4"), default="spectral",
                     help="sketch size of served builds")
-    ap.add_argument("--serve-sketch-prec", choices=("f64", "bf16"), default="bf16",
+    ap.add_argument("--serve-sketch-prec", choices=("f64", "bf16", "fp8"), default="bf16",
                     help="arithmetic of the Gaussian sketch product of served dense requests")
     ap.add_argument("--serve-outstanding", type=int, default=32,
                     help="client-side cap on submitted, unfinished requests")
@@ -528,7 +530,7 @@ def main():
                 rate_target=args.rate_target, lanczos_steps=args.lanczos_steps, timing=1,
                 gram_prec={"f64": 0, "bf16x3": 1}[args.gram_prec],
                 adaptive_m={"fixed": 0, "spectral": 1, "alg4": 2}[args.m_policy],
-                sketch_prec={"f64": 0, "bf16": 1}[args.sketch_prec],
+                sketch_prec={"f64": 0, "bf16": 1, "fp8": 2}[args.sketch_prec],
                 basis_prec={"f64": 0, "f32": 1, "mixed": 2}[args.basis_prec],
                 f32_switch=args.f32_switch)
     X = torch.empty((len(p.lambdas), p.d, p.B.shape[1]), dtype=torch.float64, device=dev)
@@ -712,7 +714,8 @@ def main():
         # CountSketch of a CSR matrix keeps SA sparse, its Gram in FP64)
         "dtype": "+".join(["f64"] + (["f32"] if rep.get("ata_f32_launches") else []) +
                           (["bf16"] if args.sketch_prec == "bf16" or
-                           (args.gram_prec == "bf16x3" and not sparse_gram) else [])),
+                           (args.gram_prec == "bf16x3" and not sparse_gram) else []) +
+                          (["fp8"] if args.sketch_prec == "fp8" else [])),
         "data": "synthetic",
         "config": {"workload": p.name, "n": p.n, "d": p.d, "K": int(p.B.shape[1]), "T": T,
                    "storage": str(p.A.dtype), "sketch": p.sketch, "m0": p.m,

@@ -117,11 +117,16 @@ typedef struct {
                               fixed point)                                       */
   const struct ihsbin_alg4_opts* alg4; /* host, optional: Algorithm 4 parameters
                               for adaptive_m = 2 (NULL: the defaults)            */
-  int32_t sketch_prec;     /* Gaussian S A: IHSBIN_SKETCH_F64 (default) or
+  int32_t sketch_prec;     /* Gaussian S A: IHSBIN_SKETCH_F64 (default),
                               IHSBIN_SKETCH_BF16 (BF16 matrix cores: S rounded
                               to BF16 - still a Gaussian-type sketch - and A in
-                              three BF16 terms, FP32 sums of <= 2048 rows, then
-                              FP64); other sketches ignore it                    */
+                              two BF16 terms, FP32 sums of <= 2048 rows, FP32
+                              sums of those, FP64 across K-splits) or
+                              IHSBIN_SKETCH_FP8 (FP8 matrix cores: S rounded to
+                              e4m3, A in three e4m3 terms under a per-column
+                              power-of-two scale, about 12 bits relative to the
+                              column's largest entry; same sums); dense A only,
+                              other sketches ignore it                           */
   double sigma_d2;         /* >= 0: sigma_d^2 of A (smallest squared singular
                               value) or an estimate; > 0 centres each interval
                               [lo, hi] at lam0 = sqrt((lo+s)(hi+s)) - s (the
@@ -148,7 +153,7 @@ typedef struct {
 enum { IHSBIN_BASIS_F64 = 0, IHSBIN_BASIS_F32 = 1, IHSBIN_BASIS_MIXED = 2 };
 
 /* Arithmetic of the Gaussian sketch product. */
-enum { IHSBIN_SKETCH_F64 = 0, IHSBIN_SKETCH_BF16 = 1 };
+enum { IHSBIN_SKETCH_F64 = 0, IHSBIN_SKETCH_BF16 = 1, IHSBIN_SKETCH_FP8 = 2 };
 
 /* Algorithm 4 (Section 5.1): IHS at lam with the direction
  * D_k = (A^T S^T S A + lam I)^-1 grad f(X_k), delta_k = <D_k, grad f(X_k)>,
@@ -378,8 +383,10 @@ int ihsbin_csr_transpose(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t* col_p
 
 /* SA = S A (Section 4, Algorithm 3 first line), FP64, m x d row-major into
  * SA (device, m*d doubles).  ihsbin_sketch_apply_prec selects the Gaussian
- * product's arithmetic (IHSBIN_SKETCH_F64 or IHSBIN_SKETCH_BF16, for which
- * S = BF16(FP32(z)) / sqrt(m) of the same draws z; dense A only). */
+ * product's arithmetic (IHSBIN_SKETCH_F64; IHSBIN_SKETCH_BF16, for which
+ * S = BF16(FP32(z)) / sqrt(m) of the same draws z; IHSBIN_SKETCH_FP8, for
+ * which S = E4M3(FP32(z)) / sqrt(m) and A enters as its three-term e4m3 split;
+ * dense A only for the last two; EINVAL for another value). */
 int ihsbin_sketch_apply_prec(ihsbin_ctx* ctx, const ihsbin_matrix* A, int32_t sketch,
                              int32_t sjlt_s, int64_t m, uint64_t seed, int32_t prec,
                              double* SA);

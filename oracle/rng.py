@@ -117,3 +117,31 @@ def round_bf16(x) -> np.ndarray:
 def gaussian_matrix_bf16(seed: int, m: int, n: int) -> np.ndarray:
     """The BF16 Gaussian sketch: BF16(FP32(z)) / sqrt(m) of the same draws."""
     return round_bf16(gaussian_draws(seed, m, n)) / np.sqrt(m)
+
+
+def e4m3_values() -> np.ndarray:
+    """The finite nonnegative values of the OCP FP8 e4m3 format (e4m3fn), by
+    code 0..126: code = 8 e + f with 3 fraction bits f; e = 0 holds the
+    subnormals f 2^-9, e >= 1 the normals (1 + f/8) 2^(e-7); code 127 is NaN
+    (no infinities), so the largest value is 1.75 * 2^8 = 448."""
+    e, f = np.divmod(np.arange(127), 8)
+    return np.where(e == 0, f * 2.0 ** -9, (1.0 + f / 8.0) * 2.0 ** (e - 7.0))
+
+
+def round_e4m3(x) -> np.ndarray:
+    """Round to the nearest e4m3 value through FP32 first, E4M3(FP32(x)): ties
+    to the even code, magnitudes beyond 448 saturate to 448.  Returned as
+    float64."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+    a = np.minimum(np.abs(f), 448.0)
+    vals = e4m3_values()
+    hi = np.clip(np.searchsorted(vals, a, side="left"), 1, 126)  # vals[hi-1] < a <= vals[hi]
+    lo = hi - 1
+    dlo, dhi = a - vals[lo], vals[hi] - a
+    pick = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(lo % 2 == 0, lo, hi)))
+    return np.copysign(vals[pick], f)
+
+
+def gaussian_matrix_fp8(seed: int, m: int, n: int) -> np.ndarray:
+    """The FP8 Gaussian sketch: E4M3(FP32(z)) / sqrt(m) of the same draws."""
+    return round_e4m3(gaussian_draws(seed, m, n)) / np.sqrt(m)

@@ -1,7 +1,8 @@
 """The sketch families of Section 4, built or applied plainly in FP64.
 
 Gaussian    S_ij ~ N(0, 1/m)                         (Section 4, bullet 1);
-            its BF16 form rounds the N(0,1) draws to BF16 before the 1/sqrt(m)
+            its BF16 form rounds the N(0,1) draws to BF16 before the 1/sqrt(m),
+            its FP8 form to e4m3 and multiplies A's three-term e4m3 form
 CountSketch one +-1 per column of S at a hashed row    (Section 4, bullet 2)
 SJLT        s stacked CountSketches of m/s rows each, scaled 1/sqrt(s)
                                                        (Section 4, bullet 3)
@@ -101,6 +102,50 @@ def gaussian_bf16_apply(A, seed: int, m: int) -> np.ndarray:
     """S A for the BF16 Gaussian sketch S = BF16(FP32(z)) / sqrt(m), FP64."""
     S = rng.gaussian_matrix_bf16(seed, m, A.shape[0])
     return S @ np.asarray(A, dtype=np.float64)
+
+
+def fp8_column_exponents(A) -> np.ndarray:
+    """Per column c the smallest integer e_c with max_k |a_kc| <= 448 * 2^e_c
+    (0 for a column of zeros): the power-of-two scale that brings the
+    column's largest entry to the top binade of e4m3."""
+    mx = np.abs(np.asarray(A, dtype=np.float64)).max(axis=0)
+    e = np.zeros(mx.shape, dtype=np.int64)
+    for c, v in enumerate(mx):
+        if v > 0:
+            k = int(np.floor(np.log2(v))) - 8
+            while v > np.ldexp(448.0, k):
+                k += 1
+            while v <= np.ldexp(448.0, k - 1):
+                k -= 1
+            e[c] = k
+    return e
+
+
+def fp8_terms(A):
+    """A split into three e4m3 terms under the per-column scale 2^e_c: with
+    r_0 = A 2^-e, t_p = E4M3(r_p) and r_{p+1} = 16 (r_p - t_p),
+    A ~ 2^e (t_0 + t_1/16 + t_2/256).  Returns (t (3 x n x d), e)."""
+    e = fp8_column_exponents(A)
+    r = np.ldexp(np.asarray(A, dtype=np.float64), -e[None, :])
+    t = []
+    for _ in range(3):
+        tp = rng.round_e4m3(r)
+        t.append(tp)
+        r = (r - tp) * 16.0
+    return np.stack(t), e
+
+
+def fp8_reconstruct(A) -> np.ndarray:
+    """The FP8 form of A the FP8 sketch multiplies: 2^e (t_0 + t_1/16 + t_2/256)."""
+    t, e = fp8_terms(A)
+    return np.ldexp(t[0] + t[1] / 16.0 + t[2] / 256.0, e[None, :])
+
+
+def gaussian_fp8_apply(A, seed: int, m: int) -> np.ndarray:
+    """S A for the FP8 Gaussian sketch: S = E4M3(FP32(z)) / sqrt(m) applied to
+    the three-term e4m3 form of A, FP64."""
+    S = rng.gaussian_matrix_fp8(seed, m, A.shape[0])
+    return S @ fp8_reconstruct(A)
 
 
 def apply(kind: str, A, seed: int, m: int, s: int = 1) -> np.ndarray:

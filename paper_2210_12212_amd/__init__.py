@@ -304,13 +304,13 @@ class Context:
     def sketch_apply(self, A, sketch: str, m: int, seed: int, sjlt_s: int = 1,
                      prec: str = "f64"):
         """ihsbin_sketch_apply_prec -> SA (m x d float64); prec "f64" or
-        "bf16" (the Gaussian sketch on the BF16 matrix cores)."""
+        "bf16" or "fp8" (the Gaussian sketch on the BF16 or FP8 matrix cores)."""
         torch = _torch()
         SA = torch.empty((m, A.shape[1]), dtype=torch.float64, device=torch.device("cuda", self.device))
         mat = _matrix(A)
         self._check(L.lib().ihsbin_sketch_apply_prec(
             self._h, C.byref(mat), L.SKETCHES[sketch], sjlt_s, m, seed,
-            {"f64": 0, "bf16": 1}[prec], C.c_void_p(SA.data_ptr())))
+            {"f64": 0, "bf16": 1, "fp8": 2}[prec], C.c_void_p(SA.data_ptr())))
         return SA
 
     def precond_factor(self, SA, lam0, want_inverse: bool = True):
@@ -349,7 +349,7 @@ class Context:
         mat = _matrix(A)
         self._check(L.lib().ihsbin_sketch_gram(
             self._h, C.byref(mat), L.SKETCHES[sketch], sjlt_s, m, seed,
-            {"f64": 0, "bf16": 1}[sketch_prec], {"f64": 0, "bf16x3": 1}[gram_prec],
+            {"f64": 0, "bf16": 1, "fp8": 2}[sketch_prec], {"f64": 0, "bf16x3": 1}[gram_prec],
             C.c_void_p(G.data_ptr())))
         return G
 

@@ -122,6 +122,15 @@ void gaussian_sketch_bf16(const MatView& A, uint64_t seed, int64_t m, double* SA
                           double* part, int64_t part_doubles, hipStream_t st,
                           int64_t r_begin = 0);
 int64_t gaussian_sketch_bf16_part_doubles(int64_t m, int64_t n, int64_t d);
+// Gaussian sketch on the FP8 matrix cores: SA = (1/sqrt(m)) S8 A~ where
+// S8 = E4M3(FP32(z)) of the same draws and A~ is A in three e4m3 terms under a
+// per-column power-of-two scale (about 12 bits relative to the column's
+// largest entry).  Sums as in the BF16 form.  Rows [r_begin, m) only.
+int64_t sketch_fp8_work_bytes(int64_t m, int64_t n, int64_t d);
+int64_t gaussian_sketch_fp8_part_doubles(int64_t m, int64_t n, int64_t d);
+void gaussian_sketch_fp8(const MatView& A, uint64_t seed, int64_t m, double* SA, void* work,
+                         double* part, int64_t part_doubles, hipStream_t st,
+                         int64_t r_begin = 0);
 
 // Dual (n < d) helpers: At = A^T (d x n row-major, A's dtype; dense A only)
 // and C = B widened to FP64 (rows x K contiguous).

@@ -125,13 +125,18 @@ static void sketch_apply_impl(Ctx& c, const MatView& A, int kind, int s, int64_t
   if (r_begin < 0 || r_begin >= m || (r_begin > 0 && kind != IHSBIN_GAUSSIAN))
     fail(IHSBIN_EINVAL, "sketch rows out of range");
   c.bytes_moved += matrix_bytes(A) + 8.0 * (double)(m - r_begin) * (double)A.d;
-  if (prec != IHSBIN_SKETCH_F64 && prec != IHSBIN_SKETCH_BF16)
+  if (prec != IHSBIN_SKETCH_F64 && prec != IHSBIN_SKETCH_BF16 && prec != IHSBIN_SKETCH_FP8)
     fail(IHSBIN_EINVAL, "unknown sketch precision");
   if (kind == IHSBIN_GAUSSIAN && prec == IHSBIN_SKETCH_BF16) {
     void* work = c.ws_sketch.ensure((size_t)sketch_bf16_work_bytes(m, A.n, A.d));
     const int64_t pd = gaussian_sketch_bf16_part_doubles(m, A.n, A.d);
     double* part = static_cast<double*>(c.ws_part.ensure(sizeof(double) * (size_t)pd));
     gaussian_sketch_bf16(A, seed, m, SA, work, part, pd, st, r_begin);
+  } else if (kind == IHSBIN_GAUSSIAN && prec == IHSBIN_SKETCH_FP8) {
+    void* work = c.ws_sketch.ensure((size_t)sketch_fp8_work_bytes(m, A.n, A.d));
+    const int64_t pd = gaussian_sketch_fp8_part_doubles(m, A.n, A.d);
+    double* part = static_cast<double*>(c.ws_part.ensure(sizeof(double) * (size_t)pd));
+    gaussian_sketch_fp8(A, seed, m, SA, work, part, pd, st, r_begin);
   } else if (kind == IHSBIN_GAUSSIAN && A.format == IHSBIN_CSR) {
     // (SA)^T = A^T S^T, O(m nnz(A)): each chunk of rows of S is drawn
     // transposed (n x rows), gathered through the column-major copy of A in
@@ -1038,6 +1043,8 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
   double sk = 5.0 * N + 256;
   if (o.sketch == IHSBIN_GAUSSIAN && o.sketch_prec == IHSBIN_SKETCH_BF16) {
     sk = std::max(sk, (double)sketch_bf16_work_bytes(mmax, N, D));
+  } else if (o.sketch == IHSBIN_GAUSSIAN && o.sketch_prec == IHSBIN_SKETCH_FP8) {
+    sk = std::max(sk, (double)sketch_fp8_work_bytes(mmax, N, D));
   } else if (o.sketch == IHSBIN_GAUSSIAN) {
     int64_t blk = (int64_t)((size_t(1) << 30) / (8 * (size_t)N));
     blk = std::min(mmax, std::max<int64_t>(64, (blk / 64) * 64));

@@ -124,3 +124,62 @@ def test_bf16_gaussian_sketch_is_the_rounded_gaussian():
     A = np.random.default_rng(1).standard_normal((n, 4))
     SA = sketch.gaussian_bf16_apply(A, 5, m)
     np.testing.assert_allclose(SA, S16 @ A, rtol=1e-12)
+
+
+def test_round_e4m3_matches_torch_and_format_facts():
+    # torch's float8_e4m3fn conversion rounds to nearest, ties to even (it
+    # gives NaN beyond the format's range, so the comparison stays within it)
+    import torch
+    r = np.random.default_rng(4)
+    x = np.concatenate([r.standard_normal(20000) * 2.0 ** r.integers(-12, 9, 20000),
+                        [0.0, 1.0, -2.5, 448.0, 464.0, -464.0, 2.0 ** -9, 2.0 ** -10]])
+    x = x[np.abs(x) <= 464.0]
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    np.testing.assert_array_equal(rng.round_e4m3(x), ref)
+    v = rng.e4m3_values()
+    assert v[0] == 0.0 and v[1] == 2.0 ** -9 and v[8] == 2.0 ** -6 and v[-1] == 448.0
+    assert np.all(np.diff(v) > 0) and v.size == 127
+    # ties: 1 + 1/16 between 1 (code even) and 1.125 -> 1; 1 + 3/16 -> 1.25;
+    # 2^-10 between 0 and 2^-9 -> 0; 3 * 2^-10 -> 2^-8; saturation beyond 448
+    assert rng.round_e4m3(1.0625) == 1.0 and rng.round_e4m3(-1.0625) == -1.0
+    assert rng.round_e4m3(1.1875) == 1.25
+    assert rng.round_e4m3(2.0 ** -10) == 0.0 and rng.round_e4m3(3 * 2.0 ** -10) == 2.0 ** -8
+    assert rng.round_e4m3(470.0) == 448.0 and rng.round_e4m3(-1e6) == -448.0
+
+
+def test_fp8_terms_scale_and_reconstruction_bound():
+    r = np.random.default_rng(8)
+    A = r.standard_normal((500, 7)) * np.array([1.0, 1e-3, 1e4, 3.0, 448.0, 0.0, 2.0 ** -20])
+    A[0, 1] = 7.0  # one large entry in a small column
+    A = A.astype(np.float32).astype(np.float64)
+    t, e = sketch.fp8_terms(A)
+    mx = np.abs(A).max(axis=0)
+    # e_c: the column maximum lands in (224, 448] * 2^e_c; a zero column keeps 0
+    nz = mx > 0
+    assert np.all(mx[nz] <= np.ldexp(448.0, e[nz])) and np.all(mx[nz] > np.ldexp(224.0, e[nz]))
+    assert e[5] == 0 and np.all(t[:, :, 5] == 0)
+    # every term is an e4m3 value
+    for p in range(3):
+        np.testing.assert_array_equal(rng.round_e4m3(t[p]), t[p])
+    # three terms leave at most 448 * 2^(e_c - 12) of each entry, and each
+    # further term shrinks what is left
+    At = sketch.fp8_reconstruct(A)
+    assert np.all(np.abs(A - At) <= np.ldexp(448.0, e[None, :] - 12))
+    A2 = np.ldexp(t[0] + t[1] / 16.0, e[None, :])
+    assert np.abs(A - At).sum() < np.abs(A - A2).sum()
+    # exact for values that fit 12 bits in the top binade (and for A = I)
+    np.testing.assert_array_equal(sketch.fp8_reconstruct(np.eye(5)), np.eye(5))
+
+
+def test_fp8_gaussian_sketch_is_the_rounded_gaussian():
+    m, n = 64, 3000
+    S = rng.gaussian_matrix(5, m, n)
+    S8 = rng.gaussian_matrix_fp8(5, m, n)
+    # within half an e4m3 unit (2^-4 relative, 2^-10 absolute below 2^-6)
+    assert np.all(np.abs(S8 - S) * np.sqrt(m) <= np.maximum(2.0 ** -4 * np.abs(S) * np.sqrt(m),
+                                                          2.0 ** -10))
+    q = S8 * np.sqrt(m)
+    np.testing.assert_array_equal(rng.round_e4m3(q), q)
+    A = np.random.default_rng(1).standard_normal((n, 4))
+    SA = sketch.gaussian_fp8_apply(A, 5, m)
+    np.testing.assert_allclose(SA, S8 @ sketch.fp8_reconstruct(A), rtol=1e-12)
