@@ -17,9 +17,11 @@ as code):
   sign = +1 if bit 0 of x is 0 else -1;
 * SRHT diagonal sign of row i: bit 0 of draw(key_1, i) (0 -> +1);
 * SRHT sampled row k (with replacement): ((draw(key_2, k) >> 32) * n') >> 32;
-* Gaussian entry q = r*n + i: u1 = ((draw(key_3, 2q) >> 11) + 1) * 2^-53,
-  u2 = (draw(key_3, 2q+1) >> 11) * 2^-53,
-  z = sqrt(-2 ln u1) cos(2 pi u2) (Box and Muller, 1958), entry = z / sqrt(m).
+* Gaussian entries by Box-Muller pairs (Box and Muller, 1958): pair p gives
+  u1 = ((draw(key_3, 2p) >> 11) + 1) * 2^-53, u2 = (draw(key_3, 2p+1) >> 11)
+  * 2^-53, and the two independent N(0, 1) values z_{2p} = rho cos(2 pi u2),
+  z_{2p+1} = rho sin(2 pi u2), rho = sqrt(-2 ln u1); entry q = r*n + i of the
+  m x n sketch is z_q / sqrt(m).
 """
 from __future__ import annotations
 
@@ -88,15 +90,21 @@ def srht_draws(seed: int, n: int, m: int):
 
 
 def gaussian_draws(seed: int, m: int, n: int) -> np.ndarray:
-    """The N(0, 1) draws z (m x n, float64) of the Gaussian sketch, entry q =
-    r * n + k from the pair (2q, 2q + 1) of its stream by Box-Muller."""
+    """The N(0, 1) draws z (m x n, float64) of the Gaussian sketch: entry q =
+    r * n + k is the cosine (q even) or sine (q odd) value of Box-Muller
+    pair q // 2, made from draws (2p, 2p + 1) of the stream."""
     key = stream_key(seed, 3)
-    q = np.arange(m * n, dtype=np.uint64)
-    x1 = draw(key, q * np.uint64(2))
-    x2 = draw(key, q * np.uint64(2) + np.uint64(1))
+    total = m * n
+    p = np.arange((total + 1) // 2, dtype=np.uint64)
+    x1 = draw(key, p * np.uint64(2))
+    x2 = draw(key, p * np.uint64(2) + np.uint64(1))
     u1 = ((x1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
     u2 = (x2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
-    return (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).reshape(m, n)
+    rho = np.sqrt(-2.0 * np.log(u1))
+    z = np.empty(2 * p.size)
+    z[0::2] = rho * np.cos(2.0 * np.pi * u2)
+    z[1::2] = rho * np.sin(2.0 * np.pi * u2)
+    return z[:total].reshape(m, n)
 
 
 def gaussian_matrix(seed: int, m: int, n: int) -> np.ndarray:

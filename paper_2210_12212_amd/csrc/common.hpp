@@ -249,20 +249,24 @@ __host__ __device__ inline uint32_t sm_range(uint64_t x, uint32_t bound) {
   return (uint32_t)(((x >> 32) * (uint64_t)bound) >> 32);
 }
 
-// Gaussian sketch entries: z of the draw pair (x1, x2) by Box-Muller.
-// FP64 form: sqrt(-2 ln u1) cos(2 pi u2)
-// with u1 = (x1 / 2^11 + 1) 2^-53 in (0, 1] and u2 = (x2 / 2^11) 2^-53.
-__device__ inline double box_muller64(uint64_t x1, uint64_t x2) {
+// Gaussian sketch entries by Box-Muller: draw pair p = (x1, x2) = (draw 2p,
+// draw 2p + 1) gives entry 2p = rho cos(2 pi u2) and entry 2p + 1 =
+// rho sin(2 pi u2), rho = sqrt(-2 ln u1), with u1 = (x1 / 2^11 + 1) 2^-53 in
+// (0, 1] and u2 = (x2 / 2^11) 2^-53 in [0, 1).  FP64 form:
+__device__ inline void box_muller64(uint64_t x1, uint64_t x2, double& zc, double& zs) {
   const double u1 = ((double)(x1 >> 11) + 1.0) * 0x1.0p-53;
   const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
-  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+  const double rho = sqrt(-2.0 * log(u1));
+  const double th = 6.283185307179586476925286766559 * u2;
+  zc = rho * cos(th);
+  zs = rho * sin(th);
 }
 
-// The same z in FP32, within a few units in the last place of FP32(z): the
-// uniforms' complements are formed exactly in integers, so ln u1 near u1 = 1
-// is log1p of an exact -(1 - u1), and cos(2 pi u2) is reduced to a quarter
-// turn (and to its complement past an eighth) before FP32 sees the angle.
-__device__ inline float box_muller32(uint64_t x1, uint64_t x2) {
+// The same pair in FP32, each within a few units in the last place of its
+// FP32 rounding: the uniforms' complements are formed exactly in integers, so
+// ln u1 near u1 = 1 is log1p of an exact -(1 - u1), and the angle is reduced
+// to a quarter turn (and to its complement past an eighth) before FP32 sees it.
+__device__ inline void box_muller32(uint64_t x1, uint64_t x2, float& zc, float& zs) {
   const uint64_t k1 = (x1 >> 11) + 1;  // u1 = k1 2^-53
   float lg;
   if (k1 >= (1ull << 52)) {
@@ -270,7 +274,7 @@ __device__ inline float box_muller32(uint64_t x1, uint64_t x2) {
   } else {
     lg = ::logf((float)k1 * 0x1.0p-53f);
   }
-  const float r = sqrtf(-2.0f * lg);
+  const float rho = sqrtf(-2.0f * lg);
   const uint64_t j = x2 >> 11;  // u2 = j 2^-53: quarter q, phi = 2 pi g 2^-53
   const uint32_t q = (uint32_t)(j >> 51);
   const uint64_t g = j & ((1ull << 51) - 1);
@@ -285,8 +289,9 @@ __device__ inline float box_muller32(uint64_t x1, uint64_t x2) {
     c = sinf(psi);
     sn = cosf(psi);
   }
-  const float t = q == 0 ? c : q == 1 ? -sn : q == 2 ? -c : sn;
-  return r * t;
+  // cos and sin of q pi/2 + phi
+  zc = rho * (q == 0 ? c : q == 1 ? -sn : q == 2 ? -c : sn);
+  zs = rho * (q == 0 ? sn : q == 1 ? c : q == 2 ? -sn : -c);
 }
 
 // ------------------------------------------------------------ helpers

@@ -67,24 +67,29 @@ void launch_draw_srht(uint64_t seed, int64_t n, int64_t npad, int64_t m, int8_t*
   IHS_CHECK_LAUNCH();
 }
 
-// Box-Muller on two 53-bit uniforms: u1 in (0, 1], u2 in [0, 1).
+// S (rows x n, row-major) = scale z for sketch rows r0 .. r0 + rows - 1:
+// entry q = r n + i of the stream by its Box-Muller pair (q / 2).  One thread
+// per pair slot: slot t holds chunk entries j = j0 + 2t and j + 1, j0 = -1
+// when the chunk starts on an odd entry (that half belongs to the previous
+// chunk and is not written).
 __global__ void gaussian_fill_kernel(uint64_t key, int64_t r0, int64_t rows, int64_t n,
                                      double scale, double* S) {
-  const int64_t total = rows * n;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+  const int64_t total = rows * n, j0 = -((r0 * n) & 1);
+  const int64_t slots = (total - j0 + 1) / 2;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < slots;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t q = (uint64_t)(r0 * n + t);
-    const uint64_t x1 = sm_draw(key, 2ull * q);
-    const uint64_t x2 = sm_draw(key, 2ull * q + 1ull);
-    const double u1 = ((double)(x1 >> 11) + 1.0) * 0x1.0p-53;
-    const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
-    S[t] = scale * sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+    const int64_t j = j0 + 2 * t;
+    const uint64_t p = (uint64_t)(r0 * n + j) >> 1;
+    double zc, zs;
+    box_muller64(sm_draw(key, 2ull * p), sm_draw(key, 2ull * p + 1ull), zc, zs);
+    if (j >= 0) S[j] = scale * zc;
+    if (j + 1 < total) S[j + 1] = scale * zs;
   }
 }
 
 void launch_gaussian_fill(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
                           double* S, hipStream_t st) {
-  int64_t blocks = cdiv(rows * n, 256);
+  int64_t blocks = cdiv(rows * n / 2 + 1, 256);
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(gaussian_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
                      stream_key(seed, 3), r0, rows, n, 1.0 / std::sqrt((double)m), S);
@@ -110,22 +115,26 @@ void launch_scale_copy(const double* X, int64_t count, double f, double* Y, hipS
 // (row stride `rows`), the layout a product A^T St gathers from.
 __global__ void gaussian_fill_t_kernel(uint64_t key, int64_t r0, int64_t rows, int64_t n,
                                        double scale, double* St) {
-  const int64_t total = rows * n;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+  const int64_t total = rows * n, j0 = -((r0 * n) & 1);
+  const int64_t slots = (total - j0 + 1) / 2;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < slots;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = t / rows, r = r0 + (t - i * rows);
-    const uint64_t q = (uint64_t)(r * n + i);
-    const uint64_t x1 = sm_draw(key, 2ull * q);
-    const uint64_t x2 = sm_draw(key, 2ull * q + 1ull);
-    const double u1 = ((double)(x1 >> 11) + 1.0) * 0x1.0p-53;
-    const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
-    St[t] = scale * sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+    const int64_t j = j0 + 2 * t;
+    const uint64_t p = (uint64_t)(r0 * n + j) >> 1;
+    double z[2];
+    box_muller64(sm_draw(key, 2ull * p), sm_draw(key, 2ull * p + 1ull), z[0], z[1]);
+    for (int h = 0; h < 2; ++h) {
+      const int64_t e = j + h;
+      if (e < 0 || e >= total) continue;
+      const int64_t r = e / n, i = e - r * n;
+      St[i * rows + r] = scale * z[h];
+    }
   }
 }
 
 void launch_gaussian_fill_t(uint64_t seed, int64_t m, int64_t r0, int64_t rows, int64_t n,
                             double* St, hipStream_t st) {
-  int64_t blocks = cdiv(rows * n, 256);
+  int64_t blocks = cdiv(rows * n / 2 + 1, 256);
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(gaussian_fill_t_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
                      stream_key(seed, 3), r0, rows, n, 1.0 / std::sqrt((double)m), St);

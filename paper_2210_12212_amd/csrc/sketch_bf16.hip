@@ -34,27 +34,42 @@ constexpr int kTerms = 2;  // BF16 terms of A
 }  // namespace
 
 // S16[r][k] = BF16(FP32(z)) for sketch row r0 + r, column k < n (0 beyond n);
-// z is the Box-Muller draw of entry (r0 + r, k) of the m x n Gaussian sketch.
-// The FP32 form decides the rounding unless it lies within 64 FP32 units of a
-// BF16 rounding tie, where the FP64 form does (the FP32 error is a few units).
+// z is entry q = (r0 + r) n + k of the Gaussian stream, from its Box-Muller
+// pair (q / 2).  One thread per pair slot of a row: slot t holds columns
+// k = k0 + 2t and k + 1, k0 = -1 when the row starts on an odd entry (halves
+// outside the row are not written).  The FP32 form decides the rounding
+// unless it lies within 64 FP32 units of a BF16 rounding tie, where the FP64
+// form does (the FP32 error is a few units).
 __global__ __launch_bounds__(256) void gauss16_fill_kernel(uint64_t key, int64_t r0, int64_t rows,
                                                            int64_t n, int64_t npad,
                                                            __bf16* __restrict__ S) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
-    const uint64_t q0 = (uint64_t)((r0 + r) * n);
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad;
-         k += (int64_t)gridDim.x * blockDim.x) {
-      float z = 0.0f;
-      if (k < n) {
-        const uint64_t q = q0 + (uint64_t)k;
-        const uint64_t x1 = sm_draw(key, 2ull * q);
-        const uint64_t x2 = sm_draw(key, 2ull * q + 1ull);
-        z = box_muller32(x1, x2);
-        const uint32_t low = __float_as_uint(z) & 0xFFFFu;
-        if (low > 0x8000u - 64u && low < 0x8000u + 64u) z = (float)box_muller64(x1, x2);
+    const int64_t q0 = (r0 + r) * n, k0 = -(q0 & 1);
+    const int64_t slots = (n - k0 + 1) / 2;
+    __bf16* row = S + r * npad;
+    for (int64_t t = tid; t < slots; t += stride) {
+      const int64_t k = k0 + 2 * t;
+      const uint64_t p = (uint64_t)(q0 + k) >> 1;
+      const uint64_t x1 = sm_draw(key, 2ull * p), x2 = sm_draw(key, 2ull * p + 1ull);
+      float z[2];
+      box_muller32(x1, x2, z[0], z[1]);
+      bool near = false;
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t low = __float_as_uint(z[h]) & 0xFFFFu;
+        near |= low > 0x8000u - 64u && low < 0x8000u + 64u;
       }
-      S[r * npad + k] = (__bf16)z;
+      if (near) {
+        double zc, zs;
+        box_muller64(x1, x2, zc, zs);
+        z[0] = (float)zc;
+        z[1] = (float)zs;
+      }
+      if (k >= 0) row[k] = (__bf16)z[0];
+      if (k + 1 < n) row[k + 1] = (__bf16)z[1];
     }
+    for (int64_t k = n + tid; k < npad; k += stride) row[k] = (__bf16)0.0f;
   }
 }
 
@@ -242,7 +257,7 @@ void gaussian_sketch_bf16(const MatView& A, uint64_t seed, int64_t m, double* SA
   for (int64_t r0 = r_begin; r0 < m; r0 += rows) {
     const int64_t rn = std::min(rows, m - r0);
     {
-      const unsigned gx = (unsigned)std::min<int64_t>(cdiv(npad, 256), 64);
+      const unsigned gx = (unsigned)std::min<int64_t>(cdiv(npad / 2 + 1, 256), 64);
       const unsigned gy = (unsigned)std::min<int64_t>(rn, 1024);
       hipLaunchKernelGGL(gauss16_fill_kernel, dim3(gx, gy), dim3(256), 0, st, key, r0, rn, n, npad,
                          S16);

@@ -83,29 +83,43 @@ __global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long* __res
     p[i] = 0ull;
 }
 
-// S8[r][k] = E4M3(FP32(z)) for sketch row r0 + r, column k < n (0 beyond n).
-// The FP32 form of z decides the code when the codes of z (1 - 2^-17), z and
-// z (1 + 2^-17) agree (rounding is monotone, and the FP32 form is within a
-// few units of FP32(z)); otherwise the FP64 form does.
+// S8[r][k] = E4M3(FP32(z)) for sketch row r0 + r, column k < n (0 beyond n),
+// z from the Box-Muller pairs as for the BF16 sketch (one thread per pair
+// slot of a row).  The FP32 form of z decides the code when the codes of
+// z (1 - 2^-17), z and z (1 + 2^-17) agree (rounding is monotone, and the FP32
+// form is within a few units of FP32(z)); otherwise the FP64 form does.
 __global__ __launch_bounds__(256) void gauss8_fill_kernel(uint64_t key, int64_t r0, int64_t rows,
                                                           int64_t n, int64_t npad,
                                                           uint8_t* __restrict__ S) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
-    const uint64_t q0 = (uint64_t)((r0 + r) * n);
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad;
-         k += (int64_t)gridDim.x * blockDim.x) {
-      uint32_t code = 0;
-      if (k < n) {
-        const uint64_t q = q0 + (uint64_t)k;
-        const uint64_t x1 = sm_draw(key, 2ull * q);
-        const uint64_t x2 = sm_draw(key, 2ull * q + 1ull);
-        const float z = box_muller32(x1, x2);
-        code = e4m3_code(z);
-        if (e4m3_code(z * (1.0f - 0x1.0p-17f)) != code || e4m3_code(z * (1.0f + 0x1.0p-17f)) != code)
-          code = e4m3_code((float)box_muller64(x1, x2));
+    const int64_t q0 = (r0 + r) * n, k0 = -(q0 & 1);
+    const int64_t slots = (n - k0 + 1) / 2;
+    uint8_t* row = S + r * npad;
+    for (int64_t t = tid; t < slots; t += stride) {
+      const int64_t k = k0 + 2 * t;
+      const uint64_t p = (uint64_t)(q0 + k) >> 1;
+      const uint64_t x1 = sm_draw(key, 2ull * p), x2 = sm_draw(key, 2ull * p + 1ull);
+      float z[2];
+      box_muller32(x1, x2, z[0], z[1]);
+      uint32_t code[2];
+      bool near = false;
+      for (int h = 0; h < 2; ++h) {
+        code[h] = e4m3_code(z[h]);
+        near |= e4m3_code(z[h] * (1.0f - 0x1.0p-17f)) != code[h] ||
+                e4m3_code(z[h] * (1.0f + 0x1.0p-17f)) != code[h];
       }
-      S[r * npad + k] = (uint8_t)code;
+      if (near) {
+        double zc, zs;
+        box_muller64(x1, x2, zc, zs);
+        code[0] = e4m3_code((float)zc);
+        code[1] = e4m3_code((float)zs);
+      }
+      if (k >= 0) row[k] = (uint8_t)code[0];
+      if (k + 1 < n) row[k + 1] = (uint8_t)code[1];
     }
+    for (int64_t k = n + tid; k < npad; k += stride) row[k] = 0;
   }
 }
 
@@ -365,7 +379,7 @@ void gaussian_sketch_fp8(const MatView& A, uint64_t seed, int64_t m, double* SA,
   for (int64_t r0 = r_begin; r0 < m; r0 += rows) {
     const int64_t rn = std::min(rows, m - r0);
     {
-      const unsigned gx = (unsigned)std::min<int64_t>(cdiv(npad, 256), 64);
+      const unsigned gx = (unsigned)std::min<int64_t>(cdiv(npad / 2 + 1, 256), 64);
       const unsigned gy = (unsigned)std::min<int64_t>(rn, 1024);
       hipLaunchKernelGGL(gauss8_fill_kernel, dim3(gx, gy), dim3(256), 0, st, key, r0, rn, n, npad,
                          S8);

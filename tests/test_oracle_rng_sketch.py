@@ -80,6 +80,31 @@ def test_gaussian_entries_are_standard_normal():
     z = (S * np.sqrt(50)).reshape(-1)
     assert abs(z.mean()) < 0.01 and abs(z.var() - 1) < 0.01
     assert stats.kstest(z, "norm").pvalue > 1e-4
+    # the two values of a Box-Muller pair are independent: uncorrelated, and
+    # their squares too
+    a, b = z[0::2], z[1::2]
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.01 and abs(np.corrcoef(a * a, b * b)[0, 1]) < 0.01
+
+
+def test_gaussian_pairs_in_polar_form():
+    # pair p in polar form: z_2p^2 + z_2p+1^2 = -2 ln u1 and the angle of
+    # (z_2p, z_2p+1) is 2 pi u2, with u1, u2 from draws 2p and 2p + 1; an odd
+    # column count puts pairs across rows (entry q = r n + i throughout)
+    m, n = 7, 13
+    z = rng.gaussian_draws(11, m, n).reshape(-1)
+    key = rng.stream_key(11, 3)
+    for p in range(0, (m * n) // 2):
+        x1 = int(rng.draw(key, 2 * p)) >> 11
+        x2 = int(rng.draw(key, 2 * p + 1)) >> 11
+        u1 = (x1 + 1) / 2.0 ** 53
+        u2 = x2 / 2.0 ** 53
+        c, s_ = z[2 * p], z[2 * p + 1]
+        assert abs(c * c + s_ * s_ + 2.0 * np.log(u1)) <= 1e-12 * (1.0 - 2.0 * np.log(u1))
+        ang = np.arctan2(s_, c) % (2.0 * np.pi)
+        d = abs(ang - 2.0 * np.pi * u2)
+        assert min(d, 2.0 * np.pi - d) <= 1e-9
+    # a row's draws do not depend on m: the first rows of a taller sketch
+    np.testing.assert_array_equal(rng.gaussian_draws(11, 9, n)[:m], z.reshape(m, n))
 
 
 @pytest.mark.parametrize("kind", ["gaussian", "srht", "countsketch"])
