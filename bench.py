@@ -430,8 +430,11 @@ def main():
                     help="arithmetic of the basis steps' A^T A products (dense FP32 A; other "
                          "inputs always FP64): FP64, FP32 matrix cores, or FP64 until the "
                          "increments are small, then FP32 (default)")
-    ap.add_argument("--f32-switch", type=float, default=1e-2,
-                    help="relative increment below which --basis-prec mixed uses FP32")
+    ap.add_argument("--f32-switch", type=float, default=3e-2,
+                    help="relative increment below which --basis-prec mixed uses FP32 "
+                         "(3e-2: on the 262144 x 4096 workload 1e-2 gives 8.3e-8 at every "
+                         "lambda, 2e-2 to 5e-2 switch one step earlier at 8.6e-8, 1e-1 "
+                         "gives 2.3e-7)")
     ap.add_argument("--m-policy", choices=("spectral", "alg4", "fixed"), default="spectral",
                     help="sketch size: spectral probe (default), Algorithm 4 at lam_min, or m0")
     ap.add_argument("--oracle-lambdas", type=int, default=12,
