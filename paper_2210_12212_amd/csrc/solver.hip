@@ -288,11 +288,16 @@ static void gram_impl(Ctx& c, const double* SA, int64_t m, int64_t d, double* G,
 
 // Whether P_S keeps its factors in split form (PsFactors) at dimension d.  The
 // split form skips two GEMMs of the inverse (about L d^3 / 4 flop) but applies
-// through three products instead of one; where those run split-K (d >= 1024)
+// through three products instead of one.  Where those run split-K (d >= 1024)
 // their extra launches outweigh the saving until d reaches about 3000
 // (measured: d = 2048 path 43.2 ms whole, 44.4 ms split; d = 4096 and 8192
-// 7 ms and 59 ms faster split).
-static bool split_factors(int64_t d) { return d < 1024 || d >= 3072; }
+// 7 ms and 59 ms faster split).  Below 1024 a single build is launch-bound
+// (256 served 2048 x 256 builds: 796 paths/s split against 914 whole), while
+// a batched build, whose launches cover every problem, gains (2990 -> 3167
+// paths/s for the same 256 problems).
+static bool split_factors(int64_t d, bool batched = false) {
+  return d >= 3072 || (batched && d < 1024);
+}
 
 // H_l = G + lam0_l I, factor in place, and Linv_l = L_l^-1.
 // gper > 0: matrix l is built from G block l / gper (blocks of d x d), so the
@@ -1752,7 +1757,7 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     double* Li1 = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)P * d * d));
     PsFactors F1;
     F1.n1 = factor_impl(c, G, d, std::vector<double>(P, lam0[0]), Lf1, Li1, dinvb, lamb, 1,
-                        split_factors(d));
+                        split_factors(d, true));
     F1.X = Li1;
     F1.Lf = Lf1;
     EarlyIfAnySlow early;
@@ -1793,7 +1798,7 @@ static int build_batch_impl(Ctx& c, int P, const ihsbin_matrix* Ain, int64_t str
     Timer tf;
     Lf = static_cast<double*>(Lb.ensure(sizeof(double) * (size_t)nl * d * d));
     Linv = static_cast<double*>(Ib.ensure(sizeof(double) * (size_t)nl * d * d));
-    PF.n1 = factor_impl(c, G, d, lam0s, Lf, Linv, dinvb, lamb, L, split_factors(d));
+    PF.n1 = factor_impl(c, G, d, lam0s, Lf, Linv, dinvb, lamb, L, split_factors(d, true));
     PF.X = Linv;
     PF.Lf = Lf;
     IHS_HIP(hipStreamSynchronize(st));
