@@ -136,9 +136,11 @@ __global__ __launch_bounds__(256) void col_absmax_kernel(const T* __restrict__ A
   atomicMax(colmax + c, (unsigned long long)__double_as_longlong(mx));
 }
 
-// e_c = the smallest e with max |a_c| <= 448 2^e (0 for a zero column).
+// e_c = the smallest e with max |a_c| <= 448 2^e (0 for a zero column, and
+// for a column holding an infinity or NaN, whose terms are then meaningless
+// but finite: the loops below stop only for finite maxima).
 __device__ inline int col_exponent(double mx) {
-  if (!(mx > 0.0)) return 0;
+  if (!(mx > 0.0) || isinf(mx)) return 0;
   int e = ilogb(mx) - 8;
   while (mx > ldexp(448.0, e)) ++e;
   while (mx <= ldexp(448.0, e - 1)) --e;

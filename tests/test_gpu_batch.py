@@ -56,6 +56,23 @@ def test_batch_paths_match_oracle(torch, ctx, kind, K, dt):
         paths[p].free()
 
 
+@pytest.mark.parametrize("prec", [1, 2])
+def test_batch_low_precision_gaussian_sketch(torch, ctx, prec):
+    # BF16 (1) and FP8 (2) Gaussian sketches in a batched build: each problem
+    # sketched on the matrix cores, every path within the bar
+    P, n, d = 4, 2048, 96
+    As, Bs, At, Bt = stack(torch, P, n, d, 1, seed=610 + prec, dtype=np.float32)
+    lams = W.lambda_grid(1e-3, 1e2, 30)
+    paths, rep = ctx.path_build_batch(At, Bt, 1e-3, 1e2, sketch="gaussian", m=64, seed=11,
+                                      tol=1e-8, sketch_prec=prec)
+    assert rep["status"] == 0 and len(paths) == P, rep
+    for p in range(P):
+        err = direct.rel_err(paths[p].eval(lams).cpu().numpy(),
+                             direct.ridge_path(As[p], Bs[p], lams))
+        assert err.max() <= 1e-6, (p, err.max())
+        paths[p].free()
+
+
 def test_batch_strided_and_noalloc_eval(torch, ctx):
     # problems taken every other block of a larger allocation (strides wider
     # than one problem), evaluated through the allocation-free entry point

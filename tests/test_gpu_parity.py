@@ -225,7 +225,8 @@ def test_path_each_sketch_matrix_rhs(torch, ctx, kind):
     _check_path(X.cpu().numpy(), A, B, lams)
 
 
-@pytest.mark.parametrize("prec,fmt", [("f64", "dense"), ("bf16", "dense"), ("f64", "csr")])
+@pytest.mark.parametrize("prec,fmt", [("f64", "dense"), ("bf16", "dense"), ("fp8", "dense"),
+                                      ("f64", "csr")])
 def test_gaussian_growth_keeps_rows(torch, ctx, prec, fmt):
     # a Gaussian sketch grown by the probes keeps the rows it has formed
     # (rescaled); the path must equal, up to rounding, the one built with the
@@ -238,7 +239,7 @@ def test_gaussian_growth_keeps_rows(torch, ctx, prec, fmt):
         Ad = dev(torch, A)
     B, _ = W.rhs(A, 2, 0.1, seed=42)
     lams = W.lambda_grid(1e-3, 1e2, 21)
-    sp = {"f64": 0, "bf16": 1}[prec]
+    sp = {"f64": 0, "bf16": 1, "fp8": 2}[prec]
     X1, r1 = ctx.solve_path(Ad, dev(torch, B), lams, sketch="gaussian", m=16, seed=5,
                             adaptive_m=1, sketch_prec=sp, rate_target=0.3)
     assert r1["status"] == 0 and r1["sketch_trials"] >= 2, r1
