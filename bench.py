@@ -145,7 +145,7 @@ def m_sweep(args, torch, W, Context):
     ev, V = direct.eig_of_gram(direct.gram(p.A))
     ref = direct.solve_from_eig(ev, V, direct.atb(p.A, p.B), p.lambdas)
     log(f"[sweep] {p.name}: oracle ready")
-    cap = min(p.n, 32 * p.d)
+    cap = args.sweep_m_max or min(p.n, 32 * p.d)
     runs = [("spectral", dict(m=p.m, adaptive_m=1))]
     for r in args.sweep_rates:
         runs.append((f"spectral_rate{r:g}", dict(m=p.m, adaptive_m=1, rate_target=r)))
@@ -465,6 +465,8 @@ def main():
                     default=[], help="--m-sweep: also the spectral policy at these rate targets")
     ap.add_argument("--sweep-m-min", type=int, default=0,
                     help="--m-sweep: fixed sketch sizes from this one up")
+    ap.add_argument("--sweep-m-max", type=int, default=0,
+                    help="--m-sweep: fixed sketch sizes up to this one (default: the cap 32 d)")
     ap.add_argument("--sweep-no-alg4", action="store_true")
     ap.add_argument("--m-sweep", action="store_true",
                     help="only compare sketch-size policies (spectral, Algorithm 4, fixed m)")
