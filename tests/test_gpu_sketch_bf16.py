@@ -28,8 +28,10 @@ def dev(torch, a):
 
 
 # ragged m, n and d; (40000, 64, 256) takes the K-split path
+# (300000, 40, 96): more rows than one split may sum in FP32, so the K-splits
+# are forced and added in FP64
 @pytest.mark.parametrize("n,d,m", [(3000, 200, 300), (1000, 129, 77), (40000, 64, 256),
-                                   (5000, 512, 1024), (257, 33, 5)])
+                                   (5000, 512, 1024), (257, 33, 5), (300000, 40, 96)])
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_bf16_gaussian_sketch_matches_oracle(torch, ctx, n, d, m, dt):
     r = np.random.default_rng(n + d)
