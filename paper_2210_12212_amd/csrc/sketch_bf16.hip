@@ -10,7 +10,7 @@
 // kMaxSplitRows rows of A, at most 128 of those added into a second FP32 sum,
 // and K-splits beyond that added in FP64.  The dropped r is of the order of
 // what the FP32 sums lose; together they stay within 2e-5 of sum |s||a| per
-// entry (a few 1e-7 in practice) and perturb the preconditioner only.
+// entry and perturb the preconditioner only.
 //
 // Layout: XS[p][col][row] (the terms of A, rows contiguous, padded to a
 // multiple of 64) and S16[row][k] (a chunk of sketch rows, same padding), so

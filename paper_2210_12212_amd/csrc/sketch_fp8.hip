@@ -8,7 +8,7 @@
 // smallest e_c with max_k |a_kc| <= 448 2^e_c) and split into three e4m3
 // terms, each the rounding of 16 times what the earlier ones leave:
 //
-//   a = 2^e_c (t0 + t1 / 16 + t2 / 256) + r,   |r| <= 2^-12 2^e_c max-scale,
+//   a = 2^e_c (t0 + t1 / 16 + t2 / 256) + r,   |r| <= 448 2^(e_c - 12),
 //
 // i.e. about 12 significant bits relative to the column's largest entry (the
 // preconditioner built from it is a fixed SPD operator: the path keeps its
