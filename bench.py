@@ -147,6 +147,8 @@ def m_sweep(args, torch, W, Context):
     log(f"[sweep] {p.name}: oracle ready")
     cap = args.sweep_m_max or min(p.n, 32 * p.d)
     runs = [("spectral", dict(m=p.m, adaptive_m=1))]
+    if p.sketch == "gaussian":
+        runs.append(("spectral_exact", dict(m=p.m, adaptive_m=3)))
     for r in args.sweep_rates:
         runs.append((f"spectral_rate{r:g}", dict(m=p.m, adaptive_m=1, rate_target=r)))
     if not args.sweep_no_alg4:
@@ -336,7 +338,7 @@ def _serve_requests(args, W):
 
 def _serve_opts(req, args):
     return dict(sketch="gaussian" if req["dense"] else "countsketch", seed=req["seed"],
-                adaptive_m={"spectral": 1, "alg4": 2}[args.serve_m_policy], tol=args.tol,
+                adaptive_m={"spectral": 1, "alg4": 2, "spectral-exact": 3}[args.serve_m_policy], tol=args.tol,
                 sketch_prec={"f64": 0, "bf16": 1, "fp8": 2}[args.serve_sketch_prec],
                 rate_target=args.rate_target,
                 lanczos_steps=args.lanczos_steps)
@@ -435,8 +437,11 @@ def main():
                          "(3e-2: on the 262144 x 4096 workload 1e-2 gives 8.3e-8 at every "
                          "lambda, 2e-2 to 5e-2 switch one step earlier at 8.6e-8, 1e-1 "
                          "gives 2.3e-7)")
-    ap.add_argument("--m-policy", choices=("spectral", "alg4", "fixed"), default="spectral",
-                    help="sketch size: spectral probe (default), Algorithm 4 at lam_min, or m0")
+    ap.add_argument("--m-policy", choices=("spectral", "alg4", "fixed", "spectral-exact"),
+                    default="spectral",
+                    help="sketch size: spectral probe (default), Algorithm 4 at lam_min, m0, "
+                         "or the spectral probe with S = I once a Gaussian sketch would cost "
+                         "more than A^T A")
     ap.add_argument("--oracle-lambdas", type=int, default=12,
                     help="lambdas of the sample the CPU oracle's Cholesky form is timed on")
     ap.add_argument("--no-oracle", action="store_true")
@@ -449,7 +454,8 @@ def main():
                     help="serve many 2048 x 256 dense problems submitted at once instead")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=4)
-    ap.add_argument("--serve-m-policy", choices=("spectral", "alg4"), default="spectral",
+    ap.add_argument("--serve-m-policy", choices=("spectral", "alg4", "spectral-exact"),
+                    default="spectral",
                     help="sketch size of served builds")
     ap.add_argument("--serve-sketch-prec", choices=("f64", "bf16", "fp8"), default="bf16",
                     help="arithmetic of the Gaussian sketch product of served dense requests")
@@ -534,7 +540,7 @@ def main():
     opts = dict(sketch=p.sketch, m=p.m, seed=p.sketch_seed, tol=args.tol,
                 rate_target=args.rate_target, lanczos_steps=args.lanczos_steps, timing=1,
                 gram_prec={"f64": 0, "bf16x3": 1}[args.gram_prec],
-                adaptive_m={"fixed": 0, "spectral": 1, "alg4": 2}[args.m_policy],
+                adaptive_m={"fixed": 0, "spectral": 1, "alg4": 2, "spectral-exact": 3}[args.m_policy],
                 sketch_prec={"f64": 0, "bf16": 1, "fp8": 2}[args.sketch_prec],
                 basis_prec={"f64": 0, "f32": 1, "mixed": 2}[args.basis_prec],
                 f32_switch=args.f32_switch)

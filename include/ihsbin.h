@@ -101,7 +101,12 @@ typedef struct {
                               the lowest interval is <= rate_target;
                               2 = Algorithm 4 (Section 5.1) at lam_min, from
                               m0 = m (0: max(16, d / 4)), parameters
-                              from alg4          */
+                              from alg4;
+                              3 = as 1, but a Gaussian sketch that would need
+                              more rows than it takes to form A^T A at the same
+                              cost (8 d for the BF16/FP8 forms, d for FP64)
+                              is replaced by S = I (the exact Hessian, m = n;
+                              single builds)                                  */
   double rate_target;      /* default 0.6                                      */
   int64_t m_max;           /* cap for adaptive m; 0 = library default           */
   int32_t lanczos_steps;   /* Lanczos steps of each spectrum estimate (default

@@ -832,7 +832,17 @@ struct Sketcher {
     const int64_t m = initial_m(2 * A.d);
     m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(A.n, 32 * A.d));
     if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(A.n)));
+    if (exact_switch() && o.m_max <= 0) m_cap = std::max(m_cap, A.n);
     G = static_cast<double*>(Gb.ensure(sizeof(double) * A.d * A.d));
+  }
+  // adaptive_m = 3: a Gaussian sketch costs 2 m n d multiply-adds against
+  // 2 n d^2 for A^T A itself; the BF16 and FP8 forms run at about 8 times the
+  // FP64 Gram's rate (the FP64 form at the same rate), so past exact_rows()
+  // rows the sketch is dearer than the exact Hessian, and m jumps to n (S = I)
+  bool exact_switch() const { return o.adaptive_m == 3 && o.sketch == IHSBIN_GAUSSIAN; }
+  int64_t exact_rows() const { return (o.sketch_prec == IHSBIN_SKETCH_F64 ? 1 : 8) * A.d; }
+  int64_t next_m(int64_t want) const {
+    return exact_switch() && want > exact_rows() ? std::max(want, A.n) : want;
   }
   // o.m rounded up to a multiple of s, or dflt when o.m is 0
   int64_t initial_m(int64_t dflt) const {
@@ -1032,6 +1042,7 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
   if (m % s) m += s - m % s;
   int64_t m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(N, 32 * D));
   if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(N)));
+  if (o.adaptive_m == 3 && o.sketch == IHSBIN_GAUSSIAN && o.m_max <= 0) m_cap = std::max(m_cap, N);
   const int64_t mmax = o.adaptive_m ? std::max(m, m_cap) : m;
   const int64_t rows = std::min(mmax, N);
   double b = 0;
@@ -1125,7 +1136,7 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   if (o.k_max < 1 || o.k_max > 4096) fail(IHSBIN_EINVAL, "k_max out of range");
   if (o.k_fixed < 0 || o.k_fixed > 4096) fail(IHSBIN_EINVAL, "k_fixed out of range");
   if (!(o.tol > 0.0)) fail(IHSBIN_EINVAL, "tol must be positive");
-  if (o.adaptive_m < 0 || o.adaptive_m > 2) fail(IHSBIN_EINVAL, "adaptive_m out of range");
+  if (o.adaptive_m < 0 || o.adaptive_m > 3) fail(IHSBIN_EINVAL, "adaptive_m out of range");
   if (!(o.sigma_d2 >= 0.0) || !std::isfinite(o.sigma_d2)) fail(IHSBIN_EINVAL, "need sigma_d2 >= 0");
   if (o.basis_prec < IHSBIN_BASIS_F64 || o.basis_prec > IHSBIN_BASIS_MIXED)
     fail(IHSBIN_EINVAL, "basis_prec out of range");
@@ -1173,8 +1184,9 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
   // ---- sketch, with adaptive m
   Timer tsk;
   Sketcher sketch_m(c, A, o);
-  int64_t m = sketch_m.initial_m(2 * d);
   const int64_t m_cap = sketch_m.m_cap;
+  int64_t m = sketch_m.initial_m(2 * d);
+  if (o.adaptive_m == 3 && !o.taus) m = std::min(m_cap, sketch_m.next_m(m));
   const int& trials = sketch_m.trials;
   PoolBuf Lb(c.pool), Ib(c.pool), dinvb(c.pool), lamb(c.pool);
   double* G = sketch_m.G;
@@ -1196,9 +1208,9 @@ static int build_impl(Ctx& c, const ihsbin_matrix* Ain, const void* B, int64_t K
     factor = std::min(16.0, std::max(2.0, factor));
     int64_t mult = 1;
     while (mult < factor) mult <<= 1;
-    return std::min(m_cap, m * mult);
+    return std::min(m_cap, sketch_m.next_m(m * mult));
   };
-  const bool adapt = o.adaptive_m == 1 && !o.taus;
+  const bool adapt = (o.adaptive_m == 1 || o.adaptive_m == 3) && !o.taus;
   // spectrum estimates on the FP32 matrix cores when the basis products may
   // run there (dense FP32 A)
   const bool spec32 = o.basis_prec != IHSBIN_BASIS_F64 && A.format == IHSBIN_DENSE &&

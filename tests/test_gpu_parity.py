@@ -251,6 +251,29 @@ def test_gaussian_growth_keeps_rows(torch, ctx, prec, fmt):
     _check_path(X1, A, B, lams)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gaussian_exact_switch(torch, ctx, prec):
+    # adaptive_m = 3: a Gaussian sketch that would need more rows than the
+    # exact Gram costs (d for FP64, 8 d for BF16) is replaced by S = I (m = n);
+    # a sketch that meets the target first is kept as the spectral policy has it
+    A = W.dense_decay(6000, 150, seed=61, dtype=np.float32)
+    B, _ = W.rhs(A, 2, 0.1, seed=62)
+    lams = W.lambda_grid(1e-3, 1e2, 21)
+    Ad, Bd = dev(torch, A), dev(torch, B)
+    X, rep = ctx.solve_path(Ad, Bd, lams, sketch="gaussian", m=64, seed=5, adaptive_m=3,
+                            sketch_prec=prec, rate_target=0.05)
+    assert rep["status"] == 0 and rep["m_used"] == 6000, rep
+    _check_path(X.cpu().numpy(), A, B, lams)
+    if prec == 0:
+        return  # an FP64 Gaussian sketch of d rows already costs the exact Gram
+    X1, r1 = ctx.solve_path(Ad, Bd, lams, sketch="gaussian", m=300, seed=5, adaptive_m=1,
+                            sketch_prec=prec, rate_target=0.9)
+    X3, r3 = ctx.solve_path(Ad, Bd, lams, sketch="gaussian", m=300, seed=5, adaptive_m=3,
+                            sketch_prec=prec, rate_target=0.9)
+    assert r3["m_used"] == r1["m_used"] <= 8 * 150, (r1, r3)
+    assert np.array_equal(X1.cpu().numpy(), X3.cpu().numpy())
+
+
 def test_path_csr(torch, ctx):
     M = W.csr_zipf(6000, 200, 8, seed=31, dtype=np.float32)
     B, _ = W.rhs(M, 1, 0.1, seed=32)
