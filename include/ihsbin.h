@@ -106,7 +106,7 @@ typedef struct {
                               more rows than it takes to form A^T A at the same
                               cost (8 d for the BF16/FP8 forms, d for FP64)
                               is replaced by S = I (the exact Hessian, m = n;
-                              single builds)                                  */
+                              dense A, single builds)                         */
   double rate_target;      /* default 0.6                                      */
   int64_t m_max;           /* cap for adaptive m; 0 = library default           */
   int32_t lanczos_steps;   /* Lanczos steps of each spectrum estimate (default

@@ -838,8 +838,11 @@ struct Sketcher {
   // adaptive_m = 3: a Gaussian sketch costs 2 m n d multiply-adds against
   // 2 n d^2 for A^T A itself; the BF16 and FP8 forms run at about 8 times the
   // FP64 Gram's rate (the FP64 form at the same rate), so past exact_rows()
-  // rows the sketch is dearer than the exact Hessian, and m jumps to n (S = I)
-  bool exact_switch() const { return o.adaptive_m == 3 && o.sketch == IHSBIN_GAUSSIAN; }
+  // rows the sketch is dearer than the exact Hessian, and m jumps to n (S = I;
+  // dense A only: S = I copies A densely)
+  bool exact_switch() const {
+    return o.adaptive_m == 3 && o.sketch == IHSBIN_GAUSSIAN && A.format == IHSBIN_DENSE;
+  }
   int64_t exact_rows() const { return (o.sketch_prec == IHSBIN_SKETCH_F64 ? 1 : 8) * A.d; }
   int64_t next_m(int64_t want) const {
     return exact_switch() && want > exact_rows() ? std::max(want, A.n) : want;
@@ -1042,7 +1045,8 @@ static int64_t footprint_impl(const ihsbin_matrix* A0, int64_t K, double lam_min
   if (m % s) m += s - m % s;
   int64_t m_cap = o.m_max > 0 ? o.m_max : std::max<int64_t>(m, std::min<int64_t>(N, 32 * D));
   if (o.sketch == IHSBIN_SRHT) m_cap = std::min(m_cap, std::max(m, next_pow2(N)));
-  if (o.adaptive_m == 3 && o.sketch == IHSBIN_GAUSSIAN && o.m_max <= 0) m_cap = std::max(m_cap, N);
+  if (o.adaptive_m == 3 && o.sketch == IHSBIN_GAUSSIAN && !csr && o.m_max <= 0)
+    m_cap = std::max(m_cap, N);
   const int64_t mmax = o.adaptive_m ? std::max(m, m_cap) : m;
   const int64_t rows = std::min(mmax, N);
   double b = 0;
