@@ -274,6 +274,22 @@ def test_gaussian_exact_switch(torch, ctx, prec):
     assert np.array_equal(X1.cpu().numpy(), X3.cpu().numpy())
 
 
+def test_gaussian_exact_switch_leaves_csr_sketched(torch, ctx):
+    # S = I would copy a CSR matrix densely: for CSR A the policy stays the
+    # spectral one (same m and path as adaptive_m = 1)
+    M = W.csr_zipf(6000, 150, 10, seed=63, dtype=np.float32)
+    B, _ = W.rhs(M, 1, 0.1, seed=64)
+    lams = W.lambda_grid(1e-3, 1e2, 15)
+    Md, Bd = csr_dev(torch, M), dev(torch, B)
+    X1, r1 = ctx.solve_path(Md, Bd, lams, sketch="gaussian", m=64, seed=5, adaptive_m=1,
+                            rate_target=0.05)
+    X3, r3 = ctx.solve_path(Md, Bd, lams, sketch="gaussian", m=64, seed=5, adaptive_m=3,
+                            rate_target=0.05)
+    assert r3["m_used"] == r1["m_used"], (r1, r3)
+    assert np.array_equal(X1.cpu().numpy(), X3.cpu().numpy())
+    _check_path(X3.cpu().numpy(), M, B, lams)
+
+
 def test_path_csr(torch, ctx):
     M = W.csr_zipf(6000, 200, 8, seed=31, dtype=np.float32)
     B, _ = W.rhs(M, 1, 0.1, seed=32)
